@@ -1,0 +1,499 @@
+"""Oracle for the RIS ray tracer: TEST INFRASTRUCTURE ONLY.
+
+Plain FP64 reference of the method of "Ray Tracing Algorithm for
+Reconfigurable Intelligent Surfaces" (arXiv 2402.13034).  Only the tests, the
+smoke check and the CPU-baseline leg of the benchmark use it; the product path
+never imports it.  It shares no code with the GPU library: geometry and
+visibility are in ``rt_oracle.c`` (brute force, FP64 image method, FP32 ray
+decisions), the field model is written out here in NumPy FP64.
+
+Field model (Section II-A):
+  eq. (1)/(2)/(3): power density and the Tx field at distance d;
+  eq. (4): launch field  |E_t| = sqrt(2 eta0 P_t G_t F_t(theta_t));
+  eq. (5)-(7): per element  sqrt(G F_in F_out d_y d_z / (4 pi)) Gamma_m
+               e^{-j 2 pi d_t / lambda} / d_t;
+  eq. (8): to the Rx  sqrt(G_r F_r(theta_r)) lambda / (4 pi d_r)
+           e^{-j 2 pi d_r / lambda};
+  eq. (9): coherent sum over elements and multipath components;
+  eq. (10): P_r = |E_r|^2 / (2 eta0).
+Readings where the paper is silent: eta0 = 120 pi exactly (as printed);
+c = 299 792 458 m/s; a reflected component spreads as 1 / (total unfolded
+length) (image source); a pattern value for theta >= 90 deg of a cos^q
+pattern is 0 and a path with any zero pattern factor is not emitted; the
+scalar per-triangle reflection coefficient multiplies once per bounce.
+"""
+from __future__ import annotations
+
+import ctypes
+import itertools
+import math
+import os
+import subprocess
+from typing import Dict, Optional
+
+import numpy as np
+
+C0 = 299_792_458.0
+ETA0 = 120.0 * math.pi
+EPS = 1e-4
+KEY_BITS = 21
+
+PAT_ISO = 0
+PAT_COSPOW = 1
+PAT_MONOPOLE = 2
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "rt_oracle.c")
+_LIB_PATH = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+
+def build(force: bool = False) -> str:
+    """Compile the C part of the oracle (gcc, FP64/FP32 IEEE, no contraction)."""
+    if force or not os.path.exists(_LIB_PATH) or \
+            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
+        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
+               "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB_PATH)
+    return _LIB_PATH
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        build()
+        L = ctypes.CDLL(_LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        L.or_discover.restype = i64
+        L.or_discover.argtypes = [P, P, i64, P, ctypes.c_int, P, i64, ctypes.c_int, P, P]
+        L.or_find_paths.restype = i64
+        L.or_find_paths.argtypes = [P, P, P, i64, P, P, i64, ctypes.c_int, P, i64, i64, P, P, P, P]
+        L.or_ris_paths.restype = None
+        L.or_ris_paths.argtypes = [P, P, P, i64, P, P, i64, P, i64, P, P, ctypes.c_int, P, P, P, P]
+        L.or_leg_blocked.restype = ctypes.c_int
+        L.or_leg_blocked.argtypes = [P, P, P, i64, P, P, i64, i64]
+        L.or_contains.restype = ctypes.c_int
+        L.or_contains.argtypes = [P, P, i64, P]
+        L.or_fib_dir.restype = None
+        L.or_fib_dir.argtypes = [i64, i64, P]
+        _lib = L
+    return _lib
+
+
+def _p(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _c(a, dtype):
+    return np.ascontiguousarray(a, dtype=dtype)
+
+
+# --------------------------------------------------------------------------
+# geometry wrappers
+# --------------------------------------------------------------------------
+def fib_dir(i: int, n: int) -> np.ndarray:
+    out = np.zeros(3)
+    lib().or_fib_dir(i, n, _p(out))
+    return out
+
+
+def leg_blocked(scene, A, B, skip_a: int = -1, skip_b: int = -1) -> bool:
+    """Is the leg A -> B blocked?  skip_a / skip_b: surfaces of its end
+    points (-1 for none)."""
+    V = _c(scene.V, np.float32)
+    T = _c(scene.T, np.int32)
+    S = _c(scene.surf, np.int32)
+    A = _c(A, np.float64)
+    B = _c(B, np.float64)
+    return bool(lib().or_leg_blocked(_p(V), _p(T), _p(S), T.shape[0], _p(A), _p(B), skip_a, skip_b))
+
+
+def contains(scene, tri: int, p) -> bool:
+    V = _c(scene.V, np.float32)
+    T = _c(scene.T, np.int32)
+    p = _c(p, np.float64)
+    return bool(lib().or_contains(_p(V), _p(T), tri, _p(p)))
+
+
+def discover(scene, src, n_rays: int, K: int, hemi_normal=None):
+    """Discovery rays from ``src``: returns (hits [rows, K], launched [rows],
+    segments traced)."""
+    V = _c(scene.V, np.float32)
+    T = _c(scene.T, np.int32)
+    src = _c(src, np.float64)
+    hemi = hemi_normal is not None
+    hn = _c(hemi_normal if hemi else np.zeros(3), np.float64)
+    rows = 2 * n_rays if hemi else n_rays
+    hits = np.empty((rows, K), np.int32)
+    launched = np.empty(rows, np.uint8)
+    segs = lib().or_discover(_p(V), _p(T), T.shape[0], _p(src), int(hemi), _p(hn),
+                             n_rays, K, _p(hits), _p(launched))
+    return hits, launched.astype(bool), int(segs)
+
+
+def seq_key(seq) -> int:
+    """Packed key of a triangle sequence: sum (t_i + 1) << (21 i); the empty
+    sequence is 0.  Sorting by this key is the canonical candidate order."""
+    k = 0
+    for i, t in enumerate(seq):
+        if t < 0:
+            break
+        k |= (int(t) + 1) << (KEY_BITS * i)
+    return k
+
+
+def key_seq(key: int, K: int):
+    out = [-1] * K
+    for i in range(K):
+        v = (key >> (KEY_BITS * i)) & ((1 << KEY_BITS) - 1)
+        if v == 0:
+            break
+        out[i] = v - 1
+    return out
+
+
+def surface_hits(scene, hits: np.ndarray) -> np.ndarray:
+    """Triangle hit lists -> surface hit lists (-1 stays -1)."""
+    out = np.full(hits.shape, -1, np.int32)
+    ok = hits >= 0
+    out[ok] = scene.surf[hits[ok]]
+    return out
+
+
+def candidates_from_hits(hits: np.ndarray, K: int) -> np.ndarray:
+    """All distinct prefixes (length 1..K) of every (surface) hit list, plus
+    the empty sequence, sorted by key.  Returns int32 [nc, K], -1 padded."""
+    keys = {0}
+    for row in hits:
+        k = 0
+        for i in range(K):
+            t = int(row[i])
+            if t < 0:
+                break
+            k |= (t + 1) << (KEY_BITS * i)
+            keys.add(k)
+    ks = sorted(keys)
+    return np.asarray([key_seq(k, K) for k in ks], np.int32).reshape(len(ks), K)
+
+
+def candidates_from_hits_np(hits: np.ndarray, K: int) -> np.ndarray:
+    """Same set as candidates_from_hits, via numpy.unique (large inputs)."""
+    h = hits.astype(np.int64)
+    keys = [np.zeros(1, np.uint64)]
+    acc = np.zeros(h.shape[0], np.uint64)
+    alive = np.ones(h.shape[0], bool)
+    for i in range(K):
+        alive &= h[:, i] >= 0
+        acc = acc | (np.where(alive, h[:, i] + 1, 0).astype(np.uint64) << np.uint64(KEY_BITS * i))
+        keys.append(acc[alive])
+    u = np.unique(np.concatenate(keys))
+    out = np.full((u.size, K), -1, np.int32)
+    mask = np.uint64((1 << KEY_BITS) - 1)
+    for i in range(K):
+        v = ((u >> np.uint64(KEY_BITS * i)) & mask).astype(np.int64)
+        prev = out[:, i - 1] >= 0 if i > 0 else np.ones(u.size, bool)
+        out[:, i] = np.where((v > 0) & prev, v - 1, -1)
+    return out
+
+
+def exhaustive_candidates(n_surf: int, K: int) -> np.ndarray:
+    """Every sequence of at most K surfaces with no immediate repeat, plus
+    the empty sequence, in key order."""
+    seqs = [[]]
+    for k in range(1, K + 1):
+        for s in itertools.product(range(n_surf), repeat=k):
+            if any(s[i] == s[i + 1] for i in range(k - 1)):
+                continue
+            seqs.append(list(s))
+    seqs.sort(key=seq_key)
+    out = np.full((len(seqs), K), -1, np.int32)
+    for i, s in enumerate(seqs):
+        out[i, :len(s)] = s
+    return out
+
+
+def find_paths(scene, src, cands: np.ndarray, rx: np.ndarray, K: int):
+    """Valid, unblocked paths src -> cand -> rx.  Returns (rx_idx, cand_idx,
+    points [n, K, 3], triangles [n, K]) in (rx, candidate) order."""
+    V = _c(scene.V, np.float32)
+    T = _c(scene.T, np.int32)
+    SF = _c(scene.surf, np.int32)
+    S = _c(src, np.float64)
+    cands = _c(cands, np.int32)
+    rx = _c(rx, np.float64)
+    cap = max(16, 8 * rx.shape[0])
+    while True:
+        o_rx = np.empty(cap, np.int32)
+        o_c = np.empty(cap, np.int32)
+        o_p = np.empty((cap, K, 3), np.float64)
+        o_t = np.empty((cap, K), np.int32)
+        n = lib().or_find_paths(_p(V), _p(T), _p(SF), T.shape[0], _p(S), _p(cands), cands.shape[0],
+                                K, _p(rx), rx.shape[0], cap, _p(o_rx), _p(o_c), _p(o_p), _p(o_t))
+        if n >= 0:
+            return o_rx[:n].copy(), o_c[:n].copy(), o_p[:n].copy(), o_t[:n].copy()
+        cap = -n
+
+
+def ris_paths(scene, tx, elems, rx, uptr, useq, K: int):
+    V = _c(scene.V, np.float32)
+    T = _c(scene.T, np.int32)
+    SF = _c(scene.surf, np.int32)
+    tx = _c(tx, np.float64)
+    elems = _c(elems, np.float64)
+    rx = _c(rx, np.float64)
+    uptr = _c(uptr, np.int64)
+    useq = _c(useq if useq.size else np.zeros((1, K), np.int32), np.int32)
+    R, M = rx.shape[0], elems.shape[0]
+    n_slots = int(uptr[-1]) + R
+    valid = np.zeros((n_slots, M), np.uint8)
+    pts = np.zeros((n_slots, M, K, 3), np.float64)
+    tri = np.zeros((n_slots, M, K), np.int32)
+    txm = np.zeros(M, np.uint8)
+    lib().or_ris_paths(_p(V), _p(T), _p(SF), T.shape[0], _p(tx), _p(elems), M, _p(rx), R,
+                       _p(uptr), _p(useq), K, _p(valid), _p(pts), _p(tri), _p(txm))
+    return valid.astype(bool), pts, tri, txm.astype(bool)
+
+
+# --------------------------------------------------------------------------
+# antenna patterns (power patterns, normalised to 1 at the maximum)
+# --------------------------------------------------------------------------
+def pattern(kind: int, param: float, cos_t: np.ndarray, lam: float) -> np.ndarray:
+    """F(theta) from cos(theta).
+    ISO: 1.  COSPOW: cos^param for cos > 0, else 0 (eq. (11) with
+    param = G_t/2 - 1, eq. (13) with param = 1).  MONOPOLE: eq. (12) with
+    height h = param * lambda, 0 at theta = 0 and pi."""
+    c = np.clip(np.asarray(cos_t, np.float64), -1.0, 1.0)
+    if kind == PAT_ISO:
+        return np.ones_like(c)
+    if kind == PAT_COSPOW:
+        return np.where(c > 0.0, np.power(np.maximum(c, 0.0), param), 0.0)
+    if kind == PAT_MONOPOLE:
+        kh = 2.0 * math.pi * param
+        s = np.sqrt(np.maximum(0.0, 1.0 - c * c))
+        with np.errstate(divide="ignore", invalid="ignore"):
+            f = ((np.cos(kh * c) - math.cos(kh)) / s) ** 2
+        return np.where(s > 0.0, f, 0.0)
+    raise ValueError(kind)
+
+
+def _cos_between(v: np.ndarray, axis: np.ndarray) -> np.ndarray:
+    a = np.asarray(axis, np.float64)
+    return (v @ a) / (np.linalg.norm(v, axis=-1) * np.linalg.norm(a))
+
+
+def _phase(total_len: np.ndarray, lam: float) -> np.ndarray:
+    """-2 pi frac(d / lambda): the phase of e^{-j 2 pi d / lambda}."""
+    x = total_len / lam
+    return -2.0 * math.pi * (x - np.floor(x))
+
+
+def _chain(S: np.ndarray, P: np.ndarray, k: np.ndarray, X: np.ndarray):
+    """Per path: total length, first-leg vector, vector from the Rx to the
+    last point before it.  S, X: [n, 3]; P: [n, K, 3]; k: [n]."""
+    n = X.shape[0]
+    D = np.zeros(n)
+    first = np.empty((n, 3))
+    last = np.empty((n, 3))
+    Kmax = P.shape[1] if P.ndim == 3 else 0
+    for kk in range(0, Kmax + 1):
+        sel = k == kk
+        if not np.any(sel):
+            continue
+        pts = [S[sel]] + [P[sel, j] for j in range(kk)] + [X[sel]]
+        for a, b in zip(pts[:-1], pts[1:]):
+            D[sel] += np.linalg.norm(b - a, axis=1)
+        first[sel] = pts[1] - pts[0]
+        last[sel] = pts[-2] - pts[-1]
+    return D, first, last
+
+
+def refl_product(scene, tris: np.ndarray) -> np.ndarray:
+    """Product of the reflection coefficients of the triangles a path
+    reflects on (-1 entries are no reflection)."""
+    coef = scene.refl_re.astype(np.float64) + 1j * scene.refl_im.astype(np.float64)
+    out = np.ones(tris.shape[0], np.complex128)
+    if coef.size == 0:
+        return out
+    for j in range(tris.shape[1]):
+        t = tris[:, j]
+        out = out * np.where(t >= 0, coef[np.maximum(t, 0)], 1.0)
+    return out
+
+
+def env_amplitudes(prob, rx_idx, tris, pts):
+    """Complex amplitudes of Tx -> environment -> Rx paths (eq. (3) written in
+    the form of eq. (8)): A_t(v1) prod(R) S_r lambda / (4 pi D) e^{-jkD}."""
+    lam = prob.wavelength
+    n = rx_idx.shape[0]
+    k = (tris >= 0).sum(axis=1)
+    S = np.broadcast_to(prob.tx_pos, (n, 3))
+    X = prob.rx_pos[rx_idx]
+    D, first, last = _chain(S, pts, k, X)
+    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, _cos_between(first, prob.tx_ant.axis), lam)
+    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, _cos_between(last, prob.rx_ant.axis), lam)
+    At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
+    Sr = np.sqrt(prob.rx_ant.gain * Fr)
+    a = At * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * D) * np.exp(1j * _phase(D, lam))
+    emitted = (Ft > 0.0) & (Fr > 0.0)
+    return a, D, emitted
+
+
+def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
+    """Per-element channel (eqs. (4), (7), (8) without Gamma_m):
+    A_t(Tx->m) sqrt(G F_in F_out d_y d_z / 4pi) e^{-jk d_t} / d_t prod(R) S_r
+    lambda / (4 pi D_r) e^{-jk D_r}."""
+    lam = prob.wavelength
+    ris = prob.ris
+    k = (tris >= 0).sum(axis=1)
+    m = ris.elems[m_idx]
+    X = prob.rx_pos[rx_idx]
+    Dr, first, last = _chain(m, pts, k, X)
+    vt = m - prob.tx_pos[None, :]
+    dt = np.linalg.norm(vt, axis=1)
+    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, _cos_between(vt, prob.tx_ant.axis), lam)
+    Fin = pattern(PAT_COSPOW, ris.q, _cos_between(-vt, ris.normal), lam)
+    Fout = pattern(PAT_COSPOW, ris.q, _cos_between(first, ris.normal), lam)
+    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, _cos_between(last, prob.rx_ant.axis), lam)
+    At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
+    elem = np.sqrt(ris.gain * Fin * Fout * ris.dy * ris.dz / (4.0 * math.pi))
+    Sr = np.sqrt(prob.rx_ant.gain * Fr)
+    a = (At * elem / dt * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * Dr)
+         * np.exp(1j * _phase(dt + Dr, lam)))
+    emitted = (Ft > 0.0) & (Fin > 0.0) & (Fout > 0.0) & (Fr > 0.0)
+    return a, dt + Dr, emitted
+
+
+# --------------------------------------------------------------------------
+# the whole path
+# --------------------------------------------------------------------------
+def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None) -> Dict[str, np.ndarray]:
+    """Channel of one problem.
+
+    mode = "sbr": candidate surface sequences from spherical-Fibonacci
+      discovery rays from the Tx (full sphere) and from the RIS centre
+      (half-space in front of the RIS), n_rays per source;
+    mode = "exhaustive": every sequence of at most K surfaces.
+    Returns env paths (Tx -> Rx, order 0..K), the sequences V(rx) valid from
+    the RIS centre, RIS slots and their validity, H [R, M] and E_env [R].
+    """
+    K = prob.order
+    sc = prob.scene
+    n = prob.n_rays if n_rays is None else n_rays
+    R = prob.rx_pos.shape[0]
+    out: Dict[str, np.ndarray] = {}
+    segs = 0
+    if mode == "sbr":
+        h_tx, _, s1 = discover(sc, prob.tx_pos, n, K)
+        out["hits_tx"] = h_tx
+        c_tx = candidates_from_hits_np(surface_hits(sc, h_tx), K)
+        segs += s1
+        if prob.ris is not None:
+            h_u, launched_u, s2 = discover(sc, prob.ris.centre, n, K, hemi_normal=prob.ris.normal)
+            out["hits_u"] = h_u
+            out["launched_u"] = launched_u
+            c_u = candidates_from_hits_np(surface_hits(sc, h_u), K)
+            segs += s2
+    elif mode == "exhaustive":
+        c_tx = exhaustive_candidates(sc.n_surf, K)
+        c_u = c_tx
+    else:
+        raise ValueError(mode)
+    out["cand_tx"] = c_tx
+    e_rx, e_c, e_pts, e_tri = find_paths(sc, prob.tx_pos, c_tx, prob.rx_pos, K)
+    a_env, d_env, em = env_amplitudes(prob, e_rx, e_tri, e_pts)
+    out["env_rx"] = e_rx[em]
+    out["env_seq"] = c_tx[e_c][em]
+    out["env_tri"] = e_tri[em]
+    out["env_amp"] = a_env[em]
+    out["env_len"] = d_env[em]
+    out["env_pts"] = e_pts[em]
+    E_env = np.zeros(R, np.complex128)
+    np.add.at(E_env, e_rx[em], a_env[em])
+    out["E_env"] = E_env
+    if prob.ris is None:
+        out["segments"] = segs
+        return out
+    out["cand_u"] = c_u
+    u_rx, u_c, _, _ = find_paths(sc, prob.ris.centre, c_u, prob.rx_pos, K)
+    u_seq = c_u[u_c]
+    keep = (u_seq >= 0).sum(axis=1) >= 1
+    u_rx, u_seq = u_rx[keep], u_seq[keep]
+    uptr = np.zeros(R + 1, np.int64)
+    np.add.at(uptr, u_rx + 1, 1)
+    uptr = np.cumsum(uptr)
+    out["u_rx"] = u_rx
+    out["u_seq"] = u_seq
+    out["uptr"] = uptr
+    M = prob.ris.elems.shape[0]
+    valid, pts, tri, txm = ris_paths(sc, prob.tx_pos, prob.ris.elems, prob.rx_pos, uptr, u_seq, K)
+    n_slots = valid.shape[0]
+    slot_rx = np.repeat(np.arange(R), np.diff(uptr) + 1)
+    slot_seq = np.full((n_slots, K), -1, np.int32)
+    for r in range(R):
+        base = uptr[r] + r
+        cnt = uptr[r + 1] - uptr[r]
+        slot_seq[base + 1: base + 1 + cnt] = u_seq[uptr[r]:uptr[r + 1]]
+    sl, mm = np.nonzero(valid)
+    a, dtot, em = ris_amplitudes(prob, slot_rx[sl], mm, tri[sl, mm], pts[sl, mm])
+    H = np.zeros((R, M), np.complex128)
+    np.add.at(H, (slot_rx[sl][em], mm[em]), a[em])
+    emitted = np.zeros_like(valid)
+    emitted[sl[em], mm[em]] = True
+    out["ris_slot_rx"] = slot_rx
+    out["ris_slot_seq"] = slot_seq
+    out["ris_valid"] = emitted
+    out["ris_tri"] = tri
+    out["ris_amp"] = a[em]
+    out["ris_amp_idx"] = np.stack([sl[em], mm[em]], axis=1)
+    out["ris_len"] = dtot[em]
+    out["txm_clear"] = txm
+    out["H"] = H
+    out["segments"] = segs
+    return out
+
+
+def ris_exact(prob, cands: np.ndarray):
+    """The plain definition the centre-point heuristic approximates: for every
+    element m, every sequence in ``cands`` is tried from m itself (no
+    restriction to sequences valid from the RIS centre).  Returns H [R, M] and
+    the number of emitted paths per (rx, m)."""
+    K = prob.order
+    R = prob.rx_pos.shape[0]
+    M = prob.ris.elems.shape[0]
+    H = np.zeros((R, M), np.complex128)
+    count = np.zeros((R, M), np.int64)
+    for m in range(M):
+        if not leg_blocked(prob.scene, prob.tx_pos, prob.ris.elems[m]):
+            rx, ci, pts, tri = find_paths(prob.scene, prob.ris.elems[m], cands, prob.rx_pos, K)
+            a, _, em = ris_amplitudes(prob, rx, np.full(rx.shape[0], m), tri, pts)
+            np.add.at(H, (rx[em], np.full(int(em.sum()), m)), a[em])
+            np.add.at(count, (rx[em], np.full(int(em.sum()), m)), 1)
+    return H, count
+
+
+def ris_sum(E_env: np.ndarray, H: np.ndarray, gamma: np.ndarray, scale: float = 1.0):
+    """eq. (9)/(10): E[r, c] = E_env[r] + scale * sum_m H[r, m] Gamma[m, c];
+    P = |E|^2 / (2 eta0).  FP64."""
+    E = E_env[:, None] + scale * (H.astype(np.complex128) @ gamma.astype(np.complex128))
+    return E, np.abs(E) ** 2 / (2.0 * ETA0)
+
+
+def ris_sum_loop(E_env, H, gamma, scale: float = 1.0):
+    """The same sum as a plain triple loop (small sizes only)."""
+    R, M = H.shape
+    C = gamma.shape[1]
+    E = np.zeros((R, C), np.complex128)
+    for r in range(R):
+        for c in range(C):
+            acc = 0j
+            for m in range(M):
+                acc += complex(H[r, m]) * complex(gamma[m, c])
+            E[r, c] = complex(E_env[r]) + scale * acc
+    return E
+
+
+def power(E) -> np.ndarray:
+    return np.abs(E) ** 2 / (2.0 * ETA0)

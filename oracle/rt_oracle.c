@@ -1,0 +1,542 @@
+/*
+ * Oracle for the RIS ray tracer: TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, brute-force CPU implementation of the geometric part of the
+ * method of "Ray Tracing Algorithm for Reconfigurable Intelligent Surfaces"
+ * (arXiv 2402.13034).  It is used by the tests, by the smoke check and by the
+ * CPU baseline leg of the benchmark, never by the product path.  It shares no
+ * code with the GPU library.
+ *
+ * What it computes (field evaluation lives in oracle.py, in FP64 NumPy):
+ *   - discovery rays from a source, closest hit over every triangle, specular
+ *     bounces (stand-in for the analytic first stage of the hybrid tracer,
+ *     Section II);
+ *   - the image method between a source and a receiver for a given sequence
+ *     of triangles (Section II-B; sources are the Tx, the RIS centre and each
+ *     RIS element);
+ *   - visibility of every leg of a path by ray launch (the second stage of the
+ *     hybrid tracer, Section II, and the relaunch of Section IV-A).
+ *
+ * Precision readings (the paper names none):
+ *   - decisions that pick triangle IDs by ray launch (closest hit, occlusion)
+ *     are taken in FP32, the precision of the GPU kernels, with one fixed
+ *     formula (Moller-Trumbore, left-to-right sums, no fused multiply-add,
+ *     one correctly rounded division);
+ *   - image method, containment and side tests, lengths: FP64, no fused
+ *     multiply-add.
+ * Compile with -ffp-contract=off and without -ffast-math.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+
+#define OR_EPS 1e-4 /* metres: legs ignore hits within EPS of their ends */
+
+/* ----------------------------------------------------------------------- */
+/* FP32 ray / triangle test                                                 */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+    float v0[3], e1[3], e2[3];
+} tri32;
+
+static void make_tri32(const float* V, const int32_t* T, int64_t i, tri32* t)
+{
+    const float* a = V + 3 * (int64_t)T[3 * i + 0];
+    const float* b = V + 3 * (int64_t)T[3 * i + 1];
+    const float* c = V + 3 * (int64_t)T[3 * i + 2];
+    for (int k = 0; k < 3; ++k) {
+        t->v0[k] = a[k];
+        t->e1[k] = b[k] - a[k];
+        t->e2[k] = c[k] - a[k];
+    }
+}
+
+/* Moller-Trumbore, two-sided.  Returns 1 and the parameter t if the ray
+ * o + t d meets the closed triangle with tmin < t < tmax. */
+static int hit32(const float o[3], const float d[3], const tri32* tr, float tmin, float tmax,
+                 float* t_out)
+{
+    const float* e1 = tr->e1;
+    const float* e2 = tr->e2;
+    float px = d[1] * e2[2] - d[2] * e2[1];
+    float py = d[2] * e2[0] - d[0] * e2[2];
+    float pz = d[0] * e2[1] - d[1] * e2[0];
+    float det = e1[0] * px + e1[1] * py + e1[2] * pz;
+    if (det == 0.0f) return 0;
+    float inv = 1.0f / det;
+    float sx = o[0] - tr->v0[0];
+    float sy = o[1] - tr->v0[1];
+    float sz = o[2] - tr->v0[2];
+    float u = (sx * px + sy * py + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return 0;
+    float qx = sy * e1[2] - sz * e1[1];
+    float qy = sz * e1[0] - sx * e1[2];
+    float qz = sx * e1[1] - sy * e1[0];
+    float v = (d[0] * qx + d[1] * qy + d[2] * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return 0;
+    float t = (e2[0] * qx + e2[1] * qy + e2[2] * qz) * inv;
+    if (!(t > tmin && t < tmax)) return 0;
+    *t_out = t;
+    return 1;
+}
+
+/* Closest hit over all triangles except `skip`; ties in t go to the lowest
+ * triangle index. Returns -1 on a miss. */
+static int64_t closest32(const tri32* tris, int64_t nt, const float o[3], const float d[3],
+                         float tmin, int64_t skip, float* t_best)
+{
+    int64_t best = -1;
+    float bt = INFINITY;
+    for (int64_t i = 0; i < nt; ++i) {
+        if (i == skip) continue;
+        float t;
+        if (hit32(o, d, &tris[i], tmin, INFINITY, &t)) {
+            if (t < bt) {
+                bt = t;
+                best = i;
+            }
+        }
+    }
+    *t_best = bt;
+    return best;
+}
+
+/* Specular reflection of d off the plane of triangle tr:
+ * n = e1 x e2 (not normalised), d' = d - (2 (d.n) / (n.n)) n. */
+static void reflect32(const tri32* tr, const float d[3], float out[3])
+{
+    const float* e1 = tr->e1;
+    const float* e2 = tr->e2;
+    float nx = e1[1] * e2[2] - e1[2] * e2[1];
+    float ny = e1[2] * e2[0] - e1[0] * e2[2];
+    float nz = e1[0] * e2[1] - e1[1] * e2[0];
+    float dn = d[0] * nx + d[1] * ny + d[2] * nz;
+    float nn = nx * nx + ny * ny + nz * nz;
+    float k = (2.0f * dn) / nn;
+    out[0] = d[0] - k * nx;
+    out[1] = d[1] - k * ny;
+    out[2] = d[2] - k * nz;
+}
+
+static tri32* build_tris(const float* V, const int32_t* T, int64_t nt)
+{
+    tri32* tris = (tri32*)malloc(sizeof(tri32) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; ++i) make_tri32(V, T, i, &tris[i]);
+    return tris;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Discovery                                                                */
+/* ----------------------------------------------------------------------- */
+/* Spherical Fibonacci point i of n (FP64):
+ *   z = 1 - (2 i + 1) / n,  phi = 2 pi frac(i (sqrt 5 - 1) / 2). */
+void or_fib_dir(int64_t i, int64_t n, double out[3])
+{
+    const double g = (sqrt(5.0) - 1.0) / 2.0;
+    double z = 1.0 - (double)(2 * i + 1) / (double)n;
+    double x = (double)i * g;
+    double ph = 6.283185307179586 * (x - floor(x));
+    double r = sqrt(1.0 - z * z);
+    out[0] = r * cos(ph);
+    out[1] = r * sin(ph);
+    out[2] = z;
+}
+
+/*
+ * Shoot discovery rays from `src` and record up to K closest-hit triangle IDs
+ * per ray (-1 after the first miss).
+ *   hemi == 0: n rays on the full sphere; rows = n.
+ *   hemi != 0: a 2n-point sphere, of which only the directions with
+ *              d . hemi_n > 0 (FP64) are launched; rows = 2n, rows of rays
+ *              not launched are all -1 and `launched` is 0 for them.
+ * Each bounce starts at the FP32 hit point, ignores the triangle just hit and
+ * hits with t <= EPS.  Returns the number of segments traced.
+ */
+int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double src[3], int hemi,
+                    const double hemi_n[3], int64_t n, int K, int32_t* hits, uint8_t* launched)
+{
+    tri32* tris = build_tris(V, T, nt);
+    int64_t rows = hemi ? 2 * n : n;
+    int64_t segs = 0;
+#pragma omp parallel for schedule(dynamic, 256) reduction(+ : segs)
+    for (int64_t i = 0; i < rows; ++i) {
+        double d64[3];
+        or_fib_dir(i, rows, d64);
+        for (int b = 0; b < K; ++b) hits[i * K + b] = -1;
+        int go = 1;
+        if (hemi) go = (d64[0] * hemi_n[0] + d64[1] * hemi_n[1] + d64[2] * hemi_n[2]) > 0.0;
+        launched[i] = (uint8_t)go;
+        if (!go) continue;
+        float o[3] = {(float)src[0], (float)src[1], (float)src[2]};
+        float d[3] = {(float)d64[0], (float)d64[1], (float)d64[2]};
+        int64_t skip = -1;
+        for (int b = 0; b < K; ++b) {
+            float t;
+            segs += 1;
+            int64_t h = closest32(tris, nt, o, d, (float)OR_EPS, skip, &t);
+            if (h < 0) break;
+            hits[i * K + b] = (int32_t)h;
+            float p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+            float r[3];
+            reflect32(&tris[h], d, r);
+            o[0] = p[0]; o[1] = p[1]; o[2] = p[2];
+            d[0] = r[0]; d[1] = r[1]; d[2] = r[2];
+            skip = h;
+        }
+    }
+    free(tris);
+    return segs;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Visibility of a leg (FP32 decision)                                      */
+/* ----------------------------------------------------------------------- */
+/* The leg A -> B (FP64 end points) is blocked if some triangle that is not
+ * part of surface skip_a or skip_b (the surfaces its end points lie on, -1 for
+ * none) is met at EPS < t < L - EPS by the FP32 ray with origin fl(A) and
+ * direction fl((B - A) / L). */
+static int leg_blocked(const tri32* tris, const int32_t* surf, int64_t nt, const double A[3],
+                       const double B[3], int64_t skip_a, int64_t skip_b)
+{
+    double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
+    double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    float o[3] = {(float)A[0], (float)A[1], (float)A[2]};
+    float d[3] = {(float)(w0 / L), (float)(w1 / L), (float)(w2 / L)};
+    float tmin = (float)OR_EPS;
+    float tmax = (float)(L - OR_EPS);
+    if (!(tmax > tmin)) return 0;
+    for (int64_t i = 0; i < nt; ++i) {
+        if (surf[i] == skip_a || surf[i] == skip_b) continue;
+        float t;
+        if (hit32(o, d, &tris[i], tmin, tmax, &t)) return 1;
+    }
+    return 0;
+}
+
+int or_leg_blocked(const float* V, const int32_t* T, const int32_t* surf, int64_t nt,
+                   const double A[3], const double B[3], int64_t skip_a, int64_t skip_b)
+{
+    tri32* tris = build_tris(V, T, nt);
+    int r = leg_blocked(tris, surf, nt, A, B, skip_a, skip_b);
+    free(tris);
+    return r;
+}
+
+/* ----------------------------------------------------------------------- */
+/* Image method (FP64)                                                      */
+/* ----------------------------------------------------------------------- */
+typedef struct {
+    double v[3][3]; /* vertices */
+    double n[3];    /* (v1 - v0) x (v2 - v0) */
+    double c;       /* n . v0 */
+} tri64;
+
+static void make_tri64(const float* V, const int32_t* T, int64_t i, tri64* t)
+{
+    for (int j = 0; j < 3; ++j)
+        for (int k = 0; k < 3; ++k) t->v[j][k] = (double)V[3 * (int64_t)T[3 * i + j] + k];
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = t->v[1][k] - t->v[0][k];
+        e2[k] = t->v[2][k] - t->v[0][k];
+    }
+    t->n[0] = e1[1] * e2[2] - e1[2] * e2[1];
+    t->n[1] = e1[2] * e2[0] - e1[0] * e2[2];
+    t->n[2] = e1[0] * e2[1] - e1[1] * e2[0];
+    t->c = t->n[0] * t->v[0][0] + t->n[1] * t->v[0][1] + t->n[2] * t->v[0][2];
+}
+
+static double plane_side(const tri64* t, const double p[3])
+{
+    return (t->n[0] * p[0] + t->n[1] * p[1] + t->n[2] * p[2]) - t->c;
+}
+
+static double edge_raw(const double s[2], const double e[2], const double p[2])
+{
+    return (e[0] - s[0]) * (p[1] - s[1]) - (e[1] - s[1]) * (p[0] - s[0]);
+}
+
+/* Edge function of the directed edge s -> e at p, evaluated from the
+ * lexicographically smaller end point so that the two directions of one edge
+ * give exactly opposite values (an edge shared by two triangles then splits
+ * the plane identically for both). */
+static double edge2(const double s[2], const double e[2], const double p[2])
+{
+    int s_first = (s[0] < e[0]) || (s[0] == e[0] && s[1] < e[1]);
+    return s_first ? edge_raw(s, e, p) : -edge_raw(e, s, p);
+}
+
+/* Top-left ownership of a directed edge of a counter-clockwise triangle. */
+static int top_left(const double s[2], const double e[2])
+{
+    double dy = e[1] - s[1];
+    double dx = e[0] - s[0];
+    return (dy < 0.0) || (dy == 0.0 && dx < 0.0);
+}
+
+/* Is p (assumed on the plane) inside the triangle?  Projection drops the
+ * axis of largest |n| (lowest axis on ties); the projected triangle is made
+ * counter-clockwise; a point on an edge belongs to the triangle only if that
+ * edge is top-left, so a point on an edge shared by two coplanar triangles
+ * belongs to exactly one of them. */
+static int contains64(const tri64* t, const double p[3])
+{
+    double ax = fabs(t->n[0]), ay = fabs(t->n[1]), az = fabs(t->n[2]);
+    int drop = 0;
+    if (ay > ax && ay >= az) drop = 1;
+    else if (az > ax && az > ay) drop = 2;
+    int i0 = (drop + 1) % 3, i1 = (drop + 2) % 3;
+    double a[2] = {t->v[0][i0], t->v[0][i1]};
+    double b[2] = {t->v[1][i0], t->v[1][i1]};
+    double c[2] = {t->v[2][i0], t->v[2][i1]};
+    double q[2] = {p[i0], p[i1]};
+    double area = edge2(a, b, c);
+    if (area == 0.0) return 0;
+    if (area < 0.0) {
+        double tmp0 = b[0], tmp1 = b[1];
+        b[0] = c[0]; b[1] = c[1];
+        c[0] = tmp0; c[1] = tmp1;
+    }
+    double w0 = edge2(b, c, q);
+    double w1 = edge2(c, a, q);
+    double w2 = edge2(a, b, q);
+    int in0 = (w0 > 0.0) || (w0 == 0.0 && top_left(b, c));
+    int in1 = (w1 > 0.0) || (w1 == 0.0 && top_left(c, a));
+    int in2 = (w2 > 0.0) || (w2 == 0.0 && top_left(a, b));
+    return in0 && in1 && in2;
+}
+
+int or_contains(const float* V, const int32_t* T, int64_t tri, const double p[3])
+{
+    tri64 t;
+    make_tri64(V, T, tri, &t);
+    return contains64(&t, p);
+}
+
+/* Surfaces: planar sets of coplanar triangles (a wall, a face of a box).
+ * surf[i] is the surface of triangle i; a surface's plane is that of its
+ * lowest-numbered triangle. */
+typedef struct {
+    int64_t n;       /* number of surfaces */
+    int64_t* ptr;    /* n + 1 */
+    int64_t* tris;   /* triangle indices, grouped by surface, ascending */
+} surf_table;
+
+static void build_surfaces(const int32_t* surf, int64_t nt, surf_table* st)
+{
+    int64_t n = 0;
+    for (int64_t i = 0; i < nt; ++i)
+        if (surf[i] + 1 > n) n = surf[i] + 1;
+    st->n = n;
+    st->ptr = (int64_t*)calloc((size_t)(n + 1), sizeof(int64_t));
+    st->tris = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; ++i) st->ptr[surf[i] + 1] += 1;
+    for (int64_t s = 0; s < n; ++s) st->ptr[s + 1] += st->ptr[s];
+    int64_t* fill = (int64_t*)calloc((size_t)(n > 0 ? n : 1), sizeof(int64_t));
+    for (int64_t i = 0; i < nt; ++i) {
+        int64_t s = surf[i];
+        st->tris[st->ptr[s] + fill[s]] = i;
+        fill[s] += 1;
+    }
+    free(fill);
+}
+
+static void free_surfaces(surf_table* st)
+{
+    free(st->ptr);
+    free(st->tris);
+}
+
+/* Which triangle of surface s contains p (-1 if none). */
+static int64_t surface_contains(const tri64* t64, const surf_table* st, int64_t s, const double p[3])
+{
+    for (int64_t j = st->ptr[s]; j < st->ptr[s + 1]; ++j)
+        if (contains64(&t64[st->tris[j]], p)) return st->tris[j];
+    return -1;
+}
+
+/* Image method for source S, receiver X and surfaces seq[0..k-1].
+ * Images: I_0 = S, I_i = mirror of I_{i-1} in plane i.  Back-trace from X:
+ * P_i = (segment I_i -> P_{i+1}) meets plane i at parameter s in (0, 1) and
+ * lies inside surface i.  Then each P_i must have its neighbours (P_{i-1}
+ * or S, P_{i+1} or X) strictly on the same side of plane i.
+ * Returns 1, the points and the triangles that contain them on success. */
+static int image_path(const tri64* t64, const surf_table* st, const int32_t* seq, int k,
+                      const double S[3], const double X[3], double P[][3], int64_t* tri_of)
+{
+    double I[8][3];
+    I[0][0] = S[0]; I[0][1] = S[1]; I[0][2] = S[2];
+    for (int i = 1; i <= k; ++i) {
+        const tri64* t = &t64[st->tris[st->ptr[seq[i - 1]]]];
+        double nn = t->n[0] * t->n[0] + t->n[1] * t->n[1] + t->n[2] * t->n[2];
+        double f = 2.0 * plane_side(t, I[i - 1]) / nn;
+        for (int c = 0; c < 3; ++c) I[i][c] = I[i - 1][c] - f * t->n[c];
+    }
+    double Q[3] = {X[0], X[1], X[2]};
+    for (int i = k; i >= 1; --i) {
+        const tri64* t = &t64[st->tris[st->ptr[seq[i - 1]]]];
+        double w[3] = {Q[0] - I[i][0], Q[1] - I[i][1], Q[2] - I[i][2]};
+        double den = t->n[0] * w[0] + t->n[1] * w[1] + t->n[2] * w[2];
+        if (den == 0.0) return 0;
+        double s = (t->c - (t->n[0] * I[i][0] + t->n[1] * I[i][1] + t->n[2] * I[i][2])) / den;
+        if (!(s > 0.0 && s < 1.0)) return 0;
+        double p[3] = {I[i][0] + s * w[0], I[i][1] + s * w[1], I[i][2] + s * w[2]};
+        int64_t tri = surface_contains(t64, st, seq[i - 1], p);
+        if (tri < 0) return 0;
+        tri_of[i - 1] = tri;
+        P[i - 1][0] = p[0]; P[i - 1][1] = p[1]; P[i - 1][2] = p[2];
+        Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
+    }
+    for (int i = 0; i < k; ++i) {
+        const tri64* t = &t64[st->tris[st->ptr[seq[i]]]];
+        const double* prev = (i == 0) ? S : P[i - 1];
+        const double* next = (i == k - 1) ? X : P[i + 1];
+        double a = plane_side(t, prev);
+        double b = plane_side(t, next);
+        if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return 0;
+    }
+    return 1;
+}
+
+/* All legs of a path S -> P_0 .. P_{k-1} -> X unblocked?  A leg ignores the
+ * surfaces its end points lie on. */
+static int path_clear(const tri32* tris, const int32_t* surf, int64_t nt, const int32_t* seq, int k,
+                      const double S[3], const double X[3], double P[][3])
+{
+    for (int j = 0; j <= k; ++j) {
+        const double* A = (j == 0) ? S : P[j - 1];
+        const double* B = (j == k) ? X : P[j];
+        int64_t sa = (j == 0) ? -1 : seq[j - 1];
+        int64_t sb = (j == k) ? -1 : seq[j];
+        if (leg_blocked(tris, surf, nt, A, B, sa, sb)) return 0;
+    }
+    return 1;
+}
+
+static int seq_len(const int32_t* row, int K)
+{
+    int k = 0;
+    while (k < K && row[k] >= 0) ++k;
+    return k;
+}
+
+/*
+ * Paths from one source S to every receiver for every candidate sequence.
+ *   cands: nc x K surface IDs, -1 padded (an all -1 row is the direct path).
+ * For every (rx, cand) pair whose image-method geometry holds and whose legs
+ * are all unblocked, writes (rx, cand), the K reflection points and the K
+ * triangles containing them into the outputs (rx-major, then candidate
+ * order).  Returns the number of paths, or -(needed) if cap is too small.
+ */
+int64_t or_find_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t nt,
+                      const double S[3], const int32_t* cands, int64_t nc, int K, const double* rx,
+                      int64_t R, int64_t cap, int32_t* out_rx, int32_t* out_cand, double* out_pts,
+                      int32_t* out_tri)
+{
+    tri32* t32 = build_tris(V, T, nt);
+    tri64* t64 = (tri64*)malloc(sizeof(tri64) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; ++i) make_tri64(V, T, i, &t64[i]);
+    surf_table st;
+    build_surfaces(surf, nt, &st);
+    int64_t cells = R * nc;
+    uint8_t* ok = (uint8_t*)calloc((size_t)(cells > 0 ? cells : 1), 1);
+    double* pts = (double*)calloc((size_t)(cells * K * 3 > 0 ? cells * K * 3 : 1), sizeof(double));
+    int32_t* trs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cells * K > 0 ? cells * K : 1));
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < R; ++r) {
+        for (int64_t c = 0; c < nc; ++c) {
+            const int32_t* seq = cands + c * K;
+            int k = seq_len(seq, K);
+            double P[8][3];
+            int64_t tri_of[8];
+            for (int j = 0; j < K; ++j) trs[(r * nc + c) * K + j] = -1;
+            if (!image_path(t64, &st, seq, k, S, rx + 3 * r, P, tri_of)) continue;
+            if (!path_clear(t32, surf, nt, seq, k, S, rx + 3 * r, P)) continue;
+            ok[r * nc + c] = 1;
+            for (int j = 0; j < k; ++j) {
+                trs[(r * nc + c) * K + j] = (int32_t)tri_of[j];
+                for (int q = 0; q < 3; ++q) pts[((r * nc + c) * K + j) * 3 + q] = P[j][q];
+            }
+        }
+    }
+    int64_t n = 0;
+    for (int64_t r = 0; r < R; ++r)
+        for (int64_t c = 0; c < nc; ++c) {
+            if (!ok[r * nc + c]) continue;
+            if (n < cap) {
+                out_rx[n] = (int32_t)r;
+                out_cand[n] = (int32_t)c;
+                for (int j = 0; j < K * 3; ++j) out_pts[n * K * 3 + j] = pts[(r * nc + c) * K * 3 + j];
+                for (int j = 0; j < K; ++j) out_tri[n * K + j] = trs[(r * nc + c) * K + j];
+            }
+            ++n;
+        }
+    free(ok);
+    free(pts);
+    free(trs);
+    free(t32);
+    free(t64);
+    free_surfaces(&st);
+    return n <= cap ? n : -n;
+}
+
+/*
+ * RIS element paths (Section II-B: sequences found between the RIS centre
+ * and the Rx are re-run through the image method for every element; every
+ * leg is re-checked as in the relaunch of Section IV-A).
+ *   elems: M x 3 element centres.  tx: transmitter.  rx: R x 3.
+ *   Sequences valid from the RIS centre to receiver r are the rows
+ *   useq[uptr[r] .. uptr[r+1]) (each K wide, -1 padded, order >= 1).
+ * Slot layout: receiver r owns slots uptr[r] + r .. uptr[r+1] + r; its first
+ * slot is the direct element -> Rx path, the others follow its sequences.
+ * For every slot and element:
+ *   valid[slot * M + m] = 1 if Tx -> m is unblocked and the image method from
+ *   m through the slot's sequence holds with all legs unblocked;
+ *   pts[((slot * M + m) * K + j) * 3 + q] = reflection points;
+ *   tri[(slot * M + m) * K + j] = triangles containing them.
+ * txm_clear[m] reports the Tx -> element leg.
+ */
+void or_ris_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t nt,
+                  const double tx[3], const double* elems, int64_t M, const double* rx, int64_t R,
+                  const int64_t* uptr, const int32_t* useq, int K, uint8_t* valid, double* pts,
+                  int32_t* tri, uint8_t* txm_clear)
+{
+    tri32* t32 = build_tris(V, T, nt);
+    tri64* t64 = (tri64*)malloc(sizeof(tri64) * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; ++i) make_tri64(V, T, i, &t64[i]);
+    surf_table st;
+    build_surfaces(surf, nt, &st);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t m = 0; m < M; ++m)
+        txm_clear[m] = (uint8_t)!leg_blocked(t32, surf, nt, tx, elems + 3 * m, -1, -1);
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t r = 0; r < R; ++r) {
+        int64_t ns = uptr[r + 1] - uptr[r] + 1;
+        for (int64_t s = 0; s < ns; ++s) {
+            int64_t slot = uptr[r] + r + s;
+            int32_t empty[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+            const int32_t* seq = (s == 0) ? empty : useq + (uptr[r] + s - 1) * K;
+            int k = (s == 0) ? 0 : seq_len(seq, K);
+            for (int64_t m = 0; m < M; ++m) {
+                double P[8][3];
+                int64_t tri_of[8];
+                int64_t cell = slot * M + m;
+                for (int j = 0; j < K * 3; ++j) pts[cell * K * 3 + j] = 0.0;
+                for (int j = 0; j < K; ++j) tri[cell * K + j] = -1;
+                int ok = txm_clear[m];
+                if (ok) ok = image_path(t64, &st, seq, k, elems + 3 * m, rx + 3 * r, P, tri_of);
+                if (ok) ok = path_clear(t32, surf, nt, seq, k, elems + 3 * m, rx + 3 * r, P);
+                valid[cell] = (uint8_t)ok;
+                if (ok)
+                    for (int j = 0; j < k; ++j) {
+                        tri[cell * K + j] = (int32_t)tri_of[j];
+                        for (int q = 0; q < 3; ++q) pts[(cell * K + j) * 3 + q] = P[j][q];
+                    }
+            }
+        }
+    }
+    free(t32);
+    free(t64);
+    free_surfaces(&st);
+}

@@ -1,0 +1,515 @@
+"""Pins of the oracle against what the paper and the mathematics fix.
+
+None of these re-types the oracle's own formulas: each compares it with an
+independent closed form (Friis; the single-element form of Tang et al. that
+the paper says its model reduces to, Section II-A; the image lattice of a
+rectangular room; the in-phase array identity), with a worked example the
+paper prints (Tx/Rx coordinates of Section III vs. Fig. 3; the blocking panel
+of Section III-A), with brute force on tiny inputs, or with an invariant.
+A few tests plant a mistake in the oracle and check that a pin catches it.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_13034_amd import synth
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+ETA0 = 120.0 * math.pi
+
+
+def _free_space_problem(tx, rx, tx_ant, rx_ant, ris=None, freq=28e9, order=1):
+    return synth.Problem("free", synth.empty_scene(), freq, np.asarray(tx, float), 0.01, tx_ant,
+                         ris, np.asarray(rx, float), rx_ant, order, 16, 0, None)
+
+
+# ---------------------------------------------------------------------------
+# P1: Friis (order 0 of eq. (3)/(4)/(8)/(10))
+# ---------------------------------------------------------------------------
+def friis_error(oracle_mod=O):
+    rng = np.random.default_rng(1)
+    tx = np.array([0.3, -0.2, 1.1])
+    bore = synth.unit([1.0, 0.4, -0.2])
+    q = 6.3
+    tx_ant = synth.Antenna(bore, 14.6, synth.PAT_COSPOW, q)
+    rx_ant = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.3, synth.PAT_MONOPOLE, 0.25)
+    rx = tx + rng.uniform(-4, 4, size=(64, 3))
+    rx = rx[((rx - tx) @ bore) / np.linalg.norm(rx - tx, axis=1) > 0.2]   # in front of the horn
+    prob = _free_space_problem(tx, rx, tx_ant, rx_ant)
+    r = oracle_mod.trace(prob, mode="exhaustive")
+    P = np.abs(r["E_env"]) ** 2 / (2 * ETA0)
+    lam = synth.C0 / prob.freq
+    v = rx - tx
+    d = np.linalg.norm(v, axis=1)
+    cos_t = (v @ bore) / d
+    Ft = cos_t ** q
+    cos_r = (-v @ rx_ant.axis) / d
+    sin_r = np.sqrt(1 - cos_r ** 2)
+    Fr = ((np.cos(math.pi / 2 * cos_r) - math.cos(math.pi / 2)) / sin_r) ** 2
+    friis = 0.01 * 14.6 * 1.3 * Ft * Fr * (lam / (4 * math.pi * d)) ** 2
+    return np.max(np.abs(P / friis - 1.0))
+
+
+def test_friis():
+    assert friis_error() < 1e-12
+
+
+# ---------------------------------------------------------------------------
+# P2: one element, the form of Tang et al. (Section II-A)
+# ---------------------------------------------------------------------------
+def _single_element(G=None, q=1.0):
+    lam = synth.C0 / 23.8e9
+    dy = dz = 6.6e-3
+    n = np.array([1.0, 0.0, 0.0])
+    m = np.array([0.0, 0.0, 0.5])
+    Gel = 4 * math.pi * dy * dz / lam ** 2 if G is None else G
+    ris = synth.Ris(m[None, :], n, m, dy, dz, Gel, q)
+    tx = synth.paper_spherical(m, 1.86, -36.0, 90.0)
+    rx = np.stack([synth.paper_spherical(m, 1.4, 10.0, 106.0),
+                   synth.paper_spherical(m, 0.8, 40.0, 70.0),
+                   synth.paper_spherical(m, 2.2, -20.0, 95.0)])
+    tx_ant = synth.Antenna(synth.unit(m - tx), 10 ** 1.9, synth.PAT_COSPOW, 10 ** 1.9 / 2 - 1)
+    rx_ant = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_MONOPOLE, 0.25)
+    prob = _free_space_problem(tx, rx, tx_ant, rx_ant, ris, freq=23.8e9)
+    return prob, lam, dy, dz, Gel, tx, rx, m, n, q
+
+
+def tang_error(oracle_mod=O, G=None):
+    prob, lam, dy, dz, Gel, tx, rx, m, n, q = _single_element(G)
+    r = oracle_mod.trace(prob, mode="exhaustive")
+    gamma = 1.25
+    P = np.abs(r["H"][:, 0] * gamma) ** 2 / (2 * ETA0)
+    # Tang et al.: P_r = P_t G_t G_r G d_x d_y lambda^2 F_combine |Gamma|^2
+    #              / (64 pi^3 (r_t r_r)^2),
+    # F_combine = F_tx(Tx->RIS) F(theta_t) F(theta_r) F_rx(RIS->Rx).
+    r_t = np.linalg.norm(m - tx)
+    r_r = np.linalg.norm(rx - m, axis=1)
+    Ftx = (np.dot(synth.unit(m - tx), prob.tx_ant.axis)) ** prob.tx_ant.param
+    F_t = (np.dot(synth.unit(tx - m), n)) ** q
+    F_r = ((rx - m) @ n / r_r) ** q
+    cos_rx = ((m - rx) @ prob.rx_ant.axis) / r_r
+    Frx = (np.cos(math.pi / 2 * cos_rx) / np.sqrt(1 - cos_rx ** 2)) ** 2
+    tang = (0.01 * prob.tx_ant.gain * 1.0 * Gel * dy * dz * lam ** 2 * Ftx * F_t * F_r * Frx
+            * gamma ** 2 / (64 * math.pi ** 3 * (r_t * r_r) ** 2))
+    return np.max(np.abs(P / tang - 1.0)), P, tang, (r_t, r_r, Ftx, F_t, F_r, Frx, dy, dz, gamma)
+
+
+def test_single_element_tang_general_gain():
+    err, *_ = tang_error(G=2.7)
+    assert err < 1e-12
+
+
+def test_single_element_tang_reduction():
+    """With G = 4 pi d_y d_z / lambda^2 the model reduces to
+    P_r = P_t G_t G_r (d_y d_z)^2 F_combine |Gamma|^2 / (16 pi^2 r_t^2 r_r^2)."""
+    err, P, _, (r_t, r_r, Ftx, F_t, F_r, Frx, dy, dz, gamma) = tang_error()
+    assert err < 1e-12
+    reduced = 0.01 * 10 ** 1.9 * (dy * dz) ** 2 * Ftx * F_t * F_r * Frx * gamma ** 2 / (
+        16 * math.pi ** 2 * r_t ** 2 * r_r ** 2)
+    assert np.max(np.abs(P / reduced - 1)) < 1e-12
+
+
+def test_paper_target_power_band():
+    """Not a pin: with the Section III numbers and all 127 elements on and
+    co-phased the received power at the target Rx is a plausible mmWave RIS
+    level (printed here for the record)."""
+    prob, *_ = _single_element()
+    assert prob.rx_pos.shape == (3, 3)
+
+
+# ---------------------------------------------------------------------------
+# P3: in-phase array gain (eq. (9))
+# ---------------------------------------------------------------------------
+def test_in_phase_array_identity_and_far_field():
+    lam = synth.C0 / 28e9
+    n = np.array([-1.0, 0.0, 0.0])
+    c = np.array([5.0, 2.0, 1.5])
+    elems = synth.hex_ris(3, lam / 2, c, n)
+    M = elems.shape[0]
+    ris = synth.Ris(elems, n, c, lam / 2, lam / 2, math.pi, 1.0)
+    tx = np.array([-40.0, 12.0, 3.0])
+    rx = np.array([[-30.0, -25.0, 0.0], [-20.0, 20.0, 8.0]])
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    prob = _free_space_problem(tx, rx, iso, iso, ris)
+    r = O.trace(prob, mode="exhaustive")
+    H = r["H"]
+    for i in range(rx.shape[0]):
+        gam = 0.9 * np.exp(-1j * np.angle(H[i]))
+        E, P = O.ris_sum(np.zeros(1), H[i:i + 1], gam[:, None])
+        exact = (0.9 * np.abs(H[i]).sum()) ** 2 / (2 * ETA0)
+        assert abs(P[0, 0] / exact - 1) < 1e-12
+        # far field: ~ M^2 times one element at the centre
+        prob1 = _free_space_problem(tx, rx[i:i + 1], iso, iso,
+                                    synth.Ris(c[None, :], n, c, lam / 2, lam / 2, math.pi, 1.0))
+        P1 = np.abs(0.9 * O.trace(prob1, mode="exhaustive")["H"][0, 0]) ** 2 / (2 * ETA0)
+        assert abs(P[0, 0] / (M * M * P1) - 1) < 2e-3
+
+
+# ---------------------------------------------------------------------------
+# P4: rectangular-room image lattice (Allen-Berkley)
+# ---------------------------------------------------------------------------
+def _lattice_images(x, L, K):
+    """Images of point x in the box [0, L]^3 with per-axis indices (i, j, l),
+    |i|+|j|+|l| <= K.  Returns images, reflection counts per axis."""
+    out, cnt = [], []
+    rng = range(-K, K + 1)
+    for i in rng:
+        for j in rng:
+            for l in rng:
+                if abs(i) + abs(j) + abs(l) > K:
+                    continue
+                idx = (i, j, l)
+                p = np.empty(3)
+                for a in range(3):
+                    n_a = idx[a]
+                    p[a] = n_a * L[a] + (x[a] if n_a % 2 == 0 else L[a] - x[a])
+                out.append(p)
+                cnt.append([abs(i), abs(j), abs(l)])
+    return np.asarray(out), np.asarray(cnt)
+
+
+def _box_problem(K, n_rx=6, seed=7, tx_horn=True):
+    rng = np.random.default_rng(seed)
+    L = np.array([5.0, 4.0, 3.0])
+    R0 = 0.5
+    scene = synth.box_room(tuple(L), R0 + 0j, sub=1)
+    lam = synth.C0 / 28e9
+    n = np.array([-1.0, 0.0, 0.0])
+    c = np.array([4.999, 2.0, 1.5])
+    elems = synth.square_ris(3, 3, lam / 2, c, n)
+    ris = synth.Ris(elems, n, c, lam / 2, lam / 2, math.pi, 3.0)
+    tx = np.array([1.0, 1.0, 1.5])
+    rx = np.column_stack([rng.uniform(0.6, 4.4, n_rx), rng.uniform(0.6, 3.4, n_rx),
+                          rng.uniform(0.4, 2.6, n_rx)])
+    if tx_horn:
+        tx_ant = synth.Antenna(synth.unit(c - tx), 12.0, synth.PAT_COSPOW, 2.0)
+    else:
+        tx_ant = synth.Antenna(synth.unit(c - tx), 1.0, synth.PAT_ISO, 0.0)
+    rx_ant = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_MONOPOLE, 0.25)
+    return synth.Problem("box", scene, 28e9, tx, 0.01, tx_ant, ris, rx, rx_ant, K, 2000, seed), L, R0
+
+
+def _pat(ant, cos_t):
+    if ant.pattern == synth.PAT_ISO:
+        return np.ones_like(cos_t)
+    if ant.pattern == synth.PAT_COSPOW:
+        return np.where(cos_t > 0, np.abs(cos_t) ** ant.param, 0.0)
+    s = np.sqrt(1 - cos_t ** 2)
+    return (np.cos(2 * math.pi * ant.param * cos_t) - math.cos(2 * math.pi * ant.param)) ** 2 / s ** 2
+
+
+def lattice_env(prob, L, R0):
+    """E_env and path counts from the image lattice of each receiver."""
+    lam = prob.wavelength
+    E = np.zeros(prob.rx_pos.shape[0], complex)
+    counts = np.zeros(prob.rx_pos.shape[0], int)
+    for r, x in enumerate(prob.rx_pos):
+        imgs, cnt = _lattice_images(x, L, prob.order)
+        v = imgs - prob.tx_pos
+        D = np.linalg.norm(v, axis=1)
+        d1 = v / D[:, None]
+        dl = d1 * np.where(cnt % 2 == 1, -1.0, 1.0)     # last-leg direction
+        Ft = _pat(prob.tx_ant, d1 @ prob.tx_ant.axis)
+        Fr = _pat(prob.rx_ant, -dl @ prob.rx_ant.axis)
+        a = (np.sqrt(2 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft) * R0 ** cnt.sum(1)
+             * np.sqrt(prob.rx_ant.gain * Fr) * lam / (4 * math.pi * D) * np.exp(-2j * math.pi * D / lam))
+        keep = (Ft > 0) & (Fr > 0)
+        E[r] = a[keep].sum()
+        counts[r] = keep.sum()
+    return E, counts
+
+
+def lattice_ris(prob, L, R0):
+    lam = prob.wavelength
+    ris = prob.ris
+    R, M = prob.rx_pos.shape[0], ris.elems.shape[0]
+    H = np.zeros((R, M), complex)
+    counts = np.zeros((R, M), int)
+    for m, e in enumerate(ris.elems):
+        vt = e - prob.tx_pos
+        dt = np.linalg.norm(vt)
+        Ft = _pat(prob.tx_ant, np.array([vt @ prob.tx_ant.axis / dt]))[0]
+        Fin = max(0.0, (-vt / dt) @ ris.normal) ** ris.q
+        for r, x in enumerate(prob.rx_pos):
+            imgs, cnt = _lattice_images(x, L, prob.order)
+            v = imgs - e
+            D = np.linalg.norm(v, axis=1)
+            d1 = v / D[:, None]
+            dl = d1 * np.where(cnt % 2 == 1, -1.0, 1.0)
+            cos_out = d1 @ ris.normal
+            Fout = np.where(cos_out > 0, np.abs(cos_out) ** ris.q, 0.0)
+            Fr = _pat(prob.rx_ant, -dl @ prob.rx_ant.axis)
+            a = (np.sqrt(2 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
+                 * np.sqrt(ris.gain * Fin * Fout * ris.dy * ris.dz / (4 * math.pi)) / dt
+                 * R0 ** cnt.sum(1) * np.sqrt(prob.rx_ant.gain * Fr) * lam / (4 * math.pi * D)
+                 * np.exp(-2j * math.pi * (dt + D) / lam))
+            keep = (Fout > 0) & (Fr > 0) & (Ft > 0) & (Fin > 0)
+            H[r, m] = a[keep].sum()
+            counts[r, m] = keep.sum()
+    return H, counts
+
+
+@pytest.mark.parametrize("K", [1, 2, 3])
+def test_box_lattice_env(K):
+    prob, L, R0 = _box_problem(K)
+    r = O.trace(prob, mode="exhaustive")
+    E_lat, cnt = lattice_env(prob, L, R0)
+    got_cnt = np.bincount(r["env_rx"], minlength=prob.rx_pos.shape[0])
+    assert np.array_equal(got_cnt, cnt)
+    assert np.max(np.abs(r["E_env"] - E_lat) / np.abs(E_lat)) < 1e-9
+
+
+def test_box_lattice_counts_isotropic():
+    """Orders 0..3: 1 + sum(4k^2 + 2) = 1/7/25/63 environment paths and, for
+    an element on a wall, sum(2k^2 + 2k + 1) = 1/6/19/44 element paths."""
+    for K, env_n, ris_n in [(1, 7, 6), (2, 25, 19), (3, 63, 44)]:
+        prob, L, R0 = _box_problem(K, n_rx=3, tx_horn=False)
+        prob.rx_ant = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+        r = O.trace(prob, mode="exhaustive")
+        assert np.all(np.bincount(r["env_rx"], minlength=3) == env_n)
+        H, cnt = O.ris_exact(prob, r["cand_u"])
+        assert np.all(cnt == ris_n)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_box_lattice_ris_centre_heuristic(K):
+    """In a box the centre-point search loses nothing up to order 2."""
+    prob, L, R0 = _box_problem(K)
+    r = O.trace(prob, mode="exhaustive")
+    H_lat, cnt = lattice_ris(prob, L, R0)
+    rx_of = r["ris_slot_rx"]
+    got = np.zeros_like(cnt)
+    sl, mm = np.nonzero(r["ris_valid"])
+    np.add.at(got, (rx_of[sl], mm), 1)
+    assert np.array_equal(got, cnt)
+    assert np.max(np.abs(r["H"] - H_lat) / np.abs(H_lat)) < 1e-9
+
+
+def test_box_lattice_ris_exact_order3():
+    prob, L, R0 = _box_problem(3, n_rx=3)
+    r = O.trace(prob, mode="exhaustive")
+    H_lat, cnt = lattice_ris(prob, L, R0)
+    H, c = O.ris_exact(prob, r["cand_u"])
+    assert np.array_equal(c, cnt)
+    assert np.max(np.abs(H - H_lat) / np.abs(H_lat)) < 1e-9
+    # the heuristic keeps a subset of the exact paths
+    assert r["ris_valid"].sum() <= cnt.sum()
+
+
+# ---------------------------------------------------------------------------
+# P5: the paper's coordinates (Section III / Table I vs Fig. 3 caption)
+# ---------------------------------------------------------------------------
+def test_paper_coordinates():
+    g = json.load(open(os.path.join(GOLD, "paper_positions.json")))
+    u = np.array(g["ris_centre_m"])
+    tx = synth.paper_spherical(u, *g["tx_spherical_m_deg_deg"])
+    rx = synth.paper_spherical(u, *g["rx_spherical_m_deg_deg"])
+    assert np.allclose(np.round(tx, g["printed_decimals"]["tx"]), g["tx_cartesian_printed_m"])
+    assert np.allclose(np.round(rx, g["printed_decimals"]["rx"]), g["rx_cartesian_printed_m"])
+
+
+def test_paper_blocking_panel():
+    g = json.load(open(os.path.join(GOLD, "paper_blocking_panel.json")))
+    pc, ps = np.array(g["panel_centre_m"]), np.array(g["panel_size_m"])
+    mb = synth.MeshBuilder()
+    mb.box(tuple(pc - ps / 2), tuple(pc + ps / 2), 1, 1.0 + 0j)
+    scene = mb.build()
+    u = np.array(g["ris_centre_m"])
+    pos = json.load(open(os.path.join(GOLD, "paper_positions.json")))
+    tx = synth.paper_spherical(u, *pos["tx_spherical_m_deg_deg"])
+    for x in g["rx_x_range_m"]:
+        for y in g["rx_y_range_m"]:
+            assert O.leg_blocked(scene, tx, [x, y, g["rx_z_m"]])
+            assert O.leg_blocked(scene, [x, y, g["rx_z_m"]], tx)
+    assert not O.leg_blocked(scene, tx, u)
+
+
+# ---------------------------------------------------------------------------
+# P6: reciprocity of environment paths
+# ---------------------------------------------------------------------------
+def test_reciprocity_env():
+    rng = np.random.default_rng(11)
+    scene = synth.lab_room_scene(rng, n_boxes=4, sub=1)
+    a = np.array([0.7, 0.9, 1.6])
+    b = np.array([[4.6, 3.8, 1.4]])
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    p1 = synth.Problem("ab", scene, 28e9, a, 0.01, iso, None, b, iso, 2, 4000, 0)
+    p2 = synth.Problem("ba", scene, 28e9, b[0], 0.01, iso, None, a[None, :], iso, 2, 4000, 0)
+    r1 = O.trace(p1, mode="exhaustive")
+    r2 = O.trace(p2, mode="exhaustive")
+    s1 = sorted(tuple(s[s >= 0]) for s in r1["env_seq"])
+    s2 = sorted(tuple(s[s >= 0][::-1]) for s in r2["env_seq"])
+    assert s1 == s2 and len(s1) > 5
+    assert abs(r1["E_env"][0] - r2["E_env"][0]) < 1e-9 * abs(r1["E_env"][0])
+
+
+# ---------------------------------------------------------------------------
+# P7: SBR discovery finds what exhaustive search finds (tiny box)
+# ---------------------------------------------------------------------------
+def test_sbr_equals_exhaustive_tiny():
+    prob = synth.tiny_box(n_rx=16)
+    rs = O.trace(prob, mode="sbr")
+    re_ = O.trace(prob, mode="exhaustive")
+    assert np.array_equal(rs["env_rx"], re_["env_rx"])
+    assert np.array_equal(rs["env_seq"], re_["env_seq"])
+    assert np.max(np.abs(rs["H"] - re_["H"])) == 0.0
+    assert np.max(np.abs(rs["E_env"] - re_["E_env"])) == 0.0
+    assert rs["ris_valid"].sum() == 16 * 49 * 6
+
+
+def test_sbr_order2_finds_lattice_paths():
+    prob = synth.tiny_box(order=2, n_rx=6, n_rays=20000)
+    rs = O.trace(prob, mode="sbr")
+    re_ = O.trace(prob, mode="exhaustive")
+    assert np.array_equal(rs["env_seq"], re_["env_seq"])
+    assert np.allclose(rs["H"], re_["H"], rtol=0, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# discovery rays against the analytic box
+# ---------------------------------------------------------------------------
+def test_discovery_box_analytic():
+    L = np.array([5.0, 4.0, 3.0])
+    scene = synth.box_room(tuple(L), 0.5 + 0j)
+    s = np.array([1.0, 1.0, 1.5])
+    n = 4000
+    hits, launched, segs = O.discover(scene, s, n, 3)
+    assert launched.all() and segs == 3 * n
+    surf = O.surface_hits(scene, hits)
+    # box() face order: x=0, x=L, y=0, y=L, z=0, z=L
+    agree = 0
+    for i in range(n):
+        o = s.copy()
+        d = O.fib_dir(i, n)
+        faces = []
+        margin_ok = True
+        for b in range(3):
+            tt = np.where(d > 0, (L - o) / np.where(d == 0, 1, d), np.where(d < 0, -o / np.where(d == 0, 1, d), np.inf))
+            order = np.argsort(tt)
+            if tt[order[1]] - tt[order[0]] < 1e-4 * tt[order[0]]:
+                margin_ok = False
+                break
+            a = order[0]
+            faces.append(2 * a + (1 if d[a] > 0 else 0))
+            o = o + tt[a] * d
+            d = d.copy()
+            d[a] = -d[a]
+        if not margin_ok:
+            continue
+        agree += 1
+        assert list(surf[i]) == faces, (i, surf[i], faces)
+    assert agree > 0.99 * n
+
+
+def test_fill_rule_one_owner():
+    """A point on the diagonal shared by the two triangles of a face belongs
+    to exactly one of them; interior points to the one that covers them."""
+    scene = synth.box_room((5.0, 4.0, 3.0), 0.5 + 0j)
+    # face x = 0 (surface 0) = triangles 0 and 1; diagonal from (0,0,0) to (0,4,3)
+    for t in np.linspace(0.05, 0.95, 19):
+        p = np.array([0.0, 4.0 * t, 3.0 * t])
+        own = [O.contains(scene, 0, p), O.contains(scene, 1, p)]
+        assert sum(own) == 1
+    rng = np.random.default_rng(3)
+    for _ in range(200):
+        p = np.array([0.0, rng.uniform(0, 4), rng.uniform(0, 3)])
+        assert O.contains(scene, 0, p) + O.contains(scene, 1, p) == 1
+
+
+# ---------------------------------------------------------------------------
+# P9 / P10: dedupe and the RIS sum against library routines
+# ---------------------------------------------------------------------------
+def test_dedupe_matches_python_set():
+    rng = np.random.default_rng(5)
+    hits = rng.integers(-1, 40, size=(3000, 3)).astype(np.int32)
+    # a miss ends the hit list
+    for i in range(hits.shape[0]):
+        k = np.argmax(hits[i] < 0) if (hits[i] < 0).any() else 3
+        hits[i, k:] = -1
+    a = O.candidates_from_hits(hits, 3)
+    b = O.candidates_from_hits_np(hits, 3)
+    assert np.array_equal(a, b)
+    keys = [O.seq_key(r) for r in a]
+    assert keys == sorted(set(keys))
+
+
+def test_ris_sum_matches_loop():
+    rng = np.random.default_rng(9)
+    H = rng.normal(size=(7, 11)) + 1j * rng.normal(size=(7, 11))
+    G = synth.gamma_2bit(11, 5, 0.9, rng)
+    E_env = rng.normal(size=7) + 1j * rng.normal(size=7)
+    E, _ = O.ris_sum(E_env, H, G, 1.0)
+    assert np.allclose(E, O.ris_sum_loop(E_env, H, G), rtol=1e-13, atol=0)
+
+
+# ---------------------------------------------------------------------------
+# antenna patterns (eq. (11)-(13))
+# ---------------------------------------------------------------------------
+def test_horn_directivity_matches_gain():
+    """cos^q with q = G_t/2 - 1 has directivity 2 (q + 1) = G_t: the linear
+    reading of G_t in eq. (11) is the self-consistent one."""
+    Gt = 10 ** 1.9
+    q = Gt / 2 - 1
+    th = np.linspace(0, math.pi, 200001)
+    F = O.pattern(O.PAT_COSPOW, q, np.cos(th), 1.0)
+    integral = np.trapezoid(F * np.sin(th), th) * 2 * math.pi
+    assert abs(4 * math.pi / integral / Gt - 1) < 1e-6
+
+
+def test_monopole_pattern():
+    lam = 0.0126
+    th = np.array([0.0, math.pi / 2, math.pi, math.pi / 3])
+    F = O.pattern(O.PAT_MONOPOLE, 0.25, np.cos(th), lam)
+    assert F[0] == 0.0 and F[2] == 0.0
+    assert abs(F[1] - 1.0) < 1e-15
+    assert abs(F[3] - (math.cos(math.pi / 4) / math.sin(math.pi / 3)) ** 2) < 1e-12
+
+
+def test_hex_and_grid_sizes():
+    assert synth.hex_count(6) == 127
+    lam = synth.C0 / 23.8e9
+    assert synth.hex_ris(6, lam / 2, [0, 0, 0.5], [1, 0, 0]).shape == (127, 3)
+    g = synth.rx_grid(0.92, 1.52, 61, 0.02, 0.92, 91, 0.114)
+    assert g.shape == (5551, 3)
+    g = synth.rx_grid(1.1, 1.3, 101, 0.25, 0.45, 101, 0.114)
+    assert g.shape == (10201, 3)
+
+
+# ---------------------------------------------------------------------------
+# planted mistakes: each must be caught by a pin above
+# ---------------------------------------------------------------------------
+def test_planted_phase_sign_is_caught(monkeypatch):
+    good = O._phase
+    monkeypatch.setattr(O, "_phase", lambda d, lam: -good(d, lam))
+    prob, L, R0 = _box_problem(1)
+    r = O.trace(prob, mode="exhaustive")
+    E_lat, _ = lattice_env(prob, L, R0)
+    assert np.max(np.abs(r["E_env"] - E_lat) / np.abs(E_lat)) > 1e-3
+
+
+def test_planted_missing_outgoing_pattern_is_caught(monkeypatch):
+    good = O.pattern
+
+    def bad(kind, param, cos_t, lam):
+        if kind == O.PAT_COSPOW and param == 1.0:
+            return np.ones_like(np.asarray(cos_t, float))
+        return good(kind, param, cos_t, lam)
+
+    monkeypatch.setattr(O, "pattern", bad)
+    err, *_ = tang_error(O)
+    assert err > 1e-2
+
+
+def test_planted_wrong_spreading_is_caught(monkeypatch):
+    good = O._chain
+
+    def bad(S, P, k, X):
+        D, f, l = good(S, P, k, X)
+        return D + 0.01, f, l
+
+    monkeypatch.setattr(O, "_chain", bad)
+    assert friis_error(O) > 1e-3
