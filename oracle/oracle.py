@@ -79,6 +79,8 @@ def lib():
         L.or_contains.argtypes = [P, P, i64, P]
         L.or_fib_dir.restype = None
         L.or_fib_dir.argtypes = [i64, i64, P]
+        L.or_leg_count.restype = i64
+        L.or_leg_count.argtypes = []
         _lib = L
     return _lib
 
@@ -94,6 +96,11 @@ def _c(a, dtype):
 # --------------------------------------------------------------------------
 # geometry wrappers
 # --------------------------------------------------------------------------
+def leg_count() -> int:
+    """Visibility legs tested since the previous call."""
+    return int(lib().or_leg_count())
+
+
 def fib_dir(i: int, n: int) -> np.ndarray:
     out = np.zeros(3)
     lib().or_fib_dir(i, n, _p(out))

@@ -33,6 +33,17 @@
 
 #define OR_EPS 1e-4 /* metres: legs ignore hits within EPS of their ends */
 
+static int64_t g_leg_count = 0; /* legs tested since the last or_leg_count() */
+
+/* Number of visibility legs tested since the last call (for timing reports). */
+int64_t or_leg_count(void)
+{
+    int64_t n;
+#pragma omp atomic capture
+    { n = g_leg_count; g_leg_count = 0; }
+    return n;
+}
+
 /* ----------------------------------------------------------------------- */
 /* FP32 ray / triangle test                                                 */
 /* ----------------------------------------------------------------------- */
@@ -205,6 +216,8 @@ static int leg_blocked(const tri32* tris, const int32_t* surf, int64_t nt, const
     float d[3] = {(float)(w0 / L), (float)(w1 / L), (float)(w2 / L)};
     float tmin = (float)OR_EPS;
     float tmax = (float)(L - OR_EPS);
+#pragma omp atomic
+    g_leg_count += 1;
     if (!(tmax > tmin)) return 0;
     for (int64_t i = 0; i < nt; ++i) {
         if (surf[i] == skip_a || surf[i] == skip_b) continue;

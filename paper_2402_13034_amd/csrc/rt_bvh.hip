@@ -1,0 +1,398 @@
+// Scene upload and linear BVH build on the device.
+//
+// LBVH after Karras, "Maximizing Parallelism in the Construction of BVHs,
+// Octrees, and k-d Trees" (HPG 2012): 30-bit Morton codes of triangle
+// centroids with the triangle index appended (unique 62-bit keys), radix
+// sort, one thread per internal node finds its key range and split, then a
+// bottom-up refit in which the second thread to reach a node writes it.
+// Node boxes are inflated so that the FP32 slab test is conservative with
+// respect to the exact ray/triangle formula.
+//
+// Layouts (leaf slot = rank of the triangle's key):
+//   tri4  [3 * n]: (v0.xyz, id), (e1.xyz, surface), (e2.xyz, 0)
+//   nodes [4 * (n - 1)]: (loL.xyz, childL), (hiL.xyz, childR), (loR.xyz, -), (hiR.xyz, -)
+//   child >= 0: internal node; child < 0: leaf slot ~child.
+// Surfaces: s_tris groups triangle indices by surface (ascending), s_ptr the
+// CSR offsets, s_plane the plane of each surface's lowest-numbered triangle.
+#pragma clang fp contract(off)
+
+#include <cstring>
+#include <vector>
+
+#include "rt_host.hpp"
+#include "rt_lbvh_core.hpp"
+
+namespace rt {
+
+__device__ __forceinline__ unsigned f2ord(float f)
+{
+    unsigned u = __float_as_uint(f);
+    return (u & 0x80000000u) ? ~u : (u | 0x80000000u);
+}
+__device__ __forceinline__ float ord2f(unsigned u)
+{
+    return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
+}
+static inline float ord2f_host(unsigned u)
+{
+    unsigned v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
+    float f;
+    std::memcpy(&f, &v, 4);
+    return f;
+}
+
+// bounds[0..2] min centroid, [3..5] max centroid, [6..8] min vertex, [9..11] max vertex
+__global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* surf_in, const float* rr,
+                             const float* ri, int64_t nv, int64_t nt, double* v64, float2* refl,
+                             int32_t* surf, float4* cent, unsigned* bounds, int32_t* bad)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    float c[3] = {0, 0, 0};
+    float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
+    for (int j = 0; j < 3; ++j) {
+        int32_t vi = T[3 * t + j];
+        if (vi < 0 || vi >= nv) {
+            atomicOr(bad, 1);
+            vi = 0;
+        }
+        for (int k = 0; k < 3; ++k) {
+            float x = V[3 * (int64_t)vi + k];
+            if (!(x == x) || fabsf(x) > 1e6f) atomicOr(bad, 2);
+            v64[9 * t + 3 * j + k] = (double)x;
+            c[k] += x;
+            lo[k] = fminf(lo[k], x);
+            hi[k] = fmaxf(hi[k], x);
+        }
+    }
+    refl[t] = make_float2(rr[t], ri[t]);
+    surf[t] = surf_in[t];
+    if (surf_in[t] < 0) atomicOr(bad, 4);
+    for (int k = 0; k < 3; ++k) c[k] = c[k] / 3.0f;
+    cent[t] = make_float4(c[0], c[1], c[2], 0.0f);
+    for (int k = 0; k < 3; ++k) {
+        atomicMin(&bounds[k], f2ord(c[k]));
+        atomicMax(&bounds[3 + k], f2ord(c[k]));
+        atomicMin(&bounds[6 + k], f2ord(lo[k]));
+        atomicMax(&bounds[9 + k], f2ord(hi[k]));
+    }
+}
+
+__device__ __forceinline__ uint32_t expand10(uint32_t v)
+{
+    v = (v * 0x00010001u) & 0xFF0000FFu;
+    v = (v * 0x00000101u) & 0x0F00F00Fu;
+    v = (v * 0x00000011u) & 0xC30C30C3u;
+    v = (v * 0x00000005u) & 0x49249249u;
+    return v;
+}
+
+__global__ void k_morton(const float4* cent, const unsigned* bounds, int64_t nt, uint64_t* keys)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    float lo[3], ext[3];
+    for (int k = 0; k < 3; ++k) {
+        lo[k] = ord2f(bounds[k]);
+        float hi = ord2f(bounds[3 + k]);
+        ext[k] = hi - lo[k];
+    }
+    float4 c = cent[t];
+    float cc[3] = {c.x, c.y, c.z};
+    uint32_t q[3];
+    for (int k = 0; k < 3; ++k) {
+        float u = ext[k] > 0.0f ? (cc[k] - lo[k]) / ext[k] : 0.5f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        q[k] = (uint32_t)fminf(u * 1024.0f, 1023.0f);
+    }
+    uint32_t m = (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
+    keys[t] = ((uint64_t)m << 32) | (uint64_t)t;
+}
+
+struct Box6 {
+    float lo[3], hi[3];
+};
+
+__global__ void k_leaves(const uint64_t* keys, const float* V, const int32_t* T, const int32_t* surf,
+                         int64_t nt, float pad, float4* tri4, float* lbox)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    int32_t t = (int32_t)(keys[i] & 0xffffffffu);
+    const float* a = V + 3 * (int64_t)T[3 * t + 0];
+    const float* b = V + 3 * (int64_t)T[3 * t + 1];
+    const float* c = V + 3 * (int64_t)T[3 * t + 2];
+    tri4[3 * i + 0] = make_float4(a[0], a[1], a[2], __int_as_float(t));
+    tri4[3 * i + 1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], __int_as_float(surf[t]));
+    tri4[3 * i + 2] = make_float4(c[0] - a[0], c[1] - a[1], c[2] - a[2], 0.0f);
+    for (int k = 0; k < 3; ++k) {
+        float lo = fminf(a[k], fminf(b[k], c[k]));
+        float hi = fmaxf(a[k], fmaxf(b[k], c[k]));
+        float p = pad + 1e-5f * fmaxf(fabsf(lo), fabsf(hi));
+        lbox[6 * i + k] = lo - p;
+        lbox[6 * i + 3 + k] = hi + p;
+    }
+}
+
+__global__ void k_karras(const uint64_t* keys, int64_t n, int32_t* child, int32_t* parent_int,
+                         int32_t* parent_leaf)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n - 1) return;
+    int32_t cl, cr;
+    lbvh_node(keys, n, i, &cl, &cr);
+    if (cl < 0) parent_leaf[~cl] = (int32_t)i;
+    else parent_int[cl] = (int32_t)i;
+    if (cr < 0) parent_leaf[~cr] = (int32_t)i;
+    else parent_int[cr] = (int32_t)i;
+    child[2 * i] = cl;
+    child[2 * i + 1] = cr;
+}
+
+__device__ __forceinline__ void load_box(int32_t c, const float* lbox, const float* ibox, float* b)
+{
+    const volatile float* src = c < 0 ? (const volatile float*)(lbox + 6 * (int64_t)(~c))
+                                      : (const volatile float*)(ibox + 6 * (int64_t)c);
+    for (int k = 0; k < 6; ++k) b[k] = src[k];
+}
+
+__global__ void k_refit(const int32_t* child, const int32_t* parent_int, const int32_t* parent_leaf,
+                        const float* lbox, float* ibox, int32_t* flags, float4* nodes, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t p = parent_leaf[i];
+    while (p >= 0 && p < n - 1) {
+        __threadfence();
+        int old = __hip_atomic_fetch_add(&flags[p], 1, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_AGENT);
+        if (old == 0) return;
+        int32_t cl = child[2 * p], cr = child[2 * p + 1];
+        float bl[6], br[6];
+        load_box(cl, lbox, ibox, bl);
+        load_box(cr, lbox, ibox, br);
+        nodes[4 * p + 0] = make_float4(bl[0], bl[1], bl[2], __int_as_float(cl));
+        nodes[4 * p + 1] = make_float4(bl[3], bl[4], bl[5], __int_as_float(cr));
+        nodes[4 * p + 2] = make_float4(br[0], br[1], br[2], 0.0f);
+        nodes[4 * p + 3] = make_float4(br[3], br[4], br[5], 0.0f);
+        volatile float* dst = ibox + 6 * (int64_t)p;
+        for (int k = 0; k < 3; ++k) {
+            dst[k] = fminf(bl[k], br[k]);
+            dst[3 + k] = fmaxf(bl[3 + k], br[3 + k]);
+        }
+        __threadfence();
+        p = parent_int[p];
+    }
+}
+
+__global__ void k_depth(const int32_t* parent_int, const int32_t* parent_leaf, int64_t n, int32_t* maxd)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int d = 0;
+    int32_t p = parent_leaf[i];
+    while (p >= 0 && p < n - 1 && d < 4096) {
+        ++d;
+        p = parent_int[p];
+    }
+    if (p != -1) d = 1 << 20;   // broken parent chain
+    atomicMax(maxd, d);
+}
+
+// every internal node reached by exactly two children during the refit
+__global__ void k_check_refit(const int32_t* flags, int64_t ni, int32_t* bad)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < ni && flags[i] != 2) atomicOr(bad, 8);
+}
+
+// surfaces
+__global__ void k_surf_keys(const int32_t* surf, int64_t nt, uint64_t* keys, int32_t* n_surf)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    keys[t] = ((uint64_t)(uint32_t)surf[t] << 32) | (uint64_t)t;
+    atomicMax(n_surf, surf[t] + 1);
+}
+
+__global__ void k_surf_csr(const uint64_t* keys, int64_t nt, int32_t n_surf, int32_t* s_ptr, int32_t* s_tris,
+                           int32_t* seen)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= nt) return;
+    int32_t s = (int32_t)(keys[i] >> 32);
+    s_tris[i] = (int32_t)(keys[i] & 0xffffffffu);
+    if (i == 0 || (int32_t)(keys[i - 1] >> 32) != s) {
+        s_ptr[s] = (int32_t)i;
+        atomicAdd(seen, 1);
+    }
+    if (i == nt - 1) s_ptr[n_surf] = (int32_t)nt;
+}
+
+__global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const double* v64, int32_t n_surf,
+                             double* s_plane, double* s_box)
+{
+    int s = blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= n_surf) return;
+    const double* v = v64 + 9 * (int64_t)s_tris[s_ptr[s]];
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v[3 + k] - v[k];
+        e2[k] = v[6 + k] - v[k];
+    }
+    double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+    double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+    double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+    s_plane[4 * s + 0] = n0;
+    s_plane[4 * s + 1] = n1;
+    s_plane[4 * s + 2] = n2;
+    s_plane[4 * s + 3] = n0 * v[0] + n1 * v[1] + n2 * v[2];
+    double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
+    for (int j = s_ptr[s]; j < s_ptr[s + 1]; ++j) {
+        const double* w = v64 + 9 * (int64_t)s_tris[j];
+        for (int a = 0; a < 3; ++a)
+            for (int k = 0; k < 3; ++k) {
+                lo[k] = fmin(lo[k], w[3 * a + k]);
+                hi[k] = fmax(hi[k], w[3 * a + k]);
+            }
+    }
+    for (int k = 0; k < 3; ++k) {
+        s_box[6 * s + k] = lo[k] - 1e-9;
+        s_box[6 * s + 3 + k] = hi[k] + 1e-9;
+    }
+}
+
+static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+
+void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,
+                 const int32_t* surf, const float* rr, const float* ri, hipStream_t st)
+{
+    s.n_tri = nt;
+    if (nt == 0) {
+        s.n_surf = 0;
+        s.root = 0;
+        return;
+    }
+    if (nt >= (int64_t)1 << 30) throw inval_error("too many triangles");
+    Scratch dV(c, sizeof(float) * 3 * (size_t)nv, st), dT(c, sizeof(int32_t) * 3 * (size_t)nt, st),
+        dS(c, sizeof(int32_t) * (size_t)nt, st), dR(c, sizeof(float) * (size_t)nt, st),
+        dI(c, sizeof(float) * (size_t)nt, st);
+    HIP_CHECK(hipMemcpyAsync(dV.p, V, dV.bytes, hipMemcpyDefault, st));
+    HIP_CHECK(hipMemcpyAsync(dT.p, T, dT.bytes, hipMemcpyDefault, st));
+    HIP_CHECK(hipMemcpyAsync(dS.p, surf, dS.bytes, hipMemcpyDefault, st));
+    HIP_CHECK(hipMemcpyAsync(dR.p, rr, dR.bytes, hipMemcpyDefault, st));
+    HIP_CHECK(hipMemcpyAsync(dI.p, ri, dI.bytes, hipMemcpyDefault, st));
+
+    s.v64 = Scratch(c, sizeof(double) * 9 * (size_t)nt, st);
+    s.refl = Scratch(c, sizeof(float2) * (size_t)nt, st);
+    s.surf = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
+    s.tri4 = Scratch(c, sizeof(float4) * 3 * (size_t)nt, st);
+    Scratch cent(c, sizeof(float4) * (size_t)nt, st);
+    // small control block: bounds[12] unsigned, bad, maxdepth, n_surf, seen
+    Scratch ctl(c, 64 * sizeof(int32_t), st);
+    unsigned* bounds = ctl.as<unsigned>();
+    int32_t* bad = ctl.as<int32_t>() + 12;
+    int32_t* maxd = ctl.as<int32_t>() + 13;
+    int32_t* nsurf = ctl.as<int32_t>() + 14;
+    int32_t* seen = ctl.as<int32_t>() + 15;
+    {
+        std::vector<unsigned> init(64, 0);
+        for (int k = 0; k < 3; ++k) {
+            init[k] = 0xffffffffu;
+            init[3 + k] = 0u;
+            init[6 + k] = 0xffffffffu;
+            init[9 + k] = 0u;
+        }
+        // staged through a small pinned buffer is unnecessary: 256 bytes
+        HIP_CHECK(hipMemcpyAsync(ctl.p, init.data(), 64 * sizeof(unsigned), hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+    }
+    const int B = 256;
+    hipLaunchKernelGGL(k_scene_prep, dim3(blocks_for(nt, B)), dim3(B), 0, st, dV.as<float>(), dT.as<int32_t>(),
+                       dS.as<int32_t>(), dR.as<float>(), dI.as<float>(), nv, nt, s.v64.as<double>(),
+                       s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad);
+    HIP_CHECK(hipGetLastError());
+    // the extent (leaf padding) and the input checks are needed before any index is used
+    unsigned hb[14];
+    HIP_CHECK(hipMemcpyAsync(hb, bounds, sizeof(hb), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    {
+        int32_t badv = (int32_t)hb[12];
+        if (badv & 1) throw inval_error("triangle vertex index out of range");
+        if (badv & 2) throw inval_error("vertex coordinate not finite or |x| > 1e6");
+        if (badv & 4) throw inval_error("negative surface id");
+    }
+    Scratch keys(c, sizeof(uint64_t) * (size_t)nt, st);
+    hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, B)), dim3(B), 0, st, cent.as<float4>(), bounds, nt,
+                       keys.as<uint64_t>());
+    HIP_CHECK(hipGetLastError());
+    sort_u64(c, keys.as<uint64_t>(), nt, 62, st);
+
+    Scratch lbox(c, sizeof(float) * 6 * (size_t)nt, st);
+    float ext = 0.0f;
+    for (int k = 0; k < 3; ++k) ext = fmaxf(ext, ord2f_host(hb[9 + k]) - ord2f_host(hb[6 + k]));
+    float pad = 1e-5f * ext + 1e-6f;
+    hipLaunchKernelGGL(k_leaves, dim3(blocks_for(nt, B)), dim3(B), 0, st, keys.as<uint64_t>(), dV.as<float>(),
+                       dT.as<int32_t>(), dS.as<int32_t>(), nt, pad, s.tri4.as<float4>(), lbox.as<float>());
+    HIP_CHECK(hipGetLastError());
+
+    if (nt >= 2) {
+        int64_t ni = nt - 1;
+        s.nodes = Scratch(c, sizeof(float4) * 4 * (size_t)ni, st);
+        Scratch child(c, sizeof(int32_t) * 2 * (size_t)ni, st), pint(c, sizeof(int32_t) * (size_t)ni, st),
+            pleaf(c, sizeof(int32_t) * (size_t)nt, st), ibox(c, sizeof(float) * 6 * (size_t)ni, st),
+            flags(c, sizeof(int32_t) * (size_t)ni, st);
+        HIP_CHECK(hipMemsetAsync(flags.p, 0, flags.bytes, st));
+        HIP_CHECK(hipMemsetAsync(pint.p, 0xff, pint.bytes, st));
+        HIP_CHECK(hipMemsetAsync(pleaf.p, 0xff, pleaf.bytes, st));
+        hipLaunchKernelGGL(k_karras, dim3(blocks_for(ni, B)), dim3(B), 0, st, keys.as<uint64_t>(), nt,
+                           child.as<int32_t>(), pint.as<int32_t>(), pleaf.as<int32_t>());
+        HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_refit, dim3(blocks_for(nt, B)), dim3(B), 0, st, child.as<int32_t>(),
+                           pint.as<int32_t>(), pleaf.as<int32_t>(), lbox.as<float>(), ibox.as<float>(),
+                           flags.as<int32_t>(), s.nodes.as<float4>(), nt);
+        HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_depth, dim3(blocks_for(nt, B)), dim3(B), 0, st, pint.as<int32_t>(),
+                           pleaf.as<int32_t>(), nt, maxd);
+        HIP_CHECK(hipGetLastError());
+        hipLaunchKernelGGL(k_check_refit, dim3(blocks_for(ni, B)), dim3(B), 0, st, flags.as<int32_t>(), ni, bad);
+        HIP_CHECK(hipGetLastError());
+        s.root = 0;
+        // keep temporaries alive until the stream has used them (stream-ordered frees)
+    } else {
+        s.root = ~0;
+    }
+
+    // surfaces
+    Scratch skeys(c, sizeof(uint64_t) * (size_t)nt, st);
+    hipLaunchKernelGGL(k_surf_keys, dim3(blocks_for(nt, B)), dim3(B), 0, st, s.surf.as<int32_t>(), nt,
+                       skeys.as<uint64_t>(), nsurf);
+    HIP_CHECK(hipGetLastError());
+    sort_u64(c, skeys.as<uint64_t>(), nt, 64, st);
+    int32_t h[4];
+    HIP_CHECK(hipMemcpyAsync(h, ctl.as<int32_t>() + 12, sizeof(h), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    if (h[0] & 8) throw hip_error("BVH build produced an inconsistent tree");
+    if (h[1] > RT_STACK - 1) throw inval_error("BVH deeper than the traversal stack");
+    if (h[2] > nt) throw inval_error("surface ids must be 0..n_surf-1, each used");
+    s.max_depth = h[1];
+    s.n_surf = h[2];
+    s.s_ptr = Scratch(c, sizeof(int32_t) * (size_t)(s.n_surf + 1), st);
+    s.s_tris = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
+    s.s_plane = Scratch(c, sizeof(double) * 4 * (size_t)s.n_surf, st);
+    s.s_box = Scratch(c, sizeof(double) * 6 * (size_t)s.n_surf, st);
+    hipLaunchKernelGGL(k_surf_csr, dim3(blocks_for(nt, B)), dim3(B), 0, st, skeys.as<uint64_t>(), nt,
+                       (int32_t)s.n_surf, s.s_ptr.as<int32_t>(), s.s_tris.as<int32_t>(), seen);
+    HIP_CHECK(hipGetLastError());
+    {
+        int32_t n_seen = 0;
+        HIP_CHECK(hipMemcpyAsync(&n_seen, seen, sizeof(int32_t), hipMemcpyDeviceToHost, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        if (n_seen != s.n_surf) throw inval_error("surface ids must be 0..n_surf-1, each used");
+    }
+    hipLaunchKernelGGL(k_surf_plane, dim3(blocks_for(s.n_surf, 64)), dim3(64), 0, st, s.s_ptr.as<int32_t>(),
+                       s.s_tris.as<int32_t>(), s.v64.as<double>(), (int32_t)s.n_surf, s.s_plane.as<double>(),
+                       s.s_box.as<double>());
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace rt

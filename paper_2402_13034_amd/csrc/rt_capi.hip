@@ -1,0 +1,548 @@
+// C ABI of the risrt library: contexts, handles, memory budget, argument
+// checks, and the calls declared in include/risrt.h.
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "../../include/risrt.h"
+#include "rt_host.hpp"
+
+namespace rt {
+
+static thread_local std::string g_err;
+
+// ---- allocation ----
+void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
+{
+    if (bytes == 0) return nullptr;
+    uint64_t cur = c.in_use.load();
+    while (true) {
+        if (cur + bytes > c.budget)
+            throw nomem_error("memory budget exceeded (" + std::to_string(cur + bytes) + " > " +
+                              std::to_string(c.budget) + " bytes)");
+        if (c.in_use.compare_exchange_weak(cur, cur + bytes)) break;
+    }
+    void* p = nullptr;
+    hipError_t e = hipMallocAsync(&p, bytes, st);
+    if (e != hipSuccess) {
+        c.in_use -= bytes;
+        (void)hipGetLastError();
+        if (e == hipErrorOutOfMemory) throw nomem_error("device out of memory");
+        throw hip_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
+    }
+    return p;
+}
+
+void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
+{
+    if (!p) return;
+    (void)hipFreeAsync(p, st);
+    c.in_use -= bytes;
+}
+
+// ---- small read-backs through a pinned buffer ----
+static int64_t* pinned_buf()
+{
+    static thread_local int64_t* buf = nullptr;
+    if (!buf) HIP_CHECK(hipHostMalloc((void**)&buf, 64 * sizeof(int64_t), hipHostMallocDefault));
+    return buf;
+}
+
+int64_t read_i64(const int64_t* d, hipStream_t st)
+{
+    int64_t* h = pinned_buf();
+    HIP_CHECK(hipMemcpyAsync(h, d, sizeof(int64_t), hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    return h[0];
+}
+
+void read_i64s(const int64_t* d, int64_t* out, int n, hipStream_t st)
+{
+    int64_t* h = pinned_buf();
+    HIP_CHECK(hipMemcpyAsync(h, d, sizeof(int64_t) * (size_t)n, hipMemcpyDeviceToHost, st));
+    HIP_CHECK(hipStreamSynchronize(st));
+    for (int i = 0; i < n; ++i) out[i] = h[i];
+}
+
+}  // namespace rt
+
+using namespace rt;
+
+// ---- handles ----
+struct Obj {
+    int kind = 0;   // 1 scene, 2 ris, 3 channel
+    std::unique_ptr<Scene> scene;
+    std::unique_ptr<RisObj> ris;
+    std::unique_ptr<Channel> channel;
+    std::vector<hipStream_t> users;
+    std::mutex mu;   // serialises calls that update the object (bf16 split cache)
+};
+
+struct rt_ctx_s {
+    Ctx c;
+    hipStream_t free_stream = nullptr;
+    uint64_t next = 1;
+    std::map<uint64_t, std::shared_ptr<Obj>> objs;
+};
+
+static_assert(sizeof(EnvRec) == sizeof(rt_env_path), "path record layout");
+
+namespace {
+
+rt_status fail(rt_status s, const std::string& msg)
+{
+    g_err = msg;
+    return s;
+}
+
+template <class F>
+rt_status guarded(rt_ctx ctx, F&& f)
+{
+    if (!ctx) return fail(RT_EINVAL, "null context");
+    try {
+        HIP_CHECK(hipSetDevice(ctx->c.device));
+        rt_status s = f();
+        if (s == RT_OK) g_err.clear();
+        return s;
+    } catch (const nomem_error& e) {
+        return fail(RT_ENOMEM, e.what());
+    } catch (const inval_error& e) {
+        return fail(RT_EINVAL, e.what());
+    } catch (const hip_error& e) {
+        return fail(RT_EDEVICE, e.what());
+    } catch (const std::exception& e) {
+        return fail(RT_EDEVICE, e.what());
+    }
+}
+
+std::shared_ptr<Obj> find(rt_ctx ctx, uint64_t h, int kind)
+{
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    auto it = ctx->objs.find(h);
+    if (it == ctx->objs.end() || it->second->kind != kind) return nullptr;
+    return it->second;
+}
+
+uint64_t insert(rt_ctx ctx, std::shared_ptr<Obj> o)
+{
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    uint64_t h = ctx->next++;
+    ctx->objs[h] = std::move(o);
+    return h;
+}
+
+void note_user(rt_ctx ctx, Obj& o, hipStream_t st)
+{
+    std::lock_guard<std::mutex> lk(ctx->c.mu);
+    for (auto u : o.users)
+        if (u == st) return;
+    o.users.push_back(st);
+}
+
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+void retarget(Scratch& s, hipStream_t st) { s.st = st; }
+
+// Release an object's memory once all work enqueued on its user streams is done.
+void release_obj(rt_ctx ctx, Obj& o)
+{
+    std::vector<hipEvent_t> evs;
+    for (auto u : o.users) {
+        hipEvent_t e;
+        HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(e, u));
+        HIP_CHECK(hipStreamWaitEvent(ctx->free_stream, e, 0));
+        evs.push_back(e);
+    }
+    hipStream_t fs = ctx->free_stream;
+    if (o.scene) {
+        Scene& s = *o.scene;
+        for (Scratch* p : {&s.tri4, &s.nodes, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane, &s.s_box})
+            retarget(*p, fs);
+    }
+    if (o.ris) retarget(o.ris->elem, fs);
+    if (o.channel) {
+        Channel& ch = *o.channel;
+        for (Scratch* p : {&ch.H, &ch.E_env, &ch.hits[0], &ch.hits[1], &ch.cand_keys[0], &ch.cand_keys[1], &ch.env,
+                           &ch.useq, &ch.ris_valid, &ch.a_hi, &ch.a_lo})
+            retarget(*p, fs);
+    }
+    if (o.scene && o.scene->ready) (void)hipEventDestroy(o.scene->ready);
+    if (o.channel) {
+        if (o.channel->ready) (void)hipEventDestroy(o.channel->ready);
+        if (o.channel->split_ev) (void)hipEventDestroy(o.channel->split_ev);
+    }
+    o.scene.reset();
+    o.ris.reset();
+    o.channel.reset();
+    for (auto e : evs) (void)hipEventDestroy(e);
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* rt_last_error(void) { return g_err.c_str(); }
+
+rt_status rt_init(int device, uint64_t mem_budget_bytes, rt_ctx* out)
+{
+    if (!out) return fail(RT_EINVAL, "null output");
+    try {
+        int n = 0;
+        HIP_CHECK(hipGetDeviceCount(&n));
+        if (device < 0 || device >= n) return fail(RT_EINVAL, "no such device");
+        HIP_CHECK(hipSetDevice(device));
+        auto* ctx = new rt_ctx_s();
+        ctx->c.device = device;
+        size_t fr = 0, tot = 0;
+        HIP_CHECK(hipMemGetInfo(&fr, &tot));
+        ctx->c.budget = mem_budget_bytes ? mem_budget_bytes : (uint64_t)(0.9 * (double)fr);
+        hipMemPool_t pool;
+        HIP_CHECK(hipDeviceGetDefaultMemPool(&pool, device));
+        uint64_t thr = UINT64_MAX;
+        HIP_CHECK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
+        HIP_CHECK(hipStreamCreateWithFlags(&ctx->free_stream, hipStreamNonBlocking));
+        *out = ctx;
+        g_err.clear();
+        return RT_OK;
+    } catch (const std::exception& e) {
+        return fail(RT_EDEVICE, e.what());
+    }
+}
+
+rt_status rt_shutdown(rt_ctx ctx)
+{
+    if (!ctx) return fail(RT_EINVAL, "null context");
+    rt_status s = guarded(ctx, [&] {
+        HIP_CHECK(hipDeviceSynchronize());
+        for (auto& kv : ctx->objs) release_obj(ctx, *kv.second);
+        ctx->objs.clear();
+        HIP_CHECK(hipStreamSynchronize(ctx->free_stream));
+        HIP_CHECK(hipStreamDestroy(ctx->free_stream));
+        return RT_OK;
+    });
+    delete ctx;
+    return s;
+}
+
+rt_status rt_mem_info(rt_ctx ctx, uint64_t* in_use, uint64_t* budget)
+{
+    return guarded(ctx, [&] {
+        if (in_use) *in_use = ctx->c.in_use.load();
+        if (budget) *budget = ctx->c.budget;
+        return RT_OK;
+    });
+}
+
+rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const int32_t* tri, int64_t n_tri,
+                          const int32_t* surf, const float* refl_re, const float* refl_im, void* stream,
+                          uint64_t* scene)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        if (!scene || n_vtx < 0 || n_tri < 0) return fail(RT_EINVAL, "bad scene arguments");
+        if (n_tri > 0 && (!vtx_xyz || !tri || !surf || !refl_re || !refl_im || n_vtx == 0))
+            return fail(RT_EINVAL, "null scene array");
+        hipStream_t st = (hipStream_t)stream;
+        auto o = std::make_shared<Obj>();
+        o->kind = 1;
+        o->scene = std::make_unique<Scene>();
+        build_scene(ctx->c, *o->scene, vtx_xyz, n_vtx, tri, n_tri, surf, refl_re, refl_im, st);
+        HIP_CHECK(hipEventCreateWithFlags(&o->scene->ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(o->scene->ready, st));
+        o->users.push_back(st);
+        *scene = insert(ctx, o);
+        return RT_OK;
+    });
+}
+
+rt_status rt_ris_create(rt_ctx ctx, const double* elem_xyz, int64_t M, const double centre[3], const double normal[3],
+                        double dy, double dz, double elem_gain, double pattern_q, uint64_t* ris)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        if (!ris || M <= 0 || !elem_xyz || !centre || !normal) return fail(RT_EINVAL, "bad RIS arguments");
+        if (M > (1 << 24)) return fail(RT_EUNSUPPORTED, "too many RIS elements");
+        if (!(dy > 0) || !(dz > 0) || !(pattern_q >= 0)) return fail(RT_EINVAL, "bad element size or pattern");
+        double nn = sqrt(normal[0] * normal[0] + normal[1] * normal[1] + normal[2] * normal[2]);
+        if (!(nn > 0)) return fail(RT_EINVAL, "zero RIS normal");
+        auto o = std::make_shared<Obj>();
+        o->kind = 2;
+        o->ris = std::make_unique<RisObj>();
+        RisObj& r = *o->ris;
+        r.M = M;
+        for (int k = 0; k < 3; ++k) {
+            r.centre[k] = centre[k];
+            r.normal[k] = normal[k] / nn;
+        }
+        r.dy = dy;
+        r.dz = dz;
+        r.gain = elem_gain;
+        r.q = pattern_q;
+        r.elem = Scratch(ctx->c, sizeof(double) * 3 * (size_t)M, nullptr);
+        HIP_CHECK(hipMemcpyAsync(r.elem.p, elem_xyz, r.elem.bytes, hipMemcpyDefault, nullptr));
+        HIP_CHECK(hipStreamSynchronize(nullptr));
+        o->users.push_back(nullptr);
+        *ris = insert(ctx, o);
+        return RT_OK;
+    });
+}
+
+static void fill_antenna(Antenna& a, const double* axis, double gain, int32_t pattern, double param)
+{
+    double n = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    for (int k = 0; k < 3; ++k) a.axis[k] = axis[k] / n;
+    a.gain = gain;
+    a.pattern = pattern;
+    a.param = param;
+}
+
+rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, const double* rx_xyz, int64_t R,
+                   const rt_rx* rx, const rt_params* params, void* stream, uint64_t* channel, rt_stats* stats)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
+        if (params->max_order < 0 || params->max_order > RT_MAX_K)
+            return fail(RT_EUNSUPPORTED, "max_order must be 0..3");
+        if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
+        if (R > ((int64_t)1 << 31) - 1) return fail(RT_EUNSUPPORTED, "too many receivers");
+        for (int32_t p : {tx->pattern, rx->pattern})
+            if (p < 0 || p > 2) return fail(RT_EINVAL, "unknown pattern kind");
+        double ta = tx->axis[0] * tx->axis[0] + tx->axis[1] * tx->axis[1] + tx->axis[2] * tx->axis[2];
+        double ra = rx->axis[0] * rx->axis[0] + rx->axis[1] * rx->axis[1] + rx->axis[2] * rx->axis[2];
+        if (!(ta > 0) || !(ra > 0)) return fail(RT_EINVAL, "zero antenna axis");
+        if (!(tx->power_w >= 0) || !(tx->gain >= 0) || !(rx->gain >= 0)) return fail(RT_EINVAL, "bad power or gain");
+        auto so = find(ctx, scene, 1);
+        if (!so) return fail(RT_ENOTFOUND, "unknown scene handle");
+        std::shared_ptr<Obj> ro;
+        if (ris) {
+            ro = find(ctx, ris, 2);
+            if (!ro) return fail(RT_ENOTFOUND, "unknown RIS handle");
+        }
+        hipStream_t st = (hipStream_t)stream;
+        note_user(ctx, *so, st);
+        if (ro) note_user(ctx, *ro, st);
+        if (so->scene->ready) HIP_CHECK(hipStreamWaitEvent(st, so->scene->ready, 0));
+        TraceArgs a;
+        a.scene = so->scene.get();
+        a.ris = ro ? ro->ris.get() : nullptr;
+        a.R = R;
+        a.n_rays = params->n_rays;
+        TraceConst& tc = a.tc;
+        tc.lambda = 299792458.0 / params->freq_hz;
+        tc.two_eta0_pt_gt = 2.0 * 120.0 * 3.141592653589793 * tx->power_w * tx->gain;
+        for (int k = 0; k < 3; ++k) tc.tx[k] = tx->pos[k];
+        fill_antenna(tc.txa, tx->axis, tx->gain, tx->pattern, tx->param);
+        fill_antenna(tc.rxa, rx->axis, rx->gain, rx->pattern, rx->param);
+        tc.K = params->max_order;
+        tc.flags = (int32_t)params->flags;
+        auto o = std::make_shared<Obj>();
+        o->kind = 3;
+        o->channel = std::make_unique<Channel>();
+        Scratch rxd(ctx->c, sizeof(double) * 3 * (size_t)R, st);
+        if (R > 0) HIP_CHECK(hipMemcpyAsync(rxd.p, rx_xyz, rxd.bytes, hipMemcpyDefault, st));
+        a.rx_dev = rxd.as<double>();
+        TraceOut out;
+        trace(ctx->c, a, *o->channel, out, stats != nullptr, st);
+        HIP_CHECK(hipEventCreateWithFlags(&o->channel->ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(o->channel->ready, st));
+        o->users.push_back(st);
+        if (stats) {
+            stats->segments = out.segments;
+            stats->discovery_segments = out.disc_segments;
+            stats->leg_segments = out.leg_segments;
+            stats->n_cand_tx = out.n_cand_tx;
+            stats->n_cand_u = out.n_cand_u;
+            stats->n_env_paths = out.n_env;
+            stats->n_u_paths = out.n_u;
+            stats->n_ris_slots = out.n_slots;
+            for (int k = 0; k < 8; ++k) stats->ms_stage[k] = out.ms[k];
+        }
+        *channel = insert(ctx, o);
+        return RT_OK;
+    });
+}
+
+rt_status rt_channel_create(rt_ctx ctx, int64_t R, int64_t M, const float* E_env, const float* H, void* stream,
+                            uint64_t* channel)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        if (!channel || R < 0 || M < 0 || (R > 0 && !E_env) || (R * M > 0 && !H))
+            return fail(RT_EINVAL, "bad channel arguments");
+        hipStream_t st = (hipStream_t)stream;
+        auto o = std::make_shared<Obj>();
+        o->kind = 3;
+        o->channel = std::make_unique<Channel>();
+        Channel& ch = *o->channel;
+        ch.R = R;
+        ch.M = M;
+        ch.E_env = Scratch(ctx->c, sizeof(float2) * (size_t)R, st);
+        ch.H = Scratch(ctx->c, sizeof(float2) * (size_t)(R * M), st);
+        if (R > 0) HIP_CHECK(hipMemcpyAsync(ch.E_env.p, E_env, ch.E_env.bytes, hipMemcpyDefault, st));
+        if (R * M > 0) HIP_CHECK(hipMemcpyAsync(ch.H.p, H, ch.H.bytes, hipMemcpyDefault, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        HIP_CHECK(hipEventCreateWithFlags(&ch.ready, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(ch.ready, st));
+        o->users.push_back(st);
+        *channel = insert(ctx, o);
+        return RT_OK;
+    });
+}
+
+rt_status rt_channel_info(rt_ctx ctx, uint64_t channel, int64_t* R, int64_t* M, int64_t* n_env, int64_t* n_slots)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        if (R) *R = o->channel->R;
+        if (M) *M = o->channel->M;
+        if (n_env) *n_env = o->channel->n_env;
+        if (n_slots) *n_slots = o->channel->n_slots;
+        return RT_OK;
+    });
+}
+
+rt_status rt_channel_read(rt_ctx ctx, uint64_t channel, float* E_env, float* H, void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        hipStream_t st = (hipStream_t)stream;
+        note_user(ctx, *o, st);
+        Channel& ch = *o->channel;
+        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        if (E_env && ch.R > 0) HIP_CHECK(hipMemcpyAsync(E_env, ch.E_env.p, ch.E_env.bytes, hipMemcpyDefault, st));
+        if (H && ch.R * ch.M > 0) HIP_CHECK(hipMemcpyAsync(H, ch.H.p, ch.H.bytes, hipMemcpyDefault, st));
+        HIP_CHECK(hipStreamSynchronize(st));
+        return RT_OK;
+    });
+}
+
+rt_status rt_hits_read(rt_ctx ctx, uint64_t channel, int32_t source, int32_t* hits, int64_t cap, int64_t* rows)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        if (source < 0 || source > 1) return fail(RT_EINVAL, "source must be 0 or 1");
+        Channel& ch = *o->channel;
+        if (ch.ready) HIP_CHECK(hipEventSynchronize(ch.ready));
+        int64_t n = ch.n_hits_rows[source];
+        if (!ch.hits[source].p && n * ch.K > 0) return fail(RT_EINVAL, "hits not kept");
+        if (rows) *rows = n;
+        if (hits) {
+            if (cap < n * ch.K) return fail(RT_EINVAL, "capacity too small");
+            if (n * ch.K > 0) HIP_CHECK(hipMemcpy(hits, ch.hits[source].p, sizeof(int32_t) * (size_t)(n * ch.K), hipMemcpyDefault));
+        }
+        return RT_OK;
+    });
+}
+
+rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t cap_env, int64_t* n_env,
+                        int32_t* useq, int64_t cap_u, int64_t* n_u, uint8_t* ris_valid, int64_t cap_slots,
+                        int64_t* n_slots)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        Channel& ch = *o->channel;
+        if (ch.ready) HIP_CHECK(hipEventSynchronize(ch.ready));
+        if (n_env) *n_env = ch.n_env;
+        if (n_u) *n_u = ch.n_u;
+        if (n_slots) *n_slots = ch.n_slots;
+        if (env) {
+            if (!ch.env.p && ch.n_env > 0) return fail(RT_EINVAL, "paths not kept");
+            if (cap_env < ch.n_env) return fail(RT_EINVAL, "capacity too small");
+            if (ch.n_env) HIP_CHECK(hipMemcpy(env, ch.env.p, sizeof(EnvRec) * (size_t)ch.n_env, hipMemcpyDefault));
+        }
+        if (useq) {
+            if (cap_u < ch.n_u) return fail(RT_EINVAL, "capacity too small");
+            if (ch.n_u) {
+                if (!ch.useq.p) return fail(RT_EINVAL, "paths not kept");
+                HIP_CHECK(hipMemcpy(useq, ch.useq.p, sizeof(int32_t) * 4 * (size_t)ch.n_u, hipMemcpyDefault));
+            }
+        }
+        if (ris_valid) {
+            if (cap_slots < ch.n_slots) return fail(RT_EINVAL, "capacity too small");
+            if (ch.n_slots * ch.M) {
+                if (!ch.ris_valid.p) return fail(RT_EINVAL, "paths not kept");
+                HIP_CHECK(hipMemcpy(ris_valid, ch.ris_valid.p, (size_t)(ch.n_slots * ch.M), hipMemcpyDefault));
+            }
+        }
+        return RT_OK;
+    });
+}
+
+rt_status rt_candidates_read(rt_ctx ctx, uint64_t channel, int32_t source, int32_t* seq, int64_t cap, int64_t* n)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        if (source < 0 || source > 1) return fail(RT_EINVAL, "source must be 0 or 1");
+        Channel& ch = *o->channel;
+        if (ch.ready) HIP_CHECK(hipEventSynchronize(ch.ready));
+        int64_t nc = ch.n_cand[source];
+        if (n) *n = nc;
+        if (seq) {
+            if (!ch.cand_keys[source].p && nc > 0) return fail(RT_EINVAL, "candidates not kept");
+            if (cap < 3 * nc) return fail(RT_EINVAL, "capacity too small");
+            std::vector<uint64_t> keys((size_t)nc);
+            if (nc) HIP_CHECK(hipMemcpy(keys.data(), ch.cand_keys[source].p, sizeof(uint64_t) * (size_t)nc, hipMemcpyDefault));
+            for (int64_t i = 0; i < nc; ++i)
+                for (int j = 0; j < 3; ++j) {
+                    uint64_t v = (keys[i] >> (RT_KEY_BITS * j)) & ((1ull << RT_KEY_BITS) - 1);
+                    bool alive = v != 0 && (j == 0 || seq[3 * i + j - 1] >= 0);
+                    seq[3 * i + j] = alive ? (int32_t)v - 1 : -1;
+                }
+        }
+        return RT_OK;
+    });
+}
+
+rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C, float gamma_scale,
+                     int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out, void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        if (C < 0 || precision < 0 || precision > 2) return fail(RT_EINVAL, "bad configuration count or precision");
+        Channel& ch = *o->channel;
+        if (C > 0 && ch.M > 0 && !is_device_ptr(gamma)) return fail(RT_EINVAL, "gamma must be device memory");
+        if ((E_out && !is_device_ptr(E_out)) || (P_out && !is_device_ptr(P_out)))
+            return fail(RT_EINVAL, "outputs must be device memory");
+        if (C > ((int64_t)1 << 31) - 1) return fail(RT_EUNSUPPORTED, "too many configurations");
+        hipStream_t st = (hipStream_t)stream;
+        note_user(ctx, *o, st);
+        std::lock_guard<std::mutex> lk(o->mu);
+        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        ris_sum(ctx->c, ch, gamma, C, gamma_scale, gamma_is_real != 0, precision, E_out, P_out, st);
+        return RT_OK;
+    });
+}
+
+rt_status rt_destroy(rt_ctx ctx, uint64_t handle)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        std::shared_ptr<Obj> o;
+        {
+            std::lock_guard<std::mutex> lk(ctx->c.mu);
+            auto it = ctx->objs.find(handle);
+            if (it == ctx->objs.end()) return fail(RT_ENOTFOUND, "unknown handle");
+            o = it->second;
+            ctx->objs.erase(it);
+        }
+        release_obj(ctx, *o);
+        return RT_OK;
+    });
+}
+
+}  // extern "C"

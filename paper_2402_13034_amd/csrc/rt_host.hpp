@@ -1,0 +1,164 @@
+// Host-side objects of the risrt runtime: context, device allocations and the
+// scene / RIS / channel objects behind the C ABI handles.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <atomic>
+#include <mutex>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "rt_internal.hpp"
+
+namespace rt {
+
+struct nomem_error : std::runtime_error {
+    explicit nomem_error(const std::string& s) : std::runtime_error(s) {}
+};
+struct inval_error : std::runtime_error {
+    explicit inval_error(const std::string& s) : std::runtime_error(s) {}
+};
+
+struct Ctx {
+    int device = 0;
+    uint64_t budget = 0;
+    std::atomic<uint64_t> in_use{0};
+    std::mutex mu;
+};
+
+// Stream-ordered device allocation charged to the context's budget.
+void* dalloc(Ctx& c, size_t bytes, hipStream_t st);
+void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st);
+
+// RAII scratch buffer on a stream.
+struct Scratch {
+    Ctx* c = nullptr;
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipStream_t st = nullptr;
+    Scratch() = default;
+    Scratch(Ctx& ctx, size_t n, hipStream_t s) : c(&ctx), bytes(n), st(s) { p = n ? dalloc(ctx, n, s) : nullptr; }
+    Scratch(const Scratch&) = delete;
+    Scratch& operator=(const Scratch&) = delete;
+    Scratch(Scratch&& o) noexcept { *this = std::move(o); }
+    Scratch& operator=(Scratch&& o) noexcept {
+        release();
+        c = o.c; p = o.p; bytes = o.bytes; st = o.st;
+        o.p = nullptr; o.bytes = 0;
+        return *this;
+    }
+    ~Scratch() { release(); }
+    void release() {
+        if (p) dfree(*c, p, bytes, st);
+        p = nullptr;
+        bytes = 0;
+    }
+    template <class T> T* as() const { return static_cast<T*>(p); }
+};
+
+struct Scene {
+    hipEvent_t ready = nullptr;   // recorded after the build
+    int64_t n_tri = 0, n_surf = 0;
+    int32_t root = 0;
+    int32_t max_depth = 0;
+    Scratch tri4, nodes, v64, refl, surf, s_ptr, s_tris, s_plane, s_box;
+    SceneView view() const {
+        SceneView v;
+        v.n_tri = (int32_t)n_tri;
+        v.n_surf = (int32_t)n_surf;
+        v.root = root;
+        v.pad = 0;
+        v.tri4 = tri4.as<float4>();
+        v.nodes = nodes.as<float4>();
+        v.v64 = v64.as<double>();
+        v.refl = refl.as<float2>();
+        v.surf = surf.as<int32_t>();
+        v.s_ptr = s_ptr.as<int32_t>();
+        v.s_tris = s_tris.as<int32_t>();
+        v.s_plane = s_plane.as<double>();
+        v.s_box = s_box.as<double>();
+        return v;
+    }
+};
+
+struct RisObj {
+    int64_t M = 0;
+    double centre[3], normal[3];
+    double dy = 0, dz = 0, gain = 0, q = 1;
+    Scratch elem;   // double [M * 3]
+};
+
+struct Channel {
+    hipEvent_t ready = nullptr;      // recorded when H / E_env are complete
+    hipEvent_t split_ev = nullptr;   // recorded after the bf16 split of H
+    int64_t R = 0, M = 0, K = 0;
+    Scratch H;          // float2 [R * M]
+    Scratch E_env;      // float2 [R]
+    // kept on request
+    int64_t n_hits_rows[2] = {0, 0};
+    Scratch hits[2];    // int32 [rows * K]
+    int64_t n_cand[2] = {0, 0};
+    Scratch cand_keys[2];  // uint64 [n_cand]
+    int64_t n_env = 0;
+    Scratch env;        // rt_env_path-like records (device EnvRec)
+    int64_t n_u = 0;
+    Scratch useq;       // int32 [n_u * 4]  (rx, s0, s1, s2)
+    int64_t n_slots = 0;
+    Scratch ris_valid;  // uint8 [n_slots * M]
+    // bf16 split of H, cached for matrix-core sums
+    int split_kind = 0; // 0 none, 1 real-Gamma layout, 2 complex-Gamma layout
+    Scratch a_hi, a_lo;
+    int64_t a_rows = 0, a_k = 0;
+    hipStream_t last_stream = nullptr;
+};
+
+// Device record of one environment path (layout shared with rt_env_path).
+struct EnvRec {
+    int32_t rx;
+    int32_t order;
+    int32_t seq[3];
+    int32_t tri[3];
+    double length;
+    float amp[2];
+};
+
+// ---- primitives (rocPRIM) ----
+void sort_u64(Ctx& c, uint64_t* keys, int64_t n, int end_bit, hipStream_t st);
+// unique of sorted keys; count written to device int64
+void unique_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t n, int64_t* d_count, hipStream_t st);
+// exclusive scan of uint8 flags into int64 offsets; total written to d_total
+void scan_flags(Ctx& c, const uint8_t* flags, int64_t* offsets, int64_t n, int64_t* d_total,
+                hipStream_t st);
+
+// ---- scene build ----
+void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,
+                 const int32_t* surf, const float* rr, const float* ri, hipStream_t st);
+
+// ---- trace ----
+struct TraceArgs {
+    const Scene* scene;
+    const RisObj* ris;       // may be null
+    TraceConst tc;
+    const double* rx_dev;    // device [R * 3]
+    int64_t R;
+    int64_t n_rays;
+};
+struct TraceOut {
+    int64_t segments = 0, disc_segments = 0, leg_segments = 0;
+    int64_t n_cand_tx = 0, n_cand_u = 0, n_env = 0, n_u = 0, n_slots = 0;
+    float ms[8] = {0};
+};
+void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st);
+
+// ---- RIS sum ----
+void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real,
+             int precision, float* E_out, float* P_out, hipStream_t st);
+
+// pinned host staging for size read-backs
+int64_t read_i64(const int64_t* d, hipStream_t st);
+void read_i64s(const int64_t* d, int64_t* h, int n, hipStream_t st);
+
+}  // namespace rt

@@ -1,0 +1,467 @@
+// Internal declarations of the risrt library (gfx950).
+//
+// Geometry decisions follow fixed formulas so that results are reproducible:
+//   * ray/triangle: Moller-Trumbore in FP32, left-to-right sums, no fused
+//     multiply-add, one correctly rounded division (1 / det);
+//   * specular bounce: d' = d - (2 (d.n) / (n.n)) n, n = e1 x e2, FP32;
+//   * image method, containment, side tests, lengths and phase: FP64 without
+//     fused multiply-add.
+// Files that include this header compile with contraction off.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <stdexcept>
+#include <string>
+
+#define RT_MAX_K 3
+#define RT_STACK 64          // BVH traversal stack entries per lane (LDS)
+#define RT_EPS 1e-4          // metres: legs and bounces ignore hits closer than this
+#define RT_KEY_BITS 21
+
+namespace rt {
+
+struct hip_error : std::runtime_error {
+    explicit hip_error(const std::string& s) : std::runtime_error(s) {}
+};
+
+#define HIP_CHECK(x)                                                                        \
+    do {                                                                                    \
+        hipError_t e_ = (x);                                                                \
+        if (e_ != hipSuccess)                                                               \
+            throw ::rt::hip_error(std::string(#x) + ": " + hipGetErrorString(e_));           \
+    } while (0)
+
+// --------------------------------------------------------------------------
+// Device views
+// --------------------------------------------------------------------------
+struct SceneView {
+    int32_t n_tri;
+    int32_t n_surf;
+    int32_t root;          // >= 0 internal node, < 0 leaf ~slot; unused if n_tri == 0
+    int32_t pad;
+    const float4* tri4;    // 3 per leaf slot: (v0, id), (e1, surf), (e2, 0)
+    const float4* nodes;   // 4 per internal node: (loL, cL), (hiL, cR), (loR, -), (hiR, -)
+    const double* v64;     // 9 per triangle (original order)
+    const float2* refl;    // per triangle
+    const int32_t* surf;   // per triangle
+    const int32_t* s_ptr;  // n_surf + 1
+    const int32_t* s_tris; // triangles grouped by surface, ascending
+    const double* s_plane; // 4 per surface: n (not unit), c = n . v0 of its first triangle
+    const double* s_box;   // 6 per surface: lo, hi (inflated by 1e-9 m)
+};
+
+struct Antenna {
+    double axis[3];
+    double gain;
+    int32_t pattern;
+    double param;
+};
+
+struct TraceConst {
+    double lambda;
+    double two_eta0_pt_gt;   // 2 eta0 P_t G_t
+    double tx[3];
+    Antenna txa;
+    Antenna rxa;
+    int32_t K;
+    int32_t flags;
+};
+
+struct RisView {
+    int32_t M;
+    int32_t pad;
+    const double* elem;    // 3 per element
+    double centre[3];
+    double normal[3];      // unit
+    double dy, dz, gain, q;
+};
+
+// --------------------------------------------------------------------------
+// FP32 ray / triangle (same formula as the definition, no contraction)
+// --------------------------------------------------------------------------
+__device__ __forceinline__ bool mt_hit(float ox, float oy, float oz, float dx, float dy, float dz,
+                                       float4 a, float4 b, float4 c, float tmin, float tmax,
+                                       float& t_out)
+{
+#pragma clang fp contract(off)
+    const float e1x = b.x, e1y = b.y, e1z = b.z;
+    const float e2x = c.x, e2y = c.y, e2z = c.z;
+    float px = dy * e2z - dz * e2y;
+    float py = dz * e2x - dx * e2z;
+    float pz = dx * e2y - dy * e2x;
+    float det = e1x * px + e1y * py + e1z * pz;
+    if (det == 0.0f) return false;
+    float inv = 1.0f / det;
+    float sx = ox - a.x;
+    float sy = oy - a.y;
+    float sz = oz - a.z;
+    float u = (sx * px + sy * py + sz * pz) * inv;
+    if (!(u >= 0.0f && u <= 1.0f)) return false;
+    float qx = sy * e1z - sz * e1y;
+    float qy = sz * e1x - sx * e1z;
+    float qz = sx * e1y - sy * e1x;
+    float v = (dx * qx + dy * qy + dz * qz) * inv;
+    if (!(v >= 0.0f && u + v <= 1.0f)) return false;
+    float t = (e2x * qx + e2y * qy + e2z * qz) * inv;
+    if (!(t > tmin && t < tmax)) return false;
+    t_out = t;
+    return true;
+}
+
+__device__ __forceinline__ void reflect32(float4 b, float4 c, float& dx, float& dy, float& dz)
+{
+#pragma clang fp contract(off)
+    float nx = b.y * c.z - b.z * c.y;
+    float ny = b.z * c.x - b.x * c.z;
+    float nz = b.x * c.y - b.y * c.x;
+    float dn = dx * nx + dy * ny + dz * nz;
+    float nn = nx * nx + ny * ny + nz * nz;
+    float k = (2.0f * dn) / nn;
+    dx = dx - k * nx;
+    dy = dy - k * ny;
+    dz = dz - k * nz;
+}
+
+// --------------------------------------------------------------------------
+// BVH walk.  Boxes are inflated at build time, so the slab test may use FMA:
+// it never rejects a box holding a triangle the exact-formula test accepts.
+// --------------------------------------------------------------------------
+struct RayBox {
+    float ix, iy, iz;     // 1 / d (zeros nudged to +-1e-30)
+    float oix, oiy, oiz;  // o / d
+};
+
+__device__ __forceinline__ RayBox make_raybox(float ox, float oy, float oz, float dx, float dy, float dz)
+{
+    RayBox r;
+    float sx = fabsf(dx) < 1e-30f ? copysignf(1e-30f, dx) : dx;
+    float sy = fabsf(dy) < 1e-30f ? copysignf(1e-30f, dy) : dy;
+    float sz = fabsf(dz) < 1e-30f ? copysignf(1e-30f, dz) : dz;
+    r.ix = 1.0f / sx;
+    r.iy = 1.0f / sy;
+    r.iz = 1.0f / sz;
+    r.oix = ox * r.ix;
+    r.oiy = oy * r.iy;
+    r.oiz = oz * r.iz;
+    return r;
+}
+
+__device__ __forceinline__ bool slab(const RayBox& r, float4 lo, float4 hi, float tmin, float tmax,
+                                     float& tn)
+{
+    float t0x = __builtin_fmaf(lo.x, r.ix, -r.oix), t1x = __builtin_fmaf(hi.x, r.ix, -r.oix);
+    float t0y = __builtin_fmaf(lo.y, r.iy, -r.oiy), t1y = __builtin_fmaf(hi.y, r.iy, -r.oiy);
+    float t0z = __builtin_fmaf(lo.z, r.iz, -r.oiz), t1z = __builtin_fmaf(hi.z, r.iz, -r.oiz);
+    float a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tn = a;
+    return a <= b;
+}
+
+// Closest hit: lowest (t, triangle id) among triangles other than skip_tri
+// with tmin < t < tmax.  Returns the leaf slot or -1.  `stack` points at this
+// lane's column of an LDS array laid out [RT_STACK][stride].
+template <bool BRUTE>
+__device__ int closest_hit(const SceneView& s, float ox, float oy, float oz, float dx, float dy,
+                           float dz, float tmin, int skip_tri, int* stack, int stride, float& t_best,
+                           int& id_best)
+{
+    t_best = __builtin_inff();
+    id_best = 0x7fffffff;
+    int slot_best = -1;
+    if (s.n_tri == 0) return -1;
+    if (BRUTE) {
+        for (int i = 0; i < s.n_tri; ++i) {
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            int id = __float_as_int(a.w);
+            if (id == skip_tri) continue;
+            float t;
+            if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, __builtin_inff(), t)) {
+                if (t < t_best || (t == t_best && id < id_best)) {
+                    t_best = t;
+                    id_best = id;
+                    slot_best = i;
+                }
+            }
+        }
+        return slot_best;
+    }
+    RayBox rb = make_raybox(ox, oy, oz, dx, dy, dz);
+    int sp = 0;
+    int node = s.root;
+    while (true) {
+        if (node >= 0) {
+            const float4* nd = s.nodes + 4 * node;
+            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            bool hl = slab(rb, n0, n1, tmin, t_best, tl);
+            bool hr = slab(rb, n2, n3, tmin, t_best, tr);
+            int cl = __float_as_int(n0.w), cr = __float_as_int(n1.w);
+            if (hl && hr) {
+                int nearc = tl <= tr ? cl : cr;
+                int farc = tl <= tr ? cr : cl;
+                stack[sp * stride] = farc;
+                ++sp;
+                node = nearc;
+                continue;
+            } else if (hl) {
+                node = cl;
+                continue;
+            } else if (hr) {
+                node = cr;
+                continue;
+            }
+        } else {
+            int i = ~node;
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            int id = __float_as_int(a.w);
+            float t;
+            if (id != skip_tri && mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, __builtin_inff(), t)) {
+                if (t < t_best || (t == t_best && id < id_best)) {
+                    t_best = t;
+                    id_best = id;
+                    slot_best = i;
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = stack[sp * stride];
+    }
+    return slot_best;
+}
+
+// Any hit of a triangle not on surface skip_a / skip_b with tmin < t < tmax.
+template <bool BRUTE>
+__device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float dx, float dy, float dz,
+                        float tmin, float tmax, int skip_a, int skip_b, int* stack, int stride)
+{
+    if (s.n_tri == 0) return false;
+    if (BRUTE) {
+        for (int i = 0; i < s.n_tri; ++i) {
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            int sf = __float_as_int(b.w);
+            if (sf == skip_a || sf == skip_b) continue;
+            float t;
+            if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) return true;
+        }
+        return false;
+    }
+    RayBox rb = make_raybox(ox, oy, oz, dx, dy, dz);
+    int sp = 0;
+    int node = s.root;
+    while (true) {
+        if (node >= 0) {
+            const float4* nd = s.nodes + 4 * node;
+            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            bool hl = slab(rb, n0, n1, tmin, tmax, tl);
+            bool hr = slab(rb, n2, n3, tmin, tmax, tr);
+            int cl = __float_as_int(n0.w), cr = __float_as_int(n1.w);
+            if (hl && hr) {
+                stack[sp * stride] = cr;
+                ++sp;
+                node = cl;
+                continue;
+            } else if (hl) {
+                node = cl;
+                continue;
+            } else if (hr) {
+                node = cr;
+                continue;
+            }
+        } else {
+            int i = ~node;
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            int sf = __float_as_int(b.w);
+            float t;
+            if (sf != skip_a && sf != skip_b &&
+                mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t))
+                return true;
+        }
+        if (sp == 0) break;
+        --sp;
+        node = stack[sp * stride];
+    }
+    return false;
+}
+
+// Leg A -> B blocked?  FP32 ray from fl(A) along fl((B - A) / L), EPS < t < L - EPS,
+// ignoring the surfaces sa, sb of its end points.
+template <bool BRUTE>
+__device__ bool leg_blocked(const SceneView& s, const double* A, const double* B, int sa, int sb,
+                            int* stack, int stride)
+{
+#pragma clang fp contract(off)
+    double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
+    double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    float tmin = (float)RT_EPS;
+    float tmax = (float)(L - RT_EPS);
+    if (!(tmax > tmin)) return false;
+    return any_hit<BRUTE>(s, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
+                          (float)(w2 / L), tmin, tmax, sa, sb, stack, stride);
+}
+
+// --------------------------------------------------------------------------
+// FP64 image method
+// --------------------------------------------------------------------------
+__device__ __forceinline__ double edge_raw(double sx, double sy, double ex, double ey, double px,
+                                           double py)
+{
+#pragma clang fp contract(off)
+    return (ex - sx) * (py - sy) - (ey - sy) * (px - sx);
+}
+
+// Edge function from the lexicographically smaller end point (exactly
+// antisymmetric in the edge direction).
+__device__ __forceinline__ double edge2(double sx, double sy, double ex, double ey, double px,
+                                        double py)
+{
+    bool s_first = (sx < ex) || (sx == ex && sy < ey);
+    return s_first ? edge_raw(sx, sy, ex, ey, px, py) : -edge_raw(ex, ey, sx, sy, px, py);
+}
+
+__device__ __forceinline__ bool top_left(double sx, double sy, double ex, double ey)
+{
+    double dy = ey - sy, dx = ex - sx;
+    return (dy < 0.0) || (dy == 0.0 && dx < 0.0);
+}
+
+// p on the triangle's plane inside triangle t (half-open top-left rule in
+// the projection that drops the axis of largest |normal|)?
+__device__ inline bool contains64(const double* v, const double* p)
+{
+#pragma clang fp contract(off)
+    double e1[3], e2[3];
+    for (int k = 0; k < 3; ++k) {
+        e1[k] = v[3 + k] - v[k];
+        e2[k] = v[6 + k] - v[k];
+    }
+    double n0 = e1[1] * e2[2] - e1[2] * e2[1];
+    double n1 = e1[2] * e2[0] - e1[0] * e2[2];
+    double n2 = e1[0] * e2[1] - e1[1] * e2[0];
+    double ax = fabs(n0), ay = fabs(n1), az = fabs(n2);
+    int drop = 0;
+    if (ay > ax && ay >= az) drop = 1;
+    else if (az > ax && az > ay) drop = 2;
+    int i0 = (drop + 1) % 3, i1 = (drop + 2) % 3;
+    double a0 = v[i0], a1 = v[i1];
+    double b0 = v[3 + i0], b1 = v[3 + i1];
+    double c0 = v[6 + i0], c1 = v[6 + i1];
+    double q0 = p[i0], q1 = p[i1];
+    double area = edge2(a0, a1, b0, b1, c0, c1);
+    if (area == 0.0) return false;
+    if (area < 0.0) {
+        double t0 = b0, t1 = b1;
+        b0 = c0; b1 = c1;
+        c0 = t0; c1 = t1;
+    }
+    double w0 = edge2(b0, b1, c0, c1, q0, q1);
+    double w1 = edge2(c0, c1, a0, a1, q0, q1);
+    double w2 = edge2(a0, a1, b0, b1, q0, q1);
+    bool in0 = (w0 > 0.0) || (w0 == 0.0 && top_left(b0, b1, c0, c1));
+    bool in1 = (w1 > 0.0) || (w1 == 0.0 && top_left(c0, c1, a0, a1));
+    bool in2 = (w2 > 0.0) || (w2 == 0.0 && top_left(a0, a1, b0, b1));
+    return in0 && in1 && in2;
+}
+
+__device__ __forceinline__ double plane_side(const double* pl, const double* p)
+{
+#pragma clang fp contract(off)
+    return (pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2]) - pl[3];
+}
+
+// Triangle of surface sf that contains p, or -1.
+__device__ inline int surface_contains(const SceneView& s, int sf, const double* p)
+{
+    const double* bx = s.s_box + 6 * sf;
+    if (p[0] < bx[0] || p[1] < bx[1] || p[2] < bx[2] || p[0] > bx[3] || p[1] > bx[4] || p[2] > bx[5])
+        return -1;
+    for (int j = s.s_ptr[sf]; j < s.s_ptr[sf + 1]; ++j) {
+        int t = s.s_tris[j];
+        if (contains64(s.v64 + 9 * t, p)) return t;
+    }
+    return -1;
+}
+
+// Mirror p in plane pl (n, c).
+__device__ __forceinline__ void mirror(const double* pl, const double* p, double* out)
+{
+#pragma clang fp contract(off)
+    double nn = pl[0] * pl[0] + pl[1] * pl[1] + pl[2] * pl[2];
+    double f = 2.0 * plane_side(pl, p) / nn;
+    out[0] = p[0] - f * pl[0];
+    out[1] = p[1] - f * pl[1];
+    out[2] = p[2] - f * pl[2];
+}
+
+// Back-trace from X through images I[1..k] (I[0] = source S) over surfaces
+// seq; on success fills P[0..k) and tri[0..k).
+__device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k, const double (*I)[3],
+                                       const double* X, double (*P)[3], int* tri)
+{
+#pragma clang fp contract(off)
+    double Q[3] = {X[0], X[1], X[2]};
+    for (int i = k; i >= 1; --i) {
+        const double* pl = s.s_plane + 4 * seq[i - 1];
+        double w0 = Q[0] - I[i][0], w1 = Q[1] - I[i][1], w2 = Q[2] - I[i][2];
+        double den = pl[0] * w0 + pl[1] * w1 + pl[2] * w2;
+        if (den == 0.0) return false;
+        double sp = (pl[3] - (pl[0] * I[i][0] + pl[1] * I[i][1] + pl[2] * I[i][2])) / den;
+        if (!(sp > 0.0 && sp < 1.0)) return false;
+        double p[3] = {I[i][0] + sp * w0, I[i][1] + sp * w1, I[i][2] + sp * w2};
+        int t = surface_contains(s, seq[i - 1], p);
+        if (t < 0) return false;
+        tri[i - 1] = t;
+        P[i - 1][0] = p[0]; P[i - 1][1] = p[1]; P[i - 1][2] = p[2];
+        Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
+    }
+    for (int i = 0; i < k; ++i) {
+        const double* pl = s.s_plane + 4 * seq[i];
+        const double* prev = (i == 0) ? I[0] : P[i - 1];
+        const double* next = (i == k - 1) ? X : P[i + 1];
+        double a = plane_side(pl, prev);
+        double b = plane_side(pl, next);
+        if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return false;
+    }
+    return true;
+}
+
+// --------------------------------------------------------------------------
+// Patterns (power), FP32
+// --------------------------------------------------------------------------
+__device__ __forceinline__ float pattern_f(int kind, float param, float c)
+{
+    c = fminf(1.0f, fmaxf(-1.0f, c));
+    if (kind == 0) return 1.0f;
+    if (kind == 1) return c > 0.0f ? powf(c, param) : 0.0f;
+    float s2 = 1.0f - c * c;
+    if (!(s2 > 0.0f)) return 0.0f;
+    float kh = 6.283185307179586f * param;
+    float num = cosf(kh * c) - cosf(kh);
+    return num * num / s2;
+}
+
+__device__ __forceinline__ float cos_between(const double* v, const double* axis)
+{
+    double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+    double a = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
+    return (float)((v[0] * axis[0] + v[1] * axis[1] + v[2] * axis[2]) / (n * a));
+}
+
+// -2 pi frac(d / lambda) in FP64
+__device__ __forceinline__ double phase_of(double d, double lambda)
+{
+#pragma clang fp contract(off)
+    double x = d / lambda;
+    return -6.283185307179586 * (x - floor(x));
+}
+
+// --------------------------------------------------------------------------
+// launchers implemented in the .hip files
+// --------------------------------------------------------------------------
+struct DeviceAlloc;   // runtime allocator (hipMallocAsync on a stream)
+
+}  // namespace rt

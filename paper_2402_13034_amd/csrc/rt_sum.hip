@@ -1,0 +1,290 @@
+// Coherent RIS sum over many configurations (eqs. (9)-(10)):
+//   E[r, c] = E_env[r] + scale * sum_m H[r, m] Gamma[m, c],  P = |E|^2 / (2 eta0).
+//
+// RT_PREC_VALU_F32: FP32 complex multiply-add, LDS-tiled, vector ALUs.
+// RT_PREC_MFMA_*:   the complex product as one real GEMM on the matrix cores:
+//   rows 2r / 2r+1 of A give Re / Im of E[r, :];
+//   real Gamma:    A[2r] = Re H[r, :],            A[2r+1] = Im H[r, :],           B = Re Gamma
+//   complex Gamma: A[2r] = [Re H, -Im H],         A[2r+1] = [Im H, Re H],         B = [Re G; Im G]
+//   H is split into bf16 hi + lo (hi = RNE(x), lo = RNE(x - hi)); Gamma into hi (and lo for X3);
+//   products hi*hi + lo*hi (+ hi*lo) accumulate in FP32 (v_mfma_f32_32x32x16_bf16).
+//   The epilogue adds E_env, scales, and writes E and/or P.
+#include <cstring>
+
+#include "rt_host.hpp"
+
+namespace rt {
+
+static inline unsigned nblk(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
+static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * m; }
+
+#define ETA0_F 376.99111843077515f  // 120 pi
+
+// --------------------------------------------------------------------------
+// VALU path
+// --------------------------------------------------------------------------
+constexpr int VT = 64;   // tile of receivers and of configurations
+constexpr int VK = 16;   // k tile
+
+__global__ __launch_bounds__(256) void k_sum_valu(const float2* H, const float2* G, const float2* Eenv, int64_t R,
+                                                  int64_t M, int64_t C, float scale, float2* Eout, float* Pout)
+{
+    __shared__ float2 sh[VK][VT + 1];
+    __shared__ float2 sg[VK][VT + 1];
+    int tx = threadIdx.x & 15, ty = threadIdx.x >> 4;
+    int64_t r0 = (int64_t)blockIdx.y * VT, c0 = (int64_t)blockIdx.x * VT;
+    float accr[4][4], acci[4][4];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 4; ++j) accr[i][j] = acci[i][j] = 0.0f;
+    for (int64_t k0 = 0; k0 < M; k0 += VK) {
+        for (int e = threadIdx.x; e < VK * VT; e += 256) {
+            int kk = e / VT, rr = e % VT;
+            int64_t r = r0 + rr, m = k0 + kk;
+            sh[kk][rr] = (r < R && m < M) ? H[r * M + m] : make_float2(0.0f, 0.0f);
+            int64_t cc = c0 + rr;
+            sg[kk][rr] = (cc < C && m < M) ? G[m * C + cc] : make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < VK; ++kk) {
+            float2 h[4], g[4];
+            for (int i = 0; i < 4; ++i) h[i] = sh[kk][ty * 4 + i];
+            for (int j = 0; j < 4; ++j) g[j] = sg[kk][tx * 4 + j];
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 4; ++j) {
+                    accr[i][j] += h[i].x * g[j].x - h[i].y * g[j].y;
+                    acci[i][j] += h[i].x * g[j].y + h[i].y * g[j].x;
+                }
+        }
+        __syncthreads();
+    }
+    for (int i = 0; i < 4; ++i) {
+        int64_t r = r0 + ty * 4 + i;
+        if (r >= R) continue;
+        float2 e0 = Eenv[r];
+        for (int j = 0; j < 4; ++j) {
+            int64_t c = c0 + tx * 4 + j;
+            if (c >= C) continue;
+            float er = e0.x + scale * accr[i][j];
+            float ei = e0.y + scale * acci[i][j];
+            if (Eout) Eout[r * C + c] = make_float2(er, ei);
+            if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
+        }
+    }
+}
+
+// --------------------------------------------------------------------------
+// bf16 split helpers
+// --------------------------------------------------------------------------
+__device__ __forceinline__ uint16_t bf16_rne(float x)
+{
+    uint32_t u = __float_as_uint(x);
+    if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+    u += 0x7fffu + ((u >> 16) & 1u);
+    return (uint16_t)(u >> 16);
+}
+__device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+
+// A [rows_p x kp] row-major (k fastest); layout 1 = real Gamma, 2 = complex Gamma
+__global__ void k_split_A(const float2* H, int64_t R, int64_t M, int layout, int64_t rows_p, int64_t kp,
+                          uint16_t* Ahi, uint16_t* Alo)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= rows_p * kp) return;
+    int64_t row = idx / kp, k = idx - row * kp;
+    int64_t r = row >> 1;
+    int part = (int)(row & 1);
+    float v = 0.0f;
+    if (r < R) {
+        if (layout == 1) {
+            if (k < M) v = part == 0 ? H[r * M + k].x : H[r * M + k].y;
+        } else {
+            if (k < M) v = part == 0 ? H[r * M + k].x : H[r * M + k].y;
+            else if (k < 2 * M) v = part == 0 ? -H[r * M + k - M].y : H[r * M + k - M].x;
+        }
+    }
+    uint16_t hi = bf16_rne(v);
+    Ahi[idx] = hi;
+    Alo[idx] = bf16_rne(v - bf16_to_f(hi));
+}
+
+// Bt [cols_p x kp] (k fastest)
+__global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int64_t cols_p, int64_t kp,
+                          uint16_t* Bhi, uint16_t* Blo)
+{
+    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (idx >= cols_p * kp) return;
+    int64_t c = idx / kp, k = idx - c * kp;
+    float v = 0.0f;
+    if (c < C) {
+        if (k < M) v = G[k * C + c].x;
+        else if (layout == 2 && k < 2 * M) v = G[(k - M) * C + c].y;
+    }
+    uint16_t hi = bf16_rne(v);
+    Bhi[idx] = hi;
+    if (Blo) Blo[idx] = bf16_rne(v - bf16_to_f(hi));
+}
+
+// --------------------------------------------------------------------------
+// MFMA GEMM: 128 x 128 tile, 4 waves (each 64 x 64 = 2 x 2 blocks of 32 x 32), BK = 32
+// --------------------------------------------------------------------------
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+
+constexpr int GBM = 128, GBN = 128, GBK = 32;
+constexpr int LDA = GBK + 8;   // padded row (bf16 elements)
+
+template <int NT>
+__global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
+                                                  const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo,
+                                                  int64_t kp, const float2* __restrict__ Eenv, int64_t R, int64_t C,
+                                                  float scale, float2* Eout, float* Pout, int n_tiles_n)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[GBM * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t sAl[GBM * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t sBh[GBN * LDA];
+    __shared__ __attribute__((aligned(16))) uint16_t sBl[(NT == 3 ? GBN : 1) * LDA];
+
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t tile_m = blockIdx.x / n_tiles_n, tile_n = blockIdx.x % n_tiles_n;
+    const int64_t row0 = tile_m * GBM, col0 = tile_n * GBN;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 64;
+
+    f32x16 acc[2][2];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    // each thread moves 16 bf16 (two 16-byte vectors) of each 128 x 32 tile
+    const int lrow = tid >> 1, lcol = (tid & 1) * 16;
+    const uint4* gAh = (const uint4*)(Ahi + (row0 + lrow) * kp + lcol);
+    const uint4* gAl = (const uint4*)(Alo + (row0 + lrow) * kp + lcol);
+    const uint4* gBh = (const uint4*)(Bhi + (col0 + lrow) * kp + lcol);
+    const uint4* gBl = NT == 3 ? (const uint4*)(Blo + (col0 + lrow) * kp + lcol) : nullptr;
+
+    uint4 rAh0 = gAh[0], rAh1 = gAh[1], rAl0 = gAl[0], rAl1 = gAl[1], rBh0 = gBh[0], rBh1 = gBh[1];
+    uint4 rBl0 = make_uint4(0, 0, 0, 0), rBl1 = rBl0;
+    if (NT == 3) {
+        rBl0 = gBl[0];
+        rBl1 = gBl[1];
+    }
+    const int64_t nk = kp / GBK;
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        *(uint4*)&sAh[lrow * LDA + lcol] = rAh0;
+        *(uint4*)&sAh[lrow * LDA + lcol + 8] = rAh1;
+        *(uint4*)&sAl[lrow * LDA + lcol] = rAl0;
+        *(uint4*)&sAl[lrow * LDA + lcol + 8] = rAl1;
+        *(uint4*)&sBh[lrow * LDA + lcol] = rBh0;
+        *(uint4*)&sBh[lrow * LDA + lcol + 8] = rBh1;
+        if (NT == 3) {
+            *(uint4*)&sBl[lrow * LDA + lcol] = rBl0;
+            *(uint4*)&sBl[lrow * LDA + lcol + 8] = rBl1;
+        }
+        __syncthreads();
+        if (kt + 1 < nk) {
+            const int64_t o = (kt + 1) * GBK / 8;   // in uint4 units
+            rAh0 = gAh[o];
+            rAh1 = gAh[o + 1];
+            rAl0 = gAl[o];
+            rAl1 = gAl[o + 1];
+            rBh0 = gBh[o];
+            rBh1 = gBh[o + 1];
+            if (NT == 3) {
+                rBl0 = gBl[o];
+                rBl1 = gBl[o + 1];
+            }
+        }
+        for (int ks = 0; ks < GBK; ks += 16) {
+            const int kofs = ks + (lane >> 5) * 8;
+            bf16x8 ah[2], al[2], bh[2], bl[2];
+            for (int i = 0; i < 2; ++i) {
+                const int r = wm + i * 32 + (lane & 31);
+                ah[i] = *(const bf16x8*)&sAh[r * LDA + kofs];
+                al[i] = *(const bf16x8*)&sAl[r * LDA + kofs];
+            }
+            for (int j = 0; j < 2; ++j) {
+                const int cix = wn + j * 32 + (lane & 31);
+                bh[j] = *(const bf16x8*)&sBh[cix * LDA + kofs];
+                if (NT == 3) bl[j] = *(const bf16x8*)&sBl[cix * LDA + kofs];
+            }
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 2; ++j) {
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
+                    if (NT == 3)
+                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                }
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4)
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int64_t c = col0 + wn + j * 32 + (lane & 31);
+            for (int e = 0; e < 16; e += 2) {
+                const int64_t row = row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+                const int64_t r = row >> 1;
+                if (r >= R || c >= C) continue;
+                float2 e0 = Eenv[r];
+                float er = e0.x + scale * acc[i][j][e];
+                float ei = e0.y + scale * acc[i][j][e + 1];
+                if (Eout) Eout[r * C + c] = make_float2(er, ei);
+                if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
+            }
+        }
+}
+
+void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real, int precision,
+             float* E_out, float* P_out, hipStream_t st)
+{
+    const int64_t R = ch.R, M = ch.M;
+    const float2* G = (const float2*)gamma;
+    if (R == 0 || C == 0) return;
+    if (precision == 0) {
+        dim3 grid(nblk(C, VT), nblk(R, VT));
+        hipLaunchKernelGGL(k_sum_valu, grid, dim3(256), 0, st, ch.H.as<float2>(), G, ch.E_env.as<float2>(), R, M, C,
+                           scale, (float2*)E_out, P_out);
+        HIP_CHECK(hipGetLastError());
+        return;
+    }
+    const int layout = gamma_real ? 1 : 2;
+    const int64_t kd = gamma_real ? M : 2 * M;
+    const int64_t kp = round_up(kd > 0 ? kd : 1, GBK);
+    const int64_t rows_p = round_up(2 * R, GBM);
+    const int64_t cols_p = round_up(C, GBN);
+    if (ch.split_kind == layout && ch.split_ev) HIP_CHECK(hipStreamWaitEvent(st, ch.split_ev, 0));
+    if (ch.split_kind != layout) {
+        ch.a_hi.release();
+        ch.a_lo.release();
+        ch.a_hi = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
+        ch.a_lo = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
+        hipLaunchKernelGGL(k_split_A, dim3(nblk(rows_p * kp, 256)), dim3(256), 0, st, ch.H.as<float2>(), R, M, layout,
+                           rows_p, kp, ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>());
+        HIP_CHECK(hipGetLastError());
+        ch.split_kind = layout;
+        ch.a_rows = rows_p;
+        ch.a_k = kp;
+        if (!ch.split_ev) HIP_CHECK(hipEventCreateWithFlags(&ch.split_ev, hipEventDisableTiming));
+        HIP_CHECK(hipEventRecord(ch.split_ev, st));
+    }
+    const bool three = precision == 2;
+    Scratch bhi(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
+    Scratch blo;
+    if (three) blo = Scratch(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
+    hipLaunchKernelGGL(k_split_B, dim3(nblk(cols_p * kp, 256)), dim3(256), 0, st, G, M, C, layout, cols_p, kp,
+                       bhi.as<uint16_t>(), blo.as<uint16_t>());
+    HIP_CHECK(hipGetLastError());
+    const int n_tn = (int)(cols_p / GBN);
+    const int64_t n_tiles = (rows_p / GBM) * n_tn;
+    if (three)
+        hipLaunchKernelGGL(k_sum_mfma<3>, dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
+                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), blo.as<uint16_t>(), kp, ch.E_env.as<float2>(),
+                           R, C, scale, (float2*)E_out, P_out, n_tn);
+    else
+        hipLaunchKernelGGL(k_sum_mfma<2>, dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
+                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), (const uint16_t*)nullptr, kp,
+                           ch.E_env.as<float2>(), R, C, scale, (float2*)E_out, P_out, n_tn);
+    HIP_CHECK(hipGetLastError());
+}
+
+}  // namespace rt

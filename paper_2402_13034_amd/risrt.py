@@ -1,0 +1,324 @@
+"""Python binding of librisrt (ctypes).  Argument marshalling only: every
+step of the computation runs in the library's HIP kernels.  Device buffers
+and streams come from PyTorch (ROCm).
+
+The library must have been built (``python -m paper_2402_13034_amd.build``);
+there is no fallback: loading fails loudly without it.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librisrt.so")
+
+RT_OK = 0
+RT_EINVAL = -1
+RT_ENOMEM = -2
+RT_EDEVICE = -3
+RT_EBUSY = -4
+RT_ENOTFOUND = -5
+RT_EUNSUPPORTED = -6
+
+PAT_ISO = 0
+PAT_COSPOW = 1
+PAT_MONOPOLE = 2
+
+FLAG_KEEP_HITS = 1
+FLAG_KEEP_PATHS = 2
+FLAG_BRUTE_FORCE = 4
+FLAG_EXHAUSTIVE = 8
+
+PREC_VALU_F32 = 0
+PREC_MFMA_BF16X2 = 1
+PREC_MFMA_BF16X3 = 2
+
+# every entry point declared in include/risrt.h
+ENTRY_POINTS = (
+    "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
+    "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
+    "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy",
+)
+
+
+class RtTx(ctypes.Structure):
+    _fields_ = [("pos", ctypes.c_double * 3), ("axis", ctypes.c_double * 3), ("power_w", ctypes.c_double),
+                ("gain", ctypes.c_double), ("pattern", ctypes.c_int32), ("param", ctypes.c_double)]
+
+
+class RtRx(ctypes.Structure):
+    _fields_ = [("axis", ctypes.c_double * 3), ("gain", ctypes.c_double), ("pattern", ctypes.c_int32),
+                ("param", ctypes.c_double)]
+
+
+class RtParams(ctypes.Structure):
+    _fields_ = [("freq_hz", ctypes.c_double), ("max_order", ctypes.c_int32), ("n_rays", ctypes.c_int64),
+                ("flags", ctypes.c_uint32)]
+
+
+class RtStats(ctypes.Structure):
+    _fields_ = [("segments", ctypes.c_int64), ("discovery_segments", ctypes.c_int64),
+                ("leg_segments", ctypes.c_int64), ("n_cand_tx", ctypes.c_int64), ("n_cand_u", ctypes.c_int64),
+                ("n_env_paths", ctypes.c_int64), ("n_u_paths", ctypes.c_int64), ("n_ris_slots", ctypes.c_int64),
+                ("ms_stage", ctypes.c_float * 8)]
+
+    def as_dict(self):
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_stage"}
+        d["ms_stage"] = list(self.ms_stage)
+        return d
+
+
+class RtEnvPath(ctypes.Structure):
+    _fields_ = [("rx", ctypes.c_int32), ("order", ctypes.c_int32), ("seq", ctypes.c_int32 * 3),
+                ("tri", ctypes.c_int32 * 3), ("length", ctypes.c_double), ("amp", ctypes.c_float * 2)]
+
+
+ENV_DTYPE = np.dtype([("rx", "<i4"), ("order", "<i4"), ("seq", "<i4", 3), ("tri", "<i4", 3),
+                      ("length", "<f8"), ("amp", "<f4", 2)])
+assert ENV_DTYPE.itemsize == ctypes.sizeof(RtEnvPath)
+
+
+class RtError(RuntimeError):
+    def __init__(self, status: int, msg: str):
+        super().__init__("risrt error %d: %s" % (status, msg))
+        self.status = status
+
+
+_lib = None
+
+
+def lib():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise ImportError("librisrt.so is not built: run python -m paper_2402_13034_amd.build")
+        L = ctypes.CDLL(LIB_PATH)
+        P = ctypes.c_void_p
+        i64 = ctypes.c_int64
+        u64 = ctypes.c_uint64
+        pu64 = ctypes.POINTER(ctypes.c_uint64)
+        pi64 = ctypes.POINTER(ctypes.c_int64)
+        sig = {
+            "rt_last_error": (ctypes.c_char_p, []),
+            "rt_init": (ctypes.c_int32, [ctypes.c_int, u64, ctypes.POINTER(P)]),
+            "rt_shutdown": (ctypes.c_int32, [P]),
+            "rt_mem_info": (ctypes.c_int32, [P, pu64, pu64]),
+            "rt_scene_create": (ctypes.c_int32, [P, P, i64, P, i64, P, P, P, P, pu64]),
+            "rt_ris_create": (ctypes.c_int32, [P, P, i64, P, P, ctypes.c_double, ctypes.c_double,
+                                               ctypes.c_double, ctypes.c_double, pu64]),
+            "rt_trace": (ctypes.c_int32, [P, u64, u64, ctypes.POINTER(RtTx), P, i64, ctypes.POINTER(RtRx),
+                                          ctypes.POINTER(RtParams), P, pu64, ctypes.POINTER(RtStats)]),
+            "rt_channel_create": (ctypes.c_int32, [P, i64, i64, P, P, P, pu64]),
+            "rt_channel_info": (ctypes.c_int32, [P, u64, pi64, pi64, pi64, pi64]),
+            "rt_channel_read": (ctypes.c_int32, [P, u64, P, P, P]),
+            "rt_hits_read": (ctypes.c_int32, [P, u64, ctypes.c_int32, P, i64, pi64]),
+            "rt_paths_read": (ctypes.c_int32, [P, u64, P, i64, pi64, P, i64, pi64, P, i64, pi64]),
+            "rt_candidates_read": (ctypes.c_int32, [P, u64, ctypes.c_int32, P, i64, pi64]),
+            "rt_ris_sum": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
+                                            P, P, P]),
+            "rt_destroy": (ctypes.c_int32, [P, u64]),
+        }
+        for name, (res, args) in sig.items():
+            f = getattr(L, name)
+            f.restype = res
+            f.argtypes = args
+        _lib = L
+    return _lib
+
+
+def _check(status: int):
+    if status != RT_OK:
+        raise RtError(status, lib().rt_last_error().decode())
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _stream_handle(stream):
+    if stream is None:
+        try:
+            import torch
+            if torch.cuda.is_available():
+                return ctypes.c_void_p(torch.cuda.current_stream().cuda_stream)
+        except ImportError:
+            pass
+        return ctypes.c_void_p(0)
+    if isinstance(stream, int):
+        return ctypes.c_void_p(stream)
+    return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _v3(x):
+    return (ctypes.c_double * 3)(*[float(v) for v in x])
+
+
+class Context:
+    """One library context on one HIP device."""
+
+    def __init__(self, device: int = 0, mem_budget_bytes: int = 0):
+        self._h = ctypes.c_void_p()
+        _check(lib().rt_init(device, mem_budget_bytes, ctypes.byref(self._h)))
+        self.device = device
+
+    def close(self):
+        if self._h:
+            _check(lib().rt_shutdown(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def mem_info(self):
+        u, b = ctypes.c_uint64(), ctypes.c_uint64()
+        _check(lib().rt_mem_info(self._h, ctypes.byref(u), ctypes.byref(b)))
+        return u.value, b.value
+
+    # ---- objects ----
+    def scene_create(self, V, T, surf, refl_re, refl_im, stream=None) -> int:
+        """Arrays may be NumPy (host) or torch device tensors."""
+        keep = []
+
+        def arg(x, dt):
+            if hasattr(x, "data_ptr"):
+                keep.append(x)
+                return ctypes.c_void_p(x.data_ptr())
+            a = np.ascontiguousarray(x, dt)
+            keep.append(a)
+            return _ptr(a)
+
+        h = ctypes.c_uint64()
+        _check(lib().rt_scene_create(self._h, arg(V, np.float32), int(V.shape[0]), arg(T, np.int32),
+                                     int(T.shape[0]), arg(surf, np.int32), arg(refl_re, np.float32),
+                                     arg(refl_im, np.float32), _stream_handle(stream), ctypes.byref(h)))
+        return h.value
+
+    def ris_create(self, elems, centre, normal, dy, dz, gain, q) -> int:
+        E = np.ascontiguousarray(elems, np.float64)
+        c = np.ascontiguousarray(centre, np.float64)
+        n = np.ascontiguousarray(normal, np.float64)
+        h = ctypes.c_uint64()
+        _check(lib().rt_ris_create(self._h, _ptr(E), E.shape[0], _ptr(c), _ptr(n), dy, dz, gain, q,
+                                   ctypes.byref(h)))
+        return h.value
+
+    def channel_create(self, E_env, H, stream=None) -> int:
+        E = np.ascontiguousarray(E_env, np.complex64)
+        Hh = np.ascontiguousarray(H, np.complex64)
+        h = ctypes.c_uint64()
+        _check(lib().rt_channel_create(self._h, Hh.shape[0], Hh.shape[1], _ptr(E), _ptr(Hh),
+                                       _stream_handle(stream), ctypes.byref(h)))
+        return h.value
+
+    def destroy(self, handle: int):
+        _check(lib().rt_destroy(self._h, handle))
+
+    # ---- tracing ----
+    def trace(self, scene: int, ris: int, tx_pos, tx_axis, tx_power_w, tx_gain, tx_pattern, tx_param, rx_pos,
+              rx_axis, rx_gain, rx_pattern, rx_param, freq_hz, max_order, n_rays, flags=0, stream=None,
+              stats=True):
+        tx = RtTx(_v3(tx_pos), _v3(tx_axis), float(tx_power_w), float(tx_gain), int(tx_pattern), float(tx_param))
+        rx = RtRx(_v3(rx_axis), float(rx_gain), int(rx_pattern), float(rx_param))
+        prm = RtParams(float(freq_hz), int(max_order), int(n_rays), int(flags))
+        if hasattr(rx_pos, "data_ptr"):
+            rp = ctypes.c_void_p(rx_pos.data_ptr())
+            R = int(rx_pos.shape[0])
+            keep = rx_pos
+        else:
+            keep = np.ascontiguousarray(rx_pos, np.float64)
+            rp = _ptr(keep)
+            R = keep.shape[0]
+        st = RtStats()
+        ch = ctypes.c_uint64()
+        _check(lib().rt_trace(self._h, scene, ris, ctypes.byref(tx), rp, R, ctypes.byref(rx), ctypes.byref(prm),
+                              _stream_handle(stream), ctypes.byref(ch), ctypes.byref(st) if stats else None))
+        del keep
+        return ch.value, (st.as_dict() if stats else None)
+
+    def channel_info(self, ch: int):
+        R, M, ne, ns = (ctypes.c_int64() for _ in range(4))
+        _check(lib().rt_channel_info(self._h, ch, ctypes.byref(R), ctypes.byref(M), ctypes.byref(ne),
+                                     ctypes.byref(ns)))
+        return R.value, M.value, ne.value, ns.value
+
+    def channel_read(self, ch: int, stream=None):
+        R, M, _, _ = self.channel_info(ch)
+        E = np.zeros(R, np.complex64)
+        H = np.zeros((R, M), np.complex64)
+        _check(lib().rt_channel_read(self._h, ch, _ptr(E), _ptr(H) if H.size else None, _stream_handle(stream)))
+        return E, H
+
+    def hits_read(self, ch: int, source: int, K: int):
+        rows = ctypes.c_int64()
+        _check(lib().rt_hits_read(self._h, ch, source, None, 0, ctypes.byref(rows)))
+        out = np.zeros((rows.value, K), np.int32)
+        _check(lib().rt_hits_read(self._h, ch, source, _ptr(out), out.size, ctypes.byref(rows)))
+        return out
+
+    def candidates_read(self, ch: int, source: int):
+        n = ctypes.c_int64()
+        _check(lib().rt_candidates_read(self._h, ch, source, None, 0, ctypes.byref(n)))
+        out = np.zeros((n.value, 3), np.int32)
+        _check(lib().rt_candidates_read(self._h, ch, source, _ptr(out), out.size, ctypes.byref(n)))
+        return out
+
+    def paths_read(self, ch: int):
+        R, M, _, _ = self.channel_info(ch)
+        ne, nu, ns = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(lib().rt_paths_read(self._h, ch, None, 0, ctypes.byref(ne), None, 0, ctypes.byref(nu), None, 0,
+                                   ctypes.byref(ns)))
+        env = np.zeros(ne.value, ENV_DTYPE)
+        useq = np.zeros((nu.value, 4), np.int32)
+        valid = np.zeros((ns.value, M), np.uint8)
+        _check(lib().rt_paths_read(self._h, ch, _ptr(env) if env.size else None, ne.value, ctypes.byref(ne),
+                                   _ptr(useq) if useq.size else None, nu.value, ctypes.byref(nu),
+                                   _ptr(valid) if valid.size else None, ns.value, ctypes.byref(ns)))
+        return {"env": env, "useq": useq, "ris_valid": valid.astype(bool)}
+
+    # ---- RIS sum ----
+    def ris_sum(self, ch: int, gamma, scale: float = 1.0, gamma_is_real: bool = False,
+                precision: int = PREC_MFMA_BF16X2, want_E: bool = False, want_P: bool = True, stream=None,
+                E_out=None, P_out=None):
+        """gamma: torch complex64 device tensor [M, C].  Returns (E, P) device
+        tensors (None where not requested)."""
+        import torch
+        R, M, _, _ = self.channel_info(ch)
+        C = int(gamma.shape[1])
+        g = gamma.contiguous()
+        dev = g.device
+        if want_E and E_out is None:
+            E_out = torch.empty((R, C), dtype=torch.complex64, device=dev)
+        if want_P and P_out is None:
+            P_out = torch.empty((R, C), dtype=torch.float32, device=dev)
+        _check(lib().rt_ris_sum(self._h, ch, ctypes.c_void_p(g.data_ptr()), C, float(scale), int(gamma_is_real),
+                                int(precision), ctypes.c_void_p(E_out.data_ptr()) if E_out is not None else None,
+                                ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None,
+                                _stream_handle(stream)))
+        return E_out, P_out
+
+
+def upload_problem(ctx: Context, prob, stream=None):
+    """Create the scene and RIS objects of a synthetic problem.  Returns
+    (scene handle, ris handle or 0)."""
+    sc = prob.scene
+    scene = ctx.scene_create(sc.V, sc.T, sc.surf, sc.refl_re, sc.refl_im, stream=stream)
+    ris = 0
+    if prob.ris is not None:
+        r = prob.ris
+        ris = ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
+    return scene, ris
+
+
+def trace_problem(ctx: Context, prob, scene: int, ris: int, flags: int = 0, n_rays: Optional[int] = None,
+                  rx=None, stream=None):
+    return ctx.trace(scene, ris, prob.tx_pos, prob.tx_ant.axis, prob.tx_power_w, prob.tx_ant.gain,
+                     prob.tx_ant.pattern, prob.tx_ant.param, prob.rx_pos if rx is None else rx,
+                     prob.rx_ant.axis, prob.rx_ant.gain, prob.rx_ant.pattern, prob.rx_ant.param, prob.freq,
+                     prob.order, prob.n_rays if n_rays is None else n_rays, flags=flags, stream=stream)

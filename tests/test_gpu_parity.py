@@ -1,0 +1,249 @@
+"""GPU path (through the C ABI) against the oracle.
+
+Integer results (hit lists, candidate sequences, path lists, RIS validity)
+must match bit for bit: both sides take each geometric decision with the
+same formula and precision.  Fields: per path power within 1e-4 relative and
+phase within 1e-3 rad; sums (H, E_env, E) within 1e-4 in power relative to
+max(P_ref, 1e-3 P_inc), P_inc being the power of the incoherent sum.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+
+from oracle import oracle as O
+from paper_2402_13034_amd import synth
+
+pytestmark = pytest.mark.gpu
+ETA0 = 120.0 * math.pi
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_13034_amd import risrt
+    c = risrt.Context(0)
+    yield c
+    c.close()
+
+
+def _say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+def _run(ctx, prob, flags, n_rays=None):
+    from paper_2402_13034_amd import risrt
+    scene, ris = risrt.upload_problem(ctx, prob)
+    ch, st = risrt.trace_problem(ctx, prob, scene, ris, flags=flags, n_rays=n_rays)
+    return scene, ris, ch, st
+
+
+def _close_complex(got, ref, inc, tol_p=1e-4):
+    """|got|^2 vs |ref|^2 within tol_p * max(|ref|^2, 1e-3 inc^2), and the
+    complex error small against the same scale."""
+    got = np.asarray(got, np.complex128)
+    ref = np.asarray(ref, np.complex128)
+    scale = np.maximum(np.abs(ref) ** 2, 1e-3 * inc ** 2)
+    dp = np.abs(np.abs(got) ** 2 - np.abs(ref) ** 2)
+    assert np.all(dp <= tol_p * scale + 1e-300), float(np.max(dp / scale))
+    de = np.abs(got - ref) ** 2
+    assert np.all(de <= tol_p * scale + 1e-300), float(np.max(de / scale))
+
+
+def _phase_err(a, b):
+    d = np.angle(np.asarray(a, np.complex128) / np.asarray(b, np.complex128))
+    return np.abs(d)
+
+
+def _incoherent(idx, amp, shape):
+    s = np.zeros(shape)
+    np.add.at(s, idx, np.abs(amp))
+    return s
+
+
+def check_problem(ctx, prob, n_rays=None, brute=False):
+    from paper_2402_13034_amd import risrt
+    K = prob.order
+    flags = risrt.FLAG_KEEP_HITS | risrt.FLAG_KEEP_PATHS | (risrt.FLAG_BRUTE_FORCE if brute else 0)
+    _say("case", prob.name, "rays", n_rays or prob.n_rays, "R", prob.rx_pos.shape[0], "K", K, "brute", brute)
+    scene, ris, ch, st = _run(ctx, prob, flags, n_rays)
+    ref = O.trace(prob, n_rays=n_rays)
+    # discovery hit lists: bit exact
+    h_tx = ctx.hits_read(ch, 0, K)
+    assert np.array_equal(h_tx, ref["hits_tx"])
+    if prob.ris is not None:
+        h_u = ctx.hits_read(ch, 1, K)
+        assert np.array_equal(h_u, ref["hits_u"])
+    # candidates
+    c_tx = ctx.candidates_read(ch, 0)[:, :K]
+    assert np.array_equal(c_tx, ref["cand_tx"])
+    # environment paths
+    p = ctx.paths_read(ch)
+    env = p["env"]
+    assert np.array_equal(env["rx"], ref["env_rx"])
+    assert np.array_equal(env["seq"][:, :K], ref["env_seq"])
+    assert np.array_equal(env["tri"][:, :K], ref["env_tri"])
+    assert np.allclose(env["length"], ref["env_len"], rtol=1e-12, atol=0)
+    a_gpu = env["amp"][:, 0] + 1j * env["amp"][:, 1]
+    a_ref = ref["env_amp"]
+    if a_ref.size:
+        assert np.max(np.abs(np.abs(a_gpu) ** 2 / np.abs(a_ref) ** 2 - 1)) < 1e-4
+        assert np.max(_phase_err(a_gpu, a_ref)) < 1e-3
+    E_env, H = ctx.channel_read(ch)
+    R = prob.rx_pos.shape[0]
+    inc_env = _incoherent(ref["env_rx"], ref["env_amp"], R)
+    _close_complex(E_env, ref["E_env"], inc_env)
+    if prob.ris is not None:
+        M = prob.ris.elems.shape[0]
+        useq = p["useq"]
+        assert np.array_equal(useq[:, 0], ref["u_rx"])
+        assert np.array_equal(useq[:, 1:1 + K], ref["u_seq"])
+        assert np.array_equal(p["ris_valid"], ref["ris_valid"])
+        sl, mm = ref["ris_amp_idx"][:, 0], ref["ris_amp_idx"][:, 1]
+        inc = _incoherent((ref["ris_slot_rx"][sl], mm), ref["ris_amp"], (R, M))
+        _close_complex(H, ref["H"], inc)
+        assert st["n_u_paths"] == useq.shape[0]
+    assert st["n_env_paths"] == env.shape[0]
+    for h in (ch, scene) + ((ris,) if ris else ()):
+        ctx.destroy(h)
+    return st
+
+
+def test_tiny_box(ctx):
+    st = check_problem(ctx, synth.tiny_box())
+    assert st["n_env_paths"] == 64 * 7
+
+
+def test_tiny_box_order3_ragged(ctx):
+    check_problem(ctx, synth.tiny_box(order=3, n_rx=37, n_rays=3001))
+
+
+def test_lab_room_reduced(ctx):
+    check_problem(ctx, synth.lab_room(nx=9, ny=7), n_rays=20_000)
+
+
+def test_lab_room_order2_brute_force(ctx):
+    check_problem(ctx, synth.lab_room(nx=5, ny=4, order=2), n_rays=4000, brute=True)
+
+
+def test_bvh_equals_brute_force(ctx):
+    """Walking the BVH gives exactly what testing every triangle gives."""
+    from paper_2402_13034_amd import risrt
+    prob = synth.lab_room(nx=8, ny=8)
+    outs = []
+    for brute in (False, True):
+        flags = risrt.FLAG_KEEP_HITS | risrt.FLAG_KEEP_PATHS | (risrt.FLAG_BRUTE_FORCE if brute else 0)
+        scene, ris, ch, st = _run(ctx, prob, flags, 50_000)
+        E, H = ctx.channel_read(ch)
+        outs.append((ctx.hits_read(ch, 0, 3), ctx.hits_read(ch, 1, 3), E, H, ctx.paths_read(ch)["ris_valid"]))
+        for h in (ch, scene, ris):
+            ctx.destroy(h)
+    for a, b in zip(outs[0], outs[1]):
+        assert np.array_equal(a, b)
+
+
+def test_deterministic(ctx):
+    from paper_2402_13034_amd import risrt
+    prob = synth.lab_room(nx=16, ny=16)
+    res = []
+    for _ in range(2):
+        scene, ris, ch, st = _run(ctx, prob, 0, 100_000)
+        res.append(ctx.channel_read(ch))
+        for h in (ch, scene, ris):
+            ctx.destroy(h)
+    assert res[0][0].tobytes() == res[1][0].tobytes()
+    assert res[0][1].tobytes() == res[1][1].tobytes()
+
+
+def test_free_space_and_single_element(ctx):
+    """No geometry: Friis env path and direct RIS paths only."""
+    lam = synth.C0 / 23.8e9
+    n = np.array([1.0, 0.0, 0.0])
+    u = np.array([0.0, 0.0, 0.5])
+    elems = synth.hex_ris(6, 9.2e-3, u, n)
+    tx = synth.paper_spherical(u, 1.86, -36.0, 90.0)
+    rx = synth.rx_grid(0.92, 1.52, 7, 0.02, 0.92, 9, 0.114)
+    prob = synth.Problem("anechoic", synth.empty_scene(), 23.8e9, tx, 0.01,
+                         synth.Antenna(synth.unit(u - tx), 10 ** 1.9, synth.PAT_COSPOW, 10 ** 1.9 / 2 - 1),
+                         synth.Ris(elems, n, u, 6.6e-3, 6.6e-3, 4 * math.pi * 6.6e-3 ** 2 / lam ** 2, 1.0),
+                         rx, synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_MONOPOLE, 0.25),
+                         2, 1000, 0)
+    check_problem(ctx, prob)
+
+
+def test_single_triangle_and_one_receiver(ctx):
+    mb = synth.MeshBuilder()
+    mb.quad((0.0, -1.0, -1.0), (0.0, 2.0, 0.0), (0.0, 0.0, 2.0), 1, 0.7 + 0.2j)
+    sc = mb.build()
+    sc = synth.Scene(sc.V, sc.T[:1], sc.refl_re[:1], sc.refl_im[:1], sc.surf[:1])
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    prob = synth.Problem("one_tri", sc, 28e9, np.array([1.0, 0.3, -0.2]), 0.01, iso, None,
+                         np.array([[1.5, -0.4, -0.3]]), iso, 1, 2000, 0)
+    check_problem(ctx, prob)
+
+
+def test_order0(ctx):
+    check_problem(ctx, synth.tiny_box(order=0, n_rx=5))
+
+
+def test_exhaustive_mode_matches_oracle(ctx):
+    from paper_2402_13034_amd import risrt
+    prob = synth.tiny_box(order=2, n_rx=9)
+    scene, ris, ch, st = _run(ctx, prob, risrt.FLAG_KEEP_PATHS | risrt.FLAG_EXHAUSTIVE)
+    ref = O.trace(prob, mode="exhaustive")
+    E, H = ctx.channel_read(ch)
+    R, M = H.shape
+    sl, mm = ref["ris_amp_idx"][:, 0], ref["ris_amp_idx"][:, 1]
+    _close_complex(H, ref["H"], _incoherent((ref["ris_slot_rx"][sl], mm), ref["ris_amp"], (R, M)))
+    assert np.array_equal(ctx.paths_read(ch)["ris_valid"], ref["ris_valid"])
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+
+
+# ---------------------------------------------------------------------------
+# RIS sum
+# ---------------------------------------------------------------------------
+def _gemm_case(ctx, R, M, C, real, precision, seed=0):
+    import torch
+    from paper_2402_13034_amd import risrt
+    rng = np.random.default_rng(seed)
+    # channel magnitudes spanning a few decades like real element channels
+    H = ((rng.normal(size=(R, M)) + 1j * rng.normal(size=(R, M))) * 10 ** rng.uniform(-7, -5, size=(R, 1)))
+    H = H.astype(np.complex64)
+    E_env = (H[:, :3].sum(axis=1) * 0.5).astype(np.complex64)
+    G = synth.gamma_binary(M, C, 1.0, rng) if real else synth.gamma_2bit(M, C, 1.0, rng)
+    G = G.astype(np.complex64)
+    ch = ctx.channel_create(E_env, H)
+    g = torch.from_numpy(G).cuda()
+    E, P = ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=real, precision=precision, want_E=True, want_P=True)
+    torch.cuda.synchronize()
+    E = E.cpu().numpy()
+    P = P.cpu().numpy()
+    E_ref, P_ref = O.ris_sum(E_env.astype(np.complex128), H.astype(np.complex128), G.astype(np.complex128), 0.9)
+    inc = np.abs(E_env)[:, None] + 0.9 * np.abs(H).astype(np.float64) @ np.abs(G).astype(np.float64)
+    P_inc = inc ** 2 / (2 * ETA0)
+    ctx.destroy(ch)
+    return E, P, E_ref, P_ref, P_inc
+
+
+@pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (257, 1024, 129, True)])
+def test_ris_sum_valu(ctx, R, M, C, real):
+    E, P, E_ref, P_ref, P_inc = _gemm_case(ctx, R, M, C, real, 0)
+    sel = P_ref >= 1e-3 * P_inc
+    assert np.max(np.abs(P[sel] / P_ref[sel] - 1)) < 1e-4
+    assert np.max(np.abs(E - E_ref) ** 2 / np.maximum(np.abs(E_ref) ** 2, 1e-3 * (P_inc * 2 * ETA0))) < 1e-6
+
+
+@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (300, 1024, 257, True),
+                                        (64, 1024, 128, False)])
+def test_ris_sum_mfma(ctx, R, M, C, real, prec):
+    E, P, E_ref, P_ref, P_inc = _gemm_case(ctx, R, M, C, real, prec)
+    sel = P_ref >= 1e-3 * P_inc
+    db = np.abs(10 * np.log10(P[sel] / P_ref[sel]))
+    assert db.max() < 0.1, db.max()
+    nrmse = np.sqrt(np.mean(np.abs(E - E_ref) ** 2) / np.mean(np.abs(E_ref) ** 2))
+    assert nrmse < 1e-3, nrmse
