@@ -28,7 +28,40 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
-FP64_VECTOR_PEAK_TFLOPS = 78.6
+VECTOR_PEAK_TFLOPS = 78.6   # FP32 (non-packed FMA) = FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
+
+# Algorithmic flops of the per-element kernel's units of work (FMA = 2):
+#   BVH node visit: two slab tests, 6 FMA + 12 min/max each      -> 48
+#   ray/triangle test (FP32 Moller-Trumbore, see rt_internal.hpp) -> 50
+#   FP64 containment test (normal, projection, 3 edge functions)  -> 50
+#   (slot, element) pair: images, back-trace, side tests, patterns,
+#     lengths, phase, complex amplitude                            -> 150
+#   visibility leg set-up (length, direction, conversions)        -> 30
+FLOPS_PER = {"node": 48, "tri": 50, "contain": 50, "pair": 150, "leg": 30}
+KERNEL_SOURCES = ["paper_2402_13034_amd/csrc/rt_trace.hip", "paper_2402_13034_amd/csrc/rt_internal.hpp"]
+COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_ris_lab_room_hbm_counters.json")
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for p in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per k_ris launch from the committed counter summary, if it
+    was taken on the current kernel sources."""
+    try:
+        with open(COUNTERS_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return d.get("bytes_per_launch")
 
 
 def log(*a):
@@ -70,8 +103,13 @@ def run_trace_bench(ctx, prob, steps, warmup):
     stats = [step() for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    # counting build of the per-element kernel (untimed; same inputs and results)
+    scene = ctx.scene_create(*mesh)
+    ch, cst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_COUNT_WORK)
+    ctx.destroy(ch)
+    ctx.destroy(scene)
     ctx.destroy(ris)
-    return stats, t1 - t0
+    return stats, t1 - t0, cst["ris_work"]
 
 
 def run_gemm_bench(ctx, reps=5):
@@ -138,6 +176,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
+                    help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: the path runs on a single device (see DESIGN.md for how it "
@@ -146,16 +186,34 @@ def main():
     import torch
     from paper_2402_13034_amd import risrt, synth
     torch.cuda.set_device(0)
+    if args.copy_calibration:
+        n = args.copy_calibration * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log("bench: copy calibration %d MiB read + %d MiB written" % (args.copy_calibration, args.copy_calibration))
+        del src, dst
     prob = synth.lab_room()
     ctx = risrt.Context(0)
     log("bench: lab room, %d triangles, M=%d, R=%d, K=%d, rays=%d" % (
         prob.scene.n_tri, prob.ris.elems.shape[0], prob.rx_pos.shape[0], prob.order, prob.n_rays))
-    stats, dt = run_trace_bench(ctx, prob, args.steps, args.warmup)
+    stats, dt, work = run_trace_bench(ctx, prob, args.steps, args.warmup)
     segs = sum(s["segments"] for s in stats)
     value = segs / dt / 1e6
     ms_step = dt / args.steps * 1e3
     log("bench: %.1f Mseg/s, %.2f ms/step" % (value, ms_step))
     st0 = stats[-1]
+    ris_ms = sum(s["ms_stage"][5] for s in stats) / len(stats)
+    units = dict(zip(["node", "tri", "contain", "pair", "leg"], work))
+    flops = sum(FLOPS_PER[k] * units[k] for k in units)
+    achieved = flops / (ris_ms * 1e-3) / 1e12
+    roofline = {"kernel": "k_ris (per-element image method + visibility legs + field)", "bound": "alu",
+                "achieved": achieved, "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
+                "frac": achieved / VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
+                "launch_ms": ris_ms, "work_per_launch": units, "flops_per_unit": FLOPS_PER}
+    log("bench: k_ris %.3f ms, work %s -> %.2f TFLOP/s" % (ris_ms, units, achieved))
     gemm = None
     if not args.no_gemm:
         gemm = run_gemm_bench(ctx)
@@ -183,6 +241,7 @@ def main():
                                % prob.scene.n_tri,
                    "segments_per_step": segs // args.steps,
                    "stage_ms": st0["ms_stage"]},
+        "roofline": roofline,
         "ris_sum": gemm,
         "cpu_baseline": cpu,
     }

@@ -57,6 +57,8 @@ typedef int32_t rt_status;
 #define RT_FLAG_BRUTE_FORCE 4u /* test every triangle instead of walking the BVH */
 #define RT_FLAG_EXHAUSTIVE 8u  /* candidates = every surface sequence of order <= K
                                   (no discovery rays; small scenes only) */
+#define RT_FLAG_COUNT_WORK 16u /* run the counting build of the per-element kernel and
+                                  report its work in rt_stats.ris_work (same results) */
 
 /* rt_ris_sum precision */
 #define RT_PREC_VALU_F32 0   /* FP32 complex multiply-add on the vector ALUs */
@@ -108,7 +110,11 @@ typedef struct {
     int64_t n_env_paths;         /* valid Tx -> Rx paths */
     int64_t n_u_paths;           /* valid RIS-centre -> Rx sequences of order >= 1 */
     int64_t n_ris_slots;         /* (rx, sequence) slots expanded per element */
-    float ms_stage[8];           /* bvh-check, discovery, dedupe, env, centre, ris, field, total */
+    float ms_stage[8];           /* setup, candidates (discovery, dedupe, images), -, Tx paths,
+                                    RIS-centre paths, per-element kernel, Tx->element legs, total */
+    int64_t ris_work[5];         /* with RT_FLAG_COUNT_WORK: BVH node visits, triangle tests,
+                                    FP64 containment tests, (slot, element) pairs, legs of
+                                    the per-element kernel */
 } rt_stats;
 
 /* Environment path record (RT_FLAG_KEEP_PATHS): Tx -> surfaces seq[0..k) ->

@@ -312,6 +312,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
 {
     return guarded(ctx, [&]() -> rt_status {
         if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
+        if (params->flags & ~31u) return fail(RT_EINVAL, "unknown flag");
         if (params->max_order < 0 || params->max_order > RT_MAX_K)
             return fail(RT_EUNSUPPORTED, "max_order must be 0..3");
         if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
@@ -367,6 +368,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
             stats->n_u_paths = out.n_u;
             stats->n_ris_slots = out.n_slots;
             for (int k = 0; k < 8; ++k) stats->ms_stage[k] = out.ms[k];
+            for (int k = 0; k < 5; ++k) stats->ris_work[k] = out.work[k];
         }
         *channel = insert(ctx, o);
         return RT_OK;
@@ -468,7 +470,11 @@ rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t 
             if (cap_u < ch.n_u) return fail(RT_EINVAL, "capacity too small");
             if (ch.n_u) {
                 if (!ch.useq.p) return fail(RT_EINVAL, "paths not kept");
-                HIP_CHECK(hipMemcpy(useq, ch.useq.p, sizeof(int32_t) * 4 * (size_t)ch.n_u, hipMemcpyDefault));
+                // internal rows: rx, s0..s2, t0..t2, 0
+                std::vector<int32_t> rows((size_t)(8 * ch.n_u));
+                HIP_CHECK(hipMemcpy(rows.data(), ch.useq.p, sizeof(int32_t) * rows.size(), hipMemcpyDefault));
+                for (int64_t i = 0; i < ch.n_u; ++i)
+                    for (int j = 0; j < 4; ++j) useq[4 * i + j] = rows[8 * i + j];
             }
         }
         if (ris_valid) {

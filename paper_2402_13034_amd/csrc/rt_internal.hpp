@@ -124,6 +124,12 @@ __device__ __forceinline__ void reflect32(float4 b, float4 c, float& dx, float& 
     dz = dz - k * nz;
 }
 
+// Work counters of the counting build of a kernel (node visits, triangle
+// tests, FP64 containment tests).
+struct WorkCount {
+    uint32_t nodes = 0, tris = 0, contain = 0;
+};
+
 // --------------------------------------------------------------------------
 // BVH walk.  Boxes are inflated at build time, so the slab test may use FMA:
 // it never rejects a box holding a triangle the exact-formula test accepts.
@@ -234,9 +240,10 @@ __device__ int closest_hit(const SceneView& s, float ox, float oy, float oz, flo
 }
 
 // Any hit of a triangle not on surface skip_a / skip_b with tmin < t < tmax.
-template <bool BRUTE>
+template <bool BRUTE, bool CNT = false>
 __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float dx, float dy, float dz,
-                        float tmin, float tmax, int skip_a, int skip_b, int* stack, int stride)
+                        float tmin, float tmax, int skip_a, int skip_b, int* stack, int stride,
+                        WorkCount* wc = nullptr)
 {
     if (s.n_tri == 0) return false;
     if (BRUTE) {
@@ -245,6 +252,7 @@ __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float 
             int sf = __float_as_int(b.w);
             if (sf == skip_a || sf == skip_b) continue;
             float t;
+            if (CNT) wc->tris++;
             if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) return true;
         }
         return false;
@@ -254,6 +262,7 @@ __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float 
     int node = s.root;
     while (true) {
         if (node >= 0) {
+            if (CNT) wc->nodes++;
             const float4* nd = s.nodes + 4 * node;
             float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
             float tl, tr;
@@ -277,6 +286,7 @@ __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float 
             float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
             int sf = __float_as_int(b.w);
             float t;
+            if (CNT && sf != skip_a && sf != skip_b) wc->tris++;
             if (sf != skip_a && sf != skip_b &&
                 mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t))
                 return true;
@@ -290,9 +300,9 @@ __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float 
 
 // Leg A -> B blocked?  FP32 ray from fl(A) along fl((B - A) / L), EPS < t < L - EPS,
 // ignoring the surfaces sa, sb of its end points.
-template <bool BRUTE>
+template <bool BRUTE, bool CNT = false>
 __device__ bool leg_blocked(const SceneView& s, const double* A, const double* B, int sa, int sb,
-                            int* stack, int stride)
+                            int* stack, int stride, WorkCount* wc = nullptr)
 {
 #pragma clang fp contract(off)
     double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
@@ -300,8 +310,8 @@ __device__ bool leg_blocked(const SceneView& s, const double* A, const double* B
     float tmin = (float)RT_EPS;
     float tmax = (float)(L - RT_EPS);
     if (!(tmax > tmin)) return false;
-    return any_hit<BRUTE>(s, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
-                          (float)(w2 / L), tmin, tmax, sa, sb, stack, stride);
+    return any_hit<BRUTE, CNT>(s, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
+                               (float)(w2 / L), tmin, tmax, sa, sb, stack, stride, wc);
 }
 
 // --------------------------------------------------------------------------
@@ -374,13 +384,15 @@ __device__ __forceinline__ double plane_side(const double* pl, const double* p)
 }
 
 // Triangle of surface sf that contains p, or -1.
-__device__ inline int surface_contains(const SceneView& s, int sf, const double* p)
+template <bool CNT = false>
+__device__ inline int surface_contains(const SceneView& s, int sf, const double* p, WorkCount* wc = nullptr)
 {
     const double* bx = s.s_box + 6 * sf;
     if (p[0] < bx[0] || p[1] < bx[1] || p[2] < bx[2] || p[0] > bx[3] || p[1] > bx[4] || p[2] > bx[5])
         return -1;
     for (int j = s.s_ptr[sf]; j < s.s_ptr[sf + 1]; ++j) {
         int t = s.s_tris[j];
+        if (CNT) wc->contain++;
         if (contains64(s.v64 + 9 * t, p)) return t;
     }
     return -1;

@@ -32,6 +32,7 @@ FLAG_KEEP_HITS = 1
 FLAG_KEEP_PATHS = 2
 FLAG_BRUTE_FORCE = 4
 FLAG_EXHAUSTIVE = 8
+FLAG_COUNT_WORK = 16
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
@@ -64,11 +65,12 @@ class RtStats(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_int64), ("discovery_segments", ctypes.c_int64),
                 ("leg_segments", ctypes.c_int64), ("n_cand_tx", ctypes.c_int64), ("n_cand_u", ctypes.c_int64),
                 ("n_env_paths", ctypes.c_int64), ("n_u_paths", ctypes.c_int64), ("n_ris_slots", ctypes.c_int64),
-                ("ms_stage", ctypes.c_float * 8)]
+                ("ms_stage", ctypes.c_float * 8), ("ris_work", ctypes.c_int64 * 5)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f != "ms_stage"}
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_stage", "ris_work")}
         d["ms_stage"] = list(self.ms_stage)
+        d["ris_work"] = list(self.ris_work)
         return d
 
 
