@@ -128,6 +128,15 @@ def run_gemm_bench(ctx, reps=5):
     g = torch.from_numpy(s).cuda()
     P = torch.empty((R, C), dtype=torch.float32, device="cuda")
     out = {}
+    # error of the matrix-core sum against FP64 on the same FP32 channel (256 sampled receivers)
+    E_env, H = ctx.channel_read(ch)
+    rows = np.random.default_rng(6).choice(R, 256, replace=False)
+    E_ref = E_env[rows].astype(np.complex128)[:, None] + 0.9 * (H[rows].astype(np.complex128) @ s.astype(np.complex128))
+    P_ref = np.abs(E_ref) ** 2 / (2 * 120 * math.pi)
+    inc = (np.abs(E_env[rows]).astype(float)[:, None] + 0.9 * np.abs(H[rows]).astype(float).sum(1)[:, None]) ** 2 \
+        / (2 * 120 * math.pi)
+    sel = P_ref >= 1e-3 * inc
+    rows_t = torch.from_numpy(rows).cuda()
     for name, prec in (("bf16x2", risrt.PREC_MFMA_BF16X2), ("valu_f32", risrt.PREC_VALU_F32)):
         ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=prec, P_out=P)
         torch.cuda.synchronize()
@@ -139,18 +148,72 @@ def run_gemm_bench(ctx, reps=5):
         e1.record()
         torch.cuda.synchronize()
         ms = e0.elapsed_time(e1) / n
+        Eo, Po = ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=prec, want_E=True, want_P=True)
+        torch.cuda.synchronize()
+        Es = Eo[rows_t].cpu().numpy().astype(np.complex128)
+        Ps = Po[rows_t].cpu().numpy().astype(np.float64)
+        del Eo, Po
         out[name] = {"ms": ms, "tflops_complex_equiv": 8.0 * R * M * C / (ms * 1e-3) / 1e12,
-                     "tflops_executed": (4.0 * R * M * C * (2 if prec == 1 else 1)) / (ms * 1e-3) / 1e12}
+                     "tflops_executed": (4.0 * R * M * C * (2 if prec == 1 else 1)) / (ms * 1e-3) / 1e12,
+                     "err_vs_fp64": {"max_db": float(np.max(np.abs(10 * np.log10(Ps[sel] / P_ref[sel])))),
+                                     "max_phase_rad": float(np.max(np.abs(np.angle(Es[sel] / E_ref[sel])))),
+                                     "nrmse": float(np.sqrt(np.mean(np.abs(Es - E_ref) ** 2) /
+                                                            np.mean(np.abs(E_ref) ** 2))),
+                                     "rows_sampled": 256, "frac_above_null_threshold": float(sel.mean())}}
     for h in (ch, scene, ris):
         ctx.destroy(h)
     out["shape"] = {"R": R, "M": M, "C": C}
     return out
 
 
-def cpu_baseline(n_rx_side=4, n_rays=1_000_000):
+def run_serving_bench(ctx, n_queries=300, n_slots=4, load=0.7):
+    """Serving mix: 12 deployments over random box rooms of 1k-200k
+    triangles (RIS 37-1024 elements, 16^2-128^2 receivers, order 1-3), query
+    batches of 1-512 2-bit configurations.  Channels are traced on first use
+    (warm-up), then a closed-loop burst measures saturation and a seeded
+    Poisson stream at `load` x saturation gives the latency percentiles."""
+    from paper_2402_13034_amd import serve, workloads
+    scenes, riss, deps = workloads.serving_mix()
+    srv = serve.Server(ctx, n_slots=n_slots)
+    for k, v in scenes.items():
+        srv.add_scene(k, v)
+    for k, v in riss.items():
+        srv.add_ris(k, v)
+    for d in deps:
+        srv.add_deployment(d)
+    t0 = time.perf_counter()
+    for d in deps:   # trace every deployment once
+        M = riss[d.ris_key].elems.shape[0]
+        srv.submit(d.key, np.ones((M, 1), np.complex64)).result()
+        log("bench: serving warm-up %s traced (%.1f s)" % (d.key, time.perf_counter() - t0))
+    t_warm = time.perf_counter() - t0
+    qs = workloads.query_stream(deps, riss, n_queries, seed=12)
+    t0 = time.perf_counter()
+    futs = [srv.submit(k, g) for k, g in qs]
+    for f in futs:
+        f.result()
+    t_sat = time.perf_counter() - t0
+    sat_qps = n_queries / t_sat
+    srv.latencies.clear()
+    qs2 = workloads.query_stream(deps, riss, n_queries, seed=13)
+    t0 = time.perf_counter()
+    serve.run_poisson(srv, qs2, rate_hz=load * sat_qps, seed=14)
+    t_run = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    cols = sum(g.shape[1] for _, g in qs2)
+    return {"p50_ms": st["p50_ms"], "p99_ms": st["p99_ms"], "mean_ms": st["mean_ms"],
+            "saturation_queries_per_s": sat_qps, "offered_queries_per_s": load * sat_qps,
+            "achieved_queries_per_s": n_queries / t_run, "configs_per_s": cols / t_run,
+            "queries": n_queries, "slots": n_slots, "batches": st["batches"], "traces": st["traces"],
+            "warmup_trace_s": t_warm, "admission_waits": st["admission_waits"], "errors": st["errors"],
+            "deployments": len(deps), "scene_triangles": sorted(int(s.n_tri) for s in scenes.values())}
+
+
+def cpu_baseline(n_rx_side=8, n_rays=1_000_000):
     """The oracle on a bounded sample of the lab-room workload: full discovery
     (1e6 rays per source, order 3) and image-method paths, legs and fields
-    for a 4 x 4 receiver subsample of the same grid."""
+    for an 8 x 8 receiver subsample of the same grid."""
     from oracle import oracle as O
     from paper_2402_13034_amd import synth
     prob = synth.lab_room()
@@ -176,6 +239,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -218,6 +282,10 @@ def main():
     if not args.no_gemm:
         gemm = run_gemm_bench(ctx)
         log("bench: RIS sum", json.dumps(gemm))
+    serving = None
+    if not args.no_serve:
+        serving = run_serving_bench(ctx)
+        log("bench: serving", json.dumps(serving))
     cpu = None
     if not args.no_cpu:
         cpu = cpu_baseline()
@@ -243,6 +311,10 @@ def main():
                    "stage_ms": st0["ms_stage"]},
         "roofline": roofline,
         "ris_sum": gemm,
+        "serving": serving,
+        "latency_p50_ms": serving["p50_ms"] if serving else None,
+        "latency_p99_ms": serving["p99_ms"] if serving else None,
+        "ris_field_tflops": gemm["bf16x2"]["tflops_complex_equiv"] if gemm else None,
         "cpu_baseline": cpu,
     }
     print(json.dumps(out))

@@ -1,0 +1,322 @@
+"""Continuous-batching serving loop over the risrt C ABI.
+
+A query names a *deployment* (scene, RIS, receiver grid, reflection order,
+transmitter) and carries a batch of RIS configurations Gamma [M x C]; its
+answer is the received power map P [R x C] (eqs. (9)-(10)).
+
+* The scene's BVH and the deployment's channel (H, E_env) stay on the device
+  in an LRU cache charged to the context's memory budget; a query whose
+  channel is missing first traces it (every other query keeps running).
+* A scheduler admits queued work into `n_slots` slots, each with its own HIP
+  stream, as slots and memory free up (continuous batching: requests that
+  arrive while others run join at the next free slot).
+* Queued queries for the same deployment and precision are merged into one
+  RIS sum: their configuration columns are concatenated, summed in one
+  matrix-core launch, and split again.  Every output column depends only on
+  its own column of Gamma, so a result is bit-identical alone and in a mix.
+* A query that does not fit the budget waits; one that cannot fit even alone
+  fails with the library's RT_ENOMEM instead of blocking the queue.
+* Latency = completion time - submission time (host clock), per query.
+"""
+from __future__ import annotations
+
+import collections
+import dataclasses
+import threading
+import time
+from concurrent.futures import Future
+from typing import Dict, List, Optional
+
+import numpy as np
+
+from . import risrt
+
+
+@dataclasses.dataclass
+class Deployment:
+    key: str
+    scene_key: str
+    ris_key: str
+    tx_pos: np.ndarray
+    tx_axis: np.ndarray
+    tx_power_w: float
+    tx_gain: float
+    tx_pattern: int
+    tx_param: float
+    rx_pos: np.ndarray
+    rx_axis: np.ndarray
+    rx_gain: float
+    rx_pattern: int
+    rx_param: float
+    freq_hz: float
+    order: int
+    n_rays: int
+
+
+@dataclasses.dataclass
+class _Query:
+    qid: int
+    dep: str
+    gamma: np.ndarray          # complex64 [M, C]
+    scale: float
+    precision: int
+    t_submit: float
+    future: Future
+
+
+def deployment_from_problem(key: str, scene_key: str, ris_key: str, prob) -> Deployment:
+    return Deployment(key, scene_key, ris_key, prob.tx_pos, prob.tx_ant.axis, prob.tx_power_w, prob.tx_ant.gain,
+                      prob.tx_ant.pattern, prob.tx_ant.param, prob.rx_pos, prob.rx_ant.axis, prob.rx_ant.gain,
+                      prob.rx_ant.pattern, prob.rx_ant.param, prob.freq, prob.order, prob.n_rays)
+
+
+class Server:
+    def __init__(self, ctx: risrt.Context, n_slots: int = 4, max_cols: int = 4096, cache_frac: float = 0.6):
+        import torch
+        self.ctx = ctx
+        self.n_slots = n_slots
+        self.max_cols = max_cols
+        self._torch = torch
+        self._budget = ctx.mem_info()[1]
+        self._cache_limit = int(cache_frac * self._budget)
+        self._scenes_host: Dict[str, object] = {}
+        self._ris_host: Dict[str, object] = {}
+        self._deps: Dict[str, Deployment] = {}
+        self._scene_h: Dict[str, int] = {}
+        self._ris_h: Dict[str, int] = {}
+        self._chan: "collections.OrderedDict[str, int]" = collections.OrderedDict()
+        self._chan_bytes: Dict[str, int] = {}
+        self._in_use: Dict[str, int] = collections.Counter()
+        self._key_locks: Dict[str, threading.Lock] = collections.defaultdict(threading.Lock)
+        self._lock = threading.Condition()
+        self._queue: List[_Query] = []
+        self._free_slots = list(range(n_slots))
+        self._streams = [torch.cuda.Stream() for _ in range(n_slots)]
+        self._reserved = 0
+        self._next_id = 0
+        self._running = True
+        self.latencies: List[float] = []
+        self.n_traces = 0
+        self.n_batches = 0
+        self.n_cols = 0
+        self.cache_hits = 0
+        self.admission_waits = 0
+        self._errors = 0
+        self._sched = threading.Thread(target=self._scheduler, name="risrt-scheduler", daemon=True)
+        self._sched.start()
+
+    # ---------------- registration ----------------
+    def add_scene(self, key: str, scene) -> None:
+        self._scenes_host[key] = scene
+
+    def add_ris(self, key: str, ris) -> None:
+        self._ris_host[key] = ris
+
+    def add_deployment(self, dep: Deployment) -> None:
+        self._deps[dep.key] = dep
+
+    # ---------------- client API ----------------
+    def submit(self, dep_key: str, gamma: np.ndarray, scale: float = 1.0,
+               precision: int = risrt.PREC_MFMA_BF16X2) -> Future:
+        if dep_key not in self._deps:
+            raise KeyError(dep_key)
+        f: Future = Future()
+        with self._lock:
+            q = _Query(self._next_id, dep_key, np.ascontiguousarray(gamma, np.complex64), float(scale),
+                       int(precision), time.perf_counter(), f)
+            self._next_id += 1
+            self._queue.append(q)
+            self._lock.notify_all()
+        return f
+
+    def drain(self, timeout: Optional[float] = None) -> None:
+        t0 = time.perf_counter()
+        with self._lock:
+            while self._queue or len(self._free_slots) < self.n_slots:
+                if timeout is not None and time.perf_counter() - t0 > timeout:
+                    raise TimeoutError("serving queue did not drain")
+                self._lock.wait(0.05)
+
+    def close(self) -> None:
+        self.drain()
+        with self._lock:
+            self._running = False
+            self._lock.notify_all()
+        self._sched.join()
+        for h in list(self._chan.values()):
+            self.ctx.destroy(h)
+        for h in list(self._scene_h.values()) + list(self._ris_h.values()):
+            self.ctx.destroy(h)
+        self._chan.clear()
+        self._scene_h.clear()
+        self._ris_h.clear()
+
+    def stats(self) -> dict:
+        lat = np.asarray(self.latencies) * 1e3
+        return {"queries": int(lat.size), "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
+                "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
+                "mean_ms": float(lat.mean()) if lat.size else None, "traces": self.n_traces,
+                "batches": self.n_batches, "columns": self.n_cols, "channel_cache_hits": self.cache_hits,
+                "admission_waits": self.admission_waits, "errors": self._errors}
+
+    # ---------------- scheduling ----------------
+    def _estimate(self, dep: Deployment, cols: int, cached: bool) -> int:
+        ris = self._ris_host[dep.ris_key]
+        R, M = dep.rx_pos.shape[0], ris.elems.shape[0]
+        out = R * cols * 4 + M * cols * 8 * 3
+        split = 2 * 2 * (2 * R + 128) * (2 * M + 32) + (cols + 128) * (2 * M + 32) * 4
+        if cached:
+            return out + split
+        chan = R * M * 8 + R * 8
+        trace_scratch = 64 * R * 300 + 64 * dep.n_rays * max(1, dep.order) + R * M * 4
+        return out + split + chan + trace_scratch
+
+    def _scheduler(self) -> None:
+        while True:
+            with self._lock:
+                while self._running and (not self._queue or not self._free_slots):
+                    self._lock.wait(0.05)
+                if not self._running:
+                    return
+                head = self._queue[0]
+                batch = [head]
+                cols = head.gamma.shape[1]
+                for q in self._queue[1:]:
+                    if q.dep == head.dep and q.precision == head.precision and q.scale == head.scale \
+                            and cols + q.gamma.shape[1] <= self.max_cols:
+                        batch.append(q)
+                        cols += q.gamma.shape[1]
+                dep = self._deps[head.dep]
+                est = self._estimate(dep, cols, head.dep in self._chan)
+                in_use = self.ctx.mem_info()[0]
+                busy = len(self._free_slots) < self.n_slots
+                if busy and in_use + self._reserved + est > self._budget:
+                    self.admission_waits += 1
+                    self._lock.wait(0.01)
+                    continue
+                for q in batch:
+                    self._queue.remove(q)
+                slot = self._free_slots.pop()
+                self._reserved += est
+            threading.Thread(target=self._run_batch, args=(slot, batch, est), daemon=True).start()
+
+    # ---------------- device work ----------------
+    def _scene(self, key: str, stream) -> int:
+        with self._key_locks["scene:" + key]:
+            if key not in self._scene_h:
+                sc = self._scenes_host[key]
+                self._scene_h[key] = self.ctx.scene_create(sc.V, sc.T, sc.surf, sc.refl_re, sc.refl_im,
+                                                           stream=stream)
+            return self._scene_h[key]
+
+    def _ris(self, key: str) -> int:
+        with self._key_locks["ris:" + key]:
+            if key not in self._ris_h:
+                r = self._ris_host[key]
+                self._ris_h[key] = self.ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
+            return self._ris_h[key]
+
+    def _channel(self, dep: Deployment, stream) -> int:
+        with self._key_locks["chan:" + dep.key]:
+            with self._lock:
+                if dep.key in self._chan:
+                    self._chan.move_to_end(dep.key)
+                    self._in_use[dep.key] += 1
+                    self.cache_hits += 1
+                    return self._chan[dep.key]
+            self._evict(dep.key)
+            scene = self._scene(dep.scene_key, stream)
+            ris = self._ris(dep.ris_key)
+            ch, _ = self.ctx.trace(scene, ris, dep.tx_pos, dep.tx_axis, dep.tx_power_w, dep.tx_gain,
+                                   dep.tx_pattern, dep.tx_param, dep.rx_pos, dep.rx_axis, dep.rx_gain,
+                                   dep.rx_pattern, dep.rx_param, dep.freq_hz, dep.order, dep.n_rays,
+                                   stream=stream, stats=False)
+            R, M, _, _ = self.ctx.channel_info(ch)
+            with self._lock:
+                self._chan[dep.key] = ch
+                self._chan_bytes[dep.key] = R * M * 8 * 3 + R * 8
+                self._in_use[dep.key] += 1
+                self.n_traces += 1
+            return ch
+
+    def _evict(self, keep: str) -> None:
+        with self._lock:
+            total = sum(self._chan_bytes.values())
+            victims = []
+            for k in list(self._chan.keys()):
+                if total <= self._cache_limit:
+                    break
+                if k != keep and self._in_use[k] == 0:
+                    victims.append((k, self._chan.pop(k)))
+                    total -= self._chan_bytes.pop(k)
+        for _, h in victims:
+            self.ctx.destroy(h)
+
+    def _run_batch(self, slot: int, batch: List[_Query], est: int) -> None:
+        torch = self._torch
+        stream = self._streams[slot]
+        dep = self._deps[batch[0].dep]
+        held = False
+        try:
+            with torch.cuda.stream(stream):
+                ch = self._channel(dep, stream)
+                held = True
+                g = np.concatenate([q.gamma for q in batch], axis=1) if len(batch) > 1 else batch[0].gamma
+                gd = torch.from_numpy(g).to("cuda", non_blocking=False)
+                _, P = self.ctx.ris_sum(ch, gd, scale=batch[0].scale, gamma_is_real=bool(np.all(g.imag == 0)),
+                                        precision=batch[0].precision, want_P=True, stream=stream)
+                Ph = P.cpu().numpy()
+            t = time.perf_counter()
+            c0 = 0
+            for q in batch:
+                c = q.gamma.shape[1]
+                q.future.set_result(Ph[:, c0:c0 + c])
+                c0 += c
+                self.latencies.append(t - q.t_submit)
+            with self._lock:
+                self.n_batches += 1
+                self.n_cols += g.shape[1]
+        except risrt.RtError as e:
+            requeue = False
+            with self._lock:
+                # out of budget while other work holds memory: wait for it instead of failing
+                if e.status == risrt.RT_ENOMEM and len(self._free_slots) < self.n_slots - 1:
+                    self._queue[0:0] = batch
+                    self.admission_waits += 1
+                    requeue = True
+                else:
+                    self._errors += 1
+            if not requeue:
+                for q in batch:
+                    if not q.future.done():
+                        q.future.set_exception(e)
+        except Exception as e:   # surfaced to the callers; the loop keeps serving
+            with self._lock:
+                self._errors += 1
+            for q in batch:
+                if not q.future.done():
+                    q.future.set_exception(e)
+        finally:
+            with self._lock:
+                if held:
+                    self._in_use[dep.key] -= 1
+                self._reserved -= est
+                self._free_slots.append(slot)
+                self._lock.notify_all()
+
+
+def run_poisson(server: Server, queries, rate_hz: float, seed: int = 0):
+    """Submit (dep_key, gamma) pairs with exponential inter-arrival times and
+    wait for all answers.  Returns the futures in submission order."""
+    rng = np.random.default_rng(seed)
+    futs = []
+    t_next = time.perf_counter()
+    for dep_key, gamma in queries:
+        t_next += rng.exponential(1.0 / rate_hz)
+        d = t_next - time.perf_counter()
+        if d > 0:
+            time.sleep(d)
+        futs.append(server.submit(dep_key, gamma))
+    for f in futs:
+        f.exception()
+    return futs

@@ -1,0 +1,103 @@
+"""Serving loop: results are the same alone and in a concurrent mix; the
+loop admits by memory and reports latencies."""
+import numpy as np
+import pytest
+
+from paper_2402_13034_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def mix():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    from paper_2402_13034_amd import workloads
+    scenes, riss, deps = workloads.serving_mix(tri_targets=(1_000, 5_000), ris_rings=(3, 6), ris_square=(),
+                                               grids=(8, 16), orders=(1, 2), n_deployments=4, n_rays=20_000)
+    return scenes, riss, deps
+
+
+def _server(ctx, mix, n_slots):
+    from paper_2402_13034_amd import serve
+    scenes, riss, deps = mix
+    s = serve.Server(ctx, n_slots=n_slots)
+    for k, v in scenes.items():
+        s.add_scene(k, v)
+    for k, v in riss.items():
+        s.add_ris(k, v)
+    for d in deps:
+        s.add_deployment(d)
+    return s
+
+
+def test_alone_equals_mix(mix):
+    from paper_2402_13034_amd import risrt, serve, workloads
+    scenes, riss, deps = mix
+    qs = workloads.query_stream(deps, riss, 40, seed=3, max_cols=64)
+    with risrt.Context(0) as ctx:
+        alone = []
+        s1 = _server(ctx, mix, 1)
+        for dk, g in qs:
+            alone.append(s1.submit(dk, g).result(timeout=120))
+        s1.close()
+        s4 = _server(ctx, mix, 4)
+        futs = serve.run_poisson(s4, qs, rate_hz=2000.0, seed=1)
+        mixed = [f.result(timeout=120) for f in futs]
+        st = s4.stats()
+        s4.close()
+    for a, b in zip(alone, mixed):
+        assert a.shape == b.shape
+        assert a.tobytes() == b.tobytes()
+    assert st["queries"] == len(qs) and st["errors"] == 0
+    assert st["batches"] <= len(qs)
+    assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_mix_matches_oracle_channel(mix):
+    """One deployment's answers against the oracle's channel and FP64 sum."""
+    from oracle import oracle as O
+    from paper_2402_13034_amd import risrt, workloads
+    scenes, riss, deps = mix
+    d = deps[0]
+    sc = scenes[d.scene_key]
+    prob = synth.Problem("dep", sc, d.freq_hz, d.tx_pos, d.tx_power_w,
+                         synth.Antenna(d.tx_axis, d.tx_gain, d.tx_pattern, d.tx_param), riss[d.ris_key],
+                         d.rx_pos, synth.Antenna(d.rx_axis, d.rx_gain, d.rx_pattern, d.rx_param), d.order,
+                         d.n_rays, 0)
+    ref = O.trace(prob)
+    rng = np.random.default_rng(5)
+    g = synth.gamma_2bit(riss[d.ris_key].elems.shape[0], 33, 0.9, rng).astype(np.complex64)
+    with risrt.Context(0) as ctx:
+        s = _server(ctx, mix, 2)
+        P = s.submit(d.key, g).result(timeout=120)
+        s.close()
+    E_ref, P_ref = O.ris_sum(ref["E_env"], ref["H"], g.astype(np.complex128))
+    inc = (np.abs(ref["E_env"])[:, None] + np.abs(ref["H"]) @ np.abs(g).astype(float)) ** 2 / (2 * O.ETA0)
+    sel = P_ref >= 1e-3 * inc
+    assert np.max(np.abs(10 * np.log10(P[sel] / P_ref[sel]))) < 0.1
+
+
+def test_small_budget_admission(mix):
+    """A tight memory budget serialises work but every query completes; a
+    query that cannot fit at all fails with RT_ENOMEM."""
+    from paper_2402_13034_amd import risrt, serve, workloads
+    scenes, riss, deps = mix
+    qs = workloads.query_stream(deps, riss, 12, seed=9, max_cols=32)
+    with risrt.Context(0, mem_budget_bytes=96 << 20) as ctx:
+        s = _server(ctx, mix, 4)
+        futs = serve.run_poisson(s, qs, rate_hz=5000.0, seed=2)
+        res = [f.result(timeout=120) for f in futs]
+        st = s.stats()
+        s.close()
+        assert len(res) == len(qs) and st["errors"] == 0
+    with risrt.Context(0, mem_budget_bytes=1 << 20) as ctx:
+        s = _server(ctx, mix, 2)
+        f = s.submit(deps[0].key, qs[0][1] if qs[0][0] == deps[0].key else
+                     synth.gamma_2bit(riss[deps[0].ris_key].elems.shape[0], 4, 0.9,
+                                      np.random.default_rng(0)).astype(np.complex64))
+        with pytest.raises(risrt.RtError) as ei:
+            f.result(timeout=120)
+        assert ei.value.status == risrt.RT_ENOMEM
+        s.close()
