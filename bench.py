@@ -88,21 +88,32 @@ def run_trace_bench(ctx, prob, steps, warmup):
     ris = ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
     P_out = torch.empty((prob.rx_pos.shape[0], gamma.shape[1]), dtype=torch.float32, device="cuda")
 
+    host_ms = []
+
     def step():
+        t0 = time.perf_counter()
         scene = ctx.scene_create(*mesh)
+        t1 = time.perf_counter()
         ch, st = risrt.trace_problem(ctx, prob, scene, ris, rx=rx)
+        t2 = time.perf_counter()
         ctx.ris_sum(ch, gamma, precision=risrt.PREC_VALU_F32, want_P=False, P_out=P_out)
+        t3 = time.perf_counter()
         ctx.destroy(ch)
         ctx.destroy(scene)
+        t4 = time.perf_counter()
+        host_ms.append([(t1 - t0) * 1e3, (t2 - t1) * 1e3, (t3 - t2) * 1e3, (t4 - t3) * 1e3])
         return st
 
     for _ in range(warmup):
         step()
     torch.cuda.synchronize()
+    host_ms.clear()
     t0 = time.perf_counter()
     stats = [step() for _ in range(steps)]
     torch.cuda.synchronize()
     t1 = time.perf_counter()
+    for s, h in zip(stats, host_ms):
+        s["host_ms"] = h
     # counting build of the per-element kernel (untimed; same inputs and results)
     scene = ctx.scene_create(*mesh)
     ch, cst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_COUNT_WORK)
@@ -308,7 +319,9 @@ def main():
                                "horn Tx cos^8, 64x64 Rx grid at 1.2 m, order<=3, 1e6 rays per source"
                                % prob.scene.n_tri,
                    "segments_per_step": segs // args.steps,
-                   "stage_ms": st0["ms_stage"]},
+                   "stage_ms": st0["ms_stage"],
+                   "host_ms_scene_trace_sum_destroy": [round(float(np.mean([s["host_ms"][k] for s in stats])), 3)
+                                                       for k in range(4)]},
         "roofline": roofline,
         "ris_sum": gemm,
         "serving": serving,

@@ -33,13 +33,6 @@ __device__ __forceinline__ float ord2f(unsigned u)
 {
     return __uint_as_float((u & 0x80000000u) ? (u & 0x7fffffffu) : ~u);
 }
-static inline float ord2f_host(unsigned u)
-{
-    unsigned v = (u & 0x80000000u) ? (u & 0x7fffffffu) : ~u;
-    float f;
-    std::memcpy(&f, &v, 4);
-    return f;
-}
 
 // bounds[0..2] min centroid, [3..5] max centroid, [6..8] min vertex, [9..11] max vertex
 __global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* surf_in, const float* rr,
@@ -113,15 +106,22 @@ struct Box6 {
     float lo[3], hi[3];
 };
 
-__global__ void k_leaves(const uint64_t* keys, const float* V, const int32_t* T, const int32_t* surf,
-                         int64_t nt, float pad, float4* tri4, float* lbox)
+__device__ __forceinline__ int64_t clamp_index(int32_t v, int64_t n) { return v < 0 ? 0 : (v >= n ? n - 1 : v); }
+
+// Leaf data in sorted order.  Box padding: 1e-5 of the scene extent + 1e-6 m
+// + 1e-5 |x| (indices are clamped: malformed input is reported after the build).
+__global__ void k_leaves(const uint64_t* keys, const float* V, const int32_t* T, const int32_t* surf, int64_t nv,
+                         int64_t nt, const unsigned* bounds, float4* tri4, float* lbox)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt) return;
+    float ext = 0.0f;
+    for (int k = 0; k < 3; ++k) ext = fmaxf(ext, ord2f(bounds[9 + k]) - ord2f(bounds[6 + k]));
+    const float pad = 1e-5f * ext + 1e-6f;
     int32_t t = (int32_t)(keys[i] & 0xffffffffu);
-    const float* a = V + 3 * (int64_t)T[3 * t + 0];
-    const float* b = V + 3 * (int64_t)T[3 * t + 1];
-    const float* c = V + 3 * (int64_t)T[3 * t + 2];
+    const float* a = V + 3 * clamp_index(T[3 * t + 0], nv);
+    const float* b = V + 3 * clamp_index(T[3 * t + 1], nv);
+    const float* c = V + 3 * clamp_index(T[3 * t + 2], nv);
     tri4[3 * i + 0] = make_float4(a[0], a[1], a[2], __int_as_float(t));
     tri4[3 * i + 1] = make_float4(b[0] - a[0], b[1] - a[1], b[2] - a[2], __int_as_float(surf[t]));
     tri4[3 * i + 2] = make_float4(c[0] - a[0], c[1] - a[1], c[2] - a[2], 0.0f);
@@ -198,6 +198,50 @@ __global__ void k_depth(const int32_t* parent_int, const int32_t* parent_leaf, i
     atomicMax(maxd, d);
 }
 
+// 4-wide nodes: every internal node of even depth lists its grandchildren
+// (a leaf child stands for itself).  Boxes are copied from the binary nodes.
+__global__ void k_node4(const int32_t* child, const int32_t* parent_int, const float4* nodes, int64_t ni,
+                        float4* node4)
+{
+    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (n >= ni) return;
+    int d = 0;
+    for (int32_t p = parent_int[n]; p >= 0 && p < ni && d < 4096; p = parent_int[p]) ++d;
+    if (d & 1) return;
+    float lo[4][3], hi[4][3];
+    int32_t ref[4];
+    int cnt = 0;
+    for (int side = 0; side < 2; ++side) {
+        const int32_t c = child[2 * n + side];
+        const float4 l = nodes[4 * n + 2 * side], h = nodes[4 * n + 2 * side + 1];
+        if (c < 0) {
+            lo[cnt][0] = l.x; lo[cnt][1] = l.y; lo[cnt][2] = l.z;
+            hi[cnt][0] = h.x; hi[cnt][1] = h.y; hi[cnt][2] = h.z;
+            ref[cnt++] = c;
+        } else {
+            for (int g = 0; g < 2; ++g) {
+                const float4 gl = nodes[4 * c + 2 * g], gh = nodes[4 * c + 2 * g + 1];
+                lo[cnt][0] = gl.x; lo[cnt][1] = gl.y; lo[cnt][2] = gl.z;
+                hi[cnt][0] = gh.x; hi[cnt][1] = gh.y; hi[cnt][2] = gh.z;
+                ref[cnt++] = child[2 * c + g];
+            }
+        }
+    }
+    for (int j = cnt; j < 4; ++j) {
+        lo[j][0] = lo[j][1] = lo[j][2] = 0.0f;   // masked out by the reference
+        hi[j][0] = hi[j][1] = hi[j][2] = 0.0f;
+        ref[j] = 0x7fffffff;
+    }
+    float4* q = node4 + 8 * n;
+    for (int a = 0; a < 3; ++a) {
+        q[2 * a] = make_float4(lo[0][a], lo[1][a], lo[2][a], lo[3][a]);
+        q[2 * a + 1] = make_float4(hi[0][a], hi[1][a], hi[2][a], hi[3][a]);
+    }
+    q[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
+                       __int_as_float(ref[3]));
+    q[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+}
+
 // every internal node reached by exactly two children during the refit
 __global__ void k_check_refit(const int32_t* flags, int64_t ni, int32_t* bad)
 {
@@ -205,34 +249,60 @@ __global__ void k_check_refit(const int32_t* flags, int64_t ni, int32_t* bad)
     if (i < ni && flags[i] != 2) atomicOr(bad, 8);
 }
 
-// surfaces
-__global__ void k_surf_keys(const int32_t* surf, int64_t nt, uint64_t* keys, int32_t* n_surf)
+__global__ void k_tri_proj(const double* v64, int64_t nt, double* proj, int32_t* axes)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (t >= nt) return;
-    keys[t] = ((uint64_t)(uint32_t)surf[t] << 32) | (uint64_t)t;
-    atomicMax(n_surf, surf[t] + 1);
+    triangle_projection(v64 + 9 * t, proj + 6 * t, axes + t);
 }
 
-__global__ void k_surf_csr(const uint64_t* keys, int64_t nt, int32_t n_surf, int32_t* s_ptr, int32_t* s_tris,
+// surfaces
+// surface ids are clamped to 0..nt-1 (larger ones are reported as invalid)
+__global__ void k_surf_keys(const int32_t* surf, int64_t nt, uint64_t* keys, int32_t* n_surf, int32_t* bad)
+{
+    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    int32_t s = surf[t];
+    if (s < 0 || s >= nt) {
+        atomicOr(bad, 4);
+        s = s < 0 ? 0 : (int32_t)(nt - 1);
+    }
+    keys[t] = ((uint64_t)(uint32_t)s << 32) | (uint64_t)t;
+    atomicMax(n_surf, s + 1);
+}
+
+// CSR over surfaces from the sorted (surface, triangle) keys; an unused id
+// gets an empty range (and is reported as invalid).
+__global__ void k_surf_csr(const uint64_t* keys, int64_t nt, const int32_t* n_surf_p, int32_t* s_ptr, int32_t* s_tris,
                            int32_t* seen)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= nt) return;
+    const int32_t n_surf = *n_surf_p;
     int32_t s = (int32_t)(keys[i] >> 32);
     s_tris[i] = (int32_t)(keys[i] & 0xffffffffu);
-    if (i == 0 || (int32_t)(keys[i - 1] >> 32) != s) {
-        s_ptr[s] = (int32_t)i;
+    int32_t prev = i == 0 ? -1 : (int32_t)(keys[i - 1] >> 32);
+    if (prev != s) {
         atomicAdd(seen, 1);
+        for (int32_t q = prev + 1; q <= s; ++q) s_ptr[q] = (int32_t)i;
     }
-    if (i == nt - 1) s_ptr[n_surf] = (int32_t)nt;
+    if (i == nt - 1)
+        for (int32_t q = s + 1; q <= n_surf; ++q) s_ptr[q] = (int32_t)nt;
 }
 
-__global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const double* v64, int32_t n_surf,
+__global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const double* v64, const int32_t* n_surf_p,
                              double* s_plane, double* s_box)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= n_surf) return;
+    if (s >= *n_surf_p) return;
+    if (s_ptr[s] >= s_ptr[s + 1]) {
+        for (int k = 0; k < 4; ++k) s_plane[4 * s + k] = 0.0;
+        for (int k = 0; k < 3; ++k) {
+            s_box[6 * s + k] = 1e300;
+            s_box[6 * s + 3 + k] = -1e300;
+        }
+        return;
+    }
     const double* v = v64 + 9 * (int64_t)s_tris[s_ptr[s]];
     double e1[3], e2[3];
     for (int k = 0; k < 3; ++k) {
@@ -263,6 +333,15 @@ __global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const 
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+__global__ void k_ctl_init(unsigned* ctl)
+{
+    int i = threadIdx.x;
+    if (i >= 64) return;
+    unsigned v = 0u;
+    if (i < 3 || (i >= 6 && i < 9)) v = 0xffffffffu;   // running minima
+    ctl[i] = v;
+}
+
 void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,
                  const int32_t* surf, const float* rr, const float* ri, hipStream_t st)
 {
@@ -283,56 +362,38 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     HIP_CHECK(hipMemcpyAsync(dI.p, ri, dI.bytes, hipMemcpyDefault, st));
 
     s.v64 = Scratch(c, sizeof(double) * 9 * (size_t)nt, st);
+    s.t_proj = Scratch(c, sizeof(double) * 6 * (size_t)nt, st);
+    s.t_axes = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
     s.refl = Scratch(c, sizeof(float2) * (size_t)nt, st);
     s.surf = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
     s.tri4 = Scratch(c, sizeof(float4) * 3 * (size_t)nt, st);
     Scratch cent(c, sizeof(float4) * (size_t)nt, st);
-    // small control block: bounds[12] unsigned, bad, maxdepth, n_surf, seen
+    // control block: bounds[12] unsigned, bad, maxdepth, n_surf, seen
     Scratch ctl(c, 64 * sizeof(int32_t), st);
     unsigned* bounds = ctl.as<unsigned>();
     int32_t* bad = ctl.as<int32_t>() + 12;
     int32_t* maxd = ctl.as<int32_t>() + 13;
     int32_t* nsurf = ctl.as<int32_t>() + 14;
     int32_t* seen = ctl.as<int32_t>() + 15;
-    {
-        std::vector<unsigned> init(64, 0);
-        for (int k = 0; k < 3; ++k) {
-            init[k] = 0xffffffffu;
-            init[3 + k] = 0u;
-            init[6 + k] = 0xffffffffu;
-            init[9 + k] = 0u;
-        }
-        // staged through a small pinned buffer is unnecessary: 256 bytes
-        HIP_CHECK(hipMemcpyAsync(ctl.p, init.data(), 64 * sizeof(unsigned), hipMemcpyHostToDevice, st));
-        HIP_CHECK(hipStreamSynchronize(st));
-    }
+    hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, bounds);
+    HIP_CHECK(hipGetLastError());
     const int B = 256;
     hipLaunchKernelGGL(k_scene_prep, dim3(blocks_for(nt, B)), dim3(B), 0, st, dV.as<float>(), dT.as<int32_t>(),
                        dS.as<int32_t>(), dR.as<float>(), dI.as<float>(), nv, nt, s.v64.as<double>(),
                        s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad);
     HIP_CHECK(hipGetLastError());
-    // the extent (leaf padding) and the input checks are needed before any index is used
-    unsigned hb[14];
-    HIP_CHECK(hipMemcpyAsync(hb, bounds, sizeof(hb), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    {
-        int32_t badv = (int32_t)hb[12];
-        if (badv & 1) throw inval_error("triangle vertex index out of range");
-        if (badv & 2) throw inval_error("vertex coordinate not finite or |x| > 1e6");
-        if (badv & 4) throw inval_error("negative surface id");
-    }
+    hipLaunchKernelGGL(k_tri_proj, dim3(blocks_for(nt, B)), dim3(B), 0, st, s.v64.as<double>(), nt,
+                       s.t_proj.as<double>(), s.t_axes.as<int32_t>());
+    HIP_CHECK(hipGetLastError());
     Scratch keys(c, sizeof(uint64_t) * (size_t)nt, st);
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, B)), dim3(B), 0, st, cent.as<float4>(), bounds, nt,
                        keys.as<uint64_t>());
     HIP_CHECK(hipGetLastError());
     sort_u64(c, keys.as<uint64_t>(), nt, 62, st);
-
     Scratch lbox(c, sizeof(float) * 6 * (size_t)nt, st);
-    float ext = 0.0f;
-    for (int k = 0; k < 3; ++k) ext = fmaxf(ext, ord2f_host(hb[9 + k]) - ord2f_host(hb[6 + k]));
-    float pad = 1e-5f * ext + 1e-6f;
     hipLaunchKernelGGL(k_leaves, dim3(blocks_for(nt, B)), dim3(B), 0, st, keys.as<uint64_t>(), dV.as<float>(),
-                       dT.as<int32_t>(), dS.as<int32_t>(), nt, pad, s.tri4.as<float4>(), lbox.as<float>());
+                       dT.as<int32_t>(), s.surf.as<int32_t>(), nv, nt, bounds, s.tri4.as<float4>(),
+                       lbox.as<float>());
     HIP_CHECK(hipGetLastError());
 
     if (nt >= 2) {
@@ -351,48 +412,50 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
                            pint.as<int32_t>(), pleaf.as<int32_t>(), lbox.as<float>(), ibox.as<float>(),
                            flags.as<int32_t>(), s.nodes.as<float4>(), nt);
         HIP_CHECK(hipGetLastError());
+        s.node4 = Scratch(c, sizeof(float4) * 8 * (size_t)ni, st);
+        hipLaunchKernelGGL(k_node4, dim3(blocks_for(ni, B)), dim3(B), 0, st, child.as<int32_t>(), pint.as<int32_t>(),
+                           s.nodes.as<float4>(), ni, s.node4.as<float4>());
+        HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(k_depth, dim3(blocks_for(nt, B)), dim3(B), 0, st, pint.as<int32_t>(),
                            pleaf.as<int32_t>(), nt, maxd);
         HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(k_check_refit, dim3(blocks_for(ni, B)), dim3(B), 0, st, flags.as<int32_t>(), ni, bad);
         HIP_CHECK(hipGetLastError());
         s.root = 0;
-        // keep temporaries alive until the stream has used them (stream-ordered frees)
     } else {
         s.root = ~0;
     }
 
-    // surfaces
+    // surfaces (tables sized for the largest valid count, n_surf <= n_tri)
     Scratch skeys(c, sizeof(uint64_t) * (size_t)nt, st);
     hipLaunchKernelGGL(k_surf_keys, dim3(blocks_for(nt, B)), dim3(B), 0, st, s.surf.as<int32_t>(), nt,
-                       skeys.as<uint64_t>(), nsurf);
+                       skeys.as<uint64_t>(), nsurf, bad);
     HIP_CHECK(hipGetLastError());
     sort_u64(c, skeys.as<uint64_t>(), nt, 64, st);
-    int32_t h[4];
-    HIP_CHECK(hipMemcpyAsync(h, ctl.as<int32_t>() + 12, sizeof(h), hipMemcpyDeviceToHost, st));
-    HIP_CHECK(hipStreamSynchronize(st));
-    if (h[0] & 8) throw hip_error("BVH build produced an inconsistent tree");
-    if (h[1] > RT_STACK - 1) throw inval_error("BVH deeper than the traversal stack");
-    if (h[2] > nt) throw inval_error("surface ids must be 0..n_surf-1, each used");
-    s.max_depth = h[1];
-    s.n_surf = h[2];
-    s.s_ptr = Scratch(c, sizeof(int32_t) * (size_t)(s.n_surf + 1), st);
+    s.s_ptr = Scratch(c, sizeof(int32_t) * (size_t)(nt + 1), st);
     s.s_tris = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
-    s.s_plane = Scratch(c, sizeof(double) * 4 * (size_t)s.n_surf, st);
-    s.s_box = Scratch(c, sizeof(double) * 6 * (size_t)s.n_surf, st);
-    hipLaunchKernelGGL(k_surf_csr, dim3(blocks_for(nt, B)), dim3(B), 0, st, skeys.as<uint64_t>(), nt,
-                       (int32_t)s.n_surf, s.s_ptr.as<int32_t>(), s.s_tris.as<int32_t>(), seen);
+    s.s_plane = Scratch(c, sizeof(double) * 4 * (size_t)nt, st);
+    s.s_box = Scratch(c, sizeof(double) * 6 * (size_t)nt, st);
+    hipLaunchKernelGGL(k_surf_csr, dim3(blocks_for(nt, B)), dim3(B), 0, st, skeys.as<uint64_t>(), nt, nsurf,
+                       s.s_ptr.as<int32_t>(), s.s_tris.as<int32_t>(), seen);
     HIP_CHECK(hipGetLastError());
-    {
-        int32_t n_seen = 0;
-        HIP_CHECK(hipMemcpyAsync(&n_seen, seen, sizeof(int32_t), hipMemcpyDeviceToHost, st));
-        HIP_CHECK(hipStreamSynchronize(st));
-        if (n_seen != s.n_surf) throw inval_error("surface ids must be 0..n_surf-1, each used");
-    }
-    hipLaunchKernelGGL(k_surf_plane, dim3(blocks_for(s.n_surf, 64)), dim3(64), 0, st, s.s_ptr.as<int32_t>(),
-                       s.s_tris.as<int32_t>(), s.v64.as<double>(), (int32_t)s.n_surf, s.s_plane.as<double>(),
+    hipLaunchKernelGGL(k_surf_plane, dim3(blocks_for(nt, 64)), dim3(64), 0, st, s.s_ptr.as<int32_t>(),
+                       s.s_tris.as<int32_t>(), s.v64.as<double>(), nsurf, s.s_plane.as<double>(),
                        s.s_box.as<double>());
     HIP_CHECK(hipGetLastError());
+    // one read-back: input checks, tree checks, surface count
+    int64_t hq[2];
+    read_i64s((const int64_t*)(ctl.as<int32_t>() + 12), hq, 2, st);
+    const int32_t badv = (int32_t)(hq[0] & 0xffffffff), depth = (int32_t)(hq[0] >> 32);
+    const int32_t n_surf = (int32_t)(hq[1] & 0xffffffff), n_seen = (int32_t)(hq[1] >> 32);
+    if (badv & 1) throw inval_error("triangle vertex index out of range");
+    if (badv & 2) throw inval_error("vertex coordinate not finite or |x| > 1e6");
+    if (badv & 4) throw inval_error("surface id outside 0..n_tri-1");
+    if (badv & 8) throw hip_error("BVH build produced an inconsistent tree");
+    if (depth > RT_STACK - 1) throw inval_error("BVH deeper than the traversal stack");
+    if (n_seen != n_surf) throw inval_error("surface ids must be 0..n_surf-1, each used");
+    s.max_depth = depth;
+    s.n_surf = n_surf;
 }
 
 }  // namespace rt

@@ -15,23 +15,77 @@ namespace rt {
 static thread_local std::string g_err;
 
 // ---- allocation ----
+// Blocks are rounded to a size class and, when released, kept in the
+// context's cache with the stream of their last use and an event recorded
+// there.  A request reuses a cached block of its class: at once on the same
+// stream (stream order), after a wait on the event on another stream.  New
+// blocks come from hipMalloc; cached blocks are returned to the device when
+// live + cached bytes would exceed the budget, and at shutdown.
+static size_t size_class(size_t bytes)
+{
+    if (bytes <= 256) return 256;
+    if (bytes <= ((size_t)4 << 20)) {
+        size_t c = 512;
+        while (c < bytes) c <<= 1;
+        return c;
+    }
+    const size_t g = (size_t)2 << 20;
+    return (bytes + g - 1) / g * g;
+}
+
+static void trim_cache_locked(Ctx& c, uint64_t need)
+{
+    // drop cached blocks (largest first) until live + cached + need fits the budget
+    if (c.in_use.load() + c.cached_bytes + need <= c.budget) return;
+    HIP_CHECK(hipDeviceSynchronize());
+    while (!c.cache.empty() && c.in_use.load() + c.cached_bytes + need > c.budget) {
+        auto it = std::prev(c.cache.end());
+        (void)hipEventDestroy(it->second.done);
+        (void)hipFree(it->second.p);
+        c.cached_bytes -= it->second.bytes;
+        c.cache.erase(it);
+    }
+}
+
 void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
 {
     if (bytes == 0) return nullptr;
+    const size_t cls = size_class(bytes);
     uint64_t cur = c.in_use.load();
     while (true) {
-        if (cur + bytes > c.budget)
-            throw nomem_error("memory budget exceeded (" + std::to_string(cur + bytes) + " > " +
+        if (cur + cls > c.budget)
+            throw nomem_error("memory budget exceeded (" + std::to_string(cur + cls) + " > " +
                               std::to_string(c.budget) + " bytes)");
-        if (c.in_use.compare_exchange_weak(cur, cur + bytes)) break;
+        if (c.in_use.compare_exchange_weak(cur, cur + cls)) break;
+    }
+    {
+        std::lock_guard<std::mutex> lk(c.alloc_mu);
+        auto range = c.cache.equal_range(cls);
+        auto pick = c.cache.end();
+        for (auto it = range.first; it != range.second; ++it) {
+            if (it->second.st == st) {
+                pick = it;
+                break;
+            }
+            if (pick == c.cache.end()) pick = it;
+        }
+        if (pick != c.cache.end()) {
+            CachedBlock b = pick->second;
+            c.cache.erase(pick);
+            c.cached_bytes -= b.bytes;
+            if (b.st != st) (void)hipStreamWaitEvent(st, b.done, 0);
+            (void)hipEventDestroy(b.done);
+            return b.p;
+        }
+        trim_cache_locked(c, cls);
     }
     void* p = nullptr;
-    hipError_t e = hipMallocAsync(&p, bytes, st);
+    hipError_t e = hipMalloc(&p, cls);
     if (e != hipSuccess) {
-        c.in_use -= bytes;
+        c.in_use -= cls;
         (void)hipGetLastError();
         if (e == hipErrorOutOfMemory) throw nomem_error("device out of memory");
-        throw hip_error(std::string("hipMallocAsync: ") + hipGetErrorString(e));
+        throw hip_error(std::string("hipMalloc: ") + hipGetErrorString(e));
     }
     return p;
 }
@@ -39,8 +93,52 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
 void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
 {
     if (!p) return;
-    (void)hipFreeAsync(p, st);
-    c.in_use -= bytes;
+    const size_t cls = size_class(bytes);
+    CachedBlock b;
+    b.p = p;
+    b.bytes = cls;
+    b.st = st;
+    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
+        hipEventRecord(b.done, st) != hipSuccess) {
+        (void)hipGetLastError();
+        (void)hipStreamSynchronize(st);
+        (void)hipFree(p);
+        c.in_use -= cls;
+        return;
+    }
+    std::lock_guard<std::mutex> lk(c.alloc_mu);
+    c.cache.emplace(cls, b);
+    c.cached_bytes += cls;
+    c.in_use -= cls;
+}
+
+void release_cache(Ctx& c)
+{
+    std::lock_guard<std::mutex> lk(c.alloc_mu);
+    for (auto& kv : c.cache) {
+        (void)hipEventDestroy(kv.second.done);
+        (void)hipFree(kv.second.p);
+    }
+    c.cache.clear();
+    c.cached_bytes = 0;
+}
+
+SideStream::SideStream(Ctx& ctx) : c(ctx)
+{
+    std::lock_guard<std::mutex> lk(c.pool_mu);
+    if (!c.side_pool.empty()) {
+        s = c.side_pool.back();
+        c.side_pool.pop_back();
+    } else {
+        HIP_CHECK(hipStreamCreateWithFlags(&s, hipStreamNonBlocking));
+        c.side_all.push_back(s);
+    }
+}
+
+SideStream::~SideStream()
+{
+    std::lock_guard<std::mutex> lk(c.pool_mu);
+    c.side_pool.push_back(s);
 }
 
 // ---- small read-backs through a pinned buffer ----
@@ -169,7 +267,8 @@ void release_obj(rt_ctx ctx, Obj& o)
     hipStream_t fs = ctx->free_stream;
     if (o.scene) {
         Scene& s = *o.scene;
-        for (Scratch* p : {&s.tri4, &s.nodes, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane, &s.s_box})
+        for (Scratch* p : {&s.tri4, &s.nodes, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane, &s.s_box,
+                           &s.t_proj, &s.t_axes})
             retarget(*p, fs);
     }
     if (o.ris) retarget(o.ris->elem, fs);
@@ -209,10 +308,6 @@ rt_status rt_init(int device, uint64_t mem_budget_bytes, rt_ctx* out)
         size_t fr = 0, tot = 0;
         HIP_CHECK(hipMemGetInfo(&fr, &tot));
         ctx->c.budget = mem_budget_bytes ? mem_budget_bytes : (uint64_t)(0.9 * (double)fr);
-        hipMemPool_t pool;
-        HIP_CHECK(hipDeviceGetDefaultMemPool(&pool, device));
-        uint64_t thr = UINT64_MAX;
-        HIP_CHECK(hipMemPoolSetAttribute(pool, hipMemPoolAttrReleaseThreshold, &thr));
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->free_stream, hipStreamNonBlocking));
         *out = ctx;
         g_err.clear();
@@ -231,6 +326,8 @@ rt_status rt_shutdown(rt_ctx ctx)
         ctx->objs.clear();
         HIP_CHECK(hipStreamSynchronize(ctx->free_stream));
         HIP_CHECK(hipStreamDestroy(ctx->free_stream));
+        for (hipStream_t s : ctx->c.side_all) (void)hipStreamDestroy(s);
+        release_cache(ctx->c);
         return RT_OK;
     });
     delete ctx;

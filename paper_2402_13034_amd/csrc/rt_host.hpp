@@ -6,6 +6,7 @@
 #include <stdint.h>
 
 #include <atomic>
+#include <map>
 #include <mutex>
 #include <stdexcept>
 #include <string>
@@ -22,16 +23,43 @@ struct inval_error : std::runtime_error {
     explicit inval_error(const std::string& s) : std::runtime_error(s) {}
 };
 
+// A device block held by the context's cache after its last stream-ordered use.
+struct CachedBlock {
+    void* p = nullptr;
+    size_t bytes = 0;
+    hipStream_t st = nullptr;   // stream of the last use
+    hipEvent_t done = nullptr;  // recorded on `st` when the block was released
+};
+
 struct Ctx {
     int device = 0;
     uint64_t budget = 0;
-    std::atomic<uint64_t> in_use{0};
+    std::atomic<uint64_t> in_use{0};   // bytes of live allocations (charged to the budget)
     std::mutex mu;
+    // caching allocator: size class -> released blocks
+    std::mutex alloc_mu;
+    std::multimap<size_t, CachedBlock> cache;
+    uint64_t cached_bytes = 0;
+    // side streams lent to calls that fork work (default priority, non-blocking)
+    std::mutex pool_mu;
+    std::vector<hipStream_t> side_pool;
+    std::vector<hipStream_t> side_all;
+};
+
+// Borrow a side stream of the context for the lifetime of the object.
+struct SideStream {
+    Ctx& c;
+    hipStream_t s = nullptr;
+    explicit SideStream(Ctx& ctx);
+    ~SideStream();
+    SideStream(const SideStream&) = delete;
+    SideStream& operator=(const SideStream&) = delete;
 };
 
 // Stream-ordered device allocation charged to the context's budget.
 void* dalloc(Ctx& c, size_t bytes, hipStream_t st);
 void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st);
+void release_cache(Ctx& c);
 
 // RAII scratch buffer on a stream.
 struct Scratch {
@@ -64,7 +92,7 @@ struct Scene {
     int64_t n_tri = 0, n_surf = 0;
     int32_t root = 0;
     int32_t max_depth = 0;
-    Scratch tri4, nodes, v64, refl, surf, s_ptr, s_tris, s_plane, s_box;
+    Scratch tri4, nodes, node4, v64, refl, surf, s_ptr, s_tris, s_plane, s_box, t_proj, t_axes;
     SceneView view() const {
         SceneView v;
         v.n_tri = (int32_t)n_tri;
@@ -73,6 +101,7 @@ struct Scene {
         v.pad = 0;
         v.tri4 = tri4.as<float4>();
         v.nodes = nodes.as<float4>();
+        v.node4 = node4.as<float4>();
         v.v64 = v64.as<double>();
         v.refl = refl.as<float2>();
         v.surf = surf.as<int32_t>();
@@ -80,6 +109,8 @@ struct Scene {
         v.s_tris = s_tris.as<int32_t>();
         v.s_plane = s_plane.as<double>();
         v.s_box = s_box.as<double>();
+        v.t_proj = t_proj.as<double>();
+        v.t_axes = t_axes.as<int32_t>();
         return v;
     }
 };

@@ -43,6 +43,7 @@ struct SceneView {
     int32_t pad;
     const float4* tri4;    // 3 per leaf slot: (v0, id), (e1, surf), (e2, 0)
     const float4* nodes;   // 4 per internal node: (loL, cL), (hiL, cR), (loR, -), (hiR, -)
+    const float4* node4;   // 8 per internal node of even depth (4-wide collapse), see RT_NODE4
     const double* v64;     // 9 per triangle (original order)
     const float2* refl;    // per triangle
     const int32_t* surf;   // per triangle
@@ -50,6 +51,8 @@ struct SceneView {
     const int32_t* s_tris; // triangles grouped by surface, ascending
     const double* s_plane; // 4 per surface: n (not unit), c = n . v0 of its first triangle
     const double* s_box;   // 6 per surface: lo, hi (inflated by 1e-9 m)
+    const double* t_proj;  // 6 per triangle: a, b, c projected (counter-clockwise), see contains_proj
+    const int32_t* t_axes; // per triangle: i0 | i1 << 2, 16 if degenerate
 };
 
 struct Antenna {
@@ -315,6 +318,170 @@ __device__ bool leg_blocked(const SceneView& s, const double* A, const double* B
 }
 
 // --------------------------------------------------------------------------
+// Wave-coherent any hit.  The lanes of one wave walk the BVH together: a
+// child is entered when its box test succeeds for any lane still searching;
+// node index and stack are wave-uniform (one LDS stack per wave).  Each lane
+// tests its own ray against every leaf reached, so its answer is exactly the
+// per-lane any-hit answer (which does not depend on the nodes visited).
+// Call from wave-uniform control flow; `searching` masks lanes out.
+// --------------------------------------------------------------------------
+template <bool CNT>
+__device__ bool any_hit_wave(const SceneView& s, bool searching, float ox, float oy, float oz, float dx, float dy,
+                             float dz, float tmin, float tmax, int skip_a, int skip_b, int* wstack,
+                             WorkCount* wc)
+{
+    bool hit = false;
+    if (s.n_tri == 0 || __ballot(searching) == 0ull) return false;
+    RayBox rb = make_raybox(ox, oy, oz, dx, dy, dz);
+    int sp = 0;
+    int node = s.root;
+    while (true) {
+        if (node >= 0) {
+            const float4* nd = s.nodes + 4 * node;
+            float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
+            float tl, tr;
+            bool hl = searching && slab(rb, n0, n1, tmin, tmax, tl);
+            bool hr = searching && slab(rb, n2, n3, tmin, tmax, tr);
+            const unsigned long long bl = __ballot(hl), br = __ballot(hr);
+            const int cl = __builtin_amdgcn_readfirstlane(__float_as_int(n0.w));
+            const int cr = __builtin_amdgcn_readfirstlane(__float_as_int(n1.w));
+            if (CNT) {
+                if (hl && cl >= 0) wc->nodes++;
+                if (hr && cr >= 0) wc->nodes++;
+            }
+            if (bl && br) {
+                wstack[sp] = cr;
+                ++sp;
+                node = cl;
+                continue;
+            } else if (bl) {
+                node = cl;
+                continue;
+            } else if (br) {
+                node = cr;
+                continue;
+            }
+        } else {
+            const int i = ~node;
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            const int sf = __float_as_int(b.w);
+            if (sf != skip_a && sf != skip_b && searching) {
+                float t;
+                if (CNT) wc->tris++;
+                if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) {
+                    hit = true;
+                    searching = false;
+                }
+            }
+            if (__ballot(searching) == 0ull) break;
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+    }
+    return hit;
+}
+
+// 4-wide collapse of the binary tree, used by the wave-coherent walk: the
+// node of every internal node n of even depth lists the grandchildren of n
+// (or a child itself where that child is a leaf), with the boxes the binary
+// nodes hold, so the boxes and the conservativeness of the test are the same.
+// Layout per node (8 float4): lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
+// entries, the four references (>= 0 node, < 0 ~leaf slot, RT_NODE4_EMPTY
+// unused), and a zero pad.  Node indices are those of the binary tree.  An
+// unused entry has a zero box and is masked out by its reference.
+#define RT_NODE4_EMPTY 0x7fffffff
+#define RT_STACK4 (3 * (RT_STACK / 2) + 4)
+
+__device__ __forceinline__ bool slab1(float lx, float hx, float ly, float hy, float lz, float hz, const RayBox& r,
+                                      float tmin, float tmax)
+{
+    float t0x = __builtin_fmaf(lx, r.ix, -r.oix), t1x = __builtin_fmaf(hx, r.ix, -r.oix);
+    float t0y = __builtin_fmaf(ly, r.iy, -r.oiy), t1y = __builtin_fmaf(hy, r.iy, -r.oiy);
+    float t0z = __builtin_fmaf(lz, r.iz, -r.oiz), t1z = __builtin_fmaf(hz, r.iz, -r.oiz);
+    float a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    return a <= b;
+}
+
+// any_hit_wave over the 4-wide nodes (same answer per lane).  `wstack` holds
+// RT_STACK4 entries for the wave.
+__device__ bool any_hit_wave4(const SceneView& s, bool searching, float ox, float oy, float oz, float dx, float dy,
+                              float dz, float tmin, float tmax, int skip_a, int skip_b, int* wstack)
+{
+    bool hit = false;
+    if (s.n_tri == 0 || __ballot(searching) == 0ull) return false;
+    const RayBox rb = make_raybox(ox, oy, oz, dx, dy, dz);
+    int sp = 0;
+    int node = s.root;
+    while (true) {
+        if (node >= 0) {
+            const float4* q = s.node4 + 8 * node;
+            const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5], cf = q[6];
+            const int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y);
+            const int c2 = __float_as_int(cf.z), c3 = __float_as_int(cf.w);
+            const unsigned long long m0 = __ballot(slab1(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, rb, tmin, tmax) & searching);
+            const unsigned long long m1 = __ballot(slab1(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, rb, tmin, tmax) & searching);
+            // unused entries (only the last two can be unused) are masked after the ballot, without a branch
+            const unsigned long long m2 = __ballot(slab1(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, rb, tmin, tmax) & searching) &
+                                          (c2 == RT_NODE4_EMPTY ? 0ull : ~0ull);
+            const unsigned long long m3 = __ballot(slab1(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, rb, tmin, tmax) & searching) &
+                                          (c3 == RT_NODE4_EMPTY ? 0ull : ~0ull);
+            // visit the first entry hit, push the others (last pushed = next visited)
+            int next = RT_NODE4_EMPTY;
+            if (m3) next = c3;
+            if (m2) {
+                if (next != RT_NODE4_EMPTY) wstack[sp++] = next;
+                next = c2;
+            }
+            if (m1) {
+                if (next != RT_NODE4_EMPTY) wstack[sp++] = next;
+                next = c1;
+            }
+            if (m0) {
+                if (next != RT_NODE4_EMPTY) wstack[sp++] = next;
+                next = c0;
+            }
+            if (next != RT_NODE4_EMPTY) {
+                node = next;
+                continue;
+            }
+        } else {
+            const int i = ~node;
+            float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            const int sf = __float_as_int(b.w);
+            if (sf != skip_a && sf != skip_b && searching) {
+                float t;
+                if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) {
+                    hit = true;
+                    searching = false;
+                }
+            }
+            if (__ballot(searching) == 0ull) break;
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+    }
+    return hit;
+}
+
+// Leg test of leg_blocked for a whole wave (`need` masks lanes out).
+template <bool CNT>
+__device__ bool leg_blocked_wave(const SceneView& s, bool need, const double* A, const double* B, int sa, int sb,
+                                 int* wstack, WorkCount* wc)
+{
+#pragma clang fp contract(off)
+    double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
+    double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+    float tmin = (float)RT_EPS;
+    float tmax = (float)(L - RT_EPS);
+    bool searching = need && (tmax > tmin);
+    return any_hit_wave<CNT>(s, searching, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
+                             (float)(w2 / L), tmin, tmax, sa, sb, wstack, wc);
+}
+
+// --------------------------------------------------------------------------
 // FP64 image method
 // --------------------------------------------------------------------------
 __device__ __forceinline__ double edge_raw(double sx, double sy, double ex, double ey, double px,
@@ -339,9 +506,12 @@ __device__ __forceinline__ bool top_left(double sx, double sy, double ex, double
     return (dy < 0.0) || (dy == 0.0 && dx < 0.0);
 }
 
-// p on the triangle's plane inside triangle t (half-open top-left rule in
-// the projection that drops the axis of largest |normal|)?
-__device__ inline bool contains64(const double* v, const double* p)
+// Projection used by the containment test, computed once per triangle (same
+// FP64 operations as a test that derives it on the fly): drop the axis of
+// largest |normal| (lowest axis on ties), keep the other two in cyclic order,
+// make the projected triangle counter-clockwise.  Writes 6 coordinates and
+// the axes (16 if the projected area is 0: such a triangle contains nothing).
+__device__ inline void triangle_projection(const double* v, double* out, int32_t* axes)
 {
 #pragma clang fp contract(off)
     double e1[3], e2[3];
@@ -360,14 +530,28 @@ __device__ inline bool contains64(const double* v, const double* p)
     double a0 = v[i0], a1 = v[i1];
     double b0 = v[3 + i0], b1 = v[3 + i1];
     double c0 = v[6 + i0], c1 = v[6 + i1];
-    double q0 = p[i0], q1 = p[i1];
     double area = edge2(a0, a1, b0, b1, c0, c1);
-    if (area == 0.0) return false;
     if (area < 0.0) {
         double t0 = b0, t1 = b1;
         b0 = c0; b1 = c1;
         c0 = t0; c1 = t1;
     }
+    out[0] = a0; out[1] = a1; out[2] = b0; out[3] = b1; out[4] = c0; out[5] = c1;
+    *axes = (area == 0.0) ? 16 : (i0 | (i1 << 2));
+}
+
+// p on the triangle's plane inside triangle t?  Half-open top-left rule in
+// the triangle's projection: a point on an edge belongs to the triangle only
+// if that edge is top-left, so a point on an edge shared by two coplanar
+// triangles belongs to exactly one of them.
+__device__ inline bool contains_proj(const SceneView& s, int t, const double* p)
+{
+#pragma clang fp contract(off)
+    const int ax = s.t_axes[t];
+    if (ax & 16) return false;
+    const double* q6 = s.t_proj + 6 * t;
+    const double a0 = q6[0], a1 = q6[1], b0 = q6[2], b1 = q6[3], c0 = q6[4], c1 = q6[5];
+    const double q0 = p[ax & 3], q1 = p[(ax >> 2) & 3];
     double w0 = edge2(b0, b1, c0, c1, q0, q1);
     double w1 = edge2(c0, c1, a0, a1, q0, q1);
     double w2 = edge2(a0, a1, b0, b1, q0, q1);
@@ -393,7 +577,7 @@ __device__ inline int surface_contains(const SceneView& s, int sf, const double*
     for (int j = s.s_ptr[sf]; j < s.s_ptr[sf + 1]; ++j) {
         int t = s.s_tris[j];
         if (CNT) wc->contain++;
-        if (contains64(s.v64 + 9 * t, p)) return t;
+        if (contains_proj(s, t, p)) return t;
     }
     return -1;
 }
@@ -410,13 +594,16 @@ __device__ __forceinline__ void mirror(const double* pl, const double* p, double
 }
 
 // Back-trace from X through images I[1..k] (I[0] = source S) over surfaces
-// seq; on success fills P[0..k) and tri[0..k).
+// seq; on success fills P[0..k) and tri[0..k).  The loops run over the
+// compile-time bound with constant indices so the arrays stay in registers.
 __device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k, const double (*I)[3],
                                        const double* X, double (*P)[3], int* tri)
 {
 #pragma clang fp contract(off)
     double Q[3] = {X[0], X[1], X[2]};
-    for (int i = k; i >= 1; --i) {
+#pragma unroll
+    for (int i = RT_MAX_K; i >= 1; --i) {
+        if (i > k) continue;
         const double* pl = s.s_plane + 4 * seq[i - 1];
         double w0 = Q[0] - I[i][0], w1 = Q[1] - I[i][1], w2 = Q[2] - I[i][2];
         double den = pl[0] * w0 + pl[1] * w1 + pl[2] * w2;
@@ -430,10 +617,15 @@ __device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k
         P[i - 1][0] = p[0]; P[i - 1][1] = p[1]; P[i - 1][2] = p[2];
         Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
     }
-    for (int i = 0; i < k; ++i) {
+#pragma unroll
+    for (int i = 0; i < RT_MAX_K; ++i) {
+        if (i >= k) break;
         const double* pl = s.s_plane + 4 * seq[i];
-        const double* prev = (i == 0) ? I[0] : P[i - 1];
-        const double* next = (i == k - 1) ? X : P[i + 1];
+        double prev[3], next[3];
+        for (int q = 0; q < 3; ++q) {
+            prev[q] = i == 0 ? I[0][q] : P[i > 0 ? i - 1 : 0][q];
+            next[q] = (i == k - 1 || i + 1 >= RT_MAX_K) ? X[q] : P[i + 1 < RT_MAX_K ? i + 1 : 0][q];
+        }
         double a = plane_side(pl, prev);
         double b = plane_side(pl, next);
         if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return false;

@@ -39,6 +39,39 @@ __device__ __forceinline__ void wave_count_add(unsigned long long* ctr, unsigned
     if ((threadIdx.x & 63) == 0 && s) atomicAdd(ctr, s);
 }
 
+// Block-staged append: a block gathers its values in LDS (LDS atomics) and
+// reserves room for all of them with one global atomic; values past `cap`
+// are dropped while the counter keeps counting (the host checks it).  The
+// order of the appended values is not fixed: callers sort them.
+template <int NMAX>
+struct BlockAppend {
+    uint64_t* vals;   // LDS, NMAX entries
+    int* n;           // LDS counter
+    unsigned long long* base;   // LDS
+    __device__ void init()
+    {
+        if (threadIdx.x == 0) *n = 0;
+        __syncthreads();
+    }
+    __device__ void push(uint64_t v)
+    {
+        int slot = atomicAdd(n, 1);
+        if (slot < NMAX) vals[slot] = v;
+    }
+    // every thread of the block must call flush
+    __device__ void flush(uint64_t* out, int64_t cap, unsigned long long* counter)
+    {
+        __syncthreads();
+        const int cnt = *n < NMAX ? *n : NMAX;
+        if (threadIdx.x == 0) *base = cnt > 0 ? atomicAdd(counter, (unsigned long long)cnt) : 0ull;
+        __syncthreads();
+        for (int t = threadIdx.x; t < cnt; t += blockDim.x) {
+            const unsigned long long idx = *base + (unsigned long long)t;
+            if (idx < (unsigned long long)cap) out[idx] = vals[t];
+        }
+    }
+};
+
 // --------------------------------------------------------------------------
 // 1. discovery
 // --------------------------------------------------------------------------
@@ -56,61 +89,143 @@ __device__ __forceinline__ void fib_dir(int64_t i, int64_t n, double* out)
 
 constexpr int DISC_B = 128;
 
-template <bool BRUTE, int STK>
-__global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, double sy, double sz, int hemi,
-                                                     double hx, double hy, double hz, int64_t rows, int K,
-                                                     int32_t* hits, unsigned long long* segs)
+__device__ __forceinline__ uint32_t spread12(uint32_t v)
 {
+    v &= 0xfffu;
+    v = (v | (v << 8)) & 0x00ff00ffu;
+    v = (v | (v << 4)) & 0x0f0f0f0fu;
+    v = (v | (v << 2)) & 0x33333333u;
+    v = (v | (v << 1)) & 0x55555555u;
+    return v;
+}
+
+// Rays to launch, keyed by direction so that a wave traces neighbouring
+// directions: key = Morton code of the octahedral map of d (12 + 12 bits)
+// << 32 | row.  Rows outside the half-space (hemi != 0) are not listed.
+constexpr int RL_B = 256, RL_PT = 4;
+__global__ __launch_bounds__(RL_B) void k_ray_list(int64_t rows, int hemi, double hx, double hy, double hz,
+                                                   uint64_t* out, int64_t cap, unsigned long long* counter)
+{
+    __shared__ uint64_t vals[RL_B * RL_PT];
+    __shared__ int n;
+    __shared__ unsigned long long base;
+    BlockAppend<RL_B * RL_PT> app{vals, &n, &base};
+    app.init();
+    for (int j = 0; j < RL_PT; ++j) {
+        int64_t i = ((int64_t)blockIdx.x * RL_PT + j) * RL_B + threadIdx.x;
+        if (i >= rows) continue;
+        double d[3];
+        fib_dir(i, rows, d);
+        bool go = hemi ? (d[0] * hx + d[1] * hy + d[2] * hz) > 0.0 : true;
+        if (!go) continue;
+        float ax = fabsf((float)d[0]), ay = fabsf((float)d[1]), az = fabsf((float)d[2]);
+        float sum = ax + ay + az;
+        float u = (float)d[0] / sum, v = (float)d[1] / sum;
+        if (d[2] < 0.0) {
+            float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
+            float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
+            u = uu;
+            v = vv;
+        }
+        uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 4096.0f, 0.0f), 4095.0f);
+        uint32_t qv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 4096.0f, 0.0f), 4095.0f);
+        app.push(((uint64_t)(spread12(qu) | (spread12(qv) << 1)) << 32) | (uint64_t)i);
+    }
+    app.flush(out, cap, counter);
+}
+
+// Rows not launched keep -1 hit lists.
+__global__ void k_fill_neg(int32_t* p, int64_t n)
+{
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = -1;
+}
+
+// De-duplication of prefix keys in an open-addressing hash set (keys != 0,
+// capacity a power of two, linear probing).  A slot is read before the
+// compare-and-swap, so the many repeats of a key cost no atomics.
+__device__ __forceinline__ uint64_t mix64(uint64_t x)
+{
+    x ^= x >> 33;
+    x *= 0xff51afd7ed558ccdull;
+    x ^= x >> 33;
+    x *= 0xc4ceb9fe1a85ec53ull;
+    x ^= x >> 33;
+    return x;
+}
+
+__device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t mask, uint64_t key, int* overflow)
+{
+    uint64_t h = mix64(key) & mask;
+    for (uint64_t probe = 0; probe <= mask; ++probe) {
+        // a plain read may be stale only as 0 (a slot changes once, 0 -> key); the CAS decides then
+        unsigned long long cur = table[h];
+        if (cur == key) return;
+        if (cur == 0ull) {
+            unsigned long long prev = atomicCAS(&table[h], 0ull, (unsigned long long)key);
+            if (prev == 0ull || prev == key) return;
+        }
+        h = (h + 1) & mask;
+    }
+    atomicOr(overflow, 1);
+}
+
+// Discovery over the direction-sorted ray list; every prefix of every hit
+// list (as surface ids) goes into the hash set.  Neighbouring lanes trace
+// neighbouring directions, so a lane skips a key equal to its left
+// neighbour's (one of them inserts it).
+template <bool BRUTE, int STK>
+__global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, double sy, double sz,
+                                                     const uint64_t* list, int64_t n_list, int64_t rows, int K,
+                                                     int32_t* hits, unsigned long long* segs,
+                                                     unsigned long long* table, uint64_t mask, int* overflow)
+{
+    static_assert(RT_MAX_K == 3, "three key registers");
     __shared__ int stack[STK * DISC_B];
-    int64_t i = (int64_t)blockIdx.x * DISC_B + threadIdx.x;
+    int64_t t = (int64_t)blockIdx.x * DISC_B + threadIdx.x;
     unsigned nseg = 0;
-    if (i < rows) {
+    uint64_t keys[RT_MAX_K] = {0, 0, 0};
+    if (t < n_list) {
+        const int64_t i = (int64_t)(list[t] & 0xffffffffull);
         double d64[3];
         fib_dir(i, rows, d64);
-        for (int b = 0; b < K; ++b) hits[i * K + b] = -1;
-        bool go = true;
-        if (hemi) go = (d64[0] * hx + d64[1] * hy + d64[2] * hz) > 0.0;
-        if (go) {
-            float ox = (float)sx, oy = (float)sy, oz = (float)sz;
-            float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
-            int skip = -1;
-            for (int b = 0; b < K; ++b) {
-                float t;
-                int id;
-                ++nseg;
-                int slot = closest_hit<BRUTE>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip,
-                                              stack + threadIdx.x, DISC_B, t, id);
-                if (slot < 0) break;
-                hits[i * K + b] = id;
-                float px = ox + t * dx, py = oy + t * dy, pz = oz + t * dz;
-                reflect32(s.tri4[3 * slot + 1], s.tri4[3 * slot + 2], dx, dy, dz);
-                ox = px;
-                oy = py;
-                oz = pz;
-                skip = id;
-            }
+        float ox = (float)sx, oy = (float)sy, oz = (float)sz;
+        float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
+        int skip = -1;
+        uint64_t acc = 0;
+        for (int b = 0; b < K; ++b) {
+            float tt;
+            int id;
+            ++nseg;
+            int slot = closest_hit<BRUTE>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, stack + threadIdx.x,
+                                          DISC_B, tt, id);
+            if (slot < 0) break;
+            if (hits) hits[i * K + b] = id;
+            acc |= (uint64_t)(__float_as_int(s.tri4[3 * slot + 1].w) + 1) << (RT_KEY_BITS * b);
+            // constant indices only, so the keys stay in registers
+            keys[0] = b == 0 ? acc : keys[0];
+            keys[1] = b == 1 ? acc : keys[1];
+            keys[2] = b == 2 ? acc : keys[2];
+            float px = ox + tt * dx, py = oy + tt * dy, pz = oz + tt * dz;
+            reflect32(s.tri4[3 * slot + 1], s.tri4[3 * slot + 2], dx, dy, dz);
+            ox = px;
+            oy = py;
+            oz = pz;
+            skip = id;
         }
+    }
+#pragma unroll
+    for (int b = 0; b < RT_MAX_K; ++b) {
+        const uint64_t left = __shfl_up(keys[b], 1, 64);
+        const bool first = (threadIdx.x & 63) == 0 || left != keys[b];
+        if (b < K && keys[b] != 0ull && first) hash_insert(table, mask, keys[b], overflow);
     }
     wave_count_add(segs, nseg);
 }
 
 // --------------------------------------------------------------------------
-// 2. keys of every prefix (surface ids + 1, 21 bits each); 0 = none
+// 2. candidate keys: surface ids + 1, 21 bits per bounce; 0 = none
 // --------------------------------------------------------------------------
-__global__ void k_prefix_keys(const int32_t* hits, const int32_t* surf, int64_t rows, int K, uint64_t* keys)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= rows) return;
-    uint64_t acc = 0;
-    bool alive = true;
-    for (int b = 0; b < K; ++b) {
-        int32_t h = hits[i * K + b];
-        alive = alive && h >= 0;
-        if (alive) acc |= (uint64_t)(surf[h] + 1) << (RT_KEY_BITS * b);
-        keys[i * K + b] = alive ? acc : 0ull;
-    }
-}
-
 // every sequence of <= K surfaces without immediate repeat, as keys (0 for skipped)
 __global__ void k_exhaustive_keys(int64_t n_surf, int K, int64_t total, uint64_t* keys)
 {
@@ -197,38 +312,55 @@ __device__ __forceinline__ bool geo_path(const SceneView& s, const CandView& cv,
     return image_backtrace(s, seq, k, I, X, P, tri);
 }
 
-// Append `value` of every lane with ok to out[0..cap) (one atomic per wave);
-// the counter keeps counting past cap so the host can detect the overflow.
-__device__ __forceinline__ void wave_append(bool ok, uint64_t value, uint64_t* out, int64_t cap,
-                                            unsigned long long* counter)
+
+
+// occupied slots of the hash set, appended per wave (order is fixed by the sort that follows)
+constexpr int TC_B = 256, TC_PT = 8;
+__global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long* table, int64_t cap, uint64_t* out,
+                                                        int64_t out_cap, unsigned long long* counter)
 {
-    const int lane = threadIdx.x & 63;
-    unsigned long long mask = __ballot(ok);
-    if (mask == 0ull) return;
-    const int leader = __ffsll((long long)mask) - 1;
-    unsigned long long base = 0;
-    if (lane == leader) base = atomicAdd(counter, (unsigned long long)__popcll(mask));
-    base = __shfl(base, leader, 64);
-    const unsigned long long idx = base + (unsigned long long)__popcll(mask & ((1ull << lane) - 1ull));
-    if (ok && idx < (unsigned long long)cap) out[idx] = value;
+    __shared__ uint64_t vals[TC_B * TC_PT];
+    __shared__ int n;
+    __shared__ unsigned long long base;
+    BlockAppend<TC_B * TC_PT> app{vals, &n, &base};
+    app.init();
+    for (int j = 0; j < TC_PT; ++j) {
+        int64_t i = ((int64_t)blockIdx.x * TC_PT + j) * TC_B + threadIdx.x;
+        if (i < cap && table[i] != 0ull) app.push((uint64_t)table[i]);
+    }
+    app.flush(out, out_cap, counter);
 }
 
-__global__ __launch_bounds__(256) void k_geo_cells(SceneView s, CandView cv, double sx, double sy, double sz,
-                                                   const double* rx, int64_t R, uint64_t* cells, int64_t cap,
-                                                   unsigned long long* counter)
+// One wave takes GEO_CPW candidates for 64 consecutive receivers, so the
+// candidate's surfaces, planes and triangles are wave-uniform (scalar loads,
+// no divergence in the loops over a surface's triangles).
+// grid: x = group of 4 x GEO_CPW candidates, y = block of 64 receivers
+constexpr int GEO_B = 256, GEO_CPW = 8;
+__global__ __launch_bounds__(GEO_B) void k_geo_cells(SceneView s, CandView cv, double sx, double sy, double sz,
+                                                     const double* rx, int64_t R, uint64_t* cells, int64_t cap,
+                                                     unsigned long long* counter)
 {
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    bool ok = false;
-    if (i < R * cv.n) {
-        int64_t r = i / cv.n, c = i - r * cv.n;
-        double S[3] = {sx, sy, sz};
-        double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
-        double P[RT_MAX_K][3];
-        int tri[RT_MAX_K];
-        int k;
-        ok = geo_path(s, cv, c, S, X, P, tri, k);
+    __shared__ uint64_t vals[GEO_B * GEO_CPW];
+    __shared__ int n;
+    __shared__ unsigned long long base;
+    BlockAppend<GEO_B * GEO_CPW> app{vals, &n, &base};
+    app.init();
+    const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+    const int64_t r = (int64_t)blockIdx.y * 64 + (threadIdx.x & 63);
+    if (r < R) {
+        const double S[3] = {sx, sy, sz};
+        const double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
+        const int64_t c0 = ((int64_t)blockIdx.x * (GEO_B / 64) + wib) * GEO_CPW;
+        for (int j = 0; j < GEO_CPW; ++j) {
+            const int64_t c = c0 + j;
+            if (c >= cv.n) break;
+            double P[RT_MAX_K][3];
+            int tri[RT_MAX_K];
+            int k;
+            if (geo_path(s, cv, c, S, X, P, tri, k)) app.push((uint64_t)(r * cv.n + c));
+        }
     }
-    wave_append(ok, (uint64_t)i, cells, cap, counter);
+    app.flush(cells, cap, counter);
 }
 
 // --------------------------------------------------------------------------
@@ -266,25 +398,37 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
         int k;
         bool ok = geo_path(s, cv, c, S, X, P, tri, k);
         float Ft = 1.0f, Fr = 1.0f;
+        // path points by value, constant indices only: V[0] = S, V[1..k] = P, V[k+1] = X
+        static_assert(RT_MAX_K == 3, "selections below list every order");
+        double V[RT_MAX_K + 2][3];
+        for (int q = 0; q < 3; ++q) {
+            V[0][q] = S[q];
+            V[1][q] = k >= 1 ? P[0][q] : X[q];
+            V[2][q] = k >= 2 ? P[1][q] : X[q];
+            V[3][q] = k >= 3 ? P[2][q] : X[q];
+            V[4][q] = X[q];
+        }
         if (FIELD && ok) {
             double v1[3], vl[3];
-            const double* f = k ? P[0] : X;
-            const double* l = k ? P[k - 1] : S;
             for (int q = 0; q < 3; ++q) {
-                v1[q] = f[q] - S[q];
-                vl[q] = l[q] - X[q];
+                v1[q] = V[1][q] - S[q];
+                const double lq = k == 0 ? S[q] : k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
+                vl[q] = lq - X[q];
             }
             Ft = pattern_f(tc.txa.pattern, (float)tc.txa.param, cos_between(v1, tc.txa.axis));
             Fr = pattern_f(tc.rxa.pattern, (float)tc.rxa.param, cos_between(vl, tc.rxa.axis));
             ok = Ft > 0.0f && Fr > 0.0f;
         }
-        for (int j = 0; j <= k && ok; ++j) {
-            const double* A = j == 0 ? S : P[j - 1];
-            const double* B = j == k ? X : P[j];
-            int sa = j == 0 ? -1 : cv.seq[3 * c + j - 1];
-            int sb = j == k ? -1 : cv.seq[3 * c + j];
+        int sq[RT_MAX_K];
+        for (int j = 0; j < RT_MAX_K; ++j) sq[j] = cv.seq[3 * c + j];
+#pragma unroll
+        for (int j = 0; j <= RT_MAX_K; ++j) {
+            if (j > k || !ok) break;
+            // leg j runs from V[j] to V[j + 1] (V[j + 1] = X when j = k)
+            const int sa = j == 0 ? -1 : sq[j > 0 ? j - 1 : 0];
+            const int sb = j == k ? -1 : sq[j < RT_MAX_K ? j : 0];
             ++nseg;
-            if (leg_blocked<BRUTE>(s, A, B, sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
+            if (leg_blocked<BRUTE>(s, V[j], V[j + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
         }
         valid[i] = ok ? 1 : 0;
         PathRec pr;
@@ -295,11 +439,15 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
         recs[i] = pr;
         if (FIELD) {
             double D = 0.0;
-            for (int j = 0; j <= k; ++j) D += seg_len(j == 0 ? S : P[j - 1], j == k ? X : P[j]);
+#pragma unroll
+            for (int j = 0; j <= RT_MAX_K; ++j)
+                if (j <= k) D += seg_len(V[j], V[j + 1]);
             float2 a = make_float2(0.0f, 0.0f);
             if (ok) {
                 float ar = 1.0f, ai = 0.0f;
-                for (int j = 0; j < k; ++j) {
+#pragma unroll
+                for (int j = 0; j < RT_MAX_K; ++j) {
+                    if (j >= k) break;
                     float2 Rc = s.refl[tri[j]];
                     float nr = ar * Rc.x - ai * Rc.y;
                     float ni = ar * Rc.y + ai * Rc.x;
@@ -392,13 +540,13 @@ __global__ void k_u_compact(const PathRec* recs, CandView cv, const uint8_t* f2,
     useq[8 * o + 7] = 0;
 }
 
-__global__ void k_uptr(const int64_t* rstart, int64_t n_rec, const int64_t* off2, int64_t total2, int64_t R,
-                       int64_t* uptr)
+__global__ void k_uptr_dev(const int64_t* rstart, int64_t n_rec, const int64_t* off2, const int64_t* total2,
+                           int64_t R, int64_t* uptr)
 {
     int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r > R) return;
     int64_t a = rstart[r];
-    uptr[r] = (r < R && a < n_rec) ? off2[a] : total2;
+    uptr[r] = (r < R && a < n_rec) ? off2[a] : *total2;
 }
 
 // --------------------------------------------------------------------------
@@ -452,7 +600,9 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 {
 #pragma clang fp contract(off)
     double Q[3] = {X[0], X[1], X[2]};
-    for (int i = k; i >= 1; --i) {
+#pragma unroll
+    for (int i = RT_MAX_K; i >= 1; --i) {
+        if (i > k) continue;
         const double* pl = s.s_plane + 4 * seq[i - 1];
         double w0 = Q[0] - I[i][0], w1 = Q[1] - I[i][1], w2 = Q[2] - I[i][2];
         double den = pl[0] * w0 + pl[1] * w1 + pl[2] * w2;
@@ -462,16 +612,21 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
         double p[3] = {I[i][0] + sp * w0, I[i][1] + sp * w1, I[i][2] + sp * w2};
         int h = hint[i - 1];
         if (CNT && h >= 0) wc->contain++;
-        int t = (h >= 0 && contains64(s.v64 + 9 * h, p)) ? h : surface_contains<CNT>(s, seq[i - 1], p, wc);
+        int t = (h >= 0 && contains_proj(s, h, p)) ? h : surface_contains<CNT>(s, seq[i - 1], p, wc);
         if (t < 0) return false;
         tri[i - 1] = t;
         P[i - 1][0] = p[0]; P[i - 1][1] = p[1]; P[i - 1][2] = p[2];
         Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
     }
-    for (int i = 0; i < k; ++i) {
+#pragma unroll
+    for (int i = 0; i < RT_MAX_K; ++i) {
+        if (i >= k) break;
         const double* pl = s.s_plane + 4 * seq[i];
-        const double* prev = (i == 0) ? I[0] : P[i - 1];
-        const double* next = (i == k - 1) ? X : P[i + 1];
+        double prev[3], next[3];
+        for (int q = 0; q < 3; ++q) {
+            prev[q] = i == 0 ? I[0][q] : P[i > 0 ? i - 1 : 0][q];
+            next[q] = (i == k - 1 || i + 1 >= RT_MAX_K) ? X[q] : P[i + 1 < RT_MAX_K ? i + 1 : 0][q];
+        }
         double a = plane_side(pl, prev);
         double b = plane_side(pl, next);
         if (!((a > 0.0 && b > 0.0) || (a < 0.0 && b < 0.0))) return false;
@@ -481,31 +636,40 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 
 // CNT: counting build; work[0..4] += node visits, triangle tests,
 // containment tests, (slot, element) pairs, legs.
+#ifndef RT_RIS_WAVES_PER_SIMD
+#define RT_RIS_WAVES_PER_SIMD 4   // register cap that measured fastest on the lab room
+#endif
 template <bool BRUTE, bool KEEP, int STK, bool CNT>
-__global__ __launch_bounds__(RIS_B) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
+__global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
                                                const int32_t* useq, int n_mchunk, float2* H, uint8_t* rvalid,
                                                unsigned long long* segs, unsigned long long* work)
 {
-    __shared__ int stack[STK * RIS_B];
+    // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
+    __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
+    static_assert(RT_STACK4 >= STK, "wave stack");
     WorkCount wc;
     unsigned pairs = 0;
-    int64_t w = ((int64_t)blockIdx.x * RIS_B + threadIdx.x) >> 6;
-    int lane = threadIdx.x & 63;
+    const int wib = __builtin_amdgcn_readfirstlane((int)(threadIdx.x >> 6));   // wave in block (uniform)
+    const int64_t w = (int64_t)blockIdx.x * (RIS_B / 64) + wib;
+    const int lane = threadIdx.x & 63;
+    int* my_stack = wstack + wib * RT_STACK4;
     unsigned nseg = 0;
     if (w < R * n_mchunk) {
-        int64_t r = w / n_mchunk;
-        int m = (int)(w - r * n_mchunk) * 64 + lane;
-        bool active = m < rv.M;
-        int mm = active ? m : 0;
+        const int64_t r = w / n_mchunk;
+        const int m = (int)(w - r * n_mchunk) * 64 + lane;
+        const bool active = m < rv.M;
+        const int mm = active ? m : 0;
         const double* e = rv.elem + 3 * mm;
-        double E[3] = {e[0], e[1], e[2]};
-        TxmRec t = txm[mm];
-        double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
-        int64_t u0 = uptr[r], u1 = uptr[r + 1];
-        int64_t nsl = 1 + (u1 - u0);
+        const double E[3] = {e[0], e[1], e[2]};
+        const TxmRec t = txm[mm];
+        const double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
+        const int64_t u0 = uptr[r], u1 = uptr[r + 1];
+        const int64_t nsl = 1 + (u1 - u0);
         double acc_r = 0.0, acc_i = 0.0;
+#pragma unroll 1
         for (int64_t sl = 0; sl < nsl; ++sl) {
+            // the slot's sequence is the same for every lane of the wave
             int seq[RT_MAX_K] = {-1, -1, -1};
             int hint[RT_MAX_K] = {-1, -1, -1};
             int k = 0;
@@ -518,52 +682,102 @@ __global__ __launch_bounds__(RIS_B) void k_ris(SceneView s, TraceConst tc, RisVi
                 }
             }
             bool ok = active && t.ok;
-            double I[RT_MAX_K + 1][3];
-            double P[RT_MAX_K][3];
-            int tri[RT_MAX_K];
-            I[0][0] = E[0];
-            I[0][1] = E[1];
-            I[0][2] = E[2];
-            for (int j = 0; j < k; ++j) mirror(s.s_plane + 4 * seq[j], I[j], I[j + 1]);
             if (CNT && active) ++pairs;
-            if (ok) ok = image_backtrace_hint<CNT>(s, seq, hint, k, I, X, P, tri, &wc);
-            float Fout = 0.0f, Fr = 0.0f;
-            if (ok) {
-                const double* f = k ? P[0] : X;
-                const double* l = k ? P[k - 1] : E;
-                double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
-                double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
-                Fout = pattern_f(1, (float)rv.q, cos_between(v1, rv.normal));
-                Fr = pattern_f(tc.rxa.pattern, (float)tc.rxa.param, cos_between(vl, tc.rxa.axis));
-                ok = Fout > 0.0f && Fr > 0.0f;
-            }
-            for (int j = 0; j <= k; ++j) {
-                if (!ok) break;
-                const double* A = j == 0 ? E : P[j - 1];
-                const double* B = j == k ? X : P[j];
-                int sa = j == 0 ? -1 : seq[j - 1];
-                int sb = j == k ? -1 : seq[j];
-                ++nseg;
-                if (leg_blocked<BRUTE, CNT>(s, A, B, sa, sb, stack + threadIdx.x, RIS_B, &wc)) ok = false;
-            }
-            if (ok) {
-                double Dr = 0.0;
-                for (int j = 0; j <= k; ++j) Dr += seg_len(j == 0 ? E : P[j - 1], j == k ? X : P[j]);
-                float ar = 1.0f, ai = 0.0f;
-                for (int j = 0; j < k; ++j) {
-                    float2 Rc = s.refl[tri[j]];
-                    float nr = ar * Rc.x - ai * Rc.y;
-                    float ni = ar * Rc.y + ai * Rc.x;
-                    ar = nr;
-                    ai = ni;
+            // phase 1 (FP64): image method, leg rays, length, amplitude
+            float ro[RT_MAX_K + 1][3], rd[RT_MAX_K + 1][3], rt[RT_MAX_K + 1];
+            float amp_r = 0.0f, amp_i = 0.0f;
+            {
+                double P[RT_MAX_K][3];
+                int tri[RT_MAX_K] = {-1, -1, -1};
+                {
+                    double I[RT_MAX_K + 1][3];
+                    I[0][0] = E[0];
+                    I[0][1] = E[1];
+                    I[0][2] = E[2];
+#pragma unroll
+                    for (int j = 0; j < RT_MAX_K; ++j)
+                        if (j < k) mirror(s.s_plane + 4 * seq[j], I[j], I[j + 1]);
+                    if (ok) ok = image_backtrace_hint<CNT>(s, seq, hint, k, I, X, P, tri, &wc);
                 }
-                float mag = t.fac * sqrtf(Fout) * sqrtf((float)tc.rxa.gain * Fr) *
-                            (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
-                float ph = (float)phase_of(t.dt + Dr, tc.lambda);
-                float cs, sn;
-                sincosf(ph, &sn, &cs);
-                acc_r += (double)(mag * (ar * cs - ai * sn));
-                acc_i += (double)(mag * (ar * sn + ai * cs));
+                float Fout = 0.0f, Fr = 0.0f;
+                if (ok) {
+                    // first and last path points, selected by value (constant indices)
+                    static_assert(RT_MAX_K == 3, "selection below lists every order");
+                    double f[3], l[3];
+                    for (int q = 0; q < 3; ++q) {
+                        f[q] = k ? P[0][q] : X[q];
+                        l[q] = k == 0 ? E[q] : k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
+                    }
+                    double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
+                    double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
+                    Fout = pattern_f(1, (float)rv.q, cos_between(v1, rv.normal));
+                    Fr = pattern_f(tc.rxa.pattern, (float)tc.rxa.param, cos_between(vl, tc.rxa.axis));
+                    ok = Fout > 0.0f && Fr > 0.0f;
+                }
+                double Dr = 0.0;
+#pragma unroll
+                for (int j = 0; j <= RT_MAX_K; ++j) {
+                    if (j <= k) {
+#pragma clang fp contract(off)
+                        const double* A = j == 0 ? E : P[j - 1];
+                        const double* B = j == k ? X : P[j];
+                        double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
+                        double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+                        Dr += L;
+                        ro[j][0] = (float)A[0];
+                        ro[j][1] = (float)A[1];
+                        ro[j][2] = (float)A[2];
+                        rd[j][0] = (float)(w0 / L);
+                        rd[j][1] = (float)(w1 / L);
+                        rd[j][2] = (float)(w2 / L);
+                        rt[j] = (float)(L - RT_EPS);
+                    }
+                }
+                if (ok) {
+                    float ar = 1.0f, ai = 0.0f;
+#pragma unroll
+                    for (int j = 0; j < RT_MAX_K; ++j) {
+                        if (j >= k) break;
+                        float2 Rc = s.refl[tri[j]];
+                        float nr = ar * Rc.x - ai * Rc.y;
+                        float ni = ar * Rc.y + ai * Rc.x;
+                        ar = nr;
+                        ai = ni;
+                    }
+                    float mag = t.fac * sqrtf(Fout) * sqrtf((float)tc.rxa.gain * Fr) *
+                                (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
+                    float ph = (float)phase_of(t.dt + Dr, tc.lambda);
+                    float cs, sn;
+                    sincosf(ph, &sn, &cs);
+                    amp_r = mag * (ar * cs - ai * sn);
+                    amp_i = mag * (ar * sn + ai * cs);
+                }
+            }
+            // phase 2 (FP32): visibility of every leg, the wave walking the BVH together
+            const float tmin = (float)RT_EPS;
+#pragma unroll
+            for (int j = 0; j <= RT_MAX_K; ++j) {
+                if (j <= k) {
+                    const int sa = j == 0 ? -1 : seq[j - 1];
+                    const int sb = j == k ? -1 : seq[j];
+                    if (ok) ++nseg;
+                    const bool searching = ok && rt[j] > tmin;
+                    bool blocked;
+                    if (BRUTE)
+                        blocked = searching && any_hit<true>(s, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
+                                                             rd[j][2], tmin, rt[j], sa, sb, nullptr, 0);
+                    else if (CNT)   // the counting build walks the binary tree: its work is what is counted
+                        blocked = any_hit_wave<true>(s, searching, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
+                                                     rd[j][2], tmin, rt[j], sa, sb, my_stack, &wc);
+                    else
+                        blocked = any_hit_wave4(s, searching, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
+                                                rd[j][2], tmin, rt[j], sa, sb, my_stack);
+                    ok = ok && !blocked;
+                }
+            }
+            if (ok) {
+                acc_r += (double)amp_r;
+                acc_i += (double)amp_i;
             }
             if (KEEP && active) rvalid[(u0 + r + sl) * rv.M + m] = ok ? 1 : 0;
         }
@@ -614,13 +828,35 @@ struct Cands {
 
 static int stack_depth_for(const Scene& s, bool brute) { return (brute || s.max_depth < 31) ? 32 : 64; }
 
-static void make_candidates(Ctx& c, const SceneView& sv, int stk, const double* src, const double* hemi_n,
-                            const TraceArgs& a, bool brute, bool exhaustive, bool keep_hits, Channel& ch,
-                            int which, Cands& out, unsigned long long* d_segs, int64_t* d_cnt, hipStream_t st)
-{
-    const int K = a.tc.K;
+struct PathSet {
+    int64_t n = 0;
+    Scratch cells, valid, amp, len, recs, rstart;
+};
+
+// One source's candidate pipeline, split where the host needs a size.
+struct Branch {
+    const double* src = nullptr;
+    const double* hemi = nullptr;
+    int which = 0;
+    hipStream_t st = nullptr;
+    int64_t* d_cnt = nullptr;
+    unsigned long long* d_app = nullptr;
     Scratch keys;
     int64_t nkeys = 0;
+    Cands cd;
+    PathSet ps;
+    int64_t cap = 0;
+};
+
+// Phase A of the candidates: discovery rays, prefix keys into a hash set,
+// occupied slots compacted behind a leading 0 (the empty sequence); the
+// count is left in d_app[0] (overflow flag in d_app[1]).  Exhaustive mode:
+// every surface sequence, sorted and de-duplicated (count in d_cnt).
+static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool exhaustive,
+                         bool keep_hits, Channel& ch, Branch& br, unsigned long long* d_segs)
+{
+    const int K = a.tc.K;
+    hipStream_t st = br.st;
     if (exhaustive) {
         int64_t ns = sv.n_surf;
         int64_t total = 0, p = 1;
@@ -629,84 +865,123 @@ static void make_candidates(Ctx& c, const SceneView& sv, int stk, const double* 
             total += p;
             if (total > (int64_t)1 << 26) throw inval_error("exhaustive candidate set too large");
         }
-        nkeys = total + 1;
-        keys = Scratch(c, sizeof(uint64_t) * (size_t)nkeys, st);
+        int64_t nkeys = total + 1;
+        Scratch keys(c, sizeof(uint64_t) * (size_t)nkeys, st);
         HIP_CHECK(hipMemsetAsync(keys.p, 0, keys.bytes, st));
         if (total > 0)
             hipLaunchKernelGGL(k_exhaustive_keys, dim3(nblk(total, 256)), dim3(256), 0, st, ns, K, total,
                                keys.as<uint64_t>());
         HIP_CHECK(hipGetLastError());
-    } else {
-        int64_t rows = hemi_n ? 2 * a.n_rays : a.n_rays;
-        Scratch hits(c, sizeof(int32_t) * (size_t)(rows * K), st);
-        if (rows > 0) {
-            SEL_BOOL(brute, BR,
-                     SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(rows, DISC_B)), dim3(DISC_B),
-                                                     0, st, sv, src[0], src[1], src[2], hemi_n ? 1 : 0,
-                                                     hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0,
-                                                     hemi_n ? hemi_n[2] : 0.0, rows, K, hits.as<int32_t>(), d_segs)));
-            HIP_CHECK(hipGetLastError());
-        }
-        nkeys = rows * K + 1;
-        keys = Scratch(c, sizeof(uint64_t) * (size_t)nkeys, st);
-        HIP_CHECK(hipMemsetAsync(keys.as<uint64_t>() + rows * K, 0, sizeof(uint64_t), st));
-        if (rows > 0 && sv.n_tri > 0) {
-            hipLaunchKernelGGL(k_prefix_keys, dim3(nblk(rows, 256)), dim3(256), 0, st, hits.as<int32_t>(), sv.surf,
-                               rows, K, keys.as<uint64_t>());
-            HIP_CHECK(hipGetLastError());
-        } else if (rows * K > 0) {
-            HIP_CHECK(hipMemsetAsync(keys.p, 0, sizeof(uint64_t) * (size_t)(rows * K), st));
-        }
-        if (keep_hits) {
-            ch.n_hits_rows[which] = rows;
-            ch.hits[which] = std::move(hits);
-        }
+        sort_u64(c, keys.as<uint64_t>(), nkeys, RT_KEY_BITS * K, st);
+        br.keys = Scratch(c, sizeof(uint64_t) * (size_t)nkeys, st);
+        unique_u64(c, keys.as<uint64_t>(), br.keys.as<uint64_t>(), nkeys, br.d_cnt, st);
+        return;
     }
-    sort_u64(c, keys.as<uint64_t>(), nkeys, RT_KEY_BITS * K, st);
-    Scratch uniq(c, sizeof(uint64_t) * (size_t)nkeys, st);
-    unique_u64(c, keys.as<uint64_t>(), uniq.as<uint64_t>(), nkeys, d_cnt, st);
-    int64_t n = read_i64(d_cnt, st);
-    out.n = n;
-    out.keys = Scratch(c, sizeof(uint64_t) * (size_t)n, st);
-    HIP_CHECK(hipMemcpyAsync(out.keys.p, uniq.p, sizeof(uint64_t) * (size_t)n, hipMemcpyDeviceToDevice, st));
-    out.k = Scratch(c, sizeof(int32_t) * (size_t)n, st);
-    out.seq = Scratch(c, sizeof(int32_t) * 3 * (size_t)n, st);
-    out.img = Scratch(c, sizeof(double) * 9 * (size_t)n, st);
-    hipLaunchKernelGGL(k_cand_prep, dim3(nblk(n, 128)), dim3(128), 0, st, out.keys.as<uint64_t>(), n, sv, src[0],
-                       src[1], src[2], out.k.as<int32_t>(), out.seq.as<int32_t>(), out.img.as<double>());
+    const double* src = br.src;
+    const double* hemi_n = br.hemi;
+    int64_t rows = hemi_n ? 2 * a.n_rays : a.n_rays;
+    if (rows > ((int64_t)1 << 31)) throw inval_error("too many discovery rays");
+    // hit lists are written only when the caller keeps them
+    Scratch hits(c, keep_hits ? sizeof(int32_t) * (size_t)(rows * K) : 0, st);
+    if (keep_hits && rows > 0 && K > 0) {
+        hipLaunchKernelGGL(k_fill_neg, dim3(nblk(rows * K, 256)), dim3(256), 0, st, hits.as<int32_t>(), rows * K);
+        HIP_CHECK(hipGetLastError());
+    }
+    // hash set of at least 2 x (keys + 1) slots, at most 2^24; filled by discovery
+    int64_t want = 2 * rows * K + 2, cap = 1024;
+    while (cap < want && cap < ((int64_t)1 << 24)) cap <<= 1;
+    Scratch table(c, sizeof(unsigned long long) * (size_t)cap, st);
+    HIP_CHECK(hipMemsetAsync(table.p, 0, table.bytes, st));
+    if (rows > 0 && K > 0 && sv.n_tri > 0) {
+        // launched rows sorted by direction (the list count is read back with the candidates)
+        Scratch list(c, sizeof(uint64_t) * (size_t)rows, st);
+        HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
+        hipLaunchKernelGGL(k_ray_list, dim3(nblk(rows, RL_B * RL_PT)), dim3(RL_B), 0, st, rows, hemi_n ? 1 : 0,
+                           hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0, hemi_n ? hemi_n[2] : 0.0,
+                           list.as<uint64_t>(), rows, br.d_app);
+        HIP_CHECK(hipGetLastError());
+        const int64_t n_list = hemi_n ? read_i64((const int64_t*)br.d_app, st) : rows;
+        sort_u64(c, list.as<uint64_t>(), n_list, 56, st);
+        SEL_BOOL(brute, BR,
+                 SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(n_list, DISC_B)), dim3(DISC_B), 0,
+                                                 st, sv, src[0], src[1], src[2], list.as<uint64_t>(), n_list, rows,
+                                                 K, keep_hits ? hits.as<int32_t>() : nullptr, d_segs,
+                                                 table.as<unsigned long long>(),
+                                                 (uint64_t)(cap - 1), (int*)(br.d_app + 1))));
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
+    }
+    if (keep_hits) {
+        ch.n_hits_rows[br.which] = rows;
+        ch.hits[br.which] = std::move(hits);
+    }
+    br.keys = Scratch(c, sizeof(uint64_t) * (size_t)(cap + 1), st);
+    HIP_CHECK(hipMemsetAsync(br.keys.p, 0, sizeof(uint64_t), st));
+    hipLaunchKernelGGL(k_table_compact, dim3(nblk(cap, TC_B * TC_PT)), dim3(TC_B), 0, st, table.as<unsigned long long>(), cap,
+                       br.keys.as<uint64_t>() + 1, cap, br.d_app);
     HIP_CHECK(hipGetLastError());
 }
 
-struct PathSet {
-    int64_t n = 0;
-    Scratch cells, valid, amp, len, recs, rstart;
-};
-
-static void find_paths(Ctx& c, const SceneView& sv, int stk, const Cands& cd, const double* src,
-                       const TraceArgs& a, bool brute, bool field, PathSet& ps, unsigned long long* d_segs,
-                       unsigned long long* d_app, hipStream_t st)
+// Size read-back after phase A: number of unique candidates (incl. order 0).
+static int64_t cand_count(const Branch& br, bool exhaustive)
 {
+    if (exhaustive) return read_i64(br.d_cnt, br.st);
+    int64_t hq[2];
+    read_i64s((const int64_t*)br.d_app, hq, 2, br.st);
+    if (hq[1] & 1) throw inval_error("candidate hash set overflow");
+    return hq[0] + 1;
+}
+
+// Phase B: the unique keys in key order (the canonical candidate order).
+static void cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch& br, int64_t n)
+{
+    if (exhaustive) return;
+    sort_u64(c, br.keys.as<uint64_t>(), n, RT_KEY_BITS * a.tc.K, br.st);
+    HIP_CHECK(hipMemsetAsync(br.d_app, 0, 2 * sizeof(unsigned long long), br.st));
+}
+
+// candidate images and the geometric test of every (receiver, candidate) cell
+static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& br, int64_t n_cand)
+{
+    hipStream_t st = br.st;
+    Cands& cd = br.cd;
+    cd.n = n_cand;
+    cd.keys = std::move(br.keys);
+    cd.k = Scratch(c, sizeof(int32_t) * (size_t)n_cand, st);
+    cd.seq = Scratch(c, sizeof(int32_t) * 3 * (size_t)n_cand, st);
+    cd.img = Scratch(c, sizeof(double) * 9 * (size_t)n_cand, st);
+    hipLaunchKernelGGL(k_cand_prep, dim3(nblk(n_cand, 128)), dim3(128), 0, st, cd.keys.as<uint64_t>(), n_cand, sv,
+                       br.src[0], br.src[1], br.src[2], cd.k.as<int32_t>(), cd.seq.as<int32_t>(),
+                       cd.img.as<double>());
+    HIP_CHECK(hipGetLastError());
     const int64_t R = a.R;
-    const int64_t cells = R * cd.n;
+    const int64_t cells = R * n_cand;
     if (cells > ((int64_t)1 << 40)) throw inval_error("receivers x candidates too large for one call");
-    CandView cv = cd.view();
-    // worst case: every cell valid; the pool hands back pages that are never touched cheaply
-    const int64_t cap = cells < ((int64_t)1 << 24) ? cells : ((int64_t)1 << 24);
-    Scratch raw(c, sizeof(uint64_t) * (size_t)(cap > 0 ? cap : 1), st);
-    HIP_CHECK(hipMemsetAsync(d_app, 0, sizeof(unsigned long long), st));
-    int64_t n = 0;
+    br.cap = cells < ((int64_t)1 << 24) ? cells : ((int64_t)1 << 24);
+    br.ps.cells = Scratch(c, sizeof(uint64_t) * (size_t)(br.cap > 0 ? br.cap : 1), st);
+    HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
     if (cells > 0) {
-        hipLaunchKernelGGL(k_geo_cells, dim3(nblk(cells, 256)), dim3(256), 0, st, sv, cv, src[0], src[1], src[2],
-                           a.rx_dev, R, raw.as<uint64_t>(), cap, d_app);
+        if (nblk(R, 64) > 65535 || n_cand > 0x7fffffff) throw inval_error("receiver or candidate count too large");
+        hipLaunchKernelGGL(k_geo_cells, dim3(nblk(n_cand, GEO_B / 64 * GEO_CPW), nblk(R, 64)), dim3(GEO_B), 0, st,
+                           sv, cd.view(),
+                           br.src[0], br.src[1], br.src[2], a.rx_dev, R, br.ps.cells.as<uint64_t>(), br.cap, br.d_app);
         HIP_CHECK(hipGetLastError());
-        n = read_i64((const int64_t*)d_app, st);
-        if (n > cap) throw inval_error("too many geometric paths for one call");
     }
+}
+
+// sort the valid cells, legs and field of each path, receiver ranges
+static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool field,
+                         Branch& br, int64_t n, unsigned long long* d_segs)
+{
+    hipStream_t st = br.st;
+    PathSet& ps = br.ps;
+    const int64_t R = a.R;
+    const int64_t cells = R * br.cd.n;
+    if (n > br.cap) throw inval_error("too many geometric paths for one call");
     ps.n = n;
     int end_bit = 1;
     while (end_bit < 64 && ((uint64_t)1 << end_bit) < (uint64_t)(cells > 1 ? cells : 2)) ++end_bit;
-    sort_u64(c, raw.as<uint64_t>(), n, end_bit, st);
-    ps.cells = std::move(raw);
+    sort_u64(c, ps.cells.as<uint64_t>(), n, end_bit, st);
     ps.valid = Scratch(c, (size_t)(n > 0 ? n : 1), st);
     ps.recs = Scratch(c, sizeof(PathRec) * (size_t)(n > 0 ? n : 1), st);
     if (field) {
@@ -714,10 +989,12 @@ static void find_paths(Ctx& c, const SceneView& sv, int stk, const Cands& cd, co
         ps.len = Scratch(c, sizeof(double) * (size_t)(n > 0 ? n : 1), st);
     }
     ps.rstart = Scratch(c, sizeof(int64_t) * (size_t)(R + 1), st);
-    hipLaunchKernelGGL(k_rx_start, dim3(nblk(R + 1, 256)), dim3(256), 0, st, ps.cells.as<uint64_t>(), n, cd.n, R,
+    hipLaunchKernelGGL(k_rx_start, dim3(nblk(R + 1, 256)), dim3(256), 0, st, ps.cells.as<uint64_t>(), n, br.cd.n, R,
                        ps.rstart.as<int64_t>());
     HIP_CHECK(hipGetLastError());
     if (n == 0) return;
+    CandView cv = br.cd.view();
+    const double* src = br.src;
     SEL_BOOL(brute, BR,
              SEL_BOOL(field, FI,
                       SEL_STK(stk, hipLaunchKernelGGL((k_paths<BR, FI, STK>), dim3(nblk(n, LEG_B)), dim3(LEG_B), 0,
@@ -745,6 +1022,12 @@ struct StageTimer {
     }
 };
 
+struct Event {
+    hipEvent_t e = nullptr;
+    Event() { HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
+    ~Event() { (void)hipEventDestroy(e); }
+};
+
 void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st)
 {
     const SceneView sv = a.scene->view();
@@ -762,87 +1045,114 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     StageTimer tm(timing, st);
     tm.mark();   // 0
 
+    // counters: [0] discovery segments, [1] leg segments, [2..4] Tx count / append / hash overflow,
+    // [5..7] centre count / append / hash overflow, [8..12] work of the counting build,
+    // [13] valid environment paths
     Scratch ctr(c, 128, st);
     HIP_CHECK(hipMemsetAsync(ctr.p, 0, 128, st));
-    unsigned long long* d_disc = ctr.as<unsigned long long>();
-    unsigned long long* d_legs = d_disc + 1;
-    int64_t* d_cnt = (int64_t*)(d_disc + 2);
-    unsigned long long* d_app = d_disc + 3;
-    unsigned long long* d_work = d_disc + 8;   // 5 counters of the counting build
+    unsigned long long* d_ctr = ctr.as<unsigned long long>();
+    unsigned long long* d_disc = d_ctr;
+    unsigned long long* d_legs = d_ctr + 1;
+    unsigned long long* d_work = d_ctr + 8;
+    ch.E_env = Scratch(c, sizeof(float2) * (size_t)R, st);
+    Scratch uptr, useq;
+    if (a.ris) uptr = Scratch(c, sizeof(int64_t) * (size_t)(R + 1), st);
     tm.mark();   // 1
 
+    // the Tx branch runs on `st`, the RIS-centre branch on a side stream
+    Branch bt, bu;
+    bt.src = a.tc.tx;
+    bt.which = 0;
+    bt.st = st;
+    bt.d_cnt = (int64_t*)(d_ctr + 2);
+    bt.d_app = d_ctr + 3;
+    const bool two = a.ris != nullptr;
+    Event fork, join;
+    SideStream side(c);   // returned to the pool after the join below
+    if (two) {
+        bu.src = a.ris->centre;
+        bu.hemi = a.ris->normal;
+        bu.which = 1;
+        bu.st = side.s;
+        bu.d_cnt = (int64_t*)(d_ctr + 5);
+        bu.d_app = d_ctr + 6;
+        HIP_CHECK(hipEventRecord(fork.e, st));
+        HIP_CHECK(hipStreamWaitEvent(bu.st, fork.e, 0));
+    }
     // 1-3: candidates
-    Cands ctx_tx, ctx_u;
-    make_candidates(c, sv, stk, a.tc.tx, nullptr, a, brute, exhaustive, keep_hits, ch, 0, ctx_tx, d_disc, d_cnt, st);
-    if (a.ris)
-        make_candidates(c, sv, stk, a.ris->centre, a.ris->normal, a, brute, exhaustive, keep_hits, ch, 1, ctx_u,
-                        d_disc, d_cnt, st);
+    cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
+    if (two) cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
+    const int64_t n_tx = cand_count(bt, exhaustive);
+    const int64_t n_u0 = two ? cand_count(bu, exhaustive) : 0;
+    cand_phase_b(c, a, exhaustive, bt, n_tx);
+    if (two) cand_phase_b(c, a, exhaustive, bu, n_u0);
+    out.n_cand_tx = n_tx;
+    out.n_cand_u = n_u0;
     tm.mark();   // 2
-    out.n_cand_tx = ctx_tx.n;
-    out.n_cand_u = a.ris ? ctx_u.n : 0;
+    // 4: geometry of every (receiver, candidate)
+    geo_launch(c, sv, a, bt, n_tx);
+    if (two) geo_launch(c, sv, a, bu, n_u0);
+    const int64_t g_tx = R * n_tx > 0 ? read_i64((const int64_t*)bt.d_app, st) : 0;
+    const int64_t g_u = two && R * n_u0 > 0 ? read_i64((const int64_t*)bu.d_app, bu.st) : 0;
+    // 5-6: legs and fields
+    paths_launch(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
+    if (two) paths_launch(c, sv, stk, a, brute, false, bu, g_u, d_legs);
 
-    // 4-6: environment paths
-    ch.E_env = Scratch(c, sizeof(float2) * (size_t)R, st);
+    // environment field per receiver (Tx branch)
     {
-        PathSet ps;
-        find_paths(c, sv, stk, ctx_tx, a.tc.tx, a, brute, true, ps, d_legs, d_app, st);
+        PathSet& ps = bt.ps;
         if (R > 0) {
             hipLaunchKernelGGL(k_env_reduce, dim3(nblk(R, 128)), dim3(128), 0, st, ps.rstart.as<int64_t>(), R,
                                ps.valid.as<uint8_t>(), ps.amp.as<float2>(), ch.E_env.as<float2>());
             HIP_CHECK(hipGetLastError());
         }
         Scratch off2(c, sizeof(int64_t) * (size_t)(ps.n > 0 ? ps.n : 1), st);
-        scan_flags(c, ps.valid.as<uint8_t>(), off2.as<int64_t>(), ps.n, d_cnt, st);
-        out.n_env = read_i64(d_cnt, st);
-        ch.n_env = out.n_env;
+        scan_flags(c, ps.valid.as<uint8_t>(), off2.as<int64_t>(), ps.n, (int64_t*)(d_ctr + 13), st);
         if (keep_paths) {
-            ch.env = Scratch(c, sizeof(EnvRec) * (size_t)out.n_env, st);
+            const int64_t n_env = read_i64((const int64_t*)(d_ctr + 13), st);
+            ch.env = Scratch(c, sizeof(EnvRec) * (size_t)n_env, st);
             if (ps.n > 0) {
                 hipLaunchKernelGGL(k_env_compact, dim3(nblk(ps.n, 128)), dim3(128), 0, st, ps.recs.as<PathRec>(),
-                                   ctx_tx.view(), ps.valid.as<uint8_t>(), off2.as<int64_t>(), ps.amp.as<float2>(),
+                                   bt.cd.view(), ps.valid.as<uint8_t>(), off2.as<int64_t>(), ps.amp.as<float2>(),
                                    ps.len.as<double>(), ps.n, ch.env.as<EnvRec>());
                 HIP_CHECK(hipGetLastError());
             }
         }
     }
+    // sequences valid from the RIS centre, grouped by receiver (centre branch)
+    int64_t n_u = 0;
+    if (two) {
+        PathSet& ps = bu.ps;
+        hipStream_t su = bu.st;
+        Scratch f2(c, (size_t)(ps.n > 0 ? ps.n : 1), su), off2(c, sizeof(int64_t) * (size_t)(ps.n > 0 ? ps.n : 1), su);
+        if (ps.n > 0) {
+            hipLaunchKernelGGL(k_u_flags, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec>(),
+                               ps.valid.as<uint8_t>(), ps.n, f2.as<uint8_t>());
+            HIP_CHECK(hipGetLastError());
+        }
+        scan_flags(c, f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, bu.d_cnt, su);
+        // rows for every geometric path (an upper bound of the valid ones)
+        useq = Scratch(c, sizeof(int32_t) * 8 * (size_t)(ps.n > 0 ? ps.n : 1), su);
+        if (ps.n > 0) {
+            hipLaunchKernelGGL(k_u_compact, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec>(),
+                               bu.cd.view(), f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, useq.as<int32_t>());
+            HIP_CHECK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_uptr_dev, dim3(nblk(R + 1, 128)), dim3(128), 0, su, ps.rstart.as<int64_t>(), ps.n,
+                           off2.as<int64_t>(), bu.d_cnt, R, uptr.as<int64_t>());
+        HIP_CHECK(hipGetLastError());
+        HIP_CHECK(hipEventRecord(join.e, su));
+        HIP_CHECK(hipStreamWaitEvent(st, join.e, 0));
+        if (keep_paths) n_u = read_i64(bu.d_cnt, st);
+    }
     tm.mark();   // 3
+    tm.mark();   // 4
 
     if (!a.ris) {
         ch.H = Scratch(c, 0, st);
         tm.mark();
         tm.mark();
-        tm.mark();
     } else {
-        // centre sequences V(rx)
-        Scratch uptr(c, sizeof(int64_t) * (size_t)(R + 1), st);
-        Scratch useq;
-        int64_t n_u = 0;
-        {
-            PathSet ps;
-            find_paths(c, sv, stk, ctx_u, a.ris->centre, a, brute, false, ps, d_legs, d_app, st);
-            Scratch f2(c, (size_t)(ps.n > 0 ? ps.n : 1), st), off2(c, sizeof(int64_t) * (size_t)(ps.n > 0 ? ps.n : 1), st);
-            if (ps.n > 0) {
-                hipLaunchKernelGGL(k_u_flags, dim3(nblk(ps.n, 256)), dim3(256), 0, st, ps.recs.as<PathRec>(),
-                                   ps.valid.as<uint8_t>(), ps.n, f2.as<uint8_t>());
-                HIP_CHECK(hipGetLastError());
-            }
-            scan_flags(c, f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, d_cnt, st);
-            n_u = read_i64(d_cnt, st);
-            useq = Scratch(c, sizeof(int32_t) * 8 * (size_t)(n_u > 0 ? n_u : 1), st);
-            if (ps.n > 0) {
-                hipLaunchKernelGGL(k_u_compact, dim3(nblk(ps.n, 256)), dim3(256), 0, st, ps.recs.as<PathRec>(),
-                                   ctx_u.view(), f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, useq.as<int32_t>());
-                HIP_CHECK(hipGetLastError());
-            }
-            hipLaunchKernelGGL(k_uptr, dim3(nblk(R + 1, 128)), dim3(128), 0, st, ps.rstart.as<int64_t>(), ps.n,
-                               off2.as<int64_t>(), n_u, R, uptr.as<int64_t>());
-            HIP_CHECK(hipGetLastError());
-        }
-        out.n_u = n_u;
-        out.n_slots = n_u + R;
-        ch.n_slots = out.n_slots;
-        tm.mark();   // 4
-
         RisView rv;
         rv.M = (int32_t)M;
         rv.pad = 0;
@@ -862,7 +1172,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                                                  txm.as<TxmRec>(), d_legs)));
         HIP_CHECK(hipGetLastError());
         ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
-        if (keep_paths) ch.ris_valid = Scratch(c, (size_t)(out.n_slots * M), st);
+        if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
         int n_mchunk = (int)((M + 63) / 64);
         int64_t waves = R * n_mchunk;
         int64_t threads = waves * 64;
@@ -892,20 +1202,32 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         }
     }
     if (keep_paths) {
-        ch.n_cand[0] = ctx_tx.n;
-        ch.cand_keys[0] = std::move(ctx_tx.keys);
-        if (a.ris) {
-            ch.n_cand[1] = ctx_u.n;
-            ch.cand_keys[1] = std::move(ctx_u.keys);
+        ch.n_cand[0] = bt.cd.n;
+        ch.cand_keys[0] = std::move(bt.cd.keys);
+        if (two) {
+            ch.n_cand[1] = bu.cd.n;
+            ch.cand_keys[1] = std::move(bu.cd.keys);
         }
     }
-    int64_t h[13];
-    read_i64s((const int64_t*)d_disc, h, 13, st);
+    // temporaries of the centre branch are released on the main stream (after the join)
+    if (two) {
+        for (Scratch* p : {&bu.keys, &bu.cd.keys, &bu.cd.k, &bu.cd.seq, &bu.cd.img, &bu.ps.cells, &bu.ps.valid,
+                           &bu.ps.amp, &bu.ps.len, &bu.ps.recs, &bu.ps.rstart})
+            p->st = st;
+        if (!keep_paths) useq.st = st;
+    }
+    int64_t h[14];
+    read_i64s((const int64_t*)d_ctr, h, 14, st);
     tm.mark();   // 7
     out.disc_segments = h[0];
     out.leg_segments = h[1];
-    for (int q = 0; q < 5; ++q) out.work[q] = h[8 + q];
     out.segments = h[0] + h[1];
+    out.n_env = h[13];
+    out.n_u = h[5];
+    out.n_slots = a.ris ? h[5] + R : 0;
+    ch.n_env = out.n_env;
+    ch.n_slots = out.n_slots;
+    for (int q = 0; q < 5; ++q) out.work[q] = h[8 + q];
     if (timing) {
         HIP_CHECK(hipStreamSynchronize(st));
         auto el = [&](int i, int j) {
@@ -914,10 +1236,10 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             return ms;
         };
         out.ms[0] = el(0, 1);                  // setup
-        out.ms[1] = el(1, 2);                  // discovery + dedupe + candidate images
+        out.ms[1] = el(1, 2);                  // discovery + dedupe (both sources)
         out.ms[2] = 0.0f;
-        out.ms[3] = el(2, 3);                  // environment paths
-        out.ms[4] = a.ris ? el(3, 4) : 0.0f;   // RIS-centre sequences
+        out.ms[3] = el(2, 3);                  // images, paths, legs, fields of both sources
+        out.ms[4] = 0.0f;
         out.ms[5] = a.ris ? el(5, 6) : 0.0f;   // per-element kernel (k_ris) alone
         out.ms[6] = a.ris ? el(4, 5) : 0.0f;   // Tx -> element legs
         out.ms[7] = el(0, 7);                  // total

@@ -22,6 +22,7 @@ from __future__ import annotations
 
 import collections
 import dataclasses
+import queue
 import threading
 import time
 from concurrent.futures import Future
@@ -102,6 +103,11 @@ class Server:
         self.cache_hits = 0
         self.admission_waits = 0
         self._errors = 0
+        self._work = [queue.Queue() for _ in range(n_slots)]
+        self._workers = [threading.Thread(target=self._worker, args=(i,), name="risrt-slot%d" % i, daemon=True)
+                         for i in range(n_slots)]
+        for t in self._workers:
+            t.start()
         self._sched = threading.Thread(target=self._scheduler, name="risrt-scheduler", daemon=True)
         self._sched.start()
 
@@ -143,6 +149,10 @@ class Server:
             self._running = False
             self._lock.notify_all()
         self._sched.join()
+        for q in self._work:
+            q.put(None)
+        for t in self._workers:
+            t.join()
         for h in list(self._chan.values()):
             self.ctx.destroy(h)
         for h in list(self._scene_h.values()) + list(self._ris_h.values()):
@@ -198,7 +208,14 @@ class Server:
                     self._queue.remove(q)
                 slot = self._free_slots.pop()
                 self._reserved += est
-            threading.Thread(target=self._run_batch, args=(slot, batch, est), daemon=True).start()
+            self._work[slot].put((batch, est))
+
+    def _worker(self, slot: int) -> None:
+        while True:
+            item = self._work[slot].get()
+            if item is None:
+                return
+            self._run_batch(slot, *item)
 
     # ---------------- device work ----------------
     def _scene(self, key: str, stream) -> int:
