@@ -15,6 +15,7 @@ configurations) and the oracle timed on a bounded sample of the same
 workload on the host cores.
 """
 import argparse
+import gc
 import json
 import math
 import os
@@ -108,10 +109,17 @@ def run_trace_bench(ctx, prob, steps, warmup):
         step()
     torch.cuda.synchronize()
     host_ms.clear()
-    t0 = time.perf_counter()
-    stats = [step() for _ in range(steps)]
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
+    # as timeit does: no interpreter garbage collection inside the timed steps
+    # (a full collection over torch's objects stalls the host for tens of ms)
+    gc.collect()
+    gc.disable()
+    try:
+        t0 = time.perf_counter()
+        stats = [step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+    finally:
+        gc.enable()
     for s, h in zip(stats, host_ms):
         s["host_ms"] = h
     # counting build of the per-element kernel (untimed; same inputs and results)
@@ -198,6 +206,9 @@ def run_serving_bench(ctx, n_queries=300, n_slots=4, load=0.7):
         srv.submit(d.key, np.ones((M, 1), np.complex64)).result()
         log("bench: serving warm-up %s traced (%.1f s)" % (d.key, time.perf_counter() - t0))
     t_warm = time.perf_counter() - t0
+    # long-lived objects out of the collector's way, as a serving process would
+    gc.collect()
+    gc.freeze()
     qs = workloads.query_stream(deps, riss, n_queries, seed=12)
     t0 = time.perf_counter()
     futs = [srv.submit(k, g) for k, g in qs]
@@ -237,7 +248,7 @@ def cpu_baseline(n_rx_side=8, n_rays=1_000_000):
     r = O.trace(prob, n_rays=n_rays)
     dt = time.perf_counter() - t0
     segs = r["segments"] + O.leg_count()
-    return {"value": segs / dt / 1e6, "unit": "Mray-segments/s", "cores": os.cpu_count(), "kind": "oracle",
+    return {"value": segs / dt / 1e6, "unit": "Mray-segments/s", "cores": O.threads(), "kind": "oracle",
             "sample": "lab room, full discovery (%d rays per source, order 3) + paths for %d receivers "
                       "(a %dx%d subsample of the 64x64 grid); %d segments in %.1f s"
                       % (n_rays, idx.size, n_rx_side, n_rx_side, segs, dt)}

@@ -81,6 +81,8 @@ def lib():
         L.or_fib_dir.argtypes = [i64, i64, P]
         L.or_leg_count.restype = i64
         L.or_leg_count.argtypes = []
+        L.or_threads.restype = ctypes.c_int
+        L.or_threads.argtypes = []
         _lib = L
     return _lib
 
@@ -96,6 +98,11 @@ def _c(a, dtype):
 # --------------------------------------------------------------------------
 # geometry wrappers
 # --------------------------------------------------------------------------
+def threads() -> int:
+    """Threads the oracle's parallel loops use."""
+    return int(lib().or_threads())
+
+
 def leg_count() -> int:
     """Visibility legs tested since the previous call."""
     return int(lib().or_leg_count())

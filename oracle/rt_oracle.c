@@ -27,6 +27,7 @@
  * Compile with -ffp-contract=off and without -ffast-math.
  */
 #include <math.h>
+#include <omp.h>
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
@@ -36,6 +37,9 @@
 static int64_t g_leg_count = 0; /* legs tested since the last or_leg_count() */
 
 /* Number of visibility legs tested since the last call (for timing reports). */
+/* threads an OpenMP loop of the oracle uses (reported with timings) */
+int or_threads(void) { return omp_get_max_threads(); }
+
 int64_t or_leg_count(void)
 {
     int64_t n;

@@ -163,6 +163,8 @@ void unique_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t n, int64_t* d
 // exclusive scan of uint8 flags into int64 offsets; total written to d_total
 void scan_flags(Ctx& c, const uint8_t* flags, int64_t* offsets, int64_t n, int64_t* d_total,
                 hipStream_t st);
+// exclusive scan of int64 values
+void scan_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n, hipStream_t st);
 
 // ---- scene build ----
 void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,

@@ -50,4 +50,13 @@ void scan_flags(Ctx& c, const uint8_t* flags, int64_t* offsets, int64_t n, int64
     HIP_CHECK(hipGetLastError());
 }
 
+void scan_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n, hipStream_t st)
+{
+    if (n == 0) return;
+    size_t bytes = 0;
+    HIP_CHECK(rocprim::exclusive_scan(nullptr, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), st));
+    Scratch tmp(c, bytes, st);
+    HIP_CHECK(rocprim::exclusive_scan(tmp.p, bytes, in, out, (int64_t)0, (size_t)n, rocprim::plus<int64_t>(), st));
+}
+
 }  // namespace rt

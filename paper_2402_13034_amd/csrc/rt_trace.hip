@@ -99,39 +99,66 @@ __device__ __forceinline__ uint32_t spread12(uint32_t v)
     return v;
 }
 
-// Rays to launch, keyed by direction so that a wave traces neighbouring
-// directions: key = Morton code of the octahedral map of d (12 + 12 bits)
-// << 32 | row.  Rows outside the half-space (hemi != 0) are not listed.
-constexpr int RL_B = 256, RL_PT = 4;
-__global__ __launch_bounds__(RL_B) void k_ray_list(int64_t rows, int hemi, double hx, double hy, double hz,
-                                                   uint64_t* out, int64_t cap, unsigned long long* counter)
+// Launch order of the discovery rays: consecutive Fibonacci rows form a thin
+// band of directions; each block sorts a chunk of RO_CH rows by the Morton
+// code of the octahedral map of d (18 bits) in LDS, so a wave traces
+// neighbouring directions.  Entry = row, or -1 for a row outside the
+// half-space (hemi != 0), which sorts to the end of its chunk.
+constexpr int RO_CH = 8192, RO_B = 512;
+__global__ __launch_bounds__(RO_B) void k_ray_order(int64_t rows, int hemi, double hx, double hy, double hz,
+                                                    int32_t* list)
 {
-    __shared__ uint64_t vals[RL_B * RL_PT];
-    __shared__ int n;
-    __shared__ unsigned long long base;
-    BlockAppend<RL_B * RL_PT> app{vals, &n, &base};
-    app.init();
-    for (int j = 0; j < RL_PT; ++j) {
-        int64_t i = ((int64_t)blockIdx.x * RL_PT + j) * RL_B + threadIdx.x;
-        if (i >= rows) continue;
-        double d[3];
-        fib_dir(i, rows, d);
-        bool go = hemi ? (d[0] * hx + d[1] * hy + d[2] * hz) > 0.0 : true;
-        if (!go) continue;
-        float ax = fabsf((float)d[0]), ay = fabsf((float)d[1]), az = fabsf((float)d[2]);
-        float sum = ax + ay + az;
-        float u = (float)d[0] / sum, v = (float)d[1] / sum;
-        if (d[2] < 0.0) {
-            float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
-            float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
-            u = uu;
-            v = vv;
+    __shared__ uint32_t key[RO_CH];
+    const int64_t base = (int64_t)blockIdx.x * RO_CH;
+    for (int j = threadIdx.x; j < RO_CH; j += RO_B) {
+        const int64_t i = base + j;
+        uint32_t k = 0xffffffffu;
+        if (i < rows) {
+            double d[3];
+            fib_dir(i, rows, d);
+            const bool go = hemi ? (d[0] * hx + d[1] * hy + d[2] * hz) > 0.0 : true;
+            if (go) {
+                float ax = fabsf((float)d[0]), ay = fabsf((float)d[1]), az = fabsf((float)d[2]);
+                float sum = ax + ay + az;
+                float u = (float)d[0] / sum, v = (float)d[1] / sum;
+                if (d[2] < 0.0) {
+                    float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
+                    float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
+                    u = uu;
+                    v = vv;
+                }
+                uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 512.0f, 0.0f), 511.0f);
+                uint32_t qv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 512.0f, 0.0f), 511.0f);
+                // 18-bit code << 13 | position in the chunk: < 2^31, below every skipped row
+                k = ((spread12(qu) | (spread12(qv) << 1)) << 13) | (uint32_t)j;
+            }
         }
-        uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 4096.0f, 0.0f), 4095.0f);
-        uint32_t qv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 4096.0f, 0.0f), 4095.0f);
-        app.push(((uint64_t)(spread12(qu) | (spread12(qv) << 1)) << 32) | (uint64_t)i);
+        key[j] = k;
     }
-    app.flush(out, cap, counter);
+    __syncthreads();
+    // bitonic sort, ascending
+    for (int size = 2; size <= RO_CH; size <<= 1) {
+        for (int stride = size >> 1; stride > 0; stride >>= 1) {
+            for (int t = threadIdx.x; t < RO_CH / 2; t += RO_B) {
+                const int lo = 2 * t - (t & (stride - 1));
+                const int hi = lo + stride;
+                const bool up = (lo & size) == 0;
+                const uint32_t x = key[lo], y = key[hi];
+                if ((x > y) == up) {
+                    key[lo] = y;
+                    key[hi] = x;
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int j = threadIdx.x; j < RO_CH; j += RO_B) {
+        const int64_t i = base + j;
+        if (i < rows) {
+            const uint32_t k = key[j];
+            list[i] = k == 0xffffffffu ? -1 : (int32_t)(base + (k & (RO_CH - 1)));
+        }
+    }
 }
 
 // Rows not launched keep -1 hit lists.
@@ -142,7 +169,8 @@ __global__ void k_fill_neg(int32_t* p, int64_t n)
 }
 
 // De-duplication of prefix keys in an open-addressing hash set (keys != 0,
-// capacity a power of two, linear probing).  A slot is read before the
+// capacity a power of two, linear probing; a probe run longer than max_probe
+// raises the overflow flag, and the caller repeats with a larger set).  A slot is read before the
 // compare-and-swap, so the many repeats of a key cost no atomics.
 __device__ __forceinline__ uint64_t mix64(uint64_t x)
 {
@@ -154,10 +182,11 @@ __device__ __forceinline__ uint64_t mix64(uint64_t x)
     return x;
 }
 
-__device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t mask, uint64_t key, int* overflow)
+__device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t mask, uint64_t max_probe,
+                                            uint64_t key, int* overflow)
 {
     uint64_t h = mix64(key) & mask;
-    for (uint64_t probe = 0; probe <= mask; ++probe) {
+    for (uint64_t probe = 0; probe <= max_probe; ++probe) {
         // a plain read may be stale only as 0 (a slot changes once, 0 -> key); the CAS decides then
         unsigned long long cur = table[h];
         if (cur == key) return;
@@ -176,17 +205,18 @@ __device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t 
 // neighbour's (one of them inserts it).
 template <bool BRUTE, int STK>
 __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, double sy, double sz,
-                                                     const uint64_t* list, int64_t n_list, int64_t rows, int K,
+                                                     const int32_t* list, int64_t n_list, int64_t rows, int K,
                                                      int32_t* hits, unsigned long long* segs,
-                                                     unsigned long long* table, uint64_t mask, int* overflow)
+                                                     unsigned long long* table, uint64_t mask, uint64_t max_probe,
+                                                     int* overflow)
 {
     static_assert(RT_MAX_K == 3, "three key registers");
     __shared__ int stack[STK * DISC_B];
     int64_t t = (int64_t)blockIdx.x * DISC_B + threadIdx.x;
     unsigned nseg = 0;
     uint64_t keys[RT_MAX_K] = {0, 0, 0};
-    if (t < n_list) {
-        const int64_t i = (int64_t)(list[t] & 0xffffffffull);
+    const int64_t i = t < n_list ? (int64_t)list[t] : -1;
+    if (i >= 0) {
         double d64[3];
         fib_dir(i, rows, d64);
         float ox = (float)sx, oy = (float)sy, oz = (float)sz;
@@ -218,7 +248,7 @@ __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, dou
     for (int b = 0; b < RT_MAX_K; ++b) {
         const uint64_t left = __shfl_up(keys[b], 1, 64);
         const bool first = (threadIdx.x & 63) == 0 || left != keys[b];
-        if (b < K && keys[b] != 0ull && first) hash_insert(table, mask, keys[b], overflow);
+        if (b < K && keys[b] != 0ull && first) hash_insert(table, mask, max_probe, keys[b], overflow);
     }
     wave_count_add(segs, nseg);
 }
@@ -333,34 +363,78 @@ __global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long
 
 // One wave takes GEO_CPW candidates for 64 consecutive receivers, so the
 // candidate's surfaces, planes and triangles are wave-uniform (scalar loads,
-// no divergence in the loops over a surface's triangles).
-// grid: x = group of 4 x GEO_CPW candidates, y = block of 64 receivers
+// no divergence in the loops over a surface's triangles).  A block covers 32
+// candidates = one 32-bit word of the receiver's row of the validity mask
+// (mask[r * n_words + w], bit b = candidate 32 w + b).
+// grid: x = word (group of 32 candidates), y = block of 64 receivers
 constexpr int GEO_B = 256, GEO_CPW = 8;
-__global__ __launch_bounds__(GEO_B) void k_geo_cells(SceneView s, CandView cv, double sx, double sy, double sz,
-                                                     const double* rx, int64_t R, uint64_t* cells, int64_t cap,
-                                                     unsigned long long* counter)
+__global__ __launch_bounds__(GEO_B) void k_geo_mask(SceneView s, CandView cv, double sx, double sy, double sz,
+                                                    const double* rx, int64_t R, int64_t n_words, uint32_t* mask)
 {
-    __shared__ uint64_t vals[GEO_B * GEO_CPW];
-    __shared__ int n;
-    __shared__ unsigned long long base;
-    BlockAppend<GEO_B * GEO_CPW> app{vals, &n, &base};
-    app.init();
+    static_assert(GEO_B / 64 * GEO_CPW == 32, "one mask word per block");
+    __shared__ uint32_t part[GEO_B / 64][64];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-    const int64_t r = (int64_t)blockIdx.y * 64 + (threadIdx.x & 63);
+    const int lane = threadIdx.x & 63;
+    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    uint32_t bits = 0;
     if (r < R) {
         const double S[3] = {sx, sy, sz};
         const double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
-        const int64_t c0 = ((int64_t)blockIdx.x * (GEO_B / 64) + wib) * GEO_CPW;
+        const int64_t c0 = (int64_t)blockIdx.x * 32 + wib * GEO_CPW;
         for (int j = 0; j < GEO_CPW; ++j) {
             const int64_t c = c0 + j;
             if (c >= cv.n) break;
             double P[RT_MAX_K][3];
             int tri[RT_MAX_K];
             int k;
-            if (geo_path(s, cv, c, S, X, P, tri, k)) app.push((uint64_t)(r * cv.n + c));
+            if (geo_path(s, cv, c, S, X, P, tri, k)) bits |= 1u << j;
         }
     }
-    app.flush(cells, cap, counter);
+    part[wib][lane] = bits << (GEO_CPW * wib);
+    __syncthreads();
+    if (wib == 0 && r < R)
+        mask[r * n_words + blockIdx.x] = part[0][lane] | part[1][lane] | part[2][lane] | part[3][lane];
+}
+
+// valid cells per receiver (one wave per receiver; entry R is 0)
+__global__ void k_cell_count(const uint32_t* mask, int64_t R, int64_t n_words, int64_t* cnt)
+{
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r > R) return;
+    int64_t n = 0;
+    if (r < R)
+        for (int64_t w = lane; w < n_words; w += 64) n += __popc(mask[r * n_words + w]);
+    for (int o = 32; o > 0; o >>= 1) n += __shfl_xor(n, o, 64);
+    if (lane == 0) cnt[r] = n;
+}
+
+// cells r * n_cand + c of the set bits, in (receiver, candidate) order, from
+// the receivers' exclusive offsets (one wave per receiver)
+__global__ void k_cell_emit(const uint32_t* mask, int64_t R, int64_t n_words, int64_t n_cand, const int64_t* rstart,
+                            uint64_t* cells)
+{
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
+    if (r >= R) return;
+    int64_t base = rstart[r];
+    for (int64_t w0 = 0; w0 < n_words; w0 += 64) {
+        const int64_t w = w0 + lane;
+        uint32_t m = w < n_words ? mask[r * n_words + w] : 0u;
+        const int cnt = __popc(m);
+        int incl = cnt;
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o, 64);
+            if (lane >= o) incl += t;
+        }
+        int64_t pos = base + (incl - cnt);
+        while (m) {
+            const int b = __ffs((int)m) - 1;
+            m &= m - 1u;
+            cells[pos++] = (uint64_t)(r * n_cand + w * 32 + b);
+        }
+        base += __shfl(incl, 63, 64);
+    }
 }
 
 // --------------------------------------------------------------------------
@@ -466,21 +540,6 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
         }
     }
     wave_count_add(segs, nseg);
-}
-
-// first record of each receiver (records sorted by cell = r * nc + c)
-__global__ void k_rx_start(const uint64_t* cells, int64_t n, int64_t nc, int64_t R, int64_t* rstart)
-{
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r > R) return;
-    const uint64_t key = (uint64_t)r * (uint64_t)nc;
-    int64_t lo = 0, hi = n;
-    while (lo < hi) {
-        int64_t mid = (lo + hi) >> 1;
-        if (cells[mid] < key) lo = mid + 1;
-        else hi = mid;
-    }
-    rstart[r] = lo;
 }
 
 // E_env[r] = sum of emitted paths of receiver r, in record order (FP64)
@@ -639,6 +698,7 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 #ifndef RT_RIS_WAVES_PER_SIMD
 #define RT_RIS_WAVES_PER_SIMD 4   // register cap that measured fastest on the lab room
 #endif
+
 template <bool BRUTE, bool KEEP, int STK, bool CNT>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
@@ -647,6 +707,8 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
 {
     // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
     __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
+    // the rays of a slot's legs wait in LDS while earlier legs are walked (fewer live registers)
+    __shared__ float legbuf[RIS_B / 64][RT_MAX_K + 1][7][64];
     static_assert(RT_STACK4 >= STK, "wave stack");
     WorkCount wc;
     unsigned pairs = 0;
@@ -684,7 +746,6 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
             bool ok = active && t.ok;
             if (CNT && active) ++pairs;
             // phase 1 (FP64): image method, leg rays, length, amplitude
-            float ro[RT_MAX_K + 1][3], rd[RT_MAX_K + 1][3], rt[RT_MAX_K + 1];
             float amp_r = 0.0f, amp_i = 0.0f;
             {
                 double P[RT_MAX_K][3];
@@ -724,13 +785,14 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
                         double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
                         Dr += L;
-                        ro[j][0] = (float)A[0];
-                        ro[j][1] = (float)A[1];
-                        ro[j][2] = (float)A[2];
-                        rd[j][0] = (float)(w0 / L);
-                        rd[j][1] = (float)(w1 / L);
-                        rd[j][2] = (float)(w2 / L);
-                        rt[j] = (float)(L - RT_EPS);
+                        float* lb = &legbuf[wib][j][0][lane];
+                        lb[0 * 64] = (float)A[0];
+                        lb[1 * 64] = (float)A[1];
+                        lb[2 * 64] = (float)A[2];
+                        lb[3 * 64] = (float)(w0 / L);
+                        lb[4 * 64] = (float)(w1 / L);
+                        lb[5 * 64] = (float)(w2 / L);
+                        lb[6 * 64] = (float)(L - RT_EPS);
                     }
                 }
                 if (ok) {
@@ -754,26 +816,27 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 }
             }
             // phase 2 (FP32): visibility of every leg, the wave walking the BVH together
+            // (one copy of the walk in the code: the leg loop is not unrolled)
             const float tmin = (float)RT_EPS;
-#pragma unroll
-            for (int j = 0; j <= RT_MAX_K; ++j) {
-                if (j <= k) {
-                    const int sa = j == 0 ? -1 : seq[j - 1];
-                    const int sb = j == k ? -1 : seq[j];
-                    if (ok) ++nseg;
-                    const bool searching = ok && rt[j] > tmin;
-                    bool blocked;
-                    if (BRUTE)
-                        blocked = searching && any_hit<true>(s, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
-                                                             rd[j][2], tmin, rt[j], sa, sb, nullptr, 0);
-                    else if (CNT)   // the counting build walks the binary tree: its work is what is counted
-                        blocked = any_hit_wave<true>(s, searching, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
-                                                     rd[j][2], tmin, rt[j], sa, sb, my_stack, &wc);
-                    else
-                        blocked = any_hit_wave4(s, searching, ro[j][0], ro[j][1], ro[j][2], rd[j][0], rd[j][1],
-                                                rd[j][2], tmin, rt[j], sa, sb, my_stack);
-                    ok = ok && !blocked;
-                }
+#pragma unroll 1
+            for (int j = 0; j <= k; ++j) {
+                const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
+                const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
+                const float* lb = &legbuf[wib][j][0][lane];
+                const float ox = lb[0 * 64], oy = lb[1 * 64], oz = lb[2 * 64];
+                const float dx = lb[3 * 64], dy = lb[4 * 64], dz = lb[5 * 64];
+                const float tmax = lb[6 * 64];
+                if (ok) ++nseg;
+                const bool searching = ok && tmax > tmin;
+                bool blocked;
+                if (BRUTE)
+                    blocked = searching && any_hit<true>(s, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, nullptr, 0);
+                else if (CNT)   // the counting build walks the binary tree: its work is what is counted
+                    blocked = any_hit_wave<true>(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, my_stack,
+                                                 &wc);
+                else
+                    blocked = any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, my_stack);
+                ok = ok && !blocked;
             }
             if (ok) {
                 acc_r += (double)amp_r;
@@ -845,7 +908,9 @@ struct Branch {
     int64_t nkeys = 0;
     Cands cd;
     PathSet ps;
-    int64_t cap = 0;
+    bool big_table = false;   // hash set sized for every prefix being distinct (after an overflow)
+    Scratch mask;             // geometric validity, R rows of n_words 32-bit words
+    int64_t n_words = 0;
 };
 
 // Phase A of the candidates: discovery rays, prefix keys into a hash set,
@@ -887,29 +952,30 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         hipLaunchKernelGGL(k_fill_neg, dim3(nblk(rows * K, 256)), dim3(256), 0, st, hits.as<int32_t>(), rows * K);
         HIP_CHECK(hipGetLastError());
     }
-    // hash set of at least 2 x (keys + 1) slots, at most 2^24; filled by discovery
+    // hash set filled by discovery: first 2^20 slots with probe runs of at most 256
+    // (overflow -> the caller repeats with the large set); the large set has at
+    // least 2 x (keys + 1) slots, at most 2^24, and unbounded probing
     int64_t want = 2 * rows * K + 2, cap = 1024;
-    while (cap < want && cap < ((int64_t)1 << 24)) cap <<= 1;
+    const int64_t limit = br.big_table ? ((int64_t)1 << 24) : ((int64_t)1 << 20);
+    while (cap < want && cap < limit) cap <<= 1;
+    const uint64_t max_probe = br.big_table ? (uint64_t)(cap - 1) : (uint64_t)255;
     Scratch table(c, sizeof(unsigned long long) * (size_t)cap, st);
     HIP_CHECK(hipMemsetAsync(table.p, 0, table.bytes, st));
     if (rows > 0 && K > 0 && sv.n_tri > 0) {
-        // launched rows sorted by direction (the list count is read back with the candidates)
-        Scratch list(c, sizeof(uint64_t) * (size_t)rows, st);
-        HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
-        hipLaunchKernelGGL(k_ray_list, dim3(nblk(rows, RL_B * RL_PT)), dim3(RL_B), 0, st, rows, hemi_n ? 1 : 0,
+        // launch order of the rows (rows outside the half-space are -1)
+        Scratch list(c, sizeof(int32_t) * (size_t)rows, st);
+        hipLaunchKernelGGL(k_ray_order, dim3(nblk(rows, RO_CH)), dim3(RO_B), 0, st, rows, hemi_n ? 1 : 0,
                            hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0, hemi_n ? hemi_n[2] : 0.0,
-                           list.as<uint64_t>(), rows, br.d_app);
+                           list.as<int32_t>());
         HIP_CHECK(hipGetLastError());
-        const int64_t n_list = hemi_n ? read_i64((const int64_t*)br.d_app, st) : rows;
-        sort_u64(c, list.as<uint64_t>(), n_list, 56, st);
+        const int64_t n_list = rows;
         SEL_BOOL(brute, BR,
                  SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(n_list, DISC_B)), dim3(DISC_B), 0,
-                                                 st, sv, src[0], src[1], src[2], list.as<uint64_t>(), n_list, rows,
+                                                 st, sv, src[0], src[1], src[2], list.as<int32_t>(), n_list, rows,
                                                  K, keep_hits ? hits.as<int32_t>() : nullptr, d_segs,
-                                                 table.as<unsigned long long>(),
-                                                 (uint64_t)(cap - 1), (int*)(br.d_app + 1))));
+                                                 table.as<unsigned long long>(), (uint64_t)(cap - 1), max_probe,
+                                                 (int*)(br.d_app + 1))));
         HIP_CHECK(hipGetLastError());
-        HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
     }
     if (keep_hits) {
         ch.n_hits_rows[br.which] = rows;
@@ -922,13 +988,17 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     HIP_CHECK(hipGetLastError());
 }
 
-// Size read-back after phase A: number of unique candidates (incl. order 0).
+// Size read-back after phase A: number of unique candidates (incl. order 0),
+// or -1 if the first hash set overflowed.
 static int64_t cand_count(const Branch& br, bool exhaustive)
 {
     if (exhaustive) return read_i64(br.d_cnt, br.st);
     int64_t hq[2];
     read_i64s((const int64_t*)br.d_app, hq, 2, br.st);
-    if (hq[1] & 1) throw inval_error("candidate hash set overflow");
+    if (hq[1] & 1) {
+        if (!br.big_table) return -1;   // repeat phase A with the large set
+        throw inval_error("candidate hash set overflow");
+    }
     return hq[0] + 1;
 }
 
@@ -955,43 +1025,46 @@ static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& 
                        cd.img.as<double>());
     HIP_CHECK(hipGetLastError());
     const int64_t R = a.R;
-    const int64_t cells = R * n_cand;
-    if (cells > ((int64_t)1 << 40)) throw inval_error("receivers x candidates too large for one call");
-    br.cap = cells < ((int64_t)1 << 24) ? cells : ((int64_t)1 << 24);
-    br.ps.cells = Scratch(c, sizeof(uint64_t) * (size_t)(br.cap > 0 ? br.cap : 1), st);
-    HIP_CHECK(hipMemsetAsync(br.d_app, 0, sizeof(unsigned long long), st));
-    if (cells > 0) {
-        if (nblk(R, 64) > 65535 || n_cand > 0x7fffffff) throw inval_error("receiver or candidate count too large");
-        hipLaunchKernelGGL(k_geo_cells, dim3(nblk(n_cand, GEO_B / 64 * GEO_CPW), nblk(R, 64)), dim3(GEO_B), 0, st,
-                           sv, cd.view(),
-                           br.src[0], br.src[1], br.src[2], a.rx_dev, R, br.ps.cells.as<uint64_t>(), br.cap, br.d_app);
+    if (R > 0 && n_cand > ((int64_t)1 << 40) / R) throw inval_error("receivers x candidates too large for one call");
+    if (nblk(R, 64) > 65535 || n_cand > 0x7fffffff) throw inval_error("receiver or candidate count too large");
+    const int64_t n_words = (n_cand + 31) / 32;
+    br.n_words = n_words;
+    br.mask = Scratch(c, sizeof(uint32_t) * (size_t)(R * n_words), st);
+    if (R * n_words > 0) {
+        hipLaunchKernelGGL(k_geo_mask, dim3((unsigned)n_words, nblk(R, 64)), dim3(GEO_B), 0, st, sv, cd.view(),
+                           br.src[0], br.src[1], br.src[2], a.rx_dev, R, n_words, br.mask.as<uint32_t>());
         HIP_CHECK(hipGetLastError());
     }
+    // receivers' offsets into the valid cells; entry R = total
+    Scratch cnt(c, sizeof(int64_t) * (size_t)(R + 1), st);
+    br.ps.rstart = Scratch(c, sizeof(int64_t) * (size_t)(R + 1), st);
+    hipLaunchKernelGGL(k_cell_count, dim3(nblk(R + 1, 4)), dim3(256), 0, st, br.mask.as<uint32_t>(), R, n_words,
+                       cnt.as<int64_t>());
+    HIP_CHECK(hipGetLastError());
+    scan_i64(c, cnt.as<int64_t>(), br.ps.rstart.as<int64_t>(), R + 1, st);
 }
 
-// sort the valid cells, legs and field of each path, receiver ranges
+// the valid cells in (receiver, candidate) order, legs and field of each path
 static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool field,
                          Branch& br, int64_t n, unsigned long long* d_segs)
 {
     hipStream_t st = br.st;
     PathSet& ps = br.ps;
     const int64_t R = a.R;
-    const int64_t cells = R * br.cd.n;
-    if (n > br.cap) throw inval_error("too many geometric paths for one call");
     ps.n = n;
-    int end_bit = 1;
-    while (end_bit < 64 && ((uint64_t)1 << end_bit) < (uint64_t)(cells > 1 ? cells : 2)) ++end_bit;
-    sort_u64(c, ps.cells.as<uint64_t>(), n, end_bit, st);
+    ps.cells = Scratch(c, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1), st);
+    if (n > 0) {
+        hipLaunchKernelGGL(k_cell_emit, dim3(nblk(R, 4)), dim3(256), 0, st, br.mask.as<uint32_t>(), R, br.n_words,
+                           br.cd.n, ps.rstart.as<int64_t>(), ps.cells.as<uint64_t>());
+        HIP_CHECK(hipGetLastError());
+    }
+    br.mask.release();
     ps.valid = Scratch(c, (size_t)(n > 0 ? n : 1), st);
     ps.recs = Scratch(c, sizeof(PathRec) * (size_t)(n > 0 ? n : 1), st);
     if (field) {
         ps.amp = Scratch(c, sizeof(float2) * (size_t)(n > 0 ? n : 1), st);
         ps.len = Scratch(c, sizeof(double) * (size_t)(n > 0 ? n : 1), st);
     }
-    ps.rstart = Scratch(c, sizeof(int64_t) * (size_t)(R + 1), st);
-    hipLaunchKernelGGL(k_rx_start, dim3(nblk(R + 1, 256)), dim3(256), 0, st, ps.cells.as<uint64_t>(), n, br.cd.n, R,
-                       ps.rstart.as<int64_t>());
-    HIP_CHECK(hipGetLastError());
     if (n == 0) return;
     CandView cv = br.cd.view();
     const double* src = br.src;
@@ -1047,7 +1120,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
 
     // counters: [0] discovery segments, [1] leg segments, [2..4] Tx count / append / hash overflow,
     // [5..7] centre count / append / hash overflow, [8..12] work of the counting build,
-    // [13] valid environment paths
+    // [13] valid environment paths, [15] discovery segments of a repeated phase A (not reported)
     Scratch ctr(c, 128, st);
     HIP_CHECK(hipMemsetAsync(ctr.p, 0, 128, st));
     unsigned long long* d_ctr = ctr.as<unsigned long long>();
@@ -1082,8 +1155,23 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 1-3: candidates
     cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
     if (two) cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
-    const int64_t n_tx = cand_count(bt, exhaustive);
-    const int64_t n_u0 = two ? cand_count(bu, exhaustive) : 0;
+    int64_t n_tx = cand_count(bt, exhaustive);
+    int64_t n_u0 = two ? cand_count(bu, exhaustive) : 0;
+    // an overflow of the first hash set: repeat phase A with the large set (the
+    // discovery segments were counted by the first pass)
+    unsigned long long* d_dummy = d_ctr + 15;
+    if (n_tx < 0) {
+        bt.big_table = true;
+        HIP_CHECK(hipMemsetAsync(bt.d_app, 0, 2 * sizeof(unsigned long long), bt.st));
+        cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_dummy);
+        n_tx = cand_count(bt, exhaustive);
+    }
+    if (n_u0 < 0) {
+        bu.big_table = true;
+        HIP_CHECK(hipMemsetAsync(bu.d_app, 0, 2 * sizeof(unsigned long long), bu.st));
+        cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_dummy);
+        n_u0 = cand_count(bu, exhaustive);
+    }
     cand_phase_b(c, a, exhaustive, bt, n_tx);
     if (two) cand_phase_b(c, a, exhaustive, bu, n_u0);
     out.n_cand_tx = n_tx;
@@ -1092,8 +1180,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 4: geometry of every (receiver, candidate)
     geo_launch(c, sv, a, bt, n_tx);
     if (two) geo_launch(c, sv, a, bu, n_u0);
-    const int64_t g_tx = R * n_tx > 0 ? read_i64((const int64_t*)bt.d_app, st) : 0;
-    const int64_t g_u = two && R * n_u0 > 0 ? read_i64((const int64_t*)bu.d_app, bu.st) : 0;
+    const int64_t g_tx = read_i64(bt.ps.rstart.as<int64_t>() + R, st);
+    const int64_t g_u = two ? read_i64(bu.ps.rstart.as<int64_t>() + R, bu.st) : 0;
     // 5-6: legs and fields
     paths_launch(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
     if (two) paths_launch(c, sv, stk, a, brute, false, bu, g_u, d_legs);
