@@ -232,10 +232,11 @@ def run_serving_bench(ctx, n_queries=300, n_slots=4, load=0.7):
             "deployments": len(deps), "scene_triangles": sorted(int(s.n_tri) for s in scenes.values())}
 
 
-def cpu_baseline(n_rx_side=8, n_rays=1_000_000):
+def cpu_baseline(n_rx_side=40, n_rays=1_000_000):
     """The oracle on a bounded sample of the lab-room workload: full discovery
     (1e6 rays per source, order 3) and image-method paths, legs and fields
-    for an 8 x 8 receiver subsample of the same grid."""
+    for a 40 x 40 receiver subsample of the same grid (about 15 s on 16
+    host threads)."""
     from oracle import oracle as O
     from paper_2402_13034_amd import synth
     prob = synth.lab_room()
