@@ -466,6 +466,277 @@ __device__ bool any_hit_wave4(const SceneView& s, bool searching, float ox, floa
     return hit;
 }
 
+// --------------------------------------------------------------------------
+// Tube walk for a wave of nearly parallel segments (the legs of one slot for
+// 64 RIS elements).  Every lane's tested segment o + t d, t in [tmin, tmax],
+// lies within r of the central segment cA -> cB (the distance between points
+// of equal parameter is at most the larger end-point distance), so a
+// triangle the lane's own test can accept has its (inflated) leaf box within
+// r of the central segment.  The wave walks the 4-wide nodes breadth first
+// with only the central segment against boxes grown by r (+ a margin for the
+// FP32 representation of the lanes' rays, the triangle test and the slab
+// test), one entry per lane, collecting candidate leaves; then every lane
+// tests its own ray against the candidates with the exact triangle test.
+// The result per lane is the any-hit answer of the lane's ray (a superset of
+// the triangles it could hit is tested with the same test).  If the frontier
+// or the candidate list outgrows its LDS space, the wave falls back to the
+// 4-wide wave walk.
+// --------------------------------------------------------------------------
+#define RT_TUBE_FRONT 128
+#define RT_TUBE_CAND 128
+
+// Maximum over the 64 lanes of a wave (every lane active), with DPP lane
+// moves: butterflies inside rows of 16, then the row broadcasts of the
+// 64-wide wave; lane 63 ends with the maximum.
+__device__ __forceinline__ float wave_max(float v)
+{
+    int x = __float_as_int(v);
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0xB1, 0xF, 0xF, false))));
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x4E, 0xF, 0xF, false))));
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x124, 0xF, 0xF, false))));
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x128, 0xF, 0xF, false))));
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x142, 0xA, 0xF, false))));
+    x = __float_as_int(fmaxf(__int_as_float(x), __int_as_float(__builtin_amdgcn_update_dpp(x, x, 0x143, 0xC, 0xF, false))));
+    return __int_as_float(__builtin_amdgcn_readlane(x, 63));
+}
+
+// front: 2 x RT_TUBE_FRONT ints, cand: RT_TUBE_CAND ints, wstack: RT_STACK4 ints (fallback); all per wave
+__device__ bool any_hit_tube(const SceneView& s, bool searching, float ox, float oy, float oz, float dx, float dy,
+                             float dz, float tmin, float tmax, int skip_a, int skip_b, int* front, int* cand,
+                             int* wstack)
+{
+    const unsigned long long act = __ballot(searching);
+    if (s.n_tri == 0 || act == 0ull) return false;
+    const int lane = threadIdx.x & 63;
+    // the lane's segment end points (FP64 from the FP32 ray: exact products)
+    const double ax = (double)ox + (double)tmin * (double)dx, ay = (double)oy + (double)tmin * (double)dy,
+                 az = (double)oz + (double)tmin * (double)dz;
+    const double bx = (double)ox + (double)tmax * (double)dx, by = (double)oy + (double)tmax * (double)dy,
+                 bz = (double)oz + (double)tmax * (double)dz;
+    // central segment: the end points of the first searching lane
+    const int lead = __ffsll((long long)act) - 1;
+    const float fax = (float)ax, fay = (float)ay, faz = (float)az, fbx = (float)bx, fby = (float)by, fbz = (float)bz;
+    const float cax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fax), lead));
+    const float cay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fay), lead));
+    const float caz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(faz), lead));
+    const float cbx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fbx), lead));
+    const float cby = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fby), lead));
+    const float cbz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fbz), lead));
+    const double da = sqrt((ax - cax) * (ax - cax) + (ay - cay) * (ay - cay) + (az - caz) * (az - caz));
+    const double db = sqrt((bx - cbx) * (bx - cbx) + (by - cby) * (by - cby) + (bz - cbz) * (bz - cbz));
+    const float scale = fmaxf(fmaxf(fabsf(cax), fmaxf(fabsf(cay), fabsf(caz))),
+                              fmaxf(fabsf(cbx), fmaxf(fabsf(cby), fabsf(cbz)))) + fabsf(tmax);
+    // radius (rounded up) plus the margin, as one maximum over the searching lanes
+    float r = wave_max(searching ? (float)fmax(da, db) * 1.0001f + 1e-4f + 4e-6f * scale : 0.0f);
+    if (!(r < 1e30f)) return any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, skip_a, skip_b, wstack);
+    // central ray cA + u (cB - cA), u in [-1e-3, 1 + 1e-3]
+    const RayBox crb = make_raybox(cax, cay, caz, cbx - cax, cby - cay, cbz - caz);
+    int nc = 0;
+    if (s.root < 0) {
+        if (lane == 0) cand[0] = ~s.root;
+        nc = 1;
+    } else {
+        int nf = 1, cur = 0;
+        if (lane == 0) front[0] = s.root;
+        while (nf > 0) {
+            int nn = 0;
+            int* fin = front + cur * RT_TUBE_FRONT;
+            int* fout = front + (cur ^ 1) * RT_TUBE_FRONT;
+            for (int base = 0; base < nf; base += 16) {
+                const int slot = base + (lane >> 2), e = lane & 3;
+                const bool valid = slot < nf;
+                const int n = valid ? fin[slot] : 0;
+                const float* q = (const float*)(s.node4 + 8 * n);
+                const int ref = __float_as_int(q[24 + e]);
+                const bool hit = valid && ref != RT_NODE4_EMPTY &&
+                                 slab1(q[e] - r, q[4 + e] + r, q[8 + e] - r, q[12 + e] + r, q[16 + e] - r,
+                                       q[20 + e] + r, crb, -1e-3f, 1.001f);
+                const unsigned long long lt = (1ull << lane) - 1ull;
+                const unsigned long long mi = __ballot(hit && ref >= 0);
+                const unsigned long long ml = __ballot(hit && ref < 0);
+                if (hit && ref >= 0) {
+                    const int idx = nn + __popcll(mi & lt);
+                    if (idx < RT_TUBE_FRONT) fout[idx] = ref;
+                }
+                if (hit && ref < 0) {
+                    const int idx = nc + __popcll(ml & lt);
+                    if (idx < RT_TUBE_CAND) cand[idx] = ~ref;
+                }
+                nn += __popcll(mi);
+                nc += __popcll(ml);
+            }
+            if (nn > RT_TUBE_FRONT || nc > RT_TUBE_CAND)
+                return any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, skip_a, skip_b, wstack);
+            nf = nn;
+            cur ^= 1;
+        }
+    }
+    bool hit = false;
+    for (int i = 0; i < nc; ++i) {
+        const int slot = __builtin_amdgcn_readfirstlane(cand[i]);
+        const float4 a = s.tri4[3 * slot], b = s.tri4[3 * slot + 1], c = s.tri4[3 * slot + 2];
+        const int sf = __float_as_int(b.w);
+        if (sf == skip_a || sf == skip_b) continue;
+        if (searching) {
+            float t;
+            if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) {
+                hit = true;
+                searching = false;
+            }
+        }
+        if (__ballot(searching) == 0ull) break;
+    }
+    return hit;
+}
+
+// All legs of one slot at once: the same tube walk with one tube per leg,
+// frontier and candidate entries tagged with their leg (2 bits), so the
+// wave walks the levels of the tree once for up to RT_MAX_K + 1 legs.
+// lb: the wave's leg rays in LDS, [leg][7][64] = ox, oy, oz, dx, dy, dz, tmax;
+// tube: 8 floats per leg in LDS; front/cand/wstack as for any_hit_tube;
+// seq: the slot's surfaces (wave-uniform), k its order; ok: the lane's path
+// is still valid.  Returns the lane's bit set of blocked legs.
+__device__ unsigned legs_blocked_tube(const SceneView& s, bool ok, int k, const int* seq, const float* lb,
+                                      float* tube, int* front, int* cand, int* wstack)
+{
+    static_assert(RT_MAX_K + 1 <= 4, "two bits of leg index");
+    const int lane = threadIdx.x & 63;
+    const float tmin = (float)RT_EPS;
+    unsigned blocked = 0;
+    if (s.n_tri == 0 || __ballot(ok) == 0ull) return 0;
+    unsigned live = 0;   // legs with a searching lane (uniform)
+#pragma unroll
+    for (int j = 0; j <= RT_MAX_K; ++j) {
+        if (j > k) break;
+        const float* r0 = lb + j * 7 * 64 + lane;
+        const float ox = r0[0], oy = r0[64], oz = r0[128], dx = r0[192], dy = r0[256], dz = r0[320], tmax = r0[384];
+        const bool searching = ok && tmax > tmin;
+        const unsigned long long act = __ballot(searching);
+        if (act == 0ull) continue;
+        live |= 1u << j;
+        const double ax = (double)ox + (double)tmin * (double)dx, ay = (double)oy + (double)tmin * (double)dy,
+                     az = (double)oz + (double)tmin * (double)dz;
+        const double bx = (double)ox + (double)tmax * (double)dx, by = (double)oy + (double)tmax * (double)dy,
+                     bz = (double)oz + (double)tmax * (double)dz;
+        const int lead = __ffsll((long long)act) - 1;
+        const float cax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)ax), lead));
+        const float cay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)ay), lead));
+        const float caz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)az), lead));
+        const float cbx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)bx), lead));
+        const float cby = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)by), lead));
+        const float cbz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)bz), lead));
+        const double da = sqrt((ax - cax) * (ax - cax) + (ay - cay) * (ay - cay) + (az - caz) * (az - caz));
+        const double db = sqrt((bx - cbx) * (bx - cbx) + (by - cby) * (by - cby) + (bz - cbz) * (bz - cbz));
+        const float scale = fmaxf(fmaxf(fabsf(cax), fmaxf(fabsf(cay), fabsf(caz))),
+                                  fmaxf(fabsf(cbx), fmaxf(fabsf(cby), fabsf(cbz)))) + fabsf(tmax);
+        const float r = wave_max(searching ? (float)fmax(da, db) * 1.0001f + 1e-4f + 4e-6f * scale : 0.0f);
+        const RayBox crb = make_raybox(cax, cay, caz, cbx - cax, cby - cay, cbz - caz);
+        if (!(r < 1e30f)) live |= 16u;   // not representable: exact walk below
+        if (lane == 0) {
+            float* t = tube + 8 * j;
+            t[0] = crb.ix;
+            t[1] = crb.iy;
+            t[2] = crb.iz;
+            t[3] = crb.oix;
+            t[4] = crb.oiy;
+            t[5] = crb.oiz;
+            t[6] = r;
+        }
+    }
+    if (live == 0) return 0;
+    int nc = 0;
+    bool overflow = (live & 16u) != 0;
+    if (!overflow) {
+        if (s.root < 0) {
+            for (int j = 0; j <= k; ++j)
+                if (live & (1u << j)) {
+                    if (lane == 0) cand[nc] = (~s.root) | (j << 30);
+                    ++nc;
+                }
+        } else {
+            int nf = 0, cur = 0;
+            for (int j = 0; j <= k; ++j)
+                if (live & (1u << j)) {
+                    if (lane == 0) front[nf] = s.root | (j << 30);
+                    ++nf;
+                }
+            while (nf > 0) {
+                int nn = 0;
+                int* fin = front + cur * RT_TUBE_FRONT;
+                int* fout = front + (cur ^ 1) * RT_TUBE_FRONT;
+                for (int base = 0; base < nf; base += 16) {
+                    const int slot = base + (lane >> 2), e = lane & 3;
+                    const bool valid = slot < nf;
+                    const unsigned v = valid ? (unsigned)fin[slot] : 0u;
+                    const int n = (int)(v & 0x3fffffffu), j = (int)(v >> 30);
+                    const float* t = tube + 8 * j;
+                    RayBox crb;
+                    crb.ix = t[0];
+                    crb.iy = t[1];
+                    crb.iz = t[2];
+                    crb.oix = t[3];
+                    crb.oiy = t[4];
+                    crb.oiz = t[5];
+                    const float r = t[6];
+                    const float* q = (const float*)(s.node4 + 8 * n);
+                    const int ref = __float_as_int(q[24 + e]);
+                    const bool hit = valid && ref != RT_NODE4_EMPTY &&
+                                     slab1(q[e] - r, q[4 + e] + r, q[8 + e] - r, q[12 + e] + r, q[16 + e] - r,
+                                           q[20 + e] + r, crb, -1e-3f, 1.001f);
+                    const unsigned long long lt = (1ull << lane) - 1ull;
+                    const unsigned long long mi = __ballot(hit && ref >= 0);
+                    const unsigned long long ml = __ballot(hit && ref < 0);
+                    if (hit && ref >= 0) {
+                        const int idx = nn + __popcll(mi & lt);
+                        if (idx < RT_TUBE_FRONT) fout[idx] = ref | (j << 30);
+                    }
+                    if (hit && ref < 0) {
+                        const int idx = nc + __popcll(ml & lt);
+                        if (idx < RT_TUBE_CAND) cand[idx] = (~ref) | (j << 30);
+                    }
+                    nn += __popcll(mi);
+                    nc += __popcll(ml);
+                }
+                if (nn > RT_TUBE_FRONT || nc > RT_TUBE_CAND) {
+                    overflow = true;
+                    break;
+                }
+                nf = nn;
+                cur ^= 1;
+            }
+        }
+    }
+    if (overflow) {   // exact walk of every leg
+        for (int j = 0; j <= k; ++j) {
+            const float* r0 = lb + j * 7 * 64 + lane;
+            const float tmax = r0[384];
+            const bool searching = ok && tmax > tmin;
+            const int sa = j == 0 ? -1 : seq[j - 1];
+            const int sb = j == k ? -1 : seq[j];
+            if (any_hit_wave4(s, searching, r0[0], r0[64], r0[128], r0[192], r0[256], r0[320], tmin, tmax, sa, sb,
+                              wstack))
+                blocked |= 1u << j;
+        }
+        return blocked;
+    }
+    for (int i = 0; i < nc; ++i) {
+        const unsigned v = (unsigned)__builtin_amdgcn_readfirstlane(cand[i]);
+        const int slot = (int)(v & 0x3fffffffu), j = (int)(v >> 30);
+        const float4 a = s.tri4[3 * slot], b = s.tri4[3 * slot + 1], c = s.tri4[3 * slot + 2];
+        const int sf = __float_as_int(b.w);
+        const int sa = j == 0 ? -1 : seq[j - 1];
+        const int sb = j == k ? -1 : seq[j];
+        if (sf == sa || sf == sb) continue;
+        const float* r0 = lb + j * 7 * 64 + lane;
+        const float tmax = r0[384];
+        if (ok && tmax > tmin && !(blocked & (1u << j))) {
+            float t;
+            if (mt_hit(r0[0], r0[64], r0[128], r0[192], r0[256], r0[320], a, b, c, tmin, tmax, t)) blocked |= 1u << j;
+        }
+    }
+    return blocked;
+}
+
 // Leg test of leg_blocked for a whole wave (`need` masks lanes out).
 template <bool CNT>
 __device__ bool leg_blocked_wave(const SceneView& s, bool need, const double* A, const double* B, int sa, int sb,

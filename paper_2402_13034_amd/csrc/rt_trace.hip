@@ -709,6 +709,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
     __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
     // the rays of a slot's legs wait in LDS while earlier legs are walked (fewer live registers)
     __shared__ float legbuf[RIS_B / 64][RT_MAX_K + 1][7][64];
+    // per-wave frontier and candidate lists of the tube walk
+    __shared__ int tfront[RIS_B / 64][2 * RT_TUBE_FRONT];
+    __shared__ int tcand[RIS_B / 64][RT_TUBE_CAND];
+    __shared__ float ttube[RIS_B / 64][8 * (RT_MAX_K + 1)];
     static_assert(RT_STACK4 >= STK, "wave stack");
     WorkCount wc;
     unsigned pairs = 0;
@@ -816,27 +820,33 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 }
             }
             // phase 2 (FP32): visibility of every leg, the wave walking the BVH together
-            // (one copy of the walk in the code: the leg loop is not unrolled)
             const float tmin = (float)RT_EPS;
+            if (BRUTE || CNT) {
 #pragma unroll 1
-            for (int j = 0; j <= k; ++j) {
-                const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
-                const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
-                const float* lb = &legbuf[wib][j][0][lane];
-                const float ox = lb[0 * 64], oy = lb[1 * 64], oz = lb[2 * 64];
-                const float dx = lb[3 * 64], dy = lb[4 * 64], dz = lb[5 * 64];
-                const float tmax = lb[6 * 64];
-                if (ok) ++nseg;
-                const bool searching = ok && tmax > tmin;
-                bool blocked;
-                if (BRUTE)
-                    blocked = searching && any_hit<true>(s, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, nullptr, 0);
-                else if (CNT)   // the counting build walks the binary tree: its work is what is counted
-                    blocked = any_hit_wave<true>(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, my_stack,
-                                                 &wc);
-                else
-                    blocked = any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, my_stack);
-                ok = ok && !blocked;
+                for (int j = 0; j <= k; ++j) {
+                    const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
+                    const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
+                    const float* lb = &legbuf[wib][j][0][lane];
+                    const float ox = lb[0 * 64], oy = lb[1 * 64], oz = lb[2 * 64];
+                    const float dx = lb[3 * 64], dy = lb[4 * 64], dz = lb[5 * 64];
+                    const float tmax = lb[6 * 64];
+                    if (ok) ++nseg;
+                    const bool searching = ok && tmax > tmin;
+                    bool blocked;
+                    if (BRUTE)
+                        blocked = searching &&
+                                  any_hit<true>(s, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb, nullptr, 0);
+                    else   // the counting build walks the binary tree: its work is what is counted
+                        blocked = any_hit_wave<true>(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, sa, sb,
+                                                     my_stack, &wc);
+                    ok = ok && !blocked;
+                }
+            } else {
+                // every leg at once; legs are counted as the sequential test would (up to the first blocked one)
+                const unsigned bl = legs_blocked_tube(s, ok, k, seq, &legbuf[wib][0][0][0], ttube[wib], tfront[wib],
+                                                      tcand[wib], my_stack);
+                if (ok) nseg += bl ? (unsigned)(__ffs((int)bl)) : (unsigned)(k + 1);
+                ok = ok && bl == 0u;
             }
             if (ok) {
                 acc_r += (double)amp_r;
