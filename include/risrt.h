@@ -115,6 +115,8 @@ typedef struct {
     int64_t ris_work[5];         /* with RT_FLAG_COUNT_WORK: BVH node visits, triangle tests,
                                     FP64 containment tests, (slot, element) pairs, legs of
                                     the per-element kernel */
+    int64_t leg_walk_fallbacks;  /* slots whose grouped leg walk outgrew its on-chip lists and
+                                    were walked leg by leg (same results, diagnostic only) */
 } rt_stats;
 
 /* Environment path record (RT_FLAG_KEEP_PATHS): Tx -> surfaces seq[0..k) ->

@@ -293,6 +293,22 @@ def pattern(kind: int, param: float, cos_t: np.ndarray, lam: float) -> np.ndarra
     raise ValueError(kind)
 
 
+def pattern_on(kind: int, cos_t: np.ndarray) -> np.ndarray:
+    """Whether F(theta) is nonzero, decided on the FP64 cosine itself rather
+    than on the value of F (which can underflow): cos^p is zero exactly for
+    cos <= 0, the monopole of eq. (12) exactly at theta = 0 and pi, the
+    isotropic pattern never.  A path is emitted when every pattern on it is
+    nonzero (reading 15: paths with a zero pattern factor are not emitted)."""
+    c = np.clip(np.asarray(cos_t, np.float64), -1.0, 1.0)
+    if kind == PAT_ISO:
+        return np.ones(c.shape, bool)
+    if kind == PAT_COSPOW:
+        return c > 0.0
+    if kind == PAT_MONOPOLE:
+        return 1.0 - c * c > 0.0
+    raise ValueError(kind)
+
+
 def _cos_between(v: np.ndarray, axis: np.ndarray) -> np.ndarray:
     a = np.asarray(axis, np.float64)
     return (v @ a) / (np.linalg.norm(v, axis=-1) * np.linalg.norm(a))
@@ -346,12 +362,14 @@ def env_amplitudes(prob, rx_idx, tris, pts):
     S = np.broadcast_to(prob.tx_pos, (n, 3))
     X = prob.rx_pos[rx_idx]
     D, first, last = _chain(S, pts, k, X)
-    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, _cos_between(first, prob.tx_ant.axis), lam)
-    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, _cos_between(last, prob.rx_ant.axis), lam)
+    ct = _cos_between(first, prob.tx_ant.axis)
+    cr = _cos_between(last, prob.rx_ant.axis)
+    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, ct, lam)
+    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, cr, lam)
     At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
     Sr = np.sqrt(prob.rx_ant.gain * Fr)
     a = At * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * D) * np.exp(1j * _phase(D, lam))
-    emitted = (Ft > 0.0) & (Fr > 0.0)
+    emitted = pattern_on(prob.tx_ant.pattern, ct) & pattern_on(prob.rx_ant.pattern, cr)
     return a, D, emitted
 
 
@@ -367,16 +385,21 @@ def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
     Dr, first, last = _chain(m, pts, k, X)
     vt = m - prob.tx_pos[None, :]
     dt = np.linalg.norm(vt, axis=1)
-    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, _cos_between(vt, prob.tx_ant.axis), lam)
-    Fin = pattern(PAT_COSPOW, ris.q, _cos_between(-vt, ris.normal), lam)
-    Fout = pattern(PAT_COSPOW, ris.q, _cos_between(first, ris.normal), lam)
-    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, _cos_between(last, prob.rx_ant.axis), lam)
+    ct = _cos_between(vt, prob.tx_ant.axis)
+    ci = _cos_between(-vt, ris.normal)
+    co = _cos_between(first, ris.normal)
+    cr = _cos_between(last, prob.rx_ant.axis)
+    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, ct, lam)
+    Fin = pattern(PAT_COSPOW, ris.q, ci, lam)
+    Fout = pattern(PAT_COSPOW, ris.q, co, lam)
+    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, cr, lam)
     At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
     elem = np.sqrt(ris.gain * Fin * Fout * ris.dy * ris.dz / (4.0 * math.pi))
     Sr = np.sqrt(prob.rx_ant.gain * Fr)
     a = (At * elem / dt * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * Dr)
          * np.exp(1j * _phase(dt + Dr, lam)))
-    emitted = (Ft > 0.0) & (Fin > 0.0) & (Fout > 0.0) & (Fr > 0.0)
+    emitted = (pattern_on(prob.tx_ant.pattern, ct) & pattern_on(PAT_COSPOW, ci) & pattern_on(PAT_COSPOW, co)
+               & pattern_on(prob.rx_ant.pattern, cr))
     return a, dt + Dr, emitted
 
 

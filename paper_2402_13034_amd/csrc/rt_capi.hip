@@ -399,6 +399,7 @@ static void fill_antenna(Antenna& a, const double* axis, double gain, int32_t pa
 {
     double n = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
     for (int k = 0; k < 3; ++k) a.axis[k] = axis[k] / n;
+    a.axis_norm = sqrt(a.axis[0] * a.axis[0] + a.axis[1] * a.axis[1] + a.axis[2] * a.axis[2]);
     a.gain = gain;
     a.pattern = pattern;
     a.param = param;
@@ -466,6 +467,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
             stats->n_ris_slots = out.n_slots;
             for (int k = 0; k < 8; ++k) stats->ms_stage[k] = out.ms[k];
             for (int k = 0; k < 5; ++k) stats->ris_work[k] = out.work[k];
+            stats->leg_walk_fallbacks = out.leg_walk_fallbacks;
         }
         *channel = insert(ctx, o);
         return RT_OK;

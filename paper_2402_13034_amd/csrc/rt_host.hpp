@@ -184,6 +184,7 @@ struct TraceOut {
     int64_t n_cand_tx = 0, n_cand_u = 0, n_env = 0, n_u = 0, n_slots = 0;
     float ms[8] = {0};
     int64_t work[5] = {0, 0, 0, 0, 0};
+    int64_t leg_walk_fallbacks = 0;
 };
 void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st);
 

@@ -57,6 +57,7 @@ struct SceneView {
 
 struct Antenna {
     double axis[3];
+    double axis_norm;      // |axis| in FP64
     double gain;
     int32_t pattern;
     double param;
@@ -78,6 +79,7 @@ struct RisView {
     const double* elem;    // 3 per element
     double centre[3];
     double normal[3];      // unit
+    double normal_norm;    // |normal| in FP64
     double dy, dz, gain, q;
 };
 
@@ -500,104 +502,20 @@ __device__ __forceinline__ float wave_max(float v)
     return __int_as_float(__builtin_amdgcn_readlane(x, 63));
 }
 
-// front: 2 x RT_TUBE_FRONT ints, cand: RT_TUBE_CAND ints, wstack: RT_STACK4 ints (fallback); all per wave
-__device__ bool any_hit_tube(const SceneView& s, bool searching, float ox, float oy, float oz, float dx, float dy,
-                             float dz, float tmin, float tmax, int skip_a, int skip_b, int* front, int* cand,
-                             int* wstack)
-{
-    const unsigned long long act = __ballot(searching);
-    if (s.n_tri == 0 || act == 0ull) return false;
-    const int lane = threadIdx.x & 63;
-    // the lane's segment end points (FP64 from the FP32 ray: exact products)
-    const double ax = (double)ox + (double)tmin * (double)dx, ay = (double)oy + (double)tmin * (double)dy,
-                 az = (double)oz + (double)tmin * (double)dz;
-    const double bx = (double)ox + (double)tmax * (double)dx, by = (double)oy + (double)tmax * (double)dy,
-                 bz = (double)oz + (double)tmax * (double)dz;
-    // central segment: the end points of the first searching lane
-    const int lead = __ffsll((long long)act) - 1;
-    const float fax = (float)ax, fay = (float)ay, faz = (float)az, fbx = (float)bx, fby = (float)by, fbz = (float)bz;
-    const float cax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fax), lead));
-    const float cay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fay), lead));
-    const float caz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(faz), lead));
-    const float cbx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fbx), lead));
-    const float cby = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fby), lead));
-    const float cbz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(fbz), lead));
-    const double da = sqrt((ax - cax) * (ax - cax) + (ay - cay) * (ay - cay) + (az - caz) * (az - caz));
-    const double db = sqrt((bx - cbx) * (bx - cbx) + (by - cby) * (by - cby) + (bz - cbz) * (bz - cbz));
-    const float scale = fmaxf(fmaxf(fabsf(cax), fmaxf(fabsf(cay), fabsf(caz))),
-                              fmaxf(fabsf(cbx), fmaxf(fabsf(cby), fabsf(cbz)))) + fabsf(tmax);
-    // radius (rounded up) plus the margin, as one maximum over the searching lanes
-    float r = wave_max(searching ? (float)fmax(da, db) * 1.0001f + 1e-4f + 4e-6f * scale : 0.0f);
-    if (!(r < 1e30f)) return any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, skip_a, skip_b, wstack);
-    // central ray cA + u (cB - cA), u in [-1e-3, 1 + 1e-3]
-    const RayBox crb = make_raybox(cax, cay, caz, cbx - cax, cby - cay, cbz - caz);
-    int nc = 0;
-    if (s.root < 0) {
-        if (lane == 0) cand[0] = ~s.root;
-        nc = 1;
-    } else {
-        int nf = 1, cur = 0;
-        if (lane == 0) front[0] = s.root;
-        while (nf > 0) {
-            int nn = 0;
-            int* fin = front + cur * RT_TUBE_FRONT;
-            int* fout = front + (cur ^ 1) * RT_TUBE_FRONT;
-            for (int base = 0; base < nf; base += 16) {
-                const int slot = base + (lane >> 2), e = lane & 3;
-                const bool valid = slot < nf;
-                const int n = valid ? fin[slot] : 0;
-                const float* q = (const float*)(s.node4 + 8 * n);
-                const int ref = __float_as_int(q[24 + e]);
-                const bool hit = valid && ref != RT_NODE4_EMPTY &&
-                                 slab1(q[e] - r, q[4 + e] + r, q[8 + e] - r, q[12 + e] + r, q[16 + e] - r,
-                                       q[20 + e] + r, crb, -1e-3f, 1.001f);
-                const unsigned long long lt = (1ull << lane) - 1ull;
-                const unsigned long long mi = __ballot(hit && ref >= 0);
-                const unsigned long long ml = __ballot(hit && ref < 0);
-                if (hit && ref >= 0) {
-                    const int idx = nn + __popcll(mi & lt);
-                    if (idx < RT_TUBE_FRONT) fout[idx] = ref;
-                }
-                if (hit && ref < 0) {
-                    const int idx = nc + __popcll(ml & lt);
-                    if (idx < RT_TUBE_CAND) cand[idx] = ~ref;
-                }
-                nn += __popcll(mi);
-                nc += __popcll(ml);
-            }
-            if (nn > RT_TUBE_FRONT || nc > RT_TUBE_CAND)
-                return any_hit_wave4(s, searching, ox, oy, oz, dx, dy, dz, tmin, tmax, skip_a, skip_b, wstack);
-            nf = nn;
-            cur ^= 1;
-        }
-    }
-    bool hit = false;
-    for (int i = 0; i < nc; ++i) {
-        const int slot = __builtin_amdgcn_readfirstlane(cand[i]);
-        const float4 a = s.tri4[3 * slot], b = s.tri4[3 * slot + 1], c = s.tri4[3 * slot + 2];
-        const int sf = __float_as_int(b.w);
-        if (sf == skip_a || sf == skip_b) continue;
-        if (searching) {
-            float t;
-            if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, tmax, t)) {
-                hit = true;
-                searching = false;
-            }
-        }
-        if (__ballot(searching) == 0ull) break;
-    }
-    return hit;
-}
-
-// All legs of one slot at once: the same tube walk with one tube per leg,
-// frontier and candidate entries tagged with their leg (2 bits), so the
-// wave walks the levels of the tree once for up to RT_MAX_K + 1 legs.
+// All legs of one slot at once: one tube per leg, frontier and candidate
+// entries tagged with their leg (2 bits), so the wave walks the levels of
+// the tree once for up to RT_MAX_K + 1 legs.
 // lb: the wave's leg rays in LDS, [leg][7][64] = ox, oy, oz, dx, dy, dz, tmax;
-// tube: 8 floats per leg in LDS; front/cand/wstack as for any_hit_tube;
+// tube: 8 floats per leg in LDS; front: 2 x RT_TUBE_FRONT ints, cand:
+// RT_TUBE_CAND ints, wstack: RT_STACK4 ints (fallback), all per wave;
 // seq: the slot's surfaces (wave-uniform), k its order; ok: the lane's path
-// is still valid.  Returns the lane's bit set of blocked legs.
-__device__ unsigned legs_blocked_tube(const SceneView& s, bool ok, int k, const int* seq, const float* lb,
-                                      float* tube, int* front, int* cand, int* wstack)
+// is still valid.  Returns the lane's bit set of blocked legs, plus
+// RT_TUBE_FELL_BACK if the lists overflowed and the legs were walked one by
+// one.
+#define RT_TUBE_FELL_BACK 256u
+__device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool ok, int k, const int* seq,
+                                                      const float* lb, float* tube, int* front, int* cand,
+                                                      int* wstack)
 {
     static_assert(RT_MAX_K + 1 <= 4, "two bits of leg index");
     const int lane = threadIdx.x & 63;
@@ -707,6 +625,7 @@ __device__ unsigned legs_blocked_tube(const SceneView& s, bool ok, int k, const 
         }
     }
     if (overflow) {   // exact walk of every leg
+        blocked = RT_TUBE_FELL_BACK;
         for (int j = 0; j <= k; ++j) {
             const float* r0 = lb + j * 7 * 64 + lane;
             const float tmax = r0[384];
@@ -905,38 +824,54 @@ __device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k
 }
 
 // --------------------------------------------------------------------------
-// Patterns (power), FP32
+// Patterns.  Whether a pattern factor is zero is decided on the FP64 cosine
+// (cos^p: cos <= 0; monopole: sin(theta) = 0; isotropic: never), so that the
+// decision does not depend on an underflow of the factor.  The amplitude
+// factor sqrt(F) is evaluated directly in FP32: cos^(p/2), and the
+// monopole's |cos(kh cos) - cos(kh)| / sin(theta) with sin^2 from FP64.
 // --------------------------------------------------------------------------
-__device__ __forceinline__ float pattern_f(int kind, float param, float c)
-{
-    c = fminf(1.0f, fmaxf(-1.0f, c));
-    if (kind == 0) return 1.0f;
-    if (kind == 1) return c > 0.0f ? powf(c, param) : 0.0f;
-    float s2 = 1.0f - c * c;
-    if (!(s2 > 0.0f)) return 0.0f;
-    float kh = 6.283185307179586f * param;
-    float num = cosf(kh * c) - cosf(kh);
-    return num * num / s2;
-}
-
-__device__ __forceinline__ float cos_between(const double* v, const double* axis)
+__device__ __forceinline__ double cos_between(const double* v, const double* axis, double axis_norm)
 {
     double n = sqrt(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
-    double a = sqrt(axis[0] * axis[0] + axis[1] * axis[1] + axis[2] * axis[2]);
-    return (float)((v[0] * axis[0] + v[1] * axis[1] + v[2] * axis[2]) / (n * a));
+    return (v[0] * axis[0] + v[1] * axis[1] + v[2] * axis[2]) / (n * axis_norm);
 }
 
-// -2 pi frac(d / lambda) in FP64
-__device__ __forceinline__ double phase_of(double d, double lambda)
+__device__ __forceinline__ bool pattern_on(int kind, double c)
+{
+    c = fmin(1.0, fmax(-1.0, c));
+    if (kind == 0) return true;
+    if (kind == 1) return c > 0.0;
+    return 1.0 - c * c > 0.0;
+}
+
+__device__ __forceinline__ float pattern_amp(int kind, double param, double c64)
+{
+    c64 = fmin(1.0, fmax(-1.0, c64));
+    if (kind == 0) return 1.0f;
+    if (kind == 1) {
+        const float c = (float)c64;
+        return c > 0.0f ? powf(c, (float)(0.5 * param)) : 0.0f;
+    }
+    const double s2 = 1.0 - c64 * c64;   // sin^2(theta) in FP64: no cancellation to 0 near the axis
+    if (!(s2 > 0.0)) return 0.0f;
+    const float c = (float)c64, kh = (float)(6.283185307179586 * param);
+    return fabsf(cosf(kh * c) - cosf(kh)) / sqrtf((float)s2);
+}
+
+// e^{-j 2 pi d / lambda} = e^{-j 2 pi f}, f = frac(d / lambda) taken in FP64;
+// cosine and sine of the fraction of a turn by the hardware's v_cos/v_sin
+// (their argument is in turns).
+__device__ __forceinline__ void phase_cs(double d, double lambda, float& cs, float& sn)
 {
 #pragma clang fp contract(off)
-    double x = d / lambda;
-    return -6.283185307179586 * (x - floor(x));
+    const double x = d / lambda;
+    const float f = (float)(x - floor(x));
+    cs = __builtin_amdgcn_cosf(f);
+    sn = -__builtin_amdgcn_sinf(f);
 }
 
 // --------------------------------------------------------------------------
 // launchers implemented in the .hip files
 // --------------------------------------------------------------------------
-struct DeviceAlloc;   // runtime allocator (hipMallocAsync on a stream)
 
 }  // namespace rt

@@ -489,9 +489,11 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                 const double lq = k == 0 ? S[q] : k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
                 vl[q] = lq - X[q];
             }
-            Ft = pattern_f(tc.txa.pattern, (float)tc.txa.param, cos_between(v1, tc.txa.axis));
-            Fr = pattern_f(tc.rxa.pattern, (float)tc.rxa.param, cos_between(vl, tc.rxa.axis));
-            ok = Ft > 0.0f && Fr > 0.0f;
+            const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
+            const double cr = cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm);
+            Ft = pattern_amp(tc.txa.pattern, tc.txa.param, ct);
+            Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);
+            ok = pattern_on(tc.txa.pattern, ct) && pattern_on(tc.rxa.pattern, cr);
         }
         int sq[RT_MAX_K];
         for (int j = 0; j < RT_MAX_K; ++j) sq[j] = cv.seq[3 * c + j];
@@ -528,11 +530,10 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                     ar = nr;
                     ai = ni;
                 }
-                float mag = sqrtf((float)tc.two_eta0_pt_gt * Ft) * sqrtf((float)tc.rxa.gain * Fr) *
+                float mag = sqrtf((float)tc.two_eta0_pt_gt) * Ft * sqrtf((float)tc.rxa.gain) * Fr *
                             (float)(tc.lambda / (4.0 * 3.141592653589793 * D));
-                float ph = (float)phase_of(D, tc.lambda);
                 float cs, sn;
-                sincosf(ph, &sn, &cs);
+                phase_cs(D, tc.lambda, cs, sn);
                 a = make_float2(mag * (ar * cs - ai * sn), mag * (ar * sn + ai * cs));
             }
             amp[i] = a;
@@ -629,9 +630,11 @@ __global__ __launch_bounds__(64) void k_txm(SceneView s, TraceConst tc, RisView 
         double vt[3] = {e[0] - tc.tx[0], e[1] - tc.tx[1], e[2] - tc.tx[2]};
         double back[3] = {-vt[0], -vt[1], -vt[2]};
         double dt = sqrt(vt[0] * vt[0] + vt[1] * vt[1] + vt[2] * vt[2]);
-        float Ft = pattern_f(tc.txa.pattern, (float)tc.txa.param, cos_between(vt, tc.txa.axis));
-        float Fin = pattern_f(1, (float)rv.q, cos_between(back, rv.normal));
-        bool ok = Ft > 0.0f && Fin > 0.0f;
+        const double ct = cos_between(vt, tc.txa.axis, tc.txa.axis_norm);
+        const double ci = cos_between(back, rv.normal, rv.normal_norm);
+        const float Ft = pattern_amp(tc.txa.pattern, tc.txa.param, ct);   // sqrt(F_t)
+        const float Fin = pattern_amp(1, rv.q, ci);                        // sqrt(F_in)
+        bool ok = pattern_on(tc.txa.pattern, ct) && pattern_on(1, ci);
         if (ok) {
             ++nseg;
             ok = !leg_blocked<BRUTE>(s, tc.tx, e, -1, -1, stack + threadIdx.x, 64);
@@ -639,8 +642,8 @@ __global__ __launch_bounds__(64) void k_txm(SceneView s, TraceConst tc, RisView 
         TxmRec r;
         r.ok = ok ? 1 : 0;
         r.dt = dt;
-        r.fac = ok ? (float)(sqrt(tc.two_eta0_pt_gt * (double)Ft) *
-                             sqrt(rv.gain * (double)Fin * rv.dy * rv.dz / (4.0 * 3.141592653589793)) / dt)
+        r.fac = ok ? (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
+                             sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / dt)
                    : 0.0f;
         out[m] = r;
     }
@@ -703,7 +706,8 @@ template <bool BRUTE, bool KEEP, int STK, bool CNT>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
                                                const int32_t* useq, int n_mchunk, float2* H, uint8_t* rvalid,
-                                               unsigned long long* segs, unsigned long long* work)
+                                               unsigned long long* segs, unsigned long long* work,
+                                               unsigned long long* fallbacks)
 {
     // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
     __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
@@ -721,6 +725,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
     const int lane = threadIdx.x & 63;
     int* my_stack = wstack + wib * RT_STACK4;
     unsigned nseg = 0;
+    unsigned n_fallback = 0;   // slots whose grouped leg walk fell back (wave-uniform)
     if (w < R * n_mchunk) {
         const int64_t r = w / n_mchunk;
         const int m = (int)(w - r * n_mchunk) * 64 + lane;
@@ -775,9 +780,11 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                     }
                     double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
                     double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
-                    Fout = pattern_f(1, (float)rv.q, cos_between(v1, rv.normal));
-                    Fr = pattern_f(tc.rxa.pattern, (float)tc.rxa.param, cos_between(vl, tc.rxa.axis));
-                    ok = Fout > 0.0f && Fr > 0.0f;
+                    const double co = cos_between(v1, rv.normal, rv.normal_norm);
+                    const double cr = cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm);
+                    Fout = pattern_amp(1, rv.q, co);                           // sqrt(F_out)
+                    Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);        // sqrt(F_r)
+                    ok = pattern_on(1, co) && pattern_on(tc.rxa.pattern, cr);
                 }
                 double Dr = 0.0;
 #pragma unroll
@@ -810,11 +817,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         ar = nr;
                         ai = ni;
                     }
-                    float mag = t.fac * sqrtf(Fout) * sqrtf((float)tc.rxa.gain * Fr) *
+                    float mag = t.fac * Fout * sqrtf((float)tc.rxa.gain) * Fr *
                                 (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
-                    float ph = (float)phase_of(t.dt + Dr, tc.lambda);
                     float cs, sn;
-                    sincosf(ph, &sn, &cs);
+                    phase_cs(t.dt + Dr, tc.lambda, cs, sn);
                     amp_r = mag * (ar * cs - ai * sn);
                     amp_i = mag * (ar * sn + ai * cs);
                 }
@@ -843,8 +849,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 }
             } else {
                 // every leg at once; legs are counted as the sequential test would (up to the first blocked one)
-                const unsigned bl = legs_blocked_tube(s, ok, k, seq, &legbuf[wib][0][0][0], ttube[wib], tfront[wib],
-                                                      tcand[wib], my_stack);
+                const unsigned res = legs_blocked_tube(s, ok, k, seq, &legbuf[wib][0][0][0], ttube[wib],
+                                                       tfront[wib], tcand[wib], my_stack);
+                n_fallback += (res & RT_TUBE_FELL_BACK) ? 1u : 0u;   // same on every lane
+                const unsigned bl = res & ~RT_TUBE_FELL_BACK;
                 if (ok) nseg += bl ? (unsigned)(__ffs((int)bl)) : (unsigned)(k + 1);
                 ok = ok && bl == 0u;
             }
@@ -864,6 +872,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
         wave_count_add(work + 4, nseg);
     }
     wave_count_add(segs, nseg);
+    if (!BRUTE && !CNT) wave_count_add(fallbacks, lane == 0 ? n_fallback : 0u);
 }
 
 // --------------------------------------------------------------------------
@@ -1130,7 +1139,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
 
     // counters: [0] discovery segments, [1] leg segments, [2..4] Tx count / append / hash overflow,
     // [5..7] centre count / append / hash overflow, [8..12] work of the counting build,
-    // [13] valid environment paths, [15] discovery segments of a repeated phase A (not reported)
+    // [13] valid environment paths, [14] per-element slots whose grouped leg walk fell back,
+    // [15] discovery segments of a repeated phase A (not reported)
     Scratch ctr(c, 128, st);
     HIP_CHECK(hipMemsetAsync(ctr.p, 0, 128, st));
     unsigned long long* d_ctr = ctr.as<unsigned long long>();
@@ -1259,6 +1269,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             rv.centre[q] = a.ris->centre[q];
             rv.normal[q] = a.ris->normal[q];
         }
+        rv.normal_norm = sqrt(rv.normal[0] * rv.normal[0] + rv.normal[1] * rv.normal[1] + rv.normal[2] * rv.normal[2]);
         rv.dy = a.ris->dy;
         rv.dz = a.ris->dz;
         rv.gain = a.ris->gain > 0 ? a.ris->gain
@@ -1280,7 +1291,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                 SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true>), dim3(nblk(threads, RIS_B)),
                                                 dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                 uptr.as<int64_t>(), useq.as<int32_t>(), n_mchunk, ch.H.as<float2>(),
-                                                ch.ris_valid.as<uint8_t>(), d_legs, d_work));
+                                                ch.ris_valid.as<uint8_t>(), d_legs, d_work, d_ctr + 14));
             } else {
                 SEL_BOOL(brute, BR,
                          SEL_BOOL(keep_paths, KP,
@@ -1289,7 +1300,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                                   uptr.as<int64_t>(), useq.as<int32_t>(), n_mchunk,
                                                                   ch.H.as<float2>(), ch.ris_valid.as<uint8_t>(),
-                                                                  d_legs, d_work))));
+                                                                  d_legs, d_work, d_ctr + 14))));
             }
         }
         HIP_CHECK(hipGetLastError());
@@ -1314,8 +1325,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             p->st = st;
         if (!keep_paths) useq.st = st;
     }
-    int64_t h[14];
-    read_i64s((const int64_t*)d_ctr, h, 14, st);
+    int64_t h[15];
+    read_i64s((const int64_t*)d_ctr, h, 15, st);
     tm.mark();   // 7
     out.disc_segments = h[0];
     out.leg_segments = h[1];
@@ -1326,6 +1337,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     ch.n_env = out.n_env;
     ch.n_slots = out.n_slots;
     for (int q = 0; q < 5; ++q) out.work[q] = h[8 + q];
+    out.leg_walk_fallbacks = h[14];
     if (timing) {
         HIP_CHECK(hipStreamSynchronize(st));
         auto el = [&](int i, int j) {

@@ -65,7 +65,8 @@ class RtStats(ctypes.Structure):
     _fields_ = [("segments", ctypes.c_int64), ("discovery_segments", ctypes.c_int64),
                 ("leg_segments", ctypes.c_int64), ("n_cand_tx", ctypes.c_int64), ("n_cand_u", ctypes.c_int64),
                 ("n_env_paths", ctypes.c_int64), ("n_u_paths", ctypes.c_int64), ("n_ris_slots", ctypes.c_int64),
-                ("ms_stage", ctypes.c_float * 8), ("ris_work", ctypes.c_int64 * 5)]
+                ("ms_stage", ctypes.c_float * 8), ("ris_work", ctypes.c_int64 * 5),
+                ("leg_walk_fallbacks", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_stage", "ris_work")}

@@ -336,6 +336,28 @@ def lab_room(seed: int = BASE_SEED + 1, n_rays: int = 1_000_000, order: int = 3,
                    order, n_rays, seed, gamma)
 
 
+def wide_ris_room(seed: int = BASE_SEED + 5, n_rays: int = 20_000, order: int = 2, nx: int = 6,
+                  ny: int = 5) -> Problem:
+    """The lab room with a sparse 8 x 8 array (0.35 m pitch, 2.45 m across) on
+    the x = 6 wall: the legs of one receiver's elements are far apart, the
+    opposite of the dense RIS the grouped leg walk is built for."""
+    rng = np.random.default_rng(seed)
+    freq = 28e9
+    lam = C0 / freq
+    scene = lab_room_scene(rng)
+    normal = np.array([-1.0, 0.0, 0.0])
+    centre = np.array([5.999, 2.5, 1.5])
+    elems = square_ris(8, 8, 0.35, centre, normal)
+    ris = Ris(elems, normal, centre, lam / 2, lam / 2, math.pi, 3.0)
+    tx = np.array([0.5, 0.5, 2.5])
+    rx = rx_grid(0.3, 5.7, nx, 0.3, 4.7, ny, 1.2, 5e-4, rng)
+    gamma = gamma_2bit(elems.shape[0], 1, 0.9, rng)
+    return Problem("wide_ris", scene, freq, tx, 0.01,
+                   Antenna(unit(centre - tx), 18.0, PAT_COSPOW, 8.0), ris, rx,
+                   Antenna(np.array([0.0, 0.0, 1.0]), 1.0, PAT_ISO, 0.0),
+                   order, n_rays, seed, gamma)
+
+
 def precision_problem(seed: int = BASE_SEED + 2, n_side: int = 32, nx: int = 128,
                       ny: int = 128, n_cfg: int = 4096, n_rays: int = 10_000) -> Problem:
     """Channel source for the many-configuration RIS sum: the tiny box room

@@ -129,6 +129,13 @@ def test_lab_room_order2_brute_force(ctx):
     check_problem(ctx, synth.lab_room(nx=5, ny=4, order=2), n_rays=4000, brute=True)
 
 
+def test_sparse_array_leg_walk_fallback(ctx):
+    """Elements 0.35 m apart: the grouped leg walk of a slot outgrows its
+    on-chip lists and walks leg by leg; results stay exact."""
+    st = check_problem(ctx, synth.wide_ris_room())
+    assert st["leg_walk_fallbacks"] > 0
+
+
 def test_bvh_equals_brute_force(ctx):
     """Walking the BVH gives exactly what testing every triangle gives."""
     from paper_2402_13034_amd import risrt

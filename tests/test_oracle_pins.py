@@ -460,6 +460,24 @@ def test_horn_directivity_matches_gain():
     assert abs(4 * math.pi / integral / Gt - 1) < 1e-6
 
 
+def test_pattern_zero_decided_on_the_cosine():
+    """A path is dropped only where a pattern is zero by definition: cos^p
+    for theta >= 90 deg, the monopole on its axis.  A cosine so small that
+    cos^p underflows to 0 in FP64 still counts as nonzero."""
+    c = np.array([1e-45, 1e-300, 0.0, -0.0, -1e-300, 0.5, 1.0])
+    assert O.pattern(O.PAT_COSPOW, 8.0, c[:1], 0.01)[0] == 0.0          # the value underflows ...
+    assert O.pattern_on(O.PAT_COSPOW, c).tolist() == [True, True, False, False, False, True, True]
+    assert O.pattern_on(O.PAT_MONOPOLE, np.array([1.0, -1.0, 0.3, 1.0 - 1e-12])).tolist() == [False, False, True,
+                                                                                             True]
+    assert O.pattern_on(O.PAT_ISO, c).all()
+    # the rule agrees with F > 0 wherever F does not underflow
+    cc = np.linspace(-1, 1, 2001)
+    for kind, prm in ((O.PAT_COSPOW, 3.0), (O.PAT_MONOPOLE, 0.25), (O.PAT_ISO, 0.0)):
+        F = O.pattern(kind, prm, cc, 0.0126)
+        on = O.pattern_on(kind, cc)
+        assert np.all(on[F > 0]) and not np.any((F > 1e-300) & ~on)
+
+
 def test_monopole_pattern():
     lam = 0.0126
     th = np.array([0.0, math.pi / 2, math.pi, math.pi / 3])
