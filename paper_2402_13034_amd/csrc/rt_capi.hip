@@ -326,6 +326,8 @@ rt_status rt_shutdown(rt_ctx ctx)
         ctx->objs.clear();
         HIP_CHECK(hipStreamSynchronize(ctx->free_stream));
         HIP_CHECK(hipStreamDestroy(ctx->free_stream));
+        if (ctx->c.fib_perm) (void)hipFree(ctx->c.fib_perm);
+        if (ctx->c.fib_off) (void)hipFree(ctx->c.fib_off);
         for (hipStream_t s : ctx->c.side_all) (void)hipStreamDestroy(s);
         release_cache(ctx->c);
         return RT_OK;

@@ -44,6 +44,10 @@ struct Ctx {
     std::mutex pool_mu;
     std::vector<hipStream_t> side_pool;
     std::vector<hipStream_t> side_all;
+    // launch order of the discovery rows (built on first use, freed at shutdown)
+    std::mutex fib_mu;
+    int32_t* fib_perm = nullptr;
+    int32_t* fib_off = nullptr;
 };
 
 // Borrow a side stream of the context for the lifetime of the object.

@@ -468,6 +468,117 @@ __device__ bool any_hit_wave4(const SceneView& s, bool searching, float ox, floa
     return hit;
 }
 
+__device__ __forceinline__ bool slab1t(float lx, float hx, float ly, float hy, float lz, float hz, const RayBox& r,
+                                       float tmin, float tmax, float& tn)
+{
+    float t0x = __builtin_fmaf(lx, r.ix, -r.oix), t1x = __builtin_fmaf(hx, r.ix, -r.oix);
+    float t0y = __builtin_fmaf(ly, r.iy, -r.oiy), t1y = __builtin_fmaf(hy, r.iy, -r.oiy);
+    float t0z = __builtin_fmaf(lz, r.iz, -r.oiz), t1z = __builtin_fmaf(hz, r.iz, -r.oiz);
+    float a = fmaxf(fmaxf(fminf(t0x, t1x), fminf(t0y, t1y)), fmaxf(fminf(t0z, t1z), tmin));
+    float b = fminf(fminf(fmaxf(t0x, t1x), fmaxf(t0y, t1y)), fminf(fmaxf(t0z, t1z), tmax));
+    tn = a;
+    return a <= b;
+}
+
+// Closest hit for a wave: the lanes walk the 4-wide nodes together (node
+// data in scalar registers), each lane pruning boxes with its own best
+// distance; the entries of a node are visited nearest first as seen by the
+// first searching lane.  A lane's answer is the lowest (t, triangle id) over
+// every triangle but skip_tri with tmin < t, as in closest_hit: a triangle
+// is tested by every lane whenever some lane's ray reaches its box, and a
+// lane only prunes boxes it cannot improve on.  wstack: RT_STACK4 entries.
+__device__ int closest_hit_wave4(const SceneView& s, bool active, float ox, float oy, float oz, float dx, float dy,
+                                 float dz, float tmin, int skip_tri, int* wstack, float& t_best, int& id_best)
+{
+    const float inf = __builtin_inff();
+    t_best = inf;
+    id_best = 0x7fffffff;
+    int slot_best = -1;
+    const unsigned long long act = __ballot(active);
+    if (s.n_tri == 0 || act == 0ull) return -1;
+    const int lead = __ffsll((long long)act) - 1;
+    const RayBox rb = make_raybox(ox, oy, oz, dx, dy, dz);
+    int sp = 0;
+    int node = s.root;
+    while (true) {
+        if (node >= 0) {
+            const float4* q = s.node4 + 8 * node;
+            const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5], cf = q[6];
+            int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y);
+            int c2 = __float_as_int(cf.z), c3 = __float_as_int(cf.w);
+            float t0, t1, t2, t3;
+            const bool h0 = slab1t(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, rb, tmin, t_best, t0) & active;
+            const bool h1 = slab1t(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, rb, tmin, t_best, t1) & active;
+            const bool h2 = slab1t(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, rb, tmin, t_best, t2) & active;
+            const bool h3 = slab1t(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, rb, tmin, t_best, t3) & active;
+            const bool v0 = __ballot(h0) != 0ull, v1 = __ballot(h1) != 0ull;
+            const bool v2 = c2 != RT_NODE4_EMPTY && __ballot(h2) != 0ull;
+            const bool v3 = c3 != RT_NODE4_EMPTY && __ballot(h3) != 0ull;
+            // sort keys: the lead lane's entry distance; entries it misses after those it hits,
+            // entries no lane hits (dropped) last
+            const float big = 3.0e38f;
+            float k0 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h0 ? t0 : big), lead));
+            float k1 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h1 ? t1 : big), lead));
+            float k2 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h2 ? t2 : big), lead));
+            float k3 = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(h3 ? t3 : big), lead));
+            k0 = v0 ? k0 : inf;
+            k1 = v1 ? k1 : inf;
+            k2 = v2 ? k2 : inf;
+            k3 = v3 ? k3 : inf;
+            c0 = v0 ? c0 : RT_NODE4_EMPTY;
+            c1 = v1 ? c1 : RT_NODE4_EMPTY;
+            c2 = v2 ? c2 : RT_NODE4_EMPTY;
+            c3 = v3 ? c3 : RT_NODE4_EMPTY;
+#define RT_CSWAP(ka, ca, kb, cb)                  \
+    {                                             \
+        const bool sw = kb < ka;                  \
+        const float tk = sw ? kb : ka;            \
+        kb = sw ? ka : kb;                        \
+        ka = tk;                                  \
+        const int tc = sw ? cb : ca;              \
+        cb = sw ? ca : cb;                        \
+        ca = tc;                                  \
+    }
+            RT_CSWAP(k0, c0, k1, c1)
+            RT_CSWAP(k2, c2, k3, c3)
+            RT_CSWAP(k0, c0, k2, c2)
+            RT_CSWAP(k1, c1, k3, c3)
+            RT_CSWAP(k1, c1, k2, c2)
+#undef RT_CSWAP
+            // the order is wave-uniform: keep it in scalar registers
+            c0 = __builtin_amdgcn_readfirstlane(c0);
+            c1 = __builtin_amdgcn_readfirstlane(c1);
+            c2 = __builtin_amdgcn_readfirstlane(c2);
+            c3 = __builtin_amdgcn_readfirstlane(c3);
+            if (c3 != RT_NODE4_EMPTY) wstack[sp++] = c3;
+            if (c2 != RT_NODE4_EMPTY) wstack[sp++] = c2;
+            if (c1 != RT_NODE4_EMPTY) wstack[sp++] = c1;
+            if (c0 != RT_NODE4_EMPTY) {
+                node = c0;
+                continue;
+            }
+        } else {
+            const int i = ~node;
+            const float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
+            const int id = __float_as_int(a.w);
+            if (active && id != skip_tri) {
+                float t;
+                if (mt_hit(ox, oy, oz, dx, dy, dz, a, b, c, tmin, inf, t)) {
+                    if (t < t_best || (t == t_best && id < id_best)) {
+                        t_best = t;
+                        id_best = id;
+                        slot_best = i;
+                    }
+                }
+            }
+        }
+        if (sp == 0) break;
+        --sp;
+        node = __builtin_amdgcn_readfirstlane(wstack[sp]);
+    }
+    return slot_best;
+}
+
 // --------------------------------------------------------------------------
 // Tube walk for a wave of nearly parallel segments (the legs of one slot for
 // 64 RIS elements).  Every lane's tested segment o + t d, t in [tmin, tmax],

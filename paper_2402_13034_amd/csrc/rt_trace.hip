@@ -22,7 +22,10 @@
 //                eqs. (4)-(8) without Gamma summed into H[r, m].
 #pragma clang fp contract(off)
 
+#include <algorithm>
+#include <cmath>
 #include <cstring>
+#include <utility>
 #include <vector>
 
 #include "rt_host.hpp"
@@ -89,76 +92,51 @@ __device__ __forceinline__ void fib_dir(int64_t i, int64_t n, double* out)
 
 constexpr int DISC_B = 128;
 
-__device__ __forceinline__ uint32_t spread12(uint32_t v)
-{
-    v &= 0xfffu;
-    v = (v | (v << 8)) & 0x00ff00ffu;
-    v = (v | (v << 4)) & 0x0f0f0f0fu;
-    v = (v | (v << 2)) & 0x33333333u;
-    v = (v | (v << 1)) & 0x55555555u;
-    return v;
-}
 
-// Launch order of the discovery rays: consecutive Fibonacci rows form a thin
-// band of directions; each block sorts a chunk of RO_CH rows by the Morton
-// code of the octahedral map of d (18 bits) in LDS, so a wave traces
-// neighbouring directions.  Entry = row, or -1 for a row outside the
-// half-space (hemi != 0), which sorts to the end of its chunk.
-constexpr int RO_CH = 8192, RO_B = 512;
-__global__ __launch_bounds__(RO_B) void k_ray_order(int64_t rows, int hemi, double hx, double hy, double hz,
-                                                    int32_t* list)
+// Launch order of the discovery rows.  Consecutive Fibonacci rows form a
+// thin band of directions (z falls linearly with the row); within a chunk of
+// RT_FIB_CHUNK rows a wave should trace neighbouring azimuths.  The azimuth
+// of row i0 + j is 2 pi frac(frac(i0 g) + frac(j g)), so the azimuth order of
+// a chunk is one fixed order of j (by frac(j g)), rotated by an offset that
+// depends on the chunk: position j of chunk c launches row
+// c RT_FIB_CHUNK + perm[(off[c] + j) mod RT_FIB_CHUNK].  The tables are built
+// once per context on the host; they only order the work (any order gives
+// the same results).
+#define RT_FIB_CHUNK 8192
+#define RT_FIB_MAX_CHUNKS (((int64_t)1 << 31) / RT_FIB_CHUNK)
+
+static void fib_tables(Ctx& c, const int32_t** perm, const int32_t** off)
 {
-    __shared__ uint32_t key[RO_CH];
-    const int64_t base = (int64_t)blockIdx.x * RO_CH;
-    for (int j = threadIdx.x; j < RO_CH; j += RO_B) {
-        const int64_t i = base + j;
-        uint32_t k = 0xffffffffu;
-        if (i < rows) {
-            double d[3];
-            fib_dir(i, rows, d);
-            const bool go = hemi ? (d[0] * hx + d[1] * hy + d[2] * hz) > 0.0 : true;
-            if (go) {
-                float ax = fabsf((float)d[0]), ay = fabsf((float)d[1]), az = fabsf((float)d[2]);
-                float sum = ax + ay + az;
-                float u = (float)d[0] / sum, v = (float)d[1] / sum;
-                if (d[2] < 0.0) {
-                    float uu = (1.0f - fabsf(v)) * (u >= 0.0f ? 1.0f : -1.0f);
-                    float vv = (1.0f - fabsf(u)) * (v >= 0.0f ? 1.0f : -1.0f);
-                    u = uu;
-                    v = vv;
-                }
-                uint32_t qu = (uint32_t)fminf(fmaxf((u * 0.5f + 0.5f) * 512.0f, 0.0f), 511.0f);
-                uint32_t qv = (uint32_t)fminf(fmaxf((v * 0.5f + 0.5f) * 512.0f, 0.0f), 511.0f);
-                // 18-bit code << 13 | position in the chunk: < 2^31, below every skipped row
-                k = ((spread12(qu) | (spread12(qv) << 1)) << 13) | (uint32_t)j;
-            }
+    std::lock_guard<std::mutex> lk(c.fib_mu);
+    if (!c.fib_perm) {
+        const double g = (std::sqrt(5.0) - 1.0) / 2.0;
+        std::vector<std::pair<double, int32_t>> fr(RT_FIB_CHUNK);
+        for (int j = 0; j < RT_FIB_CHUNK; ++j) {
+            const double x = (double)j * g;
+            fr[j] = {x - std::floor(x), j};
         }
-        key[j] = k;
-    }
-    __syncthreads();
-    // bitonic sort, ascending
-    for (int size = 2; size <= RO_CH; size <<= 1) {
-        for (int stride = size >> 1; stride > 0; stride >>= 1) {
-            for (int t = threadIdx.x; t < RO_CH / 2; t += RO_B) {
-                const int lo = 2 * t - (t & (stride - 1));
-                const int hi = lo + stride;
-                const bool up = (lo & size) == 0;
-                const uint32_t x = key[lo], y = key[hi];
-                if ((x > y) == up) {
-                    key[lo] = y;
-                    key[hi] = x;
-                }
-            }
-            __syncthreads();
+        std::sort(fr.begin(), fr.end());
+        std::vector<int32_t> pm(RT_FIB_CHUNK), of((size_t)RT_FIB_MAX_CHUNKS);
+        std::vector<double> fv(RT_FIB_CHUNK);
+        for (int k = 0; k < RT_FIB_CHUNK; ++k) {
+            pm[k] = fr[k].second;
+            fv[k] = fr[k].first;
         }
-    }
-    for (int j = threadIdx.x; j < RO_CH; j += RO_B) {
-        const int64_t i = base + j;
-        if (i < rows) {
-            const uint32_t k = key[j];
-            list[i] = k == 0xffffffffu ? -1 : (int32_t)(base + (k & (RO_CH - 1)));
+        for (int64_t ch = 0; ch < RT_FIB_MAX_CHUNKS; ++ch) {
+            const double x = (double)(ch * RT_FIB_CHUNK) * g;
+            const double f0 = x - std::floor(x);
+            of[(size_t)ch] = (int32_t)(std::lower_bound(fv.begin(), fv.end(), 1.0 - f0) - fv.begin()) % RT_FIB_CHUNK;
         }
+        int32_t *dp = nullptr, *dofs = nullptr;
+        HIP_CHECK(hipMalloc(&dp, sizeof(int32_t) * RT_FIB_CHUNK));
+        HIP_CHECK(hipMalloc(&dofs, sizeof(int32_t) * (size_t)RT_FIB_MAX_CHUNKS));
+        HIP_CHECK(hipMemcpy(dp, pm.data(), sizeof(int32_t) * RT_FIB_CHUNK, hipMemcpyHostToDevice));
+        HIP_CHECK(hipMemcpy(dofs, of.data(), sizeof(int32_t) * (size_t)RT_FIB_MAX_CHUNKS, hipMemcpyHostToDevice));
+        c.fib_perm = dp;
+        c.fib_off = dofs;
     }
+    *perm = c.fib_perm;
+    *off = c.fib_off;
 }
 
 // Rows not launched keep -1 hit lists.
@@ -205,32 +183,49 @@ __device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t 
 // neighbour's (one of them inserts it).
 template <bool BRUTE, int STK>
 __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, double sy, double sz,
-                                                     const int32_t* list, int64_t n_list, int64_t rows, int K,
+                                                     const int32_t* perm, const int32_t* off, int64_t rows,
+                                                     int hemi, double hx, double hy, double hz, int K,
                                                      int32_t* hits, unsigned long long* segs,
                                                      unsigned long long* table, uint64_t mask, uint64_t max_probe,
                                                      int* overflow)
 {
     static_assert(RT_MAX_K == 3, "three key registers");
-    __shared__ int stack[STK * DISC_B];
+    // per-lane stacks for the brute-force build, one stack per wave for the wave walk
+    __shared__ int stack[BRUTE ? 1 : RT_STACK4 * (DISC_B / 64)];
     int64_t t = (int64_t)blockIdx.x * DISC_B + threadIdx.x;
     unsigned nseg = 0;
     uint64_t keys[RT_MAX_K] = {0, 0, 0};
-    const int64_t i = t < n_list ? (int64_t)list[t] : -1;
-    if (i >= 0) {
-        double d64[3];
+    const int64_t ch = t / RT_FIB_CHUNK;
+    const int64_t i = ch * RT_FIB_CHUNK + perm[(off[ch] + (int)(t % RT_FIB_CHUNK)) % RT_FIB_CHUNK];
+    // the bounce loop runs for the whole wave; a lane drops out when its ray escapes
+    double d64[3] = {0.0, 0.0, 1.0};
+    bool alive = i < rows;
+    if (alive) {
         fib_dir(i, rows, d64);
-        float ox = (float)sx, oy = (float)sy, oz = (float)sz;
-        float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
-        int skip = -1;
-        uint64_t acc = 0;
-        for (int b = 0; b < K; ++b) {
-            float tt;
-            int id;
-            ++nseg;
-            int slot = closest_hit<BRUTE>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, stack + threadIdx.x,
-                                          DISC_B, tt, id);
-            if (slot < 0) break;
-            if (hits) hits[i * K + b] = id;
+        alive = hemi ? (d64[0] * hx + d64[1] * hy + d64[2] * hz) > 0.0 : true;
+    }
+    const bool alive0 = alive;   // launched row (its hit list is written)
+    float ox = (float)sx, oy = (float)sy, oz = (float)sz;
+    float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
+    int skip = -1;
+    uint64_t acc = 0;
+    int hid[RT_MAX_K] = {-1, -1, -1};   // hit ids, stored after the walk (no store between the walk's loads)
+    int* wst = stack + (BRUTE ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * RT_STACK4);
+    for (int b = 0; b < K; ++b) {
+        if (__ballot(alive) == 0ull) break;
+        float tt;
+        int id;
+        if (alive) ++nseg;
+        int slot;
+        if (BRUTE)
+            slot = alive ? closest_hit<true>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, nullptr, 0, tt, id) : -1;
+        else
+            slot = closest_hit_wave4(s, alive, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, wst, tt, id);
+        alive = alive && slot >= 0;
+        if (alive) {
+            hid[0] = b == 0 ? id : hid[0];
+            hid[1] = b == 1 ? id : hid[1];
+            hid[2] = b == 2 ? id : hid[2];
             acc |= (uint64_t)(__float_as_int(s.tri4[3 * slot + 1].w) + 1) << (RT_KEY_BITS * b);
             // constant indices only, so the keys stay in registers
             keys[0] = b == 0 ? acc : keys[0];
@@ -244,6 +239,8 @@ __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, dou
             skip = id;
         }
     }
+    if (hits && alive0)
+        for (int b = 0; b < K; ++b) hits[i * K + b] = hid[b < RT_MAX_K ? b : 0];
 #pragma unroll
     for (int b = 0; b < RT_MAX_K; ++b) {
         const uint64_t left = __shfl_up(keys[b], 1, 64);
@@ -981,17 +978,14 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     Scratch table(c, sizeof(unsigned long long) * (size_t)cap, st);
     HIP_CHECK(hipMemsetAsync(table.p, 0, table.bytes, st));
     if (rows > 0 && K > 0 && sv.n_tri > 0) {
-        // launch order of the rows (rows outside the half-space are -1)
-        Scratch list(c, sizeof(int32_t) * (size_t)rows, st);
-        hipLaunchKernelGGL(k_ray_order, dim3(nblk(rows, RO_CH)), dim3(RO_B), 0, st, rows, hemi_n ? 1 : 0,
-                           hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0, hemi_n ? hemi_n[2] : 0.0,
-                           list.as<int32_t>());
-        HIP_CHECK(hipGetLastError());
-        const int64_t n_list = rows;
+        const int32_t *perm, *off;
+        fib_tables(c, &perm, &off);
+        const int64_t n_launch = (rows + RT_FIB_CHUNK - 1) / RT_FIB_CHUNK * RT_FIB_CHUNK;
         SEL_BOOL(brute, BR,
-                 SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(n_list, DISC_B)), dim3(DISC_B), 0,
-                                                 st, sv, src[0], src[1], src[2], list.as<int32_t>(), n_list, rows,
-                                                 K, keep_hits ? hits.as<int32_t>() : nullptr, d_segs,
+                 SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(n_launch, DISC_B)), dim3(DISC_B),
+                                                 0, st, sv, src[0], src[1], src[2], perm, off, rows, hemi_n ? 1 : 0,
+                                                 hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0,
+                                                 hemi_n ? hemi_n[2] : 0.0, K, keep_hits ? hits.as<int32_t>() : nullptr, d_segs,
                                                  table.as<unsigned long long>(), (uint64_t)(cap - 1), max_probe,
                                                  (int*)(br.d_app + 1))));
         HIP_CHECK(hipGetLastError());
