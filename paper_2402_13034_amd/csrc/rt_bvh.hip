@@ -333,6 +333,69 @@ __global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const 
 
 static inline unsigned blocks_for(int64_t n, int b) { return (unsigned)((n + b - 1) / b); }
 
+// Containment grid: one thread per (surface, cell).  A surface gets a grid
+// only if all its non-degenerate triangles use the same projection; a
+// triangle is listed in every cell its projected box, grown by a margin that
+// covers the rounding of the FP64 edge tests (relative to the coordinates and
+// inversely to the shortest edge), overlaps.  Lists keep the surface's
+// triangle order.
+__global__ void k_surf_grid(const int32_t* s_ptr, const int32_t* s_tris, const double* t_proj,
+                            const int32_t* t_axes, const double* s_box, const int32_t* n_surf_p, int32_t* g_axes,
+                            double* g_frame, int32_t* g_cnt, int32_t* g_tris)
+{
+    const int64_t id = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int64_t n_surf = *n_surf_p;
+    if (id >= n_surf * RT_SGRID_CELLS) return;
+    const int sf = (int)(id / RT_SGRID_CELLS), cell = (int)(id % RT_SGRID_CELLS);
+    const int b = s_ptr[sf], e = s_ptr[sf + 1];
+    int ax = -1;
+    bool same = true;
+    for (int j = b; j < e; ++j) {
+        const int a = t_axes[s_tris[j]];
+        if (a & 16) continue;
+        if (ax < 0) ax = a;
+        else if (a != ax) same = false;
+    }
+    if (!same || ax < 0) {
+        if (cell == 0) g_axes[sf] = -1;
+        g_cnt[id] = 0;
+        return;
+    }
+    const int i0 = ax & 3, i1 = (ax >> 2) & 3;
+    const double* bx = s_box + 6 * sf;
+    const double u0 = bx[i0], v0 = bx[i1];
+    const double eu = bx[3 + i0] - u0, ev = bx[3 + i1] - v0;
+    const double pu = eu > 0.0 ? (double)RT_SGRID / eu : 0.0, pv = ev > 0.0 ? (double)RT_SGRID / ev : 0.0;
+    if (cell == 0) {
+        g_axes[sf] = ax;
+        g_frame[4 * sf + 0] = u0;
+        g_frame[4 * sf + 1] = v0;
+        g_frame[4 * sf + 2] = pu;
+        g_frame[4 * sf + 3] = pv;
+    }
+    const int ci = cell / RT_SGRID, cj = cell % RT_SGRID;
+    const int64_t base = (int64_t)b * RT_SGRID_CELLS + (int64_t)cell * (e - b);
+    int n = 0;
+    for (int j = b; j < e; ++j) {
+        const int t = s_tris[j];
+        if (t_axes[t] & 16) continue;   // contains nothing
+        const double* q = t_proj + 6 * (int64_t)t;
+        const double umin = fmin(q[0], fmin(q[2], q[4])), umax = fmax(q[0], fmax(q[2], q[4]));
+        const double vmin = fmin(q[1], fmin(q[3], q[5])), vmax = fmax(q[1], fmax(q[3], q[5]));
+        const double C = fmax(fmax(fabs(umin), fabs(umax)), fmax(fabs(vmin), fabs(vmax)));
+        const double l0 = hypot(q[2] - q[0], q[3] - q[1]), l1 = hypot(q[4] - q[2], q[5] - q[3]),
+                     l2 = hypot(q[0] - q[4], q[1] - q[5]);
+        const double lmin = fmax(fmin(l0, fmin(l1, l2)), 1e-300);
+        const double m = 1e-13 * (C * C / lmin) + 1e-9 * C + 1e-12;
+        const int c0 = sgrid_index(umin - m, u0, pu), c1 = sgrid_index(umax + m, u0, pu);
+        const int d0 = sgrid_index(vmin - m, v0, pv), d1 = sgrid_index(vmax + m, v0, pv);
+        if (ci >= c0 && ci <= c1 && cj >= d0 && cj <= d1) g_tris[base + n++] = t;
+    }
+    g_cnt[id] = n;
+}
+
+
+
 __global__ void k_ctl_init(unsigned* ctl)
 {
     int i = threadIdx.x;
@@ -442,6 +505,15 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     hipLaunchKernelGGL(k_surf_plane, dim3(blocks_for(nt, 64)), dim3(64), 0, st, s.s_ptr.as<int32_t>(),
                        s.s_tris.as<int32_t>(), s.v64.as<double>(), nsurf, s.s_plane.as<double>(),
                        s.s_box.as<double>());
+    HIP_CHECK(hipGetLastError());
+    s.g_axes = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
+    s.g_frame = Scratch(c, sizeof(double) * 4 * (size_t)nt, st);
+    s.g_cnt = Scratch(c, sizeof(int32_t) * RT_SGRID_CELLS * (size_t)nt, st);
+    s.g_tris = Scratch(c, sizeof(int32_t) * RT_SGRID_CELLS * (size_t)nt, st);
+    hipLaunchKernelGGL(k_surf_grid, dim3(blocks_for(nt * RT_SGRID_CELLS, 128)), dim3(128), 0, st,
+                       s.s_ptr.as<int32_t>(), s.s_tris.as<int32_t>(), s.t_proj.as<double>(), s.t_axes.as<int32_t>(),
+                       s.s_box.as<double>(), nsurf, s.g_axes.as<int32_t>(), s.g_frame.as<double>(),
+                       s.g_cnt.as<int32_t>(), s.g_tris.as<int32_t>());
     HIP_CHECK(hipGetLastError());
     // one read-back: input checks, tree checks, surface count
     int64_t hq[2];

@@ -97,6 +97,7 @@ struct Scene {
     int32_t root = 0;
     int32_t max_depth = 0;
     Scratch tri4, nodes, node4, v64, refl, surf, s_ptr, s_tris, s_plane, s_box, t_proj, t_axes;
+    Scratch g_axes, g_frame, g_cnt, g_tris;
     SceneView view() const {
         SceneView v;
         v.n_tri = (int32_t)n_tri;
@@ -115,6 +116,10 @@ struct Scene {
         v.s_box = s_box.as<double>();
         v.t_proj = t_proj.as<double>();
         v.t_axes = t_axes.as<int32_t>();
+        v.g_axes = g_axes.as<int32_t>();
+        v.g_frame = g_frame.as<double>();
+        v.g_cnt = g_cnt.as<int32_t>();
+        v.g_tris = g_tris.as<int32_t>();
         return v;
     }
 };

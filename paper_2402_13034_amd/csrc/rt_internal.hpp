@@ -53,7 +53,24 @@ struct SceneView {
     const double* s_box;   // 6 per surface: lo, hi (inflated by 1e-9 m)
     const double* t_proj;  // 6 per triangle: a, b, c projected (counter-clockwise), see contains_proj
     const int32_t* t_axes; // per triangle: i0 | i1 << 2, 16 if degenerate
+    // containment grid per surface (RT_SGRID x RT_SGRID cells over the surface box in the
+    // projection all its triangles share; g_axes -1: no grid, scan every triangle)
+    const int32_t* g_axes;   // per surface
+    const double* g_frame;   // 4 per surface: u0, v0, cells per unit along u and v
+    const int32_t* g_cnt;    // per (surface, cell): triangles listed
+    const int32_t* g_tris;   // cell (c) of surface sf lists from s_ptr[sf] * cells + c * n_tris(sf)
 };
+
+#define RT_SGRID 4
+#define RT_SGRID_CELLS (RT_SGRID * RT_SGRID)
+
+// Grid cell coordinate of x (monotone in x, clamped to the grid)
+__host__ __device__ __forceinline__ int sgrid_index(double x, double origin, double per_unit)
+{
+    double y = (x - origin) * per_unit;
+    y = fmin(fmax(y, 0.0), (double)(RT_SGRID - 1));
+    return (int)y;
+}
 
 struct Antenna {
     double axis[3];
@@ -868,13 +885,30 @@ __device__ __forceinline__ double plane_side(const double* pl, const double* p)
     return (pl[0] * p[0] + pl[1] * p[1] + pl[2] * p[2]) - pl[3];
 }
 
-// Triangle of surface sf that contains p, or -1.
+// Triangle of surface sf that contains p, or -1: the first in the
+// surface's list.  With a grid, only the triangles listed for p's cell are
+// tested, in list order: every triangle whose test could accept p overlaps
+// that cell, so the answer is the same.  The counting build scans the whole
+// list (the method's work).
 template <bool CNT = false>
 __device__ inline int surface_contains(const SceneView& s, int sf, const double* p, WorkCount* wc = nullptr)
 {
     const double* bx = s.s_box + 6 * sf;
     if (p[0] < bx[0] || p[1] < bx[1] || p[2] < bx[2] || p[0] > bx[3] || p[1] > bx[4] || p[2] > bx[5])
         return -1;
+    const int gax = CNT ? -1 : s.g_axes[sf];
+    if (gax >= 0) {
+        const double* fr = s.g_frame + 4 * sf;
+        const int cell = sgrid_index(p[gax & 3], fr[0], fr[2]) * RT_SGRID + sgrid_index(p[(gax >> 2) & 3], fr[1], fr[3]);
+        const int b = s.s_ptr[sf];
+        const int64_t beg = (int64_t)b * RT_SGRID_CELLS + (int64_t)cell * (s.s_ptr[sf + 1] - b);
+        const int cnt = s.g_cnt[sf * RT_SGRID_CELLS + cell];
+        for (int j = 0; j < cnt; ++j) {
+            const int t = s.g_tris[beg + j];
+            if (contains_proj(s, t, p)) return t;
+        }
+        return -1;
+    }
     for (int j = s.s_ptr[sf]; j < s.s_ptr[sf + 1]; ++j) {
         int t = s.s_tris[j];
         if (CNT) wc->contain++;
