@@ -660,23 +660,36 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
         const unsigned long long act = __ballot(searching);
         if (act == 0ull) continue;
         live |= 1u << j;
-        const double ax = (double)ox + (double)tmin * (double)dx, ay = (double)oy + (double)tmin * (double)dy,
-                     az = (double)oz + (double)tmin * (double)dz;
-        const double bx = (double)ox + (double)tmax * (double)dx, by = (double)oy + (double)tmax * (double)dy,
-                     bz = (double)oz + (double)tmax * (double)dz;
+        // end points and distances in FP32: their rounding (a few 1e-7 relative) is far inside
+        // the margin (1e-4 relative on r, 1e-4 m + 4e-6 x the coordinates' scale)
+        const float ax = __builtin_fmaf(tmin, dx, ox), ay = __builtin_fmaf(tmin, dy, oy), az = __builtin_fmaf(tmin, dz, oz);
+        const float bx = __builtin_fmaf(tmax, dx, ox), by = __builtin_fmaf(tmax, dy, oy), bz = __builtin_fmaf(tmax, dz, oz);
         const int lead = __ffsll((long long)act) - 1;
-        const float cax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)ax), lead));
-        const float cay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)ay), lead));
-        const float caz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)az), lead));
-        const float cbx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)bx), lead));
-        const float cby = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)by), lead));
-        const float cbz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int((float)bz), lead));
-        const double da = sqrt((ax - cax) * (ax - cax) + (ay - cay) * (ay - cay) + (az - caz) * (az - caz));
-        const double db = sqrt((bx - cbx) * (bx - cbx) + (by - cby) * (by - cby) + (bz - cbz) * (bz - cbz));
+        const float cax = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ax), lead));
+        const float cay = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(ay), lead));
+        const float caz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(az), lead));
+        const float cbx = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bx), lead));
+        const float cby = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(by), lead));
+        const float cbz = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(bz), lead));
+        const float da = sqrtf((ax - cax) * (ax - cax) + (ay - cay) * (ay - cay) + (az - caz) * (az - caz));
+        const float db = sqrtf((bx - cbx) * (bx - cbx) + (by - cby) * (by - cby) + (bz - cbz) * (bz - cbz));
         const float scale = fmaxf(fmaxf(fabsf(cax), fmaxf(fabsf(cay), fabsf(caz))),
                                   fmaxf(fabsf(cbx), fmaxf(fabsf(cby), fabsf(cbz)))) + fabsf(tmax);
-        const float r = wave_max(searching ? (float)fmax(da, db) * 1.0001f + 1e-4f + 4e-6f * scale : 0.0f);
-        const RayBox crb = make_raybox(cax, cay, caz, cbx - cax, cby - cay, cbz - caz);
+        const float r = wave_max(searching ? fmaxf(da, db) * 1.0001f + 1e-4f + 4e-6f * scale : 0.0f);
+        // central ray with hardware reciprocals (1 ulp): their error is inside the margin too
+        RayBox crb;
+        {
+            float ex = cbx - cax, ey = cby - cay, ez = cbz - caz;
+            ex = fabsf(ex) < 1e-30f ? copysignf(1e-30f, ex) : ex;
+            ey = fabsf(ey) < 1e-30f ? copysignf(1e-30f, ey) : ey;
+            ez = fabsf(ez) < 1e-30f ? copysignf(1e-30f, ez) : ez;
+            crb.ix = __builtin_amdgcn_rcpf(ex);
+            crb.iy = __builtin_amdgcn_rcpf(ey);
+            crb.iz = __builtin_amdgcn_rcpf(ez);
+            crb.oix = cax * crb.ix;
+            crb.oiy = cay * crb.iy;
+            crb.oiz = caz * crb.iz;
+        }
         if (!(r < 1e30f)) live |= 16u;   // not representable: exact walk below
         if (lane == 0) {
             float* t = tube + 8 * j;
