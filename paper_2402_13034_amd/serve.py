@@ -59,6 +59,7 @@ class _Query:
     qid: int
     dep: str
     gamma: np.ndarray          # complex64 [M, C]
+    real: bool                 # Gamma has no imaginary part (checked at submission)
     scale: float
     precision: int
     t_submit: float
@@ -127,9 +128,10 @@ class Server:
         if dep_key not in self._deps:
             raise KeyError(dep_key)
         f: Future = Future()
+        g = np.ascontiguousarray(gamma, np.complex64)
+        real = not np.any(g.imag)   # on the caller's thread, off the device workers' path
         with self._lock:
-            q = _Query(self._next_id, dep_key, np.ascontiguousarray(gamma, np.complex64), float(scale),
-                       int(precision), time.perf_counter(), f)
+            q = _Query(self._next_id, dep_key, g, real, float(scale), int(precision), time.perf_counter(), f)
             self._next_id += 1
             self._queue.append(q)
             self._lock.notify_all()
@@ -278,11 +280,24 @@ class Server:
             with torch.cuda.stream(stream):
                 ch = self._channel(dep, stream)
                 held = True
-                g = np.concatenate([q.gamma for q in batch], axis=1) if len(batch) > 1 else batch[0].gamma
-                gd = torch.from_numpy(g).to("cuda", non_blocking=False)
-                _, P = self.ctx.ris_sum(ch, gd, scale=batch[0].scale, gamma_is_real=bool(np.all(g.imag == 0)),
+                # the batch's columns are gathered straight into pinned memory and uploaded on the slot's stream
+                M = batch[0].gamma.shape[0]
+                cols = sum(q.gamma.shape[1] for q in batch)
+                gt = torch.empty((M, cols), dtype=torch.complex64, pin_memory=True)
+                gv = gt.numpy()
+                c0 = 0
+                for q in batch:
+                    gv[:, c0:c0 + q.gamma.shape[1]] = q.gamma
+                    c0 += q.gamma.shape[1]
+                gd = gt.to("cuda", non_blocking=True)
+                _, P = self.ctx.ris_sum(ch, gd, scale=batch[0].scale, gamma_is_real=all(q.real for q in batch),
                                         precision=batch[0].precision, want_P=True, stream=stream)
-                Ph = P.cpu().numpy()
+                # the answer goes to pinned host memory (pageable copies of tens of MB dominate
+                # a large query's latency otherwise); torch's host allocator reuses the blocks
+                Pt = torch.empty(P.shape, dtype=P.dtype, pin_memory=True)
+                Pt.copy_(P, non_blocking=True)
+                stream.synchronize()
+                Ph = Pt.numpy()
             t = time.perf_counter()
             c0 = 0
             for q in batch:
@@ -292,7 +307,7 @@ class Server:
                 self.latencies.append(t - q.t_submit)
             with self._lock:
                 self.n_batches += 1
-                self.n_cols += g.shape[1]
+                self.n_cols += cols
         except risrt.RtError as e:
             requeue = False
             with self._lock:
