@@ -200,8 +200,8 @@ __global__ void k_depth(const int32_t* parent_int, const int32_t* parent_leaf, i
 
 // 4-wide nodes: every internal node of even depth lists its grandchildren
 // (a leaf child stands for itself).  Boxes are copied from the binary nodes.
-__global__ void k_node4(const int32_t* child, const int32_t* parent_int, const float4* nodes, int64_t ni,
-                        float4* node4)
+__global__ void k_node4(const int32_t* child, const int32_t* parent_int, const float4* nodes, const float4* tri4,
+                        int64_t ni, float4* node4)
 {
     int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (n >= ni) return;
@@ -239,7 +239,12 @@ __global__ void k_node4(const int32_t* child, const int32_t* parent_int, const f
     }
     q[6] = make_float4(__int_as_float(ref[0]), __int_as_float(ref[1]), __int_as_float(ref[2]),
                        __int_as_float(ref[3]));
-    q[7] = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    // surface of each leaf entry (-1 for inner and unused entries): walks that ignore a surface
+    // drop its leaves without visiting them
+    int lsf[4];
+    for (int j = 0; j < 4; ++j)
+        lsf[j] = (ref[j] < 0 && ref[j] != 0x7fffffff) ? __float_as_int(tri4[3 * (int64_t)(~ref[j]) + 1].w) : -1;
+    q[7] = make_float4(__int_as_float(lsf[0]), __int_as_float(lsf[1]), __int_as_float(lsf[2]), __int_as_float(lsf[3]));
 }
 
 // every internal node reached by exactly two children during the refit
@@ -477,7 +482,7 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         HIP_CHECK(hipGetLastError());
         s.node4 = Scratch(c, sizeof(float4) * 8 * (size_t)ni, st);
         hipLaunchKernelGGL(k_node4, dim3(blocks_for(ni, B)), dim3(B), 0, st, child.as<int32_t>(), pint.as<int32_t>(),
-                           s.nodes.as<float4>(), ni, s.node4.as<float4>());
+                           s.nodes.as<float4>(), s.tri4.as<float4>(), ni, s.node4.as<float4>());
         HIP_CHECK(hipGetLastError());
         hipLaunchKernelGGL(k_depth, dim3(blocks_for(nt, B)), dim3(B), 0, st, pint.as<int32_t>(),
                            pleaf.as<int32_t>(), nt, maxd);

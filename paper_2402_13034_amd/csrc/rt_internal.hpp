@@ -407,7 +407,7 @@ __device__ bool any_hit_wave(const SceneView& s, bool searching, float ox, float
 // nodes hold, so the boxes and the conservativeness of the test are the same.
 // Layout per node (8 float4): lo.x, hi.x, lo.y, hi.y, lo.z, hi.z of the four
 // entries, the four references (>= 0 node, < 0 ~leaf slot, RT_NODE4_EMPTY
-// unused), and a zero pad.  Node indices are those of the binary tree.  An
+// unused), and the surface of each leaf entry (-1 otherwise).  Node indices are those of the binary tree.  An
 // unused entry has a zero box and is masked out by its reference.
 #define RT_NODE4_EMPTY 0x7fffffff
 #define RT_STACK4 (3 * (RT_STACK / 2) + 4)
@@ -436,16 +436,20 @@ __device__ bool any_hit_wave4(const SceneView& s, bool searching, float ox, floa
     while (true) {
         if (node >= 0) {
             const float4* q = s.node4 + 8 * node;
-            const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5], cf = q[6];
+            const float4 lx = q[0], hx = q[1], ly = q[2], hy = q[3], lz = q[4], hz = q[5], cf = q[6], sfs = q[7];
             const int c0 = __float_as_int(cf.x), c1 = __float_as_int(cf.y);
             const int c2 = __float_as_int(cf.z), c3 = __float_as_int(cf.w);
-            const unsigned long long m0 = __ballot(slab1(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, rb, tmin, tmax) & searching);
-            const unsigned long long m1 = __ballot(slab1(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, rb, tmin, tmax) & searching);
-            // unused entries (only the last two can be unused) are masked after the ballot, without a branch
+            // unused entries and leaves of an ignored surface are masked after the ballot, without a branch
+            const int f0 = __float_as_int(sfs.x), f1 = __float_as_int(sfs.y);
+            const int f2 = __float_as_int(sfs.z), f3 = __float_as_int(sfs.w);
+            const unsigned long long m0 = __ballot(slab1(lx.x, hx.x, ly.x, hy.x, lz.x, hz.x, rb, tmin, tmax) & searching) &
+                                          ((f0 >= 0 && (f0 == skip_a || f0 == skip_b)) ? 0ull : ~0ull);
+            const unsigned long long m1 = __ballot(slab1(lx.y, hx.y, ly.y, hy.y, lz.y, hz.y, rb, tmin, tmax) & searching) &
+                                          ((f1 >= 0 && (f1 == skip_a || f1 == skip_b)) ? 0ull : ~0ull);
             const unsigned long long m2 = __ballot(slab1(lx.z, hx.z, ly.z, hy.z, lz.z, hz.z, rb, tmin, tmax) & searching) &
-                                          (c2 == RT_NODE4_EMPTY ? 0ull : ~0ull);
+                                          ((c2 == RT_NODE4_EMPTY || (f2 >= 0 && (f2 == skip_a || f2 == skip_b))) ? 0ull : ~0ull);
             const unsigned long long m3 = __ballot(slab1(lx.w, hx.w, ly.w, hy.w, lz.w, hz.w, rb, tmin, tmax) & searching) &
-                                          (c3 == RT_NODE4_EMPTY ? 0ull : ~0ull);
+                                          ((c3 == RT_NODE4_EMPTY || (f3 >= 0 && (f3 == skip_a || f3 == skip_b))) ? 0ull : ~0ull);
             // visit the first entry hit, push the others (last pushed = next visited)
             int next = RT_NODE4_EMPTY;
             if (m3) next = c3;
@@ -739,7 +743,12 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
                     const float r = t[6];
                     const float* q = (const float*)(s.node4 + 8 * n);
                     const int ref = __float_as_int(q[24 + e]);
-                    const bool hit = valid && ref != RT_NODE4_EMPTY &&
+                    // a leaf of one of the leg's end-point surfaces is never a candidate of that leg
+                    const int lsf = __float_as_int(q[28 + e]);
+                    const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
+                    const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
+                    const bool skip = lsf >= 0 && (lsf == sa || lsf == sb);
+                    const bool hit = valid && ref != RT_NODE4_EMPTY && !skip &&
                                      slab1(q[e] - r, q[4 + e] + r, q[8 + e] - r, q[12 + e] + r, q[16 + e] - r,
                                            q[20 + e] + r, crb, -1e-3f, 1.001f);
                     const unsigned long long lt = (1ull << lane) - 1ull;
