@@ -35,39 +35,62 @@ __device__ __forceinline__ float ord2f(unsigned u)
 }
 
 // bounds[0..2] min centroid, [3..5] max centroid, [6..8] min vertex, [9..11] max vertex
+__device__ __forceinline__ unsigned wave_umin(unsigned v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, (unsigned)__shfl_xor((int)v, o, 64));
+    return v;
+}
+__device__ __forceinline__ unsigned wave_umax(unsigned v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, (unsigned)__shfl_xor((int)v, o, 64));
+    return v;
+}
+
+// FP64 vertices, reflection coefficients, surface ids, centroids; bounds of
+// the centroids and of the vertices (order-preserving unsigned keys, reduced
+// per wave, one atomic per wave and value).
 __global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* surf_in, const float* rr,
                              const float* ri, int64_t nv, int64_t nt, double* v64, float2* refl,
                              int32_t* surf, float4* cent, unsigned* bounds, int32_t* bad)
 {
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = t < nt;
     float c[3] = {0, 0, 0};
     float lo[3] = {3e38f, 3e38f, 3e38f}, hi[3] = {-3e38f, -3e38f, -3e38f};
-    for (int j = 0; j < 3; ++j) {
-        int32_t vi = T[3 * t + j];
-        if (vi < 0 || vi >= nv) {
-            atomicOr(bad, 1);
-            vi = 0;
+    if (live) {
+        for (int j = 0; j < 3; ++j) {
+            int32_t vi = T[3 * t + j];
+            if (vi < 0 || vi >= nv) {
+                atomicOr(bad, 1);
+                vi = 0;
+            }
+            for (int k = 0; k < 3; ++k) {
+                float x = V[3 * (int64_t)vi + k];
+                if (!(x == x) || fabsf(x) > 1e6f) atomicOr(bad, 2);
+                v64[9 * t + 3 * j + k] = (double)x;
+                c[k] += x;
+                lo[k] = fminf(lo[k], x);
+                hi[k] = fmaxf(hi[k], x);
+            }
         }
-        for (int k = 0; k < 3; ++k) {
-            float x = V[3 * (int64_t)vi + k];
-            if (!(x == x) || fabsf(x) > 1e6f) atomicOr(bad, 2);
-            v64[9 * t + 3 * j + k] = (double)x;
-            c[k] += x;
-            lo[k] = fminf(lo[k], x);
-            hi[k] = fmaxf(hi[k], x);
-        }
+        refl[t] = make_float2(rr[t], ri[t]);
+        surf[t] = surf_in[t];
+        if (surf_in[t] < 0) atomicOr(bad, 4);
+        for (int k = 0; k < 3; ++k) c[k] = c[k] / 3.0f;
+        cent[t] = make_float4(c[0], c[1], c[2], 0.0f);
     }
-    refl[t] = make_float2(rr[t], ri[t]);
-    surf[t] = surf_in[t];
-    if (surf_in[t] < 0) atomicOr(bad, 4);
-    for (int k = 0; k < 3; ++k) c[k] = c[k] / 3.0f;
-    cent[t] = make_float4(c[0], c[1], c[2], 0.0f);
+    const bool lead = (threadIdx.x & 63) == 0;
     for (int k = 0; k < 3; ++k) {
-        atomicMin(&bounds[k], f2ord(c[k]));
-        atomicMax(&bounds[3 + k], f2ord(c[k]));
-        atomicMin(&bounds[6 + k], f2ord(lo[k]));
-        atomicMax(&bounds[9 + k], f2ord(hi[k]));
+        const unsigned cmin = wave_umin(live ? f2ord(c[k]) : 0xffffffffu);
+        const unsigned cmax = wave_umax(live ? f2ord(c[k]) : 0u);
+        const unsigned vmin = wave_umin(live ? f2ord(lo[k]) : 0xffffffffu);
+        const unsigned vmax = wave_umax(live ? f2ord(hi[k]) : 0u);
+        if (lead) {
+            atomicMin(&bounds[k], cmin);
+            atomicMax(&bounds[3 + k], cmax);
+            atomicMin(&bounds[6 + k], vmin);
+            atomicMax(&bounds[9 + k], vmax);
+        }
     }
 }
 
@@ -196,6 +219,67 @@ __global__ void k_depth(const int32_t* parent_int, const int32_t* parent_leaf, i
     }
     if (p != -1) d = 1 << 20;   // broken parent chain
     atomicMax(maxd, d);
+}
+
+// Refit of a small tree in one workgroup, the leaf-to-root walk of the
+// atomic refit with every shared word in LDS.  A walker carries the box of
+// the node it comes from in registers and leaves it in the parent's slot for
+// that side; per node one word holds the parent link (plus one, low 29
+// bits) with the arrival count above it, so one LDS atomic per level both
+// counts the arrival and yields the next node.  The first arrival at a node
+// stops; the second has both boxes and takes the union.  A node that does
+// not see exactly two arrivals marks the tree inconsistent (flag 8).
+constexpr int RT_REFIT_SMALL = 2048;   // leaves
+constexpr uint32_t RT_UP_LINK = (1u << 29) - 1;
+__global__ __launch_bounds__(1024) void k_refit_small(const int32_t* child, const int32_t* parent_int,
+                                                      const int32_t* parent_leaf, const float* lbox, float4* nodes,
+                                                      int64_t n, int32_t* bad)
+{
+    __shared__ float side[(RT_REFIT_SMALL - 1) * 12];   // [node][left, right][lo xyz, hi xyz]
+    __shared__ int32_t ch[2 * (RT_REFIT_SMALL - 1)];
+    __shared__ uint32_t up[RT_REFIT_SMALL - 1];
+    const int ni = (int)n - 1;
+    for (int p = threadIdx.x; p < ni; p += blockDim.x) {
+        ch[2 * p] = child[2 * p];
+        ch[2 * p + 1] = child[2 * p + 1];
+        const int32_t q = parent_int[p];
+        up[p] = q >= -1 && q < ni ? (uint32_t)(q + 1) : RT_UP_LINK;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < (int)n; i += blockDim.x) {
+        float b[6];
+        for (int k = 0; k < 6; ++k) b[k] = lbox[6 * (int64_t)i + k];
+        int32_t from = ~i;
+        int32_t p = parent_leaf[i];
+        while (p >= 0 && p < ni) {
+            const int32_t cl = ch[2 * p], cr = ch[2 * p + 1];
+            const int me = from == cl ? 0 : 1;
+            if (me == 1 && from != cr) {
+                atomicOr(bad, 8);
+                break;
+            }
+            float* mine = side + 12 * p + 6 * me;
+            for (int k = 0; k < 6; ++k) mine[k] = b[k];
+            const uint32_t old =
+                __hip_atomic_fetch_add(&up[p], 1u << 29, __ATOMIC_ACQ_REL, __HIP_MEMORY_SCOPE_WORKGROUP);
+            if ((old >> 29) == 0) break;   // first arrival: the other child completes p
+            const float* l = side + 12 * p;
+            const float* r = l + 6;
+            nodes[4 * p + 0] = make_float4(l[0], l[1], l[2], __int_as_float(cl));
+            nodes[4 * p + 1] = make_float4(l[3], l[4], l[5], __int_as_float(cr));
+            nodes[4 * p + 2] = make_float4(r[0], r[1], r[2], 0.0f);
+            nodes[4 * p + 3] = make_float4(r[3], r[4], r[5], 0.0f);
+            for (int k = 0; k < 3; ++k) {
+                b[k] = fminf(l[k], r[k]);
+                b[3 + k] = fmaxf(l[3 + k], r[3 + k]);
+            }
+            from = p;
+            p = (int32_t)(old & RT_UP_LINK) - 1;
+        }
+    }
+    __syncthreads();
+    for (int p = threadIdx.x; p < ni; p += blockDim.x)
+        if ((up[p] >> 29) != 2) atomicOr(bad, 8);
 }
 
 // 4-wide nodes: every internal node of even depth lists its grandchildren
@@ -470,15 +554,20 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         Scratch child(c, sizeof(int32_t) * 2 * (size_t)ni, st), pint(c, sizeof(int32_t) * (size_t)ni, st),
             pleaf(c, sizeof(int32_t) * (size_t)nt, st), ibox(c, sizeof(float) * 6 * (size_t)ni, st),
             flags(c, sizeof(int32_t) * (size_t)ni, st);
-        HIP_CHECK(hipMemsetAsync(flags.p, 0, flags.bytes, st));
+        const bool small = nt <= RT_REFIT_SMALL;
+        if (!small) HIP_CHECK(hipMemsetAsync(flags.p, 0, flags.bytes, st));
         HIP_CHECK(hipMemsetAsync(pint.p, 0xff, pint.bytes, st));
         HIP_CHECK(hipMemsetAsync(pleaf.p, 0xff, pleaf.bytes, st));
         hipLaunchKernelGGL(k_karras, dim3(blocks_for(ni, B)), dim3(B), 0, st, keys.as<uint64_t>(), nt,
                            child.as<int32_t>(), pint.as<int32_t>(), pleaf.as<int32_t>());
         HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_refit, dim3(blocks_for(nt, B)), dim3(B), 0, st, child.as<int32_t>(),
-                           pint.as<int32_t>(), pleaf.as<int32_t>(), lbox.as<float>(), ibox.as<float>(),
-                           flags.as<int32_t>(), s.nodes.as<float4>(), nt);
+        if (small)
+            hipLaunchKernelGGL(k_refit_small, dim3(1), dim3(1024), 0, st, child.as<int32_t>(), pint.as<int32_t>(),
+                               pleaf.as<int32_t>(), lbox.as<float>(), s.nodes.as<float4>(), nt, bad);
+        else
+            hipLaunchKernelGGL(k_refit, dim3(blocks_for(nt, B)), dim3(B), 0, st, child.as<int32_t>(),
+                               pint.as<int32_t>(), pleaf.as<int32_t>(), lbox.as<float>(), ibox.as<float>(),
+                               flags.as<int32_t>(), s.nodes.as<float4>(), nt);
         HIP_CHECK(hipGetLastError());
         s.node4 = Scratch(c, sizeof(float4) * 8 * (size_t)ni, st);
         hipLaunchKernelGGL(k_node4, dim3(blocks_for(ni, B)), dim3(B), 0, st, child.as<int32_t>(), pint.as<int32_t>(),
@@ -487,8 +576,10 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         hipLaunchKernelGGL(k_depth, dim3(blocks_for(nt, B)), dim3(B), 0, st, pint.as<int32_t>(),
                            pleaf.as<int32_t>(), nt, maxd);
         HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_check_refit, dim3(blocks_for(ni, B)), dim3(B), 0, st, flags.as<int32_t>(), ni, bad);
-        HIP_CHECK(hipGetLastError());
+        if (!small) {
+            hipLaunchKernelGGL(k_check_refit, dim3(blocks_for(ni, B)), dim3(B), 0, st, flags.as<int32_t>(), ni, bad);
+            HIP_CHECK(hipGetLastError());
+        }
         s.root = 0;
     } else {
         s.root = ~0;

@@ -48,6 +48,9 @@ struct Ctx {
     std::mutex fib_mu;
     int32_t* fib_perm = nullptr;
     int32_t* fib_off = nullptr;
+    // unique candidate counts of the last call per branch (Tx, RIS centre):
+    // the first hash set of the next call is sized from them
+    std::atomic<int64_t> cand_hint[2] = {0, 0};
 };
 
 // Borrow a side stream of the context for the lifetime of the object.

@@ -351,10 +351,13 @@ __global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long
     __shared__ unsigned long long base;
     BlockAppend<TC_B * TC_PT> app{vals, &n, &base};
     app.init();
+    unsigned long long v[TC_PT];   // all loads in flight before the first append
     for (int j = 0; j < TC_PT; ++j) {
-        int64_t i = ((int64_t)blockIdx.x * TC_PT + j) * TC_B + threadIdx.x;
-        if (i < cap && table[i] != 0ull) app.push((uint64_t)table[i]);
+        const int64_t i = ((int64_t)blockIdx.x * TC_PT + j) * TC_B + threadIdx.x;
+        v[j] = i < cap ? table[i] : 0ull;
     }
+    for (int j = 0; j < TC_PT; ++j)
+        if (v[j] != 0ull) app.push((uint64_t)v[j]);
     app.flush(out, out_cap, counter);
 }
 
@@ -540,18 +543,29 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
     wave_count_add(segs, nseg);
 }
 
-// E_env[r] = sum of emitted paths of receiver r, in record order (FP64)
-__global__ void k_env_reduce(const int64_t* rstart, int64_t R, const uint8_t* valid, const float2* amp, float2* E)
+// E_env[r] = sum of emitted paths of receiver r (FP64): one wave per
+// receiver, lane l sums records l, l + 64, ... of its range, then a fixed
+// butterfly over the lanes (the same order on every run).
+constexpr int ENV_B = 256;
+__global__ __launch_bounds__(ENV_B) void k_env_reduce(const int64_t* rstart, int64_t R, const uint8_t* valid,
+                                                      const float2* amp, float2* E)
 {
-    int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (r >= R) return;
+    const int64_t r = (int64_t)blockIdx.x * (ENV_B / 64) + (threadIdx.x >> 6);
+    if (r >= R) return;   // whole waves leave together
+    const int lane = threadIdx.x & 63;
     double er = 0.0, ei = 0.0;
-    for (int64_t j = rstart[r]; j < rstart[r + 1]; ++j)
+    const int64_t j1 = rstart[r + 1];
+    for (int64_t j = rstart[r] + lane; j < j1; j += 64)
         if (valid[j]) {
-            er += (double)amp[j].x;
-            ei += (double)amp[j].y;
+            const float2 a = amp[j];
+            er += (double)a.x;
+            ei += (double)a.y;
         }
-    E[r] = make_float2((float)er, (float)ei);
+    for (int o = 32; o > 0; o >>= 1) {
+        er += __shfl_xor(er, o, 64);
+        ei += __shfl_xor(ei, o, 64);
+    }
+    if (lane == 0) E[r] = make_float2((float)er, (float)ei);
 }
 
 // keep valid records: env path records for read-back
@@ -924,7 +938,9 @@ struct Branch {
     int64_t nkeys = 0;
     Cands cd;
     PathSet ps;
-    bool big_table = false;   // hash set sized for every prefix being distinct (after an overflow)
+    // hash set: 0 sized from the last call's count, 1 the standard set,
+    // 2 sized for every prefix being distinct (after overflows)
+    int table_level = 0;
     Scratch mask;             // geometric validity, R rows of n_words 32-bit words
     int64_t n_words = 0;
 };
@@ -968,13 +984,27 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         hipLaunchKernelGGL(k_fill_neg, dim3(nblk(rows * K, 256)), dim3(256), 0, st, hits.as<int32_t>(), rows * K);
         HIP_CHECK(hipGetLastError());
     }
-    // hash set filled by discovery: first 2^20 slots with probe runs of at most 256
-    // (overflow -> the caller repeats with the large set); the large set has at
-    // least 2 x (keys + 1) slots, at most 2^24, and unbounded probing
-    int64_t want = 2 * rows * K + 2, cap = 1024;
-    const int64_t limit = br.big_table ? ((int64_t)1 << 24) : ((int64_t)1 << 20);
-    while (cap < want && cap < limit) cap <<= 1;
-    const uint64_t max_probe = br.big_table ? (uint64_t)(cap - 1) : (uint64_t)255;
+    // hash set filled by discovery, probe runs of at most 256 (an overflow makes
+    // the caller repeat with the next level): first a set of at least 4x the
+    // last call's unique count, then 2^20 slots, then at least 2 x (keys + 1)
+    // slots, at most 2^24, with unbounded probing
+    const int64_t want = 2 * rows * K + 2;
+    auto set_size = [want](int64_t limit) {
+        int64_t cap = 1024;
+        while (cap < want && cap < limit) cap <<= 1;
+        return cap;
+    };
+    int64_t cap = set_size(br.table_level == 2 ? ((int64_t)1 << 24) : ((int64_t)1 << 20));
+    if (br.table_level == 0) {
+        const int64_t h = c.cand_hint[br.which].load();
+        int64_t l = 1024;
+        while (h > 0 && l < 4 * h && l < cap) l <<= 1;
+        if (h > 0 && l < cap)
+            cap = set_size(l);
+        else
+            br.table_level = 1;   // no smaller set: an overflow goes straight to the last level
+    }
+    const uint64_t max_probe = br.table_level == 2 ? (uint64_t)(cap - 1) : (uint64_t)255;
     Scratch table(c, sizeof(unsigned long long) * (size_t)cap, st);
     HIP_CHECK(hipMemsetAsync(table.p, 0, table.bytes, st));
     if (rows > 0 && K > 0 && sv.n_tri > 0) {
@@ -1002,16 +1032,17 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
 }
 
 // Size read-back after phase A: number of unique candidates (incl. order 0),
-// or -1 if the first hash set overflowed.
-static int64_t cand_count(const Branch& br, bool exhaustive)
+// or -1 if the hash set overflowed below the last level.
+static int64_t cand_count(Ctx& c, const Branch& br, bool exhaustive)
 {
     if (exhaustive) return read_i64(br.d_cnt, br.st);
     int64_t hq[2];
     read_i64s((const int64_t*)br.d_app, hq, 2, br.st);
     if (hq[1] & 1) {
-        if (!br.big_table) return -1;   // repeat phase A with the large set
+        if (br.table_level < 2) return -1;   // repeat phase A with the next set
         throw inval_error("candidate hash set overflow");
     }
+    c.cand_hint[br.which].store(hq[0] + 1);
     return hq[0] + 1;
 }
 
@@ -1169,22 +1200,22 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 1-3: candidates
     cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
     if (two) cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
-    int64_t n_tx = cand_count(bt, exhaustive);
-    int64_t n_u0 = two ? cand_count(bu, exhaustive) : 0;
-    // an overflow of the first hash set: repeat phase A with the large set (the
+    int64_t n_tx = cand_count(c, bt, exhaustive);
+    int64_t n_u0 = two ? cand_count(c, bu, exhaustive) : 0;
+    // an overflow of a hash set: repeat phase A with the next level (the
     // discovery segments were counted by the first pass)
     unsigned long long* d_dummy = d_ctr + 15;
-    if (n_tx < 0) {
-        bt.big_table = true;
+    while (n_tx < 0) {
+        bt.table_level += 1;
         HIP_CHECK(hipMemsetAsync(bt.d_app, 0, 2 * sizeof(unsigned long long), bt.st));
         cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_dummy);
-        n_tx = cand_count(bt, exhaustive);
+        n_tx = cand_count(c, bt, exhaustive);
     }
-    if (n_u0 < 0) {
-        bu.big_table = true;
+    while (n_u0 < 0) {
+        bu.table_level += 1;
         HIP_CHECK(hipMemsetAsync(bu.d_app, 0, 2 * sizeof(unsigned long long), bu.st));
         cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_dummy);
-        n_u0 = cand_count(bu, exhaustive);
+        n_u0 = cand_count(c, bu, exhaustive);
     }
     cand_phase_b(c, a, exhaustive, bt, n_tx);
     if (two) cand_phase_b(c, a, exhaustive, bu, n_u0);
@@ -1204,7 +1235,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     {
         PathSet& ps = bt.ps;
         if (R > 0) {
-            hipLaunchKernelGGL(k_env_reduce, dim3(nblk(R, 128)), dim3(128), 0, st, ps.rstart.as<int64_t>(), R,
+            hipLaunchKernelGGL(k_env_reduce, dim3(nblk(R, ENV_B / 64)), dim3(ENV_B), 0, st, ps.rstart.as<int64_t>(), R,
                                ps.valid.as<uint8_t>(), ps.amp.as<float2>(), ch.E_env.as<float2>());
             HIP_CHECK(hipGetLastError());
         }

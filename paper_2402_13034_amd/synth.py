@@ -313,16 +313,18 @@ def lab_room_scene(rng, size=(6.0, 5.0, 3.0), n_boxes: int = 20, sub: int = 3,
 
 
 def lab_room(seed: int = BASE_SEED + 1, n_rays: int = 1_000_000, order: int = 3,
-             nx: int = 64, ny: int = 64, n_cfg: int = 1) -> Problem:
+             nx: int = 64, ny: int = 64, n_cfg: int = 1, sub: int = 3) -> Problem:
     """6 x 5 x 3 m room (walls 3 x 3 subdivided) with 20 seeded furniture
     boxes (~1.9k triangles, coefficients U(0.3, 0.7) per object), 28 GHz,
     127-element hexagonal RIS at lambda/2 pitch on the x = 6 wall with 2-bit
     phases, Tx horn cos^8 (G_t = 18) aimed at the RIS centre, 64 x 64
-    isotropic receiver grid at z = 1.2, order <= 3."""
+    isotropic receiver grid at z = 1.2, order <= 3.  ``sub`` subdivides
+    every face into sub x sub squares (3 by default; 5 gives ~5.3k
+    triangles)."""
     rng = np.random.default_rng(seed)
     freq = 28e9
     lam = C0 / freq
-    scene = lab_room_scene(rng)
+    scene = lab_room_scene(rng, sub=sub)
     normal = np.array([-1.0, 0.0, 0.0])
     centre = np.array([5.999, 2.5, 1.5])
     elems = hex_ris(6, lam / 2, centre, normal)

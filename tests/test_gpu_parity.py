@@ -129,6 +129,22 @@ def test_lab_room_order2_brute_force(ctx):
     check_problem(ctx, synth.lab_room(nx=5, ny=4, order=2), n_rays=4000, brute=True)
 
 
+def test_first_hash_set_sized_from_last_call(ctx):
+    """A call with few candidates sizes the next call's first hash set (at
+    least 4x its count, 1024 slots at least) below what the next scene
+    needs: the overflow repeats discovery with the standard set and every
+    result still matches the oracle; the call after that fits at once."""
+    from paper_2402_13034_amd import risrt
+    c = risrt.Context(0)
+    try:
+        check_problem(c, synth.tiny_box())
+        st = check_problem(c, synth.lab_room(nx=8, ny=8), n_rays=50_000)
+        assert st["n_cand_tx"] > 1024 and st["n_cand_u"] > 1024   # more keys than slots
+        check_problem(c, synth.lab_room(nx=8, ny=8), n_rays=50_000)
+    finally:
+        c.close()
+
+
 def test_sparse_array_leg_walk_fallback(ctx):
     """Elements 0.35 m apart: the grouped leg walk of a slot outgrows its
     on-chip lists and walks leg by leg; results stay exact."""
@@ -136,10 +152,13 @@ def test_sparse_array_leg_walk_fallback(ctx):
     assert st["leg_walk_fallbacks"] > 0
 
 
-def test_bvh_equals_brute_force(ctx):
-    """Walking the BVH gives exactly what testing every triangle gives."""
+@pytest.mark.parametrize("sub", [3, 5])
+def test_bvh_equals_brute_force(ctx, sub):
+    """Walking the BVH gives exactly what testing every triangle gives
+    (1.9k triangles: one-workgroup refit; 5.3k: the atomic refit)."""
     from paper_2402_13034_amd import risrt
-    prob = synth.lab_room(nx=8, ny=8)
+    prob = synth.lab_room(nx=8, ny=8, sub=sub)
+    _say("case bvh vs brute, triangles", prob.scene.n_tri)
     outs = []
     for brute in (False, True):
         flags = risrt.FLAG_KEEP_HITS | risrt.FLAG_KEEP_PATHS | (risrt.FLAG_BRUTE_FORCE if brute else 0)
