@@ -620,6 +620,22 @@ __global__ void k_uptr_dev(const int64_t* rstart, int64_t n_rec, const int64_t* 
     uptr[r] = (r < R && a < n_rec) ? off2[a] : *total2;
 }
 
+// Launch order of the per-element kernel, heaviest receiver first (the
+// longest waves start first and short ones fill the tail): key = inverted
+// cost (slots weighted by legs, 20 bits) above the receiver index.
+__global__ void k_ris_order(const int64_t* uptr, const int32_t* useq, int64_t R, uint64_t* keys)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    int64_t cost = 1;   // the direct slot: one leg
+    for (int64_t u = uptr[r]; u < uptr[r + 1]; ++u) {
+        const int32_t* row = useq + 8 * u;
+        cost += 2 + (row[2] >= 0) + (row[3] >= 0);   // k + 1 legs, k >= 1
+    }
+    const uint64_t c = (uint64_t)(cost < 0xFFFFF ? cost : 0xFFFFF);
+    keys[r] = ((0xFFFFFull - c) << 32) | (uint64_t)r;
+}
+
 // --------------------------------------------------------------------------
 // 7. RIS
 // --------------------------------------------------------------------------
@@ -716,8 +732,8 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 template <bool BRUTE, bool KEEP, int STK, bool CNT>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
-                                               const int32_t* useq, int n_mchunk, float2* H, uint8_t* rvalid,
-                                               unsigned long long* segs, unsigned long long* work,
+                                               const int32_t* useq, const uint64_t* order, int n_mchunk, float2* H,
+                                               uint8_t* rvalid, unsigned long long* segs, unsigned long long* work,
                                                unsigned long long* fallbacks)
 {
     // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
@@ -738,8 +754,9 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
     unsigned nseg = 0;
     unsigned n_fallback = 0;   // slots whose grouped leg walk fell back (wave-uniform)
     if (w < R * n_mchunk) {
-        const int64_t r = w / n_mchunk;
-        const int m = (int)(w - r * n_mchunk) * 64 + lane;
+        const int64_t wr = w / n_mchunk;
+        const int64_t r = (int64_t)(order[wr] & 0xFFFFFFFFull);
+        const int m = (int)(w - wr * n_mchunk) * 64 + lane;
         const bool active = m < rv.M;
         const int mm = active ? m : 0;
         const double* e = rv.elem + 3 * mm;
@@ -1310,12 +1327,20 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         int n_mchunk = (int)((M + 63) / 64);
         int64_t waves = R * n_mchunk;
         int64_t threads = waves * 64;
+        if (R >= ((int64_t)1 << 32)) throw inval_error("too many receivers");
+        Scratch order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), st);
+        if (R > 0) {
+            hipLaunchKernelGGL(k_ris_order, dim3(nblk(R, 256)), dim3(256), 0, st, uptr.as<int64_t>(),
+                               useq.as<int32_t>(), R, order.as<uint64_t>());
+            HIP_CHECK(hipGetLastError());
+            sort_u64(c, order.as<uint64_t>(), R, 52, st);
+        }
         tm.mark();   // 5
         if (threads > 0) {
             if (count_work && !brute && !keep_paths) {
                 SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true>), dim3(nblk(threads, RIS_B)),
                                                 dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
-                                                uptr.as<int64_t>(), useq.as<int32_t>(), n_mchunk, ch.H.as<float2>(),
+                                                uptr.as<int64_t>(), useq.as<int32_t>(), order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
                                                 ch.ris_valid.as<uint8_t>(), d_legs, d_work, d_ctr + 14));
             } else {
                 SEL_BOOL(brute, BR,
@@ -1323,8 +1348,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                                   SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false>),
                                                                   dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, st, sv,
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
-                                                                  uptr.as<int64_t>(), useq.as<int32_t>(), n_mchunk,
-                                                                  ch.H.as<float2>(), ch.ris_valid.as<uint8_t>(),
+                                                                  uptr.as<int64_t>(), useq.as<int32_t>(),
+                                                                  order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(), ch.ris_valid.as<uint8_t>(),
                                                                   d_legs, d_work, d_ctr + 14))));
             }
         }
