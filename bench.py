@@ -11,8 +11,9 @@ per-element expansion into H, and the coherent sum for the configured
 Prints one JSON line: value = ray segments traced per second (millions),
 plus the dominant kernel's roofline, the many-configuration RIS sum on the
 matrix cores (TFLOP/s, 16384 receivers x 1024 elements x 4096
-configurations) and the oracle timed on a bounded sample of the same
-workload on the host cores.
+configurations; bf16 and fp16 split products, the VALU sum, and the plain
+per-configuration tracer that traces again for every configuration) and the
+oracle timed on a bounded sample of the same workload on the host cores.
 """
 import argparse
 import gc
@@ -156,7 +157,8 @@ def run_gemm_bench(ctx, reps=5):
         / (2 * 120 * math.pi)
     sel = P_ref >= 1e-3 * inc
     rows_t = torch.from_numpy(rows).cuda()
-    for name, prec in (("bf16x2", risrt.PREC_MFMA_BF16X2), ("valu_f32", risrt.PREC_VALU_F32)):
+    for name, prec in (("bf16x2", risrt.PREC_MFMA_BF16X2), ("f16x2", risrt.PREC_MFMA_F16X2),
+                       ("valu_f32", risrt.PREC_VALU_F32)):
         ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=prec, P_out=P)
         torch.cuda.synchronize()
         n = reps if prec != risrt.PREC_VALU_F32 else 2
@@ -173,12 +175,32 @@ def run_gemm_bench(ctx, reps=5):
         Ps = Po[rows_t].cpu().numpy().astype(np.float64)
         del Eo, Po
         out[name] = {"ms": ms, "tflops_complex_equiv": 8.0 * R * M * C / (ms * 1e-3) / 1e12,
-                     "tflops_executed": (4.0 * R * M * C * (2 if prec == 1 else 1)) / (ms * 1e-3) / 1e12,
+                     "tflops_executed": (4.0 * R * M * C * (1 if prec == risrt.PREC_VALU_F32 else 2)) / (ms * 1e-3) / 1e12,
                      "err_vs_fp64": {"max_db": float(np.max(np.abs(10 * np.log10(Ps[sel] / P_ref[sel])))),
                                      "max_phase_rad": float(np.max(np.abs(np.angle(Es[sel] / E_ref[sel])))),
                                      "nrmse": float(np.sqrt(np.mean(np.abs(Es - E_ref) ** 2) /
                                                             np.mean(np.abs(E_ref) ** 2))),
                                      "rows_sampled": 256, "frac_above_null_threshold": float(sel.mean())}}
+    # the plain per-configuration tracer: the whole trace again for every
+    # configuration, then that configuration's field (timed for a few, scaled to C)
+    n_rt = 4
+    g1 = [g[:, j:j + 1].contiguous() for j in range(n_rt)]
+    P1 = torch.empty((R, 1), dtype=torch.float32, device="cuda")
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for j in range(n_rt):
+        ch_j, _ = risrt.trace_problem(ctx, prob, scene, ris)
+        ctx.ris_sum(ch_j, g1[j], scale=0.9, gamma_is_real=True, precision=risrt.PREC_VALU_F32, P_out=P1)
+        ctx.destroy(ch_j)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_cfg = e0.elapsed_time(e1) / n_rt
+    out["per_config_retrace"] = {"ms_per_config": ms_cfg, "configs_timed": n_rt,
+                                 "ms_for_all_configs": ms_cfg * C,
+                                 "speedup_bf16x2": ms_cfg * C / out["bf16x2"]["ms"],
+                                 "speedup_f16x2": ms_cfg * C / out["f16x2"]["ms"],
+                                 "speedup_valu_f32": ms_cfg * C / out["valu_f32"]["ms"]}
     for h in (ch, scene, ris):
         ctx.destroy(h)
     out["shape"] = {"R": R, "M": M, "C": C}

@@ -65,6 +65,10 @@ typedef int32_t rt_status;
 #define RT_PREC_MFMA_BF16X2 1 /* H = H_hi + H_lo (bf16 each), Gamma rounded once to bf16,
                                  two bf16 matrix-core products, FP32 accumulation */
 #define RT_PREC_MFMA_BF16X3 2 /* also Gamma = G_hi + G_lo: three products */
+#define RT_PREC_MFMA_F16X2 3  /* each receiver's H rows scaled by a power of two that puts their largest
+                                 magnitude in [2^14, 2^15), split into fp16 hi + lo; Gamma rounded once
+                                 to fp16 (|Gamma| below 6.1e-5 falls into fp16's subnormal range); two fp16
+                                 matrix-core products, FP32 accumulation, the scale undone exactly */
 
 typedef struct rt_ctx_s* rt_ctx;
 

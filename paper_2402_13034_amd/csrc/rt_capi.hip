@@ -275,7 +275,7 @@ void release_obj(rt_ctx ctx, Obj& o)
     if (o.channel) {
         Channel& ch = *o.channel;
         for (Scratch* p : {&ch.H, &ch.E_env, &ch.hits[0], &ch.hits[1], &ch.cand_keys[0], &ch.cand_keys[1], &ch.env,
-                           &ch.useq, &ch.ris_valid, &ch.a_hi, &ch.a_lo})
+                           &ch.useq, &ch.ris_valid, &ch.a_hi, &ch.a_lo, &ch.a_sexp})
             retarget(*p, fs);
     }
     if (o.scene && o.scene->ready) (void)hipEventDestroy(o.scene->ready);
@@ -621,7 +621,7 @@ rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C
     return guarded(ctx, [&]() -> rt_status {
         auto o = find(ctx, channel, 3);
         if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
-        if (C < 0 || precision < 0 || precision > 2) return fail(RT_EINVAL, "bad configuration count or precision");
+        if (C < 0 || precision < 0 || precision > 3) return fail(RT_EINVAL, "bad configuration count or precision");
         Channel& ch = *o->channel;
         if (C > 0 && ch.M > 0 && !is_device_ptr(gamma)) return fail(RT_EINVAL, "gamma must be device memory");
         if ((E_out && !is_device_ptr(E_out)) || (P_out && !is_device_ptr(P_out)))

@@ -136,7 +136,7 @@ struct RisObj {
 
 struct Channel {
     hipEvent_t ready = nullptr;      // recorded when H / E_env are complete
-    hipEvent_t split_ev = nullptr;   // recorded after the bf16 split of H
+    hipEvent_t split_ev = nullptr;   // recorded after the split of H
     int64_t R = 0, M = 0, K = 0;
     Scratch H;          // float2 [R * M]
     Scratch E_env;      // float2 [R]
@@ -151,9 +151,10 @@ struct Channel {
     Scratch useq;       // int32 [n_u * 4]  (rx, s0, s1, s2)
     int64_t n_slots = 0;
     Scratch ris_valid;  // uint8 [n_slots * M]
-    // bf16 split of H, cached for matrix-core sums
-    int split_kind = 0; // 0 none, 1 real-Gamma layout, 2 complex-Gamma layout
+    // split of H, cached for matrix-core sums
+    int split_kind = 0; // 0 none; bf16: 1 real-Gamma layout, 2 complex-Gamma layout; fp16: 3, 4
     Scratch a_hi, a_lo;
+    Scratch a_sexp;     // int32 [R]: fp16 split, per-receiver power-of-two scale exponents
     int64_t a_rows = 0, a_k = 0;
     hipStream_t last_stream = nullptr;
 };

@@ -6,8 +6,12 @@
 //   rows 2r / 2r+1 of A give Re / Im of E[r, :];
 //   real Gamma:    A[2r] = Re H[r, :],            A[2r+1] = Im H[r, :],           B = Re Gamma
 //   complex Gamma: A[2r] = [Re H, -Im H],         A[2r+1] = [Im H, Re H],         B = [Re G; Im G]
-//   H is split into bf16 hi + lo (hi = RNE(x), lo = RNE(x - hi)); Gamma into hi (and lo for X3);
-//   products hi*hi + lo*hi (+ hi*lo) accumulate in FP32 (v_mfma_f32_32x32x16_bf16).
+//   H is split into hi + lo (hi = RNE(x), lo = RNE(x - hi)); Gamma into hi (and lo for X3);
+//   products hi*hi + lo*hi (+ hi*lo) accumulate in FP32 on the matrix cores:
+//   bf16 (v_mfma_f32_32x32x16_bf16), or fp16 (v_mfma_f32_32x32x16_f16) with
+//   each receiver's two rows scaled by a power of two 2^s_r that brings their
+//   largest magnitude into [2^14, 2^15) (fp16 has 5 exponent bits: unscaled
+//   fields of 1e-6 V/m would be subnormal); the epilogue multiplies by 2^-s_r.
 //   The epilogue adds E_env, scales, and writes E and/or P.
 #include <cstring>
 
@@ -83,10 +87,40 @@ __device__ __forceinline__ uint16_t bf16_rne(float x)
     return (uint16_t)(u >> 16);
 }
 __device__ __forceinline__ float bf16_to_f(uint16_t b) { return __uint_as_float((uint32_t)b << 16); }
+__device__ __forceinline__ uint16_t f16_rne(float x)
+{
+    const _Float16 h = (_Float16)x;   // round to nearest even
+    uint16_t u;
+    __builtin_memcpy(&u, &h, 2);
+    return u;
+}
+__device__ __forceinline__ float f16_to_f(uint16_t b)
+{
+    _Float16 h;
+    __builtin_memcpy(&h, &b, 2);
+    return (float)h;
+}
 
-// A [rows_p x kp] row-major (k fastest); layout 1 = real Gamma, 2 = complex Gamma
+// fp16 split: per receiver, the power of two s_r with max |Re H|, |Im H| of the
+// row times 2^s_r in [2^14, 2^15) (s_r = 0 for an all-zero row); one wave per receiver
+__global__ void k_row_scale(const float2* H, int64_t R, int64_t M, int32_t* sexp)
+{
+    const int64_t r = (int64_t)blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    if (r >= R) return;
+    const int lane = threadIdx.x & 63;
+    float m = 0.0f;
+    for (int64_t k = lane; k < M; k += 64) {
+        const float2 h = H[r * M + k];
+        m = fmaxf(m, fmaxf(fabsf(h.x), fabsf(h.y)));
+    }
+    for (int o = 32; o > 0; o >>= 1) m = fmaxf(m, __shfl_xor(m, o, 64));
+    if (lane == 0) sexp[r] = m > 0.0f ? 14 - ilogbf(m) : 0;
+}
+
+// A [rows_p x kp] row-major (k fastest); layout 1 = real Gamma, 2 = complex Gamma;
+// sexp: per-receiver scale exponents of the fp16 split (nullptr: bf16)
 __global__ void k_split_A(const float2* H, int64_t R, int64_t M, int layout, int64_t rows_p, int64_t kp,
-                          uint16_t* Ahi, uint16_t* Alo)
+                          const int32_t* sexp, uint16_t* Ahi, uint16_t* Alo)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (idx >= rows_p * kp) return;
@@ -102,13 +136,20 @@ __global__ void k_split_A(const float2* H, int64_t R, int64_t M, int layout, int
             else if (k < 2 * M) v = part == 0 ? -H[r * M + k - M].y : H[r * M + k - M].x;
         }
     }
+    if (sexp) {
+        v = r < R ? ldexpf(v, sexp[r]) : 0.0f;
+        const uint16_t hi = f16_rne(v);
+        Ahi[idx] = hi;
+        Alo[idx] = f16_rne(v - f16_to_f(hi));
+        return;
+    }
     uint16_t hi = bf16_rne(v);
     Ahi[idx] = hi;
     Alo[idx] = bf16_rne(v - bf16_to_f(hi));
 }
 
 // Bt [cols_p x kp] (k fastest)
-__global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int64_t cols_p, int64_t kp,
+__global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int64_t cols_p, int64_t kp, bool f16,
                           uint16_t* Bhi, uint16_t* Blo)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -119,6 +160,12 @@ __global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int
         if (k < M) v = G[k * C + c].x;
         else if (layout == 2 && k < 2 * M) v = G[(k - M) * C + c].y;
     }
+    if (f16) {
+        const uint16_t hi = f16_rne(v);
+        Bhi[idx] = hi;
+        if (Blo) Blo[idx] = f16_rne(v - f16_to_f(hi));
+        return;
+    }
     uint16_t hi = bf16_rne(v);
     Bhi[idx] = hi;
     if (Blo) Blo[idx] = bf16_rne(v - bf16_to_f(hi));
@@ -128,15 +175,28 @@ __global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int
 // MFMA GEMM: 128 x 128 tile, 4 waves (each 64 x 64 = 2 x 2 blocks of 32 x 32), BK = 32
 // --------------------------------------------------------------------------
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
 
 constexpr int GBM = 128, GBN = 128, GBK = 32;
 constexpr int LDA = GBK + 8;   // padded row (bf16 elements)
 
-template <int NT>
+// one 32 x 32 x 16 product of 8-element operands, bf16 or fp16
+template <bool F16>
+__device__ __forceinline__ f32x16 mfma16(const uint16_t* a, const uint16_t* b, f32x16 acc)
+{
+    if constexpr (F16)
+        return __builtin_amdgcn_mfma_f32_32x32x16_f16(*(const f16x8*)a, *(const f16x8*)b, acc, 0, 0, 0);
+    else
+        return __builtin_amdgcn_mfma_f32_32x32x16_bf16(*(const bf16x8*)a, *(const bf16x8*)b, acc, 0, 0, 0);
+}
+
+// sexp: per-receiver scale exponents of the fp16 split (F16 only)
+template <int NT, bool F16>
 __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
                                                   const uint16_t* __restrict__ Bhi, const uint16_t* __restrict__ Blo,
-                                                  int64_t kp, const float2* __restrict__ Eenv, int64_t R, int64_t C,
+                                                  int64_t kp, const float2* __restrict__ Eenv,
+                                                  const int32_t* __restrict__ sexp, int64_t R, int64_t C,
                                                   float scale, float2* Eout, float* Pout, int n_tiles_n)
 {
     __shared__ __attribute__((aligned(16))) uint16_t sAh[GBM * LDA];
@@ -196,23 +256,22 @@ __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ A
         }
         for (int ks = 0; ks < GBK; ks += 16) {
             const int kofs = ks + (lane >> 5) * 8;
-            bf16x8 ah[2], al[2], bh[2], bl[2];
+            uint4 ah[2], al[2], bh[2], bl[2];
             for (int i = 0; i < 2; ++i) {
                 const int r = wm + i * 32 + (lane & 31);
-                ah[i] = *(const bf16x8*)&sAh[r * LDA + kofs];
-                al[i] = *(const bf16x8*)&sAl[r * LDA + kofs];
+                ah[i] = *(const uint4*)&sAh[r * LDA + kofs];
+                al[i] = *(const uint4*)&sAl[r * LDA + kofs];
             }
             for (int j = 0; j < 2; ++j) {
                 const int cix = wn + j * 32 + (lane & 31);
-                bh[j] = *(const bf16x8*)&sBh[cix * LDA + kofs];
-                if (NT == 3) bl[j] = *(const bf16x8*)&sBl[cix * LDA + kofs];
+                bh[j] = *(const uint4*)&sBh[cix * LDA + kofs];
+                if (NT == 3) bl[j] = *(const uint4*)&sBl[cix * LDA + kofs];
             }
             for (int i = 0; i < 2; ++i)
                 for (int j = 0; j < 2; ++j) {
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bh[j], acc[i][j], 0, 0, 0);
-                    acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al[i], bh[j], acc[i][j], 0, 0, 0);
-                    if (NT == 3)
-                        acc[i][j] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah[i], bl[j], acc[i][j], 0, 0, 0);
+                    acc[i][j] = mfma16<F16>((const uint16_t*)&ah[i], (const uint16_t*)&bh[j], acc[i][j]);
+                    acc[i][j] = mfma16<F16>((const uint16_t*)&al[i], (const uint16_t*)&bh[j], acc[i][j]);
+                    if (NT == 3) acc[i][j] = mfma16<F16>((const uint16_t*)&ah[i], (const uint16_t*)&bl[j], acc[i][j]);
                 }
         }
         __syncthreads();
@@ -226,8 +285,9 @@ __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ A
                 const int64_t r = row >> 1;
                 if (r >= R || c >= C) continue;
                 float2 e0 = Eenv[r];
-                float er = e0.x + scale * acc[i][j][e];
-                float ei = e0.y + scale * acc[i][j][e + 1];
+                const float sr = F16 ? ldexpf(scale, -sexp[r]) : scale;   // exact: a power of two
+                float er = e0.x + sr * acc[i][j][e];
+                float ei = e0.y + sr * acc[i][j][e + 1];
                 if (Eout) Eout[r * C + c] = make_float2(er, ei);
                 if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
             }
@@ -247,7 +307,9 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
         HIP_CHECK(hipGetLastError());
         return;
     }
-    const int layout = gamma_real ? 1 : 2;
+    const bool f16 = precision == 3;
+    const int layout = (gamma_real ? 1 : 2) + (f16 ? 2 : 0);   // cached split: layout and number format
+    const int lay = gamma_real ? 1 : 2;
     const int64_t kd = gamma_real ? M : 2 * M;
     const int64_t kp = round_up(kd > 0 ? kd : 1, GBK);
     const int64_t rows_p = round_up(2 * R, GBM);
@@ -258,8 +320,16 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
         ch.a_lo.release();
         ch.a_hi = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
         ch.a_lo = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
-        hipLaunchKernelGGL(k_split_A, dim3(nblk(rows_p * kp, 256)), dim3(256), 0, st, ch.H.as<float2>(), R, M, layout,
-                           rows_p, kp, ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>());
+        ch.a_sexp.release();
+        if (f16) {
+            ch.a_sexp = Scratch(c, sizeof(int32_t) * (size_t)R, st);
+            hipLaunchKernelGGL(k_row_scale, dim3(nblk(R, 4)), dim3(256), 0, st, ch.H.as<float2>(), R, M,
+                               ch.a_sexp.as<int32_t>());
+            HIP_CHECK(hipGetLastError());
+        }
+        hipLaunchKernelGGL(k_split_A, dim3(nblk(rows_p * kp, 256)), dim3(256), 0, st, ch.H.as<float2>(), R, M, lay,
+                           rows_p, kp, f16 ? ch.a_sexp.as<int32_t>() : (const int32_t*)nullptr, ch.a_hi.as<uint16_t>(),
+                           ch.a_lo.as<uint16_t>());
         HIP_CHECK(hipGetLastError());
         ch.split_kind = layout;
         ch.a_rows = rows_p;
@@ -271,19 +341,24 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
     Scratch bhi(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
     Scratch blo;
     if (three) blo = Scratch(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
-    hipLaunchKernelGGL(k_split_B, dim3(nblk(cols_p * kp, 256)), dim3(256), 0, st, G, M, C, layout, cols_p, kp,
+    hipLaunchKernelGGL(k_split_B, dim3(nblk(cols_p * kp, 256)), dim3(256), 0, st, G, M, C, lay, cols_p, kp, f16,
                        bhi.as<uint16_t>(), blo.as<uint16_t>());
     HIP_CHECK(hipGetLastError());
     const int n_tn = (int)(cols_p / GBN);
     const int64_t n_tiles = (rows_p / GBM) * n_tn;
+    const int32_t* sexp = f16 ? ch.a_sexp.as<int32_t>() : nullptr;
     if (three)
-        hipLaunchKernelGGL(k_sum_mfma<3>, dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
+        hipLaunchKernelGGL((k_sum_mfma<3, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
                            ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), blo.as<uint16_t>(), kp, ch.E_env.as<float2>(),
-                           R, C, scale, (float2*)E_out, P_out, n_tn);
-    else
-        hipLaunchKernelGGL(k_sum_mfma<2>, dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
+                           sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
+    else if (f16)
+        hipLaunchKernelGGL((k_sum_mfma<2, true>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
                            ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), (const uint16_t*)nullptr, kp,
-                           ch.E_env.as<float2>(), R, C, scale, (float2*)E_out, P_out, n_tn);
+                           ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
+    else
+        hipLaunchKernelGGL((k_sum_mfma<2, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
+                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), (const uint16_t*)nullptr, kp,
+                           ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
     HIP_CHECK(hipGetLastError());
 }
 

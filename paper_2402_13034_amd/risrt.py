@@ -37,6 +37,7 @@ FLAG_COUNT_WORK = 16
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
 PREC_MFMA_BF16X3 = 2
+PREC_MFMA_F16X2 = 3
 
 # every entry point declared in include/risrt.h
 ENTRY_POINTS = (

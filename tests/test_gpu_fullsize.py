@@ -96,7 +96,7 @@ def test_lab_room_full_size(ctx):
          % (st["segments"], hits_tx.shape[0], hits_u.shape[0], len(sample), he.max()))
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 def test_many_configuration_sum_full_size(ctx, prec):
     import torch
     from paper_2402_13034_amd import risrt

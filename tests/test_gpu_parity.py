@@ -263,7 +263,7 @@ def test_ris_sum_valu(ctx, R, M, C, real):
     assert np.max(np.abs(E - E_ref) ** 2 / np.maximum(np.abs(E_ref) ** 2, 1e-3 * (P_inc * 2 * ETA0))) < 1e-6
 
 
-@pytest.mark.parametrize("prec", [1, 2])
+@pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (300, 1024, 257, True),
                                         (64, 1024, 128, False)])
 def test_ris_sum_mfma(ctx, R, M, C, real, prec):
@@ -273,3 +273,35 @@ def test_ris_sum_mfma(ctx, R, M, C, real, prec):
     assert db.max() < 0.1, db.max()
     nrmse = np.sqrt(np.mean(np.abs(E - E_ref) ** 2) / np.mean(np.abs(E_ref) ** 2))
     assert nrmse < 1e-3, nrmse
+
+
+def test_ris_sum_f16_row_scaling_and_split_cache(ctx):
+    """fp16 split: rows of very different magnitude (1e-12 ... 1e3 V/m) and an
+    all-zero row each get their own power-of-two scale; switching the number
+    format on one channel rebuilds the cached split."""
+    import torch
+    from paper_2402_13034_amd import risrt
+    rng = np.random.default_rng(11)
+    R, M, C = 70, 200, 33
+    mag = 10.0 ** np.linspace(-12, 3, R)
+    H = ((rng.normal(size=(R, M)) + 1j * rng.normal(size=(R, M))) * mag[:, None]).astype(np.complex64)
+    H[5] = 0
+    E_env = (H[:, :2].sum(axis=1) * 0.5).astype(np.complex64)
+    G = synth.gamma_2bit(M, C, 1.0, rng).astype(np.complex64)
+    E_ref, P_ref = O.ris_sum(E_env.astype(np.complex128), H.astype(np.complex128), G.astype(np.complex128), 0.9)
+    inc = np.abs(E_env)[:, None] + 0.9 * np.abs(H).astype(np.float64) @ np.abs(G).astype(np.float64)
+    sel = (np.abs(E_ref) ** 2 >= 1e-3 * inc ** 2) & (inc > 0)   # the zero row is checked exactly below
+    ch = ctx.channel_create(E_env, H)
+    g = torch.from_numpy(G).cuda()
+    outs = {}
+    for prec in (3, 1, 3):
+        E, P = ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=False, precision=prec, want_E=True, want_P=True)
+        torch.cuda.synchronize()
+        E = E.cpu().numpy()
+        db = np.abs(10 * np.log10(np.abs(E[sel]) ** 2 / np.abs(E_ref[sel]) ** 2))
+        assert db.max() < 0.1, (prec, db.max())
+        assert np.all(E[5] == E_env[5])   # zero channel row: E = E_env exactly
+        if prec in outs:
+            assert outs[prec].tobytes() == E.tobytes()
+        outs[prec] = E
+    ctx.destroy(ch)
