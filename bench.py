@@ -253,7 +253,7 @@ def run_serving_bench(ctx, n_queries=300, n_slots=4, load=0.7):
 
     sweep = []
     sustained = None
-    for i, frac in enumerate((0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8)):
+    for i, frac in enumerate((0.1, 0.2, 0.3, 0.4, 0.5, 0.6, 0.7, 0.8, 0.9)):
         r = poisson(frac * burst_qps, 100 + 2 * i)
         sweep.append({k: round(v, 3) if isinstance(v, float) else v for k, v in r.items()})
         if r["achieved_qps"] >= 0.95 * r["offered_qps"]:
@@ -269,6 +269,8 @@ def run_serving_bench(ctx, n_queries=300, n_slots=4, load=0.7):
             "sustained_queries_per_s": sustained, "burst_saturation_queries_per_s": burst_qps, "sweep": sweep,
             "queries_per_stream": n_queries, "slots": n_slots, "traces": st["traces"], "warmup_trace_s": t_warm,
             "admission_waits": st["admission_waits"], "errors": st["errors"], "deployments": len(deps),
+            "channel_cache_hits": st["channel_cache_hits"],
+            "channel_cache_hit_rate": st["channel_cache_hits"] / max(1, st["channel_cache_hits"] + st["traces"]),
             "scene_triangles": sorted(int(s.n_tri) for s in scenes.values())}
 
 
