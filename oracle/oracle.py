@@ -72,7 +72,7 @@ def lib():
         L.or_find_paths.restype = i64
         L.or_find_paths.argtypes = [P, P, P, i64, P, P, i64, ctypes.c_int, P, i64, i64, P, P, P, P]
         L.or_ris_paths.restype = None
-        L.or_ris_paths.argtypes = [P, P, P, i64, P, P, i64, P, i64, P, P, ctypes.c_int, P, P, P, P]
+        L.or_ris_paths.argtypes = [P, P, P, i64, P, P, i64, P, i64, P, P, ctypes.c_int, P, P, P, P, P]
         L.or_leg_blocked.restype = ctypes.c_int
         L.or_leg_blocked.argtypes = [P, P, P, i64, P, P, i64, i64]
         L.or_contains.restype = ctypes.c_int
@@ -251,7 +251,12 @@ def find_paths(scene, src, cands: np.ndarray, rx: np.ndarray, K: int):
         cap = -n
 
 
-def ris_paths(scene, tx, elems, rx, uptr, useq, K: int):
+def ris_paths(scene, tx, elems, rx, uptr, useq, K: int, lit=None):
+    """Out side of the RIS paths: for every slot (direct, then the sequences
+    of V(rx)) and element, the image-method path m -> seq -> rx, valid and
+    unblocked, for the elements a field reaches (the clear direct leg, or
+    ``lit`` when the incoming reflections are modelled)."""
+    lit_a = None if lit is None else _c(lit, np.uint8)
     V = _c(scene.V, np.float32)
     T = _c(scene.T, np.int32)
     SF = _c(scene.surf, np.int32)
@@ -267,7 +272,8 @@ def ris_paths(scene, tx, elems, rx, uptr, useq, K: int):
     tri = np.zeros((n_slots, M, K), np.int32)
     txm = np.zeros(M, np.uint8)
     lib().or_ris_paths(_p(V), _p(T), _p(SF), T.shape[0], _p(tx), _p(elems), M, _p(rx), R,
-                       _p(uptr), _p(useq), K, _p(valid), _p(pts), _p(tri), _p(txm))
+                       _p(uptr), _p(useq), K, _p(valid), _p(pts), _p(tri), _p(txm),
+                       None if lit_a is None else _p(lit_a))
     return valid.astype(bool), pts, tri, txm.astype(bool)
 
 
@@ -373,6 +379,66 @@ def env_amplitudes(prob, rx_idx, tris, pts):
     return a, D, emitted
 
 
+def ris_incoming(prob, c_tx: np.ndarray):
+    """Fields reaching every element from the Tx (Section II-B, supporting
+    reflections: the image method from the Tx to the RIS, with the same
+    centre-point restriction as on the out side).  The sequences tried per
+    element are those valid and unblocked from the Tx to the RIS centre; the
+    empty sequence is the direct leg.  Per element (eqs. (4)-(6) without
+    Gamma_m, F_out and the element factor):
+      T_m = sum_p A_t(v1_p) sqrt(F_in(p)) prod(R_p) e^{-jk d_p} / d_p,
+    d_p the unfolded length, v1_p the departure and F_in the arrival
+    direction of path p.  Returns T [M], lit [M] (some path emitted), the
+    sequences valid at the centre (order >= 1), and per emitted path its
+    element, sequence row (0 = direct, i = in_seq[i - 1]) and triangles."""
+    sc = prob.scene
+    K = prob.order
+    ris = prob.ris
+    lam = prob.wavelength
+    M = ris.elems.shape[0]
+    _, c_c, _, _ = find_paths(sc, prob.tx_pos, c_tx, ris.centre[None, :], K)
+    in_seq = c_tx[c_c]
+    in_seq = in_seq[(in_seq >= 0).sum(axis=1) >= 1]
+    cands = np.concatenate([np.full((1, K), -1, np.int32), in_seq.astype(np.int32)], axis=0)
+    m_idx, j_idx, pts, tris = find_paths(sc, prob.tx_pos, cands, ris.elems, K)
+    n = m_idx.shape[0]
+    k = (tris >= 0).sum(axis=1)
+    D, first, last = _chain(np.broadcast_to(prob.tx_pos, (n, 3)), pts, k, ris.elems[m_idx])
+    ct = _cos_between(first, prob.tx_ant.axis)
+    ci = _cos_between(last, ris.normal)
+    Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, ct, lam)
+    Fin = pattern(PAT_COSPOW, ris.q, ci, lam)
+    At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
+    a = At * np.sqrt(Fin) * refl_product(sc, tris) / D * np.exp(1j * _phase(D, lam))
+    on = pattern_on(prob.tx_ant.pattern, ct) & pattern_on(PAT_COSPOW, ci)
+    T = np.zeros(M, np.complex128)
+    np.add.at(T, m_idx[on], a[on])
+    lit = np.zeros(M, bool)
+    lit[m_idx[on]] = True
+    return T, lit, in_seq, m_idx[on], j_idx[on], tris[on]
+
+
+def ris_amplitudes_in(prob, T, rx_idx, m_idx, tris, pts):
+    """Per-element channel with the incoming field T_m of ``ris_incoming``:
+    T_m sqrt(G F_out d_y d_z / 4pi) prod(R) S_r lambda / (4 pi D_r) e^{-jk D_r}."""
+    lam = prob.wavelength
+    ris = prob.ris
+    k = (tris >= 0).sum(axis=1)
+    m = ris.elems[m_idx]
+    X = prob.rx_pos[rx_idx]
+    Dr, first, last = _chain(m, pts, k, X)
+    co = _cos_between(first, ris.normal)
+    cr = _cos_between(last, prob.rx_ant.axis)
+    Fout = pattern(PAT_COSPOW, ris.q, co, lam)
+    Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, cr, lam)
+    elem = np.sqrt(ris.gain * Fout * ris.dy * ris.dz / (4.0 * math.pi))
+    Sr = np.sqrt(prob.rx_ant.gain * Fr)
+    a = (T[m_idx] * elem * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * Dr)
+         * np.exp(1j * _phase(Dr, lam)))
+    emitted = pattern_on(PAT_COSPOW, co) & pattern_on(prob.rx_ant.pattern, cr)
+    return a, Dr, emitted
+
+
 def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
     """Per-element channel (eqs. (4), (7), (8) without Gamma_m):
     A_t(Tx->m) sqrt(G F_in F_out d_y d_z / 4pi) e^{-jk d_t} / d_t prod(R) S_r
@@ -406,7 +472,7 @@ def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
 # --------------------------------------------------------------------------
 # the whole path
 # --------------------------------------------------------------------------
-def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None) -> Dict[str, np.ndarray]:
+def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = False) -> Dict[str, np.ndarray]:
     """Channel of one problem.
 
     mode = "sbr": candidate surface sequences from spherical-Fibonacci
@@ -415,6 +481,9 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None) -> Dict[str, np
     mode = "exhaustive": every sequence of at most K surfaces.
     Returns env paths (Tx -> Rx, order 0..K), the sequences V(rx) valid from
     the RIS centre, RIS slots and their validity, H [R, M] and E_env [R].
+    ris_in: the field reaching each element also by reflections Tx ->
+    surfaces -> m (``ris_incoming``; sequences of the Tx candidates valid at
+    the RIS centre); otherwise by the direct leg alone.
     """
     K = prob.order
     sc = prob.scene
@@ -465,7 +534,16 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None) -> Dict[str, np
     out["u_seq"] = u_seq
     out["uptr"] = uptr
     M = prob.ris.elems.shape[0]
-    valid, pts, tri, txm = ris_paths(sc, prob.tx_pos, prob.ris.elems, prob.rx_pos, uptr, u_seq, K)
+    T_in = lit = None
+    if ris_in:
+        T_in, lit, in_seq, in_m, in_j, in_tri = ris_incoming(prob, c_tx)
+        out["in_seq"] = in_seq
+        out["in_m"] = in_m
+        out["in_row"] = in_j
+        out["in_tri"] = in_tri
+        out["T_in"] = T_in
+        out["lit"] = lit
+    valid, pts, tri, txm = ris_paths(sc, prob.tx_pos, prob.ris.elems, prob.rx_pos, uptr, u_seq, K, lit)
     n_slots = valid.shape[0]
     slot_rx = np.repeat(np.arange(R), np.diff(uptr) + 1)
     slot_seq = np.full((n_slots, K), -1, np.int32)
@@ -474,7 +552,10 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None) -> Dict[str, np
         cnt = uptr[r + 1] - uptr[r]
         slot_seq[base + 1: base + 1 + cnt] = u_seq[uptr[r]:uptr[r + 1]]
     sl, mm = np.nonzero(valid)
-    a, dtot, em = ris_amplitudes(prob, slot_rx[sl], mm, tri[sl, mm], pts[sl, mm])
+    if ris_in:
+        a, dtot, em = ris_amplitudes_in(prob, T_in, slot_rx[sl], mm, tri[sl, mm], pts[sl, mm])
+    else:
+        a, dtot, em = ris_amplitudes(prob, slot_rx[sl], mm, tri[sl, mm], pts[sl, mm])
     H = np.zeros((R, M), np.complex128)
     np.add.at(H, (slot_rx[sl][em], mm[em]), a[em])
     emitted = np.zeros_like(valid)

@@ -514,10 +514,13 @@ int64_t or_find_paths(const float* V, const int32_t* T, const int32_t* surf, int
  *   tri[(slot * M + m) * K + j] = triangles containing them.
  * txm_clear[m] reports the Tx -> element leg.
  */
+/* lit: NULL, or per element whether any field reaches it (the incoming paths
+ * of Section II-B's supporting reflections); NULL means the direct leg
+ * Tx -> m alone decides. */
 void or_ris_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t nt,
                   const double tx[3], const double* elems, int64_t M, const double* rx, int64_t R,
                   const int64_t* uptr, const int32_t* useq, int K, uint8_t* valid, double* pts,
-                  int32_t* tri, uint8_t* txm_clear)
+                  int32_t* tri, uint8_t* txm_clear, const uint8_t* lit)
 {
     tri32* t32 = build_tris(V, T, nt);
     tri64* t64 = (tri64*)malloc(sizeof(tri64) * (size_t)(nt > 0 ? nt : 1));
@@ -541,7 +544,7 @@ void or_ris_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t
                 int64_t cell = slot * M + m;
                 for (int j = 0; j < K * 3; ++j) pts[cell * K * 3 + j] = 0.0;
                 for (int j = 0; j < K; ++j) tri[cell * K + j] = -1;
-                int ok = txm_clear[m];
+                int ok = lit ? lit[m] : txm_clear[m];
                 if (ok) ok = image_path(t64, &st, seq, k, elems + 3 * m, rx + 3 * r, P, tri_of);
                 if (ok) ok = path_clear(t32, surf, nt, seq, k, elems + 3 * m, rx + 3 * r, P);
                 valid[cell] = (uint8_t)ok;

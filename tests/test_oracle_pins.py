@@ -348,6 +348,80 @@ def test_reciprocity_env():
 
 
 # ---------------------------------------------------------------------------
+# Incoming reflections (Section II-B, supporting reflections: the image method
+# from the Tx to the RIS): one wall in closed form, and reciprocity of the
+# whole RIS field once both sides reflect
+# ---------------------------------------------------------------------------
+def test_ris_incoming_single_wall_closed_form():
+    """Field reaching each element = direct wave + the wave of the Tx's mirror
+    image in the wall (written out here from the mirror construction)."""
+    mb = synth.MeshBuilder()
+    mb.quad((0.0, -5.0, -5.0), (0.0, 10.0, 0.0), (0.0, 0.0, 10.0), 1, complex(0.4, -0.3))
+    scene = mb.build()
+    freq = 28e9
+    lam = O.C0 / freq
+    normal = np.array([0.0, -1.0, 0.0])
+    centre = np.array([1.0, 3.0, 0.0])
+    elems = synth.square_ris(2, 2, lam / 2, centre, normal)
+    ris = synth.Ris(elems, normal, centre, lam / 2, lam / 2, math.pi, 3.0)
+    tx = np.array([2.0, 0.3, 0.2])
+    bore = synth.unit([-1.0, 1.0, 0.0])
+    tx_ant = synth.Antenna(bore, 10.0, synth.PAT_COSPOW, 4.0)
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    prob = synth.Problem("wall", scene, freq, tx, 0.02, tx_ant, ris, np.array([[1.5, 1.0, 0.3]]), iso, 1, 16, 0)
+    r = O.trace(prob, mode="exhaustive", ris_in=True)
+    assert r["in_seq"].shape[0] == 1 and np.all(r["lit"])
+    img = tx * np.array([-1.0, 1.0, 1.0])   # mirror of the Tx in x = 0
+    k = 2 * math.pi / lam
+    for m, e in enumerate(elems):
+        T = 0j
+        wall = complex(float(np.float32(0.4)), float(np.float32(-0.3)))   # as the scene stores it
+        for src, start, coef in ((tx, None, 1.0), (img, True, wall)):
+            d = np.linalg.norm(e - src)
+            if start:   # reflection point on the wall, departure direction from the real Tx
+                P = src + (e - src) * (-src[0]) / (e[0] - src[0])
+                dep = P - tx
+                arr = P - e
+            else:
+                dep = e - tx
+                arr = tx - e
+            ct = dep @ bore / np.linalg.norm(dep)
+            ci = arr @ normal / np.linalg.norm(arr)
+            amp = math.sqrt(2 * ETA0 * 0.02 * 10.0 * ct ** 4.0) * math.sqrt(ci ** 3.0) * coef / d
+            T += amp * np.exp(-1j * k * d)
+        assert abs(r["T_in"][m] - T) < 1e-9 * abs(T)
+
+
+@pytest.mark.parametrize("K", [1, 2])
+def test_reciprocity_ris_with_incoming_reflections(K):
+    """Swapping isotropic Tx and Rx leaves the RIS field unchanged when
+    reflections are modelled on both sides of the RIS; with the direct
+    incoming leg alone it does not (the pin has teeth)."""
+    rng = np.random.default_rng(21)
+    scene = synth.lab_room_scene(rng, n_boxes=3, sub=1)
+    freq = 28e9
+    lam = O.C0 / freq
+    normal = np.array([-1.0, 0.0, 0.0])
+    centre = np.array([5.999, 2.5, 1.5])
+    elems = synth.square_ris(3, 3, lam / 2, centre, normal)
+    ris = synth.Ris(elems, normal, centre, lam / 2, lam / 2, math.pi, 3.0)
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    a = np.array([2.1, 1.2, 1.6])
+    b = np.array([3.3, 4.1, 1.3])
+    g = np.exp(1j * rng.uniform(0, 2 * math.pi, size=9)) * 0.9
+
+    def field(src, dst, ris_in):
+        p = synth.Problem("r", scene, freq, src, 0.01, iso, ris, dst[None, :], iso, K, 16, 0)
+        r = O.trace(p, mode="exhaustive", ris_in=ris_in)
+        return r["H"][0] @ g
+
+    e_ab, e_ba = field(a, b, True), field(b, a, True)
+    assert abs(e_ab - e_ba) < 1e-9 * abs(e_ab)
+    d_ab, d_ba = field(a, b, False), field(b, a, False)
+    assert abs(d_ab - d_ba) > 1e-3 * abs(d_ab)
+
+
+# ---------------------------------------------------------------------------
 # P7: SBR discovery finds what exhaustive search finds (tiny box)
 # ---------------------------------------------------------------------------
 def test_sbr_equals_exhaustive_tiny():
