@@ -59,6 +59,11 @@ typedef int32_t rt_status;
                                   (no discovery rays; small scenes only) */
 #define RT_FLAG_COUNT_WORK 16u /* run the counting build of the per-element kernel and
                                   report its work in rt_stats.ris_work (same results) */
+#define RT_FLAG_RIS_INCOMING 32u /* the field reaching each element also by reflections
+                                  Tx -> surfaces -> element (Section II-B, supporting
+                                  reflections): image method per element for the Tx
+                                  candidate sequences (order 1..K) valid and unblocked from
+                                  the Tx to the RIS centre; without it, the direct leg alone */
 
 /* rt_ris_sum precision */
 #define RT_PREC_VALU_F32 0   /* FP32 complex multiply-add on the vector ALUs */
@@ -121,6 +126,9 @@ typedef struct {
                                     the per-element kernel */
     int64_t leg_walk_fallbacks;  /* slots whose grouped leg walk outgrew its on-chip lists and
                                     were walked leg by leg (same results, diagnostic only) */
+    int64_t n_in_seq;            /* RT_FLAG_RIS_INCOMING: Tx candidate sequences valid and unblocked
+                                    from the Tx to the RIS centre (order >= 1) */
+    int64_t n_in_paths;          /* RT_FLAG_RIS_INCOMING: emitted paths Tx -> surfaces -> element */
 } rt_stats;
 
 /* Environment path record (RT_FLAG_KEEP_PATHS): Tx -> surfaces seq[0..k) ->

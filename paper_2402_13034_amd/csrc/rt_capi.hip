@@ -412,7 +412,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
 {
     return guarded(ctx, [&]() -> rt_status {
         if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
-        if (params->flags & ~31u) return fail(RT_EINVAL, "unknown flag");
+        if (params->flags & ~63u) return fail(RT_EINVAL, "unknown flag");
         if (params->max_order < 0 || params->max_order > RT_MAX_K)
             return fail(RT_EUNSUPPORTED, "max_order must be 0..3");
         if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
@@ -470,6 +470,8 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
             for (int k = 0; k < 8; ++k) stats->ms_stage[k] = out.ms[k];
             for (int k = 0; k < 5; ++k) stats->ris_work[k] = out.work[k];
             stats->leg_walk_fallbacks = out.leg_walk_fallbacks;
+            stats->n_in_seq = out.n_in_seq;
+            stats->n_in_paths = out.n_in_paths;
         }
         *channel = insert(ctx, o);
         return RT_OK;

@@ -198,6 +198,7 @@ struct TraceOut {
     float ms[8] = {0};
     int64_t work[5] = {0, 0, 0, 0, 0};
     int64_t leg_walk_fallbacks = 0;
+    int64_t n_in_seq = 0, n_in_paths = 0;
 };
 void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st);
 

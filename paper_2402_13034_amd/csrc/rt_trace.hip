@@ -639,10 +639,14 @@ __global__ void k_ris_order(const int64_t* uptr, const int32_t* useq, int64_t R,
 // --------------------------------------------------------------------------
 // 7. RIS
 // --------------------------------------------------------------------------
+// Field reaching element m (eqs. (4)-(6) without Gamma_m and F_out):
+// T = sum over incoming paths p of A_t(v1_p) sqrt(G F_in(p) d_y d_z / 4pi)
+// prod(R_p) e^{-jk d_p} / d_p; the direct leg, plus the reflections Tx ->
+// surfaces -> m when they are modelled.
 struct TxmRec {
-    float fac;     // A_t(Tx->m) sqrt(G F_in d_y d_z / 4pi) / d_t
-    int ok;        // leg clear and F_t, F_in > 0
-    double dt;
+    float2 T;
+    int ok;        // some incoming path emitted (clear legs, F_t, F_in > 0)
+    int pad;
 };
 
 template <bool BRUTE, int STK>
@@ -668,13 +672,171 @@ __global__ __launch_bounds__(64) void k_txm(SceneView s, TraceConst tc, RisView 
         }
         TxmRec r;
         r.ok = ok ? 1 : 0;
-        r.dt = dt;
-        r.fac = ok ? (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
-                             sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / dt)
-                   : 0.0f;
+        r.pad = 0;
+        r.T = make_float2(0.0f, 0.0f);
+        if (ok) {
+            const float fac = (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
+                                      sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / dt);
+            float cs, sn;
+            phase_cs(dt, tc.lambda, cs, sn);
+            r.T = make_float2(fac * cs, fac * sn);
+        }
         out[m] = r;
     }
     wave_count_add(segs, nseg);
+}
+
+// Incoming reflections (Section II-B, supporting reflections): the image
+// method from the Tx to the RIS, restricted like the out side to the
+// sequences valid from the Tx to the RIS centre u.
+// 1) per Tx candidate of order >= 1: valid and unblocked from the Tx to u?
+template <bool BRUTE, int STK>
+__global__ __launch_bounds__(LEG_B) void k_in_centre(SceneView s, CandView cv, double sx, double sy, double sz,
+                                                     double ux, double uy, double uz, uint8_t* ok_out,
+                                                     unsigned long long* segs)
+{
+    __shared__ int stack[STK * LEG_B];
+    const int64_t c = (int64_t)blockIdx.x * LEG_B + threadIdx.x;
+    unsigned nseg = 0;
+    if (c < cv.n) {
+        const double S[3] = {sx, sy, sz};
+        const double X[3] = {ux, uy, uz};
+        double P[RT_MAX_K][3];
+        int tri[RT_MAX_K] = {-1, -1, -1};
+        int k = 0;
+        bool ok = cv.k[c] >= 1 && geo_path(s, cv, c, S, X, P, tri, k);
+        double V[RT_MAX_K + 2][3];
+        for (int q = 0; q < 3; ++q) {
+            V[0][q] = S[q];
+            V[1][q] = k >= 1 ? P[0][q] : X[q];
+            V[2][q] = k >= 2 ? P[1][q] : X[q];
+            V[3][q] = k >= 3 ? P[2][q] : X[q];
+            V[4][q] = X[q];
+        }
+        int sq[RT_MAX_K];
+        for (int j = 0; j < RT_MAX_K; ++j) sq[j] = cv.seq[3 * c + j];
+#pragma unroll
+        for (int j = 0; j <= RT_MAX_K; ++j) {
+            if (j > k || !ok) break;
+            const int sa = j == 0 ? -1 : sq[j > 0 ? j - 1 : 0];
+            const int sb = j == k ? -1 : sq[j < RT_MAX_K ? j : 0];
+            ++nseg;
+            if (leg_blocked<BRUTE>(s, V[j], V[j + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
+        }
+        ok_out[c] = ok ? 1 : 0;
+    }
+    wave_count_add(segs, nseg);
+}
+
+__global__ void k_in_list(const uint8_t* ok, const int64_t* off, int64_t n, int32_t* list)
+{
+    const int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (c < n && ok[c]) list[off[c]] = (int32_t)c;
+}
+
+// 2) per (sequence j of the list, element m): the path Tx -> seq -> m, its legs
+// and its contribution to T_m (zero if not emitted); *n_in = list length
+template <bool BRUTE, int STK>
+__global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, TraceConst tc, RisView rv,
+                                                   const int32_t* list, const int64_t* n_in, float2* contrib,
+                                                   uint8_t* emitted_out, unsigned long long* segs,
+                                                   unsigned long long* n_paths)
+{
+    __shared__ int stack[STK * LEG_B];
+    const int64_t i = (int64_t)blockIdx.x * LEG_B + threadIdx.x;
+    const int64_t M = rv.M;
+    const int64_t nl = *n_in;
+    unsigned nseg = 0, emitted = 0;
+    if (i < nl * M) {
+        const int64_t j = i / M, m = i - j * M;
+        const int64_t c = list[j];
+        const double S[3] = {tc.tx[0], tc.tx[1], tc.tx[2]};
+        const double X[3] = {rv.elem[3 * m], rv.elem[3 * m + 1], rv.elem[3 * m + 2]};
+        double P[RT_MAX_K][3];
+        int tri[RT_MAX_K] = {-1, -1, -1};
+        int k = 0;
+        bool ok = geo_path(s, cv, c, S, X, P, tri, k);
+        double V[RT_MAX_K + 2][3];
+        for (int q = 0; q < 3; ++q) {
+            V[0][q] = S[q];
+            V[1][q] = k >= 1 ? P[0][q] : X[q];
+            V[2][q] = k >= 2 ? P[1][q] : X[q];
+            V[3][q] = k >= 3 ? P[2][q] : X[q];
+            V[4][q] = X[q];
+        }
+        float Ft = 0.0f, Fin = 0.0f;
+        if (ok) {
+            double v1[3], back[3];
+            for (int q = 0; q < 3; ++q) {
+                v1[q] = V[1][q] - S[q];
+                const double lq = k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
+                back[q] = lq - X[q];
+            }
+            const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
+            const double ci = cos_between(back, rv.normal, rv.normal_norm);
+            Ft = pattern_amp(tc.txa.pattern, tc.txa.param, ct);
+            Fin = pattern_amp(1, rv.q, ci);
+            ok = pattern_on(tc.txa.pattern, ct) && pattern_on(1, ci);
+        }
+        int sq[RT_MAX_K];
+        for (int q = 0; q < RT_MAX_K; ++q) sq[q] = cv.seq[3 * c + q];
+#pragma unroll
+        for (int q = 0; q <= RT_MAX_K; ++q) {
+            if (q > k || !ok) break;
+            const int sa = q == 0 ? -1 : sq[q > 0 ? q - 1 : 0];
+            const int sb = q == k ? -1 : sq[q < RT_MAX_K ? q : 0];
+            ++nseg;
+            if (leg_blocked<BRUTE>(s, V[q], V[q + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
+        }
+        float2 a = make_float2(0.0f, 0.0f);
+        if (ok) {
+            double D = 0.0;
+#pragma unroll
+            for (int q = 0; q <= RT_MAX_K; ++q)
+                if (q <= k) D += seg_len(V[q], V[q + 1]);
+            float ar = 1.0f, ai = 0.0f;
+#pragma unroll
+            for (int q = 0; q < RT_MAX_K; ++q) {
+                if (q >= k) break;
+                const float2 Rc = s.refl[tri[q]];
+                const float nr = ar * Rc.x - ai * Rc.y;
+                const float ni = ar * Rc.y + ai * Rc.x;
+                ar = nr;
+                ai = ni;
+            }
+            const float mag = (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
+                                      sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / D);
+            float cs, sn;
+            phase_cs(D, tc.lambda, cs, sn);
+            a = make_float2(mag * (ar * cs - ai * sn), mag * (ar * sn + ai * cs));
+            emitted = 1;
+        }
+        contrib[i] = a;
+        emitted_out[i] = (uint8_t)emitted;
+    }
+    wave_count_add(segs, nseg);
+    wave_count_add(n_paths, emitted);
+}
+
+// 3) per element: T_m += the contributions of the list in list order (FP64)
+__global__ void k_in_sum(const float2* contrib, const uint8_t* emitted, const int64_t* n_in, int64_t M,
+                         TxmRec* txm)
+{
+    const int64_t m = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (m >= M) return;
+    const int64_t nl = *n_in;
+    TxmRec r = txm[m];
+    double tr = r.T.x, ti = r.T.y;
+    bool lit = r.ok != 0;
+    for (int64_t j = 0; j < nl; ++j) {
+        const float2 a = contrib[j * M + m];
+        if (emitted[j * M + m]) lit = true;
+        tr += (double)a.x;
+        ti += (double)a.y;
+    }
+    r.T = make_float2((float)tr, (float)ti);
+    r.ok = lit ? 1 : 0;
+    txm[m] = r;
 }
 
 constexpr int RIS_B = 128;
@@ -845,12 +1007,14 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         ar = nr;
                         ai = ni;
                     }
-                    float mag = t.fac * Fout * sqrtf((float)tc.rxa.gain) * Fr *
-                                (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
+                    const float mag = Fout * sqrtf((float)tc.rxa.gain) * Fr *
+                                      (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
                     float cs, sn;
-                    phase_cs(t.dt + Dr, tc.lambda, cs, sn);
-                    amp_r = mag * (ar * cs - ai * sn);
-                    amp_i = mag * (ar * sn + ai * cs);
+                    phase_cs(Dr, tc.lambda, cs, sn);
+                    // incoming field x reflections x out-going phase
+                    const float zr = t.T.x * ar - t.T.y * ai, zi = t.T.x * ai + t.T.y * ar;
+                    amp_r = mag * (zr * cs - zi * sn);
+                    amp_i = mag * (zr * sn + zi * cs);
                 }
             }
             // phase 2 (FP32): visibility of every leg, the wave walking the BVH together
@@ -1170,6 +1334,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     const bool keep_paths = (a.tc.flags & 2) != 0;
     const bool exhaustive = (a.tc.flags & 8) != 0;
     const bool count_work = (a.tc.flags & 16) != 0;
+    const bool incoming = (a.tc.flags & 32) != 0;   // reflections Tx -> surfaces -> element
     const int stk = stack_depth_for(*a.scene, brute);
     const int64_t R = a.R;
     const int64_t M = a.ris ? a.ris->M : 0;
@@ -1183,8 +1348,11 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // [5..7] centre count / append / hash overflow, [8..12] work of the counting build,
     // [13] valid environment paths, [14] per-element slots whose grouped leg walk fell back,
     // [15] discovery segments of a repeated phase A (not reported)
-    Scratch ctr(c, 128, st);
-    HIP_CHECK(hipMemsetAsync(ctr.p, 0, 128, st));
+    // 0 discovery segments, 1 legs, 2-4 Tx branch counts, 5-7 centre branch counts,
+    // 8-12 work, 13 env paths, 14 leg-walk fallbacks, 15 dummy segments,
+    // 16 incoming sequences, 17 incoming element paths
+    Scratch ctr(c, 8 * 18, st);
+    HIP_CHECK(hipMemsetAsync(ctr.p, 0, 8 * 18, st));
     unsigned long long* d_ctr = ctr.as<unsigned long long>();
     unsigned long long* d_disc = d_ctr;
     unsigned long long* d_legs = d_ctr + 1;
@@ -1322,6 +1490,35 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                  SEL_STK(stk, hipLaunchKernelGGL((k_txm<BR, STK>), dim3(nblk(M, 64)), dim3(64), 0, st, sv, a.tc, rv,
                                                  txm.as<TxmRec>(), d_legs)));
         HIP_CHECK(hipGetLastError());
+        if (incoming && M > 0 && bt.cd.n > 0) {
+            // sequences valid from the Tx to the RIS centre, then every (sequence, element)
+            const int64_t nc = bt.cd.n;
+            Scratch in_ok(c, (size_t)nc, st), in_off(c, sizeof(int64_t) * (size_t)nc, st),
+                in_list(c, sizeof(int32_t) * (size_t)nc, st);
+            int64_t* d_nin = (int64_t*)(d_ctr + 16);
+            SEL_BOOL(brute, BR,
+                     SEL_STK(stk, hipLaunchKernelGGL((k_in_centre<BR, STK>), dim3(nblk(nc, LEG_B)), dim3(LEG_B), 0,
+                                                     st, sv, bt.cd.view(), a.tc.tx[0], a.tc.tx[1], a.tc.tx[2],
+                                                     rv.centre[0], rv.centre[1], rv.centre[2], in_ok.as<uint8_t>(),
+                                                     d_legs)));
+            HIP_CHECK(hipGetLastError());
+            scan_flags(c, in_ok.as<uint8_t>(), in_off.as<int64_t>(), nc, d_nin, st);
+            hipLaunchKernelGGL(k_in_list, dim3(nblk(nc, 256)), dim3(256), 0, st, in_ok.as<uint8_t>(),
+                               in_off.as<int64_t>(), nc, in_list.as<int32_t>());
+            HIP_CHECK(hipGetLastError());
+            // launched for every candidate (no size read-back); rows past the list's length exit
+            if (nc > ((int64_t)1 << 40) / M) throw inval_error("candidates x elements too large");
+            Scratch contrib(c, sizeof(float2) * (size_t)(nc * M), st), emitted(c, (size_t)(nc * M), st);
+            SEL_BOOL(brute, BR,
+                     SEL_STK(stk, hipLaunchKernelGGL((k_in_elem<BR, STK>), dim3(nblk(nc * M, LEG_B)), dim3(LEG_B),
+                                                     0, st, sv, bt.cd.view(), a.tc, rv, in_list.as<int32_t>(), d_nin,
+                                                     contrib.as<float2>(), emitted.as<uint8_t>(), d_legs,
+                                                     d_ctr + 17)));
+            HIP_CHECK(hipGetLastError());
+            hipLaunchKernelGGL(k_in_sum, dim3(nblk(M, 128)), dim3(128), 0, st, contrib.as<float2>(),
+                               emitted.as<uint8_t>(), d_nin, M, txm.as<TxmRec>());
+            HIP_CHECK(hipGetLastError());
+        }
         ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
         if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
         int n_mchunk = (int)((M + 63) / 64);
@@ -1375,8 +1572,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             p->st = st;
         if (!keep_paths) useq.st = st;
     }
-    int64_t h[15];
-    read_i64s((const int64_t*)d_ctr, h, 15, st);
+    int64_t h[18];
+    read_i64s((const int64_t*)d_ctr, h, 18, st);
     tm.mark();   // 7
     out.disc_segments = h[0];
     out.leg_segments = h[1];
@@ -1388,6 +1585,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     ch.n_slots = out.n_slots;
     for (int q = 0; q < 5; ++q) out.work[q] = h[8 + q];
     out.leg_walk_fallbacks = h[14];
+    out.n_in_seq = incoming && a.ris ? h[16] : 0;
+    out.n_in_paths = incoming && a.ris ? h[17] : 0;
     if (timing) {
         HIP_CHECK(hipStreamSynchronize(st));
         auto el = [&](int i, int j) {

@@ -33,6 +33,7 @@ FLAG_KEEP_PATHS = 2
 FLAG_BRUTE_FORCE = 4
 FLAG_EXHAUSTIVE = 8
 FLAG_COUNT_WORK = 16
+FLAG_RIS_INCOMING = 32
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
@@ -67,7 +68,8 @@ class RtStats(ctypes.Structure):
                 ("leg_segments", ctypes.c_int64), ("n_cand_tx", ctypes.c_int64), ("n_cand_u", ctypes.c_int64),
                 ("n_env_paths", ctypes.c_int64), ("n_u_paths", ctypes.c_int64), ("n_ris_slots", ctypes.c_int64),
                 ("ms_stage", ctypes.c_float * 8), ("ris_work", ctypes.c_int64 * 5),
-                ("leg_walk_fallbacks", ctypes.c_int64)]
+                ("leg_walk_fallbacks", ctypes.c_int64), ("n_in_seq", ctypes.c_int64),
+                ("n_in_paths", ctypes.c_int64)]
 
     def as_dict(self):
         d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_stage", "ris_work")}

@@ -64,13 +64,19 @@ def _incoherent(idx, amp, shape):
     return s
 
 
-def check_problem(ctx, prob, n_rays=None, brute=False):
+def check_problem(ctx, prob, n_rays=None, brute=False, incoming=False):
     from paper_2402_13034_amd import risrt
     K = prob.order
-    flags = risrt.FLAG_KEEP_HITS | risrt.FLAG_KEEP_PATHS | (risrt.FLAG_BRUTE_FORCE if brute else 0)
-    _say("case", prob.name, "rays", n_rays or prob.n_rays, "R", prob.rx_pos.shape[0], "K", K, "brute", brute)
+    flags = risrt.FLAG_KEEP_HITS | risrt.FLAG_KEEP_PATHS | (risrt.FLAG_BRUTE_FORCE if brute else 0) | \
+        (risrt.FLAG_RIS_INCOMING if incoming else 0)
+    _say("case", prob.name, "rays", n_rays or prob.n_rays, "R", prob.rx_pos.shape[0], "K", K, "brute", brute,
+         "incoming", incoming)
     scene, ris, ch, st = _run(ctx, prob, flags, n_rays)
-    ref = O.trace(prob, n_rays=n_rays)
+    ref = O.trace(prob, n_rays=n_rays, ris_in=incoming)
+    if incoming:
+        # sequences valid from the Tx to the RIS centre, and emitted reflected paths Tx -> seq -> m
+        assert st["n_in_seq"] == ref["in_seq"].shape[0]
+        assert st["n_in_paths"] == int((ref["in_row"] > 0).sum())
     # discovery hit lists: bit exact
     h_tx = ctx.hits_read(ch, 0, K)
     assert np.array_equal(h_tx, ref["hits_tx"])
@@ -143,6 +149,23 @@ def test_first_hash_set_sized_from_last_call(ctx):
         check_problem(c, synth.lab_room(nx=8, ny=8), n_rays=50_000)
     finally:
         c.close()
+
+
+def test_ris_incoming_reflections_tiny_box(ctx):
+    """Fields reaching the elements by wall reflections from the Tx too
+    (direct + 5 walls per element; the wall behind the RIS is seen from
+    behind and dropped by the element pattern)."""
+    st = check_problem(ctx, synth.tiny_box(), incoming=True)
+    assert st["n_in_paths"] == 49 * 5
+
+
+def test_ris_incoming_reflections_lab_room(ctx):
+    st = check_problem(ctx, synth.lab_room(nx=9, ny=7), n_rays=20_000, incoming=True)
+    assert st["n_in_seq"] > 10 and st["n_in_paths"] > 127
+
+
+def test_ris_incoming_reflections_brute_force(ctx):
+    check_problem(ctx, synth.lab_room(nx=5, ny=4, order=2), n_rays=4000, brute=True, incoming=True)
 
 
 def test_sparse_array_leg_walk_fallback(ctx):
