@@ -127,9 +127,33 @@ def run_trace_bench(ctx, prob, steps, warmup):
     scene = ctx.scene_create(*mesh)
     ch, cst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_COUNT_WORK)
     ctx.destroy(ch)
+    # the same step with the reflections Tx -> surfaces -> element as well (its own line,
+    # not the headline: the workload's channel has the direct incoming leg only)
+    n_in = max(2, steps // 2)
+    ch, _ = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_RIS_INCOMING)   # warm-up
+    ctx.destroy(ch)
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        t2 = time.perf_counter()
+        in_stats = []
+        for _ in range(n_in):
+            ch, sti = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_RIS_INCOMING)
+            ctx.ris_sum(ch, gamma, precision=risrt.PREC_VALU_F32, want_P=False, P_out=P_out)
+            ctx.destroy(ch)
+            in_stats.append(sti)
+        torch.cuda.synchronize()
+        t3 = time.perf_counter()
+    finally:
+        gc.enable()
+    incoming = {"ms_per_step_without_scene_build": (t3 - t2) / n_in * 1e3, "steps": n_in,
+                "segments_per_step": in_stats[-1]["segments"], "n_in_seq": in_stats[-1]["n_in_seq"],
+                "n_in_paths": in_stats[-1]["n_in_paths"],
+                "Mray_segments_per_s": sum(x["segments"] for x in in_stats) / (t3 - t2) / 1e6}
     ctx.destroy(scene)
     ctx.destroy(ris)
-    return stats, t1 - t0, cst["ris_work"]
+    return stats, t1 - t0, cst["ris_work"], incoming
 
 
 def run_gemm_bench(ctx, reps=5):
@@ -328,7 +352,8 @@ def main():
     ctx = risrt.Context(0)
     log("bench: lab room, %d triangles, M=%d, R=%d, K=%d, rays=%d" % (
         prob.scene.n_tri, prob.ris.elems.shape[0], prob.rx_pos.shape[0], prob.order, prob.n_rays))
-    stats, dt, work = run_trace_bench(ctx, prob, args.steps, args.warmup)
+    stats, dt, work, incoming = run_trace_bench(ctx, prob, args.steps, args.warmup)
+    log("bench: with incoming reflections %s" % json.dumps(incoming))
     segs = sum(s["segments"] for s in stats)
     value = segs / dt / 1e6
     ms_step = dt / args.steps * 1e3
@@ -377,6 +402,7 @@ def main():
                    "host_ms_scene_trace_sum_destroy": [round(float(np.mean([s["host_ms"][k] for s in stats])), 3)
                                                        for k in range(4)]},
         "roofline": roofline,
+        "ris_incoming_reflections": incoming,
         "ris_sum": gemm,
         "serving": serving,
         "latency_p50_ms": serving["p50_ms"] if serving else None,

@@ -1126,6 +1126,67 @@ struct Branch {
     int64_t n_words = 0;
 };
 
+// RIS description for the kernels
+static RisView make_ris_view(const TraceArgs& a)
+{
+    RisView rv;
+    rv.M = (int32_t)a.ris->M;
+    rv.pad = 0;
+    rv.elem = a.ris->elem.as<double>();
+    for (int q = 0; q < 3; ++q) {
+        rv.centre[q] = a.ris->centre[q];
+        rv.normal[q] = a.ris->normal[q];
+    }
+    rv.normal_norm = sqrt(rv.normal[0] * rv.normal[0] + rv.normal[1] * rv.normal[1] + rv.normal[2] * rv.normal[2]);
+    rv.dy = a.ris->dy;
+    rv.dz = a.ris->dz;
+    rv.gain = a.ris->gain > 0 ? a.ris->gain
+                              : 4.0 * 3.141592653589793 * a.ris->dy * a.ris->dz / (a.tc.lambda * a.tc.lambda);
+    rv.q = a.ris->q;
+    return rv;
+}
+
+// The field reaching every element (TxmRec per element, in txm): the direct
+// leg, and with `incoming` the reflections Tx -> surfaces -> element for the
+// Tx candidates valid at the RIS centre.  Launched on stream si (beside the
+// path kernels); its scratch lives on si.
+static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool incoming,
+                         const Branch& bt, const RisView& rv, unsigned long long* d_ctr, TxmRec* txm, hipStream_t si)
+{
+    const int64_t M = rv.M;
+    unsigned long long* d_legs = d_ctr + 1;
+    SEL_BOOL(brute, BR,
+             SEL_STK(stk, hipLaunchKernelGGL((k_txm<BR, STK>), dim3(nblk(M, 64)), dim3(64), 0, si, sv, a.tc, rv, txm,
+                                             d_legs)));
+    HIP_CHECK(hipGetLastError());
+    if (!incoming || M == 0 || bt.cd.n == 0) return;
+    // sequences valid from the Tx to the RIS centre, then every (sequence, element)
+    const int64_t nc = bt.cd.n;
+    Scratch in_ok(c, (size_t)nc, si), in_off(c, sizeof(int64_t) * (size_t)nc, si),
+        in_list(c, sizeof(int32_t) * (size_t)nc, si);
+    int64_t* d_nin = (int64_t*)(d_ctr + 16);
+    SEL_BOOL(brute, BR,
+             SEL_STK(stk, hipLaunchKernelGGL((k_in_centre<BR, STK>), dim3(nblk(nc, LEG_B)), dim3(LEG_B), 0, si, sv,
+                                             bt.cd.view(), a.tc.tx[0], a.tc.tx[1], a.tc.tx[2], rv.centre[0],
+                                             rv.centre[1], rv.centre[2], in_ok.as<uint8_t>(), d_legs)));
+    HIP_CHECK(hipGetLastError());
+    scan_flags(c, in_ok.as<uint8_t>(), in_off.as<int64_t>(), nc, d_nin, si);
+    hipLaunchKernelGGL(k_in_list, dim3(nblk(nc, 256)), dim3(256), 0, si, in_ok.as<uint8_t>(), in_off.as<int64_t>(),
+                       nc, in_list.as<int32_t>());
+    HIP_CHECK(hipGetLastError());
+    // launched for every candidate (no size read-back); rows past the list's length exit
+    if (nc > ((int64_t)1 << 40) / M) throw inval_error("candidates x elements too large");
+    Scratch contrib(c, sizeof(float2) * (size_t)(nc * M), si), emitted(c, (size_t)(nc * M), si);
+    SEL_BOOL(brute, BR,
+             SEL_STK(stk, hipLaunchKernelGGL((k_in_elem<BR, STK>), dim3(nblk(nc * M, LEG_B)), dim3(LEG_B), 0, si, sv,
+                                             bt.cd.view(), a.tc, rv, in_list.as<int32_t>(), d_nin,
+                                             contrib.as<float2>(), emitted.as<uint8_t>(), d_legs, d_ctr + 17)));
+    HIP_CHECK(hipGetLastError());
+    hipLaunchKernelGGL(k_in_sum, dim3(nblk(M, 128)), dim3(128), 0, si, contrib.as<float2>(), emitted.as<uint8_t>(),
+                       d_nin, M, txm);
+    HIP_CHECK(hipGetLastError());
+}
+
 // Phase A of the candidates: discovery rays, prefix keys into a hash set,
 // occupied slots compacted behind a leading 0 (the empty sequence); the
 // count is left in d_app[0] (overflow flag in d_app[1]).  Exhaustive mode:
@@ -1410,11 +1471,27 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 4: geometry of every (receiver, candidate)
     geo_launch(c, sv, a, bt, n_tx);
     if (two) geo_launch(c, sv, a, bu, n_u0);
+    // the field reaching every element, on its own stream (forked here, launched
+    // after the path kernels so that they go first)
+    RisView rv{};
+    Scratch txm;
+    Event in_fork, in_ready;
+    SideStream side_in(c);
+    if (a.ris) {
+        rv = make_ris_view(a);
+        txm = Scratch(c, sizeof(TxmRec) * (size_t)rv.M, st);
+        HIP_CHECK(hipEventRecord(in_fork.e, st));
+        HIP_CHECK(hipStreamWaitEvent(side_in.s, in_fork.e, 0));
+    }
     const int64_t g_tx = read_i64(bt.ps.rstart.as<int64_t>() + R, st);
     const int64_t g_u = two ? read_i64(bu.ps.rstart.as<int64_t>() + R, bu.st) : 0;
     // 5-6: legs and fields
     paths_launch(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
     if (two) paths_launch(c, sv, stk, a, brute, false, bu, g_u, d_legs);
+    if (a.ris) {
+        ris_incident(c, sv, stk, a, brute, incoming, bt, rv, d_ctr, txm.as<TxmRec>(), side_in.s);
+        HIP_CHECK(hipEventRecord(in_ready.e, side_in.s));
+    }
 
     // environment field per receiver (Tx branch)
     {
@@ -1471,54 +1548,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         tm.mark();
         tm.mark();
     } else {
-        RisView rv;
-        rv.M = (int32_t)M;
-        rv.pad = 0;
-        rv.elem = a.ris->elem.as<double>();
-        for (int q = 0; q < 3; ++q) {
-            rv.centre[q] = a.ris->centre[q];
-            rv.normal[q] = a.ris->normal[q];
-        }
-        rv.normal_norm = sqrt(rv.normal[0] * rv.normal[0] + rv.normal[1] * rv.normal[1] + rv.normal[2] * rv.normal[2]);
-        rv.dy = a.ris->dy;
-        rv.dz = a.ris->dz;
-        rv.gain = a.ris->gain > 0 ? a.ris->gain
-                                  : 4.0 * 3.141592653589793 * a.ris->dy * a.ris->dz / (a.tc.lambda * a.tc.lambda);
-        rv.q = a.ris->q;
-        Scratch txm(c, sizeof(TxmRec) * (size_t)M, st);
-        SEL_BOOL(brute, BR,
-                 SEL_STK(stk, hipLaunchKernelGGL((k_txm<BR, STK>), dim3(nblk(M, 64)), dim3(64), 0, st, sv, a.tc, rv,
-                                                 txm.as<TxmRec>(), d_legs)));
-        HIP_CHECK(hipGetLastError());
-        if (incoming && M > 0 && bt.cd.n > 0) {
-            // sequences valid from the Tx to the RIS centre, then every (sequence, element)
-            const int64_t nc = bt.cd.n;
-            Scratch in_ok(c, (size_t)nc, st), in_off(c, sizeof(int64_t) * (size_t)nc, st),
-                in_list(c, sizeof(int32_t) * (size_t)nc, st);
-            int64_t* d_nin = (int64_t*)(d_ctr + 16);
-            SEL_BOOL(brute, BR,
-                     SEL_STK(stk, hipLaunchKernelGGL((k_in_centre<BR, STK>), dim3(nblk(nc, LEG_B)), dim3(LEG_B), 0,
-                                                     st, sv, bt.cd.view(), a.tc.tx[0], a.tc.tx[1], a.tc.tx[2],
-                                                     rv.centre[0], rv.centre[1], rv.centre[2], in_ok.as<uint8_t>(),
-                                                     d_legs)));
-            HIP_CHECK(hipGetLastError());
-            scan_flags(c, in_ok.as<uint8_t>(), in_off.as<int64_t>(), nc, d_nin, st);
-            hipLaunchKernelGGL(k_in_list, dim3(nblk(nc, 256)), dim3(256), 0, st, in_ok.as<uint8_t>(),
-                               in_off.as<int64_t>(), nc, in_list.as<int32_t>());
-            HIP_CHECK(hipGetLastError());
-            // launched for every candidate (no size read-back); rows past the list's length exit
-            if (nc > ((int64_t)1 << 40) / M) throw inval_error("candidates x elements too large");
-            Scratch contrib(c, sizeof(float2) * (size_t)(nc * M), st), emitted(c, (size_t)(nc * M), st);
-            SEL_BOOL(brute, BR,
-                     SEL_STK(stk, hipLaunchKernelGGL((k_in_elem<BR, STK>), dim3(nblk(nc * M, LEG_B)), dim3(LEG_B),
-                                                     0, st, sv, bt.cd.view(), a.tc, rv, in_list.as<int32_t>(), d_nin,
-                                                     contrib.as<float2>(), emitted.as<uint8_t>(), d_legs,
-                                                     d_ctr + 17)));
-            HIP_CHECK(hipGetLastError());
-            hipLaunchKernelGGL(k_in_sum, dim3(nblk(M, 128)), dim3(128), 0, st, contrib.as<float2>(),
-                               emitted.as<uint8_t>(), d_nin, M, txm.as<TxmRec>());
-            HIP_CHECK(hipGetLastError());
-        }
+        HIP_CHECK(hipStreamWaitEvent(st, in_ready.e, 0));   // the field reaching every element
         ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
         if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
         int n_mchunk = (int)((M + 63) / 64);
