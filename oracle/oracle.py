@@ -346,6 +346,63 @@ def _chain(S: np.ndarray, P: np.ndarray, k: np.ndarray, X: np.ndarray):
     return D, first, last
 
 
+EPS0 = 8.8541878128e-12   # F/m
+
+
+def fresnel(eps: np.ndarray, cos_i: np.ndarray, pol: int) -> np.ndarray:
+    """Fresnel reflection coefficient of a half-space of complex relative
+    permittivity eps for a plane wave from free space at incidence angle
+    theta (cos_i = cos theta >= 0), Section II-B's specular reflection:
+      TE (pol 1, E perpendicular to the plane of incidence):
+        (cos - sqrt(eps - sin^2)) / (cos + sqrt(eps - sin^2));
+      TM (pol 2, E in the plane of incidence):
+        (eps cos - sqrt(eps - sin^2)) / (eps cos + sqrt(eps - sin^2)),
+    principal square root (the transmitted wave decays into a lossy medium)."""
+    c = np.asarray(cos_i, np.float64)
+    e = np.asarray(eps, np.complex128)
+    root = np.sqrt(e - (1.0 - c * c))
+    if pol == 1:
+        return (c - root) / (c + root)
+    if pol == 2:
+        return (e * c - root) / (e * c + root)
+    raise ValueError(pol)
+
+
+def material_eps(prob, tris: np.ndarray) -> np.ndarray:
+    """Complex relative permittivity eps_r - j sigma / (omega eps0) of the
+    triangles at the problem's frequency."""
+    er = prob.mat_eps_r.astype(np.float64)[tris]
+    sg = prob.mat_sigma.astype(np.float64)[tris]
+    return er - 1j * sg / (2.0 * math.pi * prob.freq * EPS0)
+
+
+def bounce_coefs(prob, S: np.ndarray, pts: np.ndarray, tris: np.ndarray) -> np.ndarray:
+    """Product over the bounces of a path of its reflection coefficients: the
+    triangle's fixed coefficient, or with ``prob.fresnel`` the Fresnel
+    coefficient of its material at the angle between the arriving leg
+    (previous point -> reflection point) and the triangle's normal
+    (e1 x e2 from its FP64 vertices).  S: [n, 3] path start; pts: [n, K, 3]."""
+    if not prob.fresnel:
+        return refl_product(prob.scene, tris)
+    V = prob.scene.V.astype(np.float64)
+    T = prob.scene.T
+    n = tris.shape[0]
+    out = np.ones(n, np.complex128)
+    for j in range(tris.shape[1]):
+        t = tris[:, j]
+        sel = t >= 0
+        if not np.any(sel):
+            continue
+        tt = t[sel]
+        a, b, c = V[T[tt, 0]], V[T[tt, 1]], V[T[tt, 2]]
+        nrm = np.cross(b - a, c - a)
+        prev = S[sel] if j == 0 else pts[sel, j - 1]
+        d = pts[sel, j] - prev
+        cos_i = np.abs(np.sum(d * nrm, axis=1)) / (np.linalg.norm(d, axis=1) * np.linalg.norm(nrm, axis=1))
+        out[sel] *= fresnel(material_eps(prob, tt), np.minimum(cos_i, 1.0), prob.fresnel)
+    return out
+
+
 def refl_product(scene, tris: np.ndarray) -> np.ndarray:
     """Product of the reflection coefficients of the triangles a path
     reflects on (-1 entries are no reflection)."""
@@ -374,7 +431,7 @@ def env_amplitudes(prob, rx_idx, tris, pts):
     Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, cr, lam)
     At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
     Sr = np.sqrt(prob.rx_ant.gain * Fr)
-    a = At * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * D) * np.exp(1j * _phase(D, lam))
+    a = At * bounce_coefs(prob, S, pts, tris) * Sr * lam / (4.0 * math.pi * D) * np.exp(1j * _phase(D, lam))
     emitted = pattern_on(prob.tx_ant.pattern, ct) & pattern_on(prob.rx_ant.pattern, cr)
     return a, D, emitted
 
@@ -409,7 +466,8 @@ def ris_incoming(prob, c_tx: np.ndarray):
     Ft = pattern(prob.tx_ant.pattern, prob.tx_ant.param, ct, lam)
     Fin = pattern(PAT_COSPOW, ris.q, ci, lam)
     At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
-    a = At * np.sqrt(Fin) * refl_product(sc, tris) / D * np.exp(1j * _phase(D, lam))
+    a = (At * np.sqrt(Fin) * bounce_coefs(prob, np.broadcast_to(prob.tx_pos, (n, 3)), pts, tris) / D
+         * np.exp(1j * _phase(D, lam)))
     on = pattern_on(prob.tx_ant.pattern, ct) & pattern_on(PAT_COSPOW, ci)
     T = np.zeros(M, np.complex128)
     np.add.at(T, m_idx[on], a[on])
@@ -433,7 +491,7 @@ def ris_amplitudes_in(prob, T, rx_idx, m_idx, tris, pts):
     Fr = pattern(prob.rx_ant.pattern, prob.rx_ant.param, cr, lam)
     elem = np.sqrt(ris.gain * Fout * ris.dy * ris.dz / (4.0 * math.pi))
     Sr = np.sqrt(prob.rx_ant.gain * Fr)
-    a = (T[m_idx] * elem * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * Dr)
+    a = (T[m_idx] * elem * bounce_coefs(prob, m, pts, tris) * Sr * lam / (4.0 * math.pi * Dr)
          * np.exp(1j * _phase(Dr, lam)))
     emitted = pattern_on(PAT_COSPOW, co) & pattern_on(prob.rx_ant.pattern, cr)
     return a, Dr, emitted
@@ -462,7 +520,7 @@ def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
     At = np.sqrt(2.0 * ETA0 * prob.tx_power_w * prob.tx_ant.gain * Ft)
     elem = np.sqrt(ris.gain * Fin * Fout * ris.dy * ris.dz / (4.0 * math.pi))
     Sr = np.sqrt(prob.rx_ant.gain * Fr)
-    a = (At * elem / dt * refl_product(prob.scene, tris) * Sr * lam / (4.0 * math.pi * Dr)
+    a = (At * elem / dt * bounce_coefs(prob, m, pts, tris) * Sr * lam / (4.0 * math.pi * Dr)
          * np.exp(1j * _phase(dt + Dr, lam)))
     emitted = (pattern_on(prob.tx_ant.pattern, ct) & pattern_on(PAT_COSPOW, ci) & pattern_on(PAT_COSPOW, co)
                & pattern_on(prob.rx_ant.pattern, cr))

@@ -95,6 +95,11 @@ class Problem:
     n_rays: int
     seed: int
     gamma: Optional[np.ndarray] = None   # complex128 [M, C]
+    # Fresnel reflection instead of the fixed coefficients: 0 off, 1 TE, 2 TM,
+    # with a material per triangle (relative permittivity, conductivity S/m)
+    fresnel: int = 0
+    mat_eps_r: Optional[np.ndarray] = None   # float32 [n_t]
+    mat_sigma: Optional[np.ndarray] = None   # float32 [n_t]
 
     @property
     def wavelength(self) -> float:

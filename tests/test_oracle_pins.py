@@ -422,6 +422,76 @@ def test_reciprocity_ris_with_incoming_reflections(K):
 
 
 # ---------------------------------------------------------------------------
+# Fresnel reflection (Section II-B: reflected rays follow the Fresnel
+# equations; materials as in Section III's table)
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("eps", [4.0, 2.5 - 0.3j, 81.0 - 40.0j])
+def test_fresnel_normal_incidence(eps):
+    """At normal incidence both polarisations reduce to the index form
+    (1 - n) / (1 + n), n = sqrt(eps) (TM with the opposite sign)."""
+    n = np.sqrt(complex(eps))
+    assert abs(O.fresnel(eps, 1.0, 1) - (1 - n) / (1 + n)) < 1e-14
+    assert abs(O.fresnel(eps, 1.0, 2) - (n - 1) / (n + 1)) < 1e-14
+
+
+def test_fresnel_sine_and_tangent_laws():
+    """Lossless dielectric: Fresnel's sine law for TE and tangent law for TM
+    (angles from Snell's law), Brewster's zero, grazing -1, |R| <= 1."""
+    er = 3.7
+    for th in np.linspace(0.05, 1.5, 13):
+        tt = math.asin(math.sin(th) / math.sqrt(er))
+        te = -math.sin(th - tt) / math.sin(th + tt)
+        tm = math.tan(th - tt) / math.tan(th + tt)
+        assert abs(O.fresnel(er, math.cos(th), 1) - te) < 1e-12
+        assert abs(O.fresnel(er, math.cos(th), 2) - tm) < 1e-12
+        assert abs(O.fresnel(er, math.cos(th), 1)) <= 1.0 and abs(O.fresnel(er, math.cos(th), 2)) <= 1.0
+    assert abs(O.fresnel(er, math.cos(math.atan(math.sqrt(er))), 2)) < 1e-12
+    assert abs(O.fresnel(er, 0.0, 1) + 1) < 1e-15 and abs(O.fresnel(er, 0.0, 2) + 1) < 1e-15
+
+
+def test_fresnel_paper_metal_is_nearly_a_perfect_conductor():
+    """eps_r = 1, sigma = 1e7 S/m (the paper's metal) at 28 GHz: TE -> -1,
+    TM -> +1 away from grazing, within the surface-impedance order
+    |Z| = 1 / |sqrt(eps)| (times cos theta for TE, over it for TM)."""
+    prob = synth.Problem("m", synth.empty_scene(), 28e9, np.zeros(3), 0.01, None, None, np.zeros((1, 3)), None,
+                         1, 1, 0, fresnel=1, mat_eps_r=np.array([1.0], np.float32),
+                         mat_sigma=np.array([1e7], np.float32))
+    eps = O.material_eps(prob, np.array([0]))[0]
+    z = 1.0 / abs(np.sqrt(eps))
+    assert z < 1e-3
+    for th in (0.0, 0.6, 1.2):
+        assert abs(O.fresnel(eps, math.cos(th), 1) + 1) < 3 * z * math.cos(th)
+        assert abs(O.fresnel(eps, math.cos(th), 2) - 1) < 3 * z / math.cos(th)
+
+
+@pytest.mark.parametrize("pol", [1, 2])
+def test_fresnel_single_wall_path_closed_form(pol):
+    """The order-1 path off one wall: free-space amplitude over the mirror
+    distance times the sine-law (TE) or tangent-law (TM) coefficient at the
+    mirror geometry's angle."""
+    mb = synth.MeshBuilder()
+    mb.quad((0.0, -5.0, -5.0), (0.0, 10.0, 0.0), (0.0, 0.0, 10.0), 1, complex(0.5, 0.0))
+    scene = mb.build()
+    er = 5.0
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    tx = np.array([1.3, 0.2, 0.1])
+    rx = np.array([[0.7, 2.9, -0.4]])
+    prob = synth.Problem("w", scene, 28e9, tx, 0.01, iso, None, rx, iso, 1, 16, 0, fresnel=pol,
+                         mat_eps_r=np.full(scene.n_tri, er, np.float32), mat_sigma=np.zeros(scene.n_tri, np.float32))
+    r = O.trace(prob, mode="exhaustive")
+    k1 = (r["env_seq"] >= 0).sum(axis=1) == 1
+    assert k1.sum() == 1
+    img = tx * np.array([-1.0, 1.0, 1.0])
+    d = np.linalg.norm(rx[0] - img)
+    th = math.acos(abs(rx[0][0] - img[0]) / d)
+    tt = math.asin(math.sin(th) / math.sqrt(er))
+    R = -math.sin(th - tt) / math.sin(th + tt) if pol == 1 else math.tan(th - tt) / math.tan(th + tt)
+    lam = O.C0 / 28e9
+    a = math.sqrt(2 * ETA0 * 0.01) * R * lam / (4 * math.pi * d) * np.exp(-2j * math.pi * d / lam)
+    assert abs(r["env_amp"][k1][0] - a) < 1e-9 * abs(a)
+
+
+# ---------------------------------------------------------------------------
 # P7: SBR discovery finds what exhaustive search finds (tiny box)
 # ---------------------------------------------------------------------------
 def test_sbr_equals_exhaustive_tiny():
