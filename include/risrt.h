@@ -59,6 +59,12 @@ typedef int32_t rt_status;
                                   (no discovery rays; small scenes only) */
 #define RT_FLAG_COUNT_WORK 16u /* run the counting build of the per-element kernel and
                                   report its work in rt_stats.ris_work (same results) */
+#define RT_FLAG_FRESNEL_TE 64u /* per bounce, the Fresnel coefficient (Section II-B) of the triangle's
+                                  material (rt_scene_set_materials) at the incidence angle, for the
+                                  field perpendicular to the plane of incidence, instead of the
+                                  fixed coefficient; eps = eps_r - j sigma / (2 pi f eps0) */
+#define RT_FLAG_FRESNEL_TM 128u /* the same for the field in the plane of incidence; at most one of the
+                                  two; not with RT_FLAG_COUNT_WORK */
 #define RT_FLAG_RIS_INCOMING 32u /* the field reaching each element also by reflections
                                   Tx -> surfaces -> element (Section II-B, supporting
                                   reflections): image method per element for the Tx
@@ -232,6 +238,15 @@ rt_status rt_candidates_read(rt_ctx ctx, uint64_t channel, int32_t source, int32
 rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C, float gamma_scale,
                      int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out,
                      void* stream);
+
+/* Materials of a scene's triangles (original order) for the Fresnel
+ * coefficients (RT_FLAG_FRESNEL_TE/TM; Section III's table gives metal as
+ * eps_r = 1, sigma = 1e7 S/m): relative permittivity eps_r >= 1 and
+ * conductivity sigma >= 0 [S/m], host or device arrays of n_tri floats,
+ * copied (the call waits for the copy).  Calling again replaces them for
+ * later traces.  RT_EINVAL on a null array or an out-of-range value. */
+rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r, const float* sigma,
+                                 void* stream);
 
 /* Release a scene, RIS or channel. */
 rt_status rt_destroy(rt_ctx ctx, uint64_t handle);

@@ -1,5 +1,6 @@
 // C ABI of the risrt library: contexts, handles, memory budget, argument
 // checks, and the calls declared in include/risrt.h.
+#include <cmath>
 #include <cstring>
 #include <map>
 #include <memory>
@@ -267,8 +268,8 @@ void release_obj(rt_ctx ctx, Obj& o)
     hipStream_t fs = ctx->free_stream;
     if (o.scene) {
         Scene& s = *o.scene;
-        for (Scratch* p : {&s.tri4, &s.nodes, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane, &s.s_box,
-                           &s.t_proj, &s.t_axes})
+        for (Scratch* p : {&s.tri4, &s.nodes, &s.node4, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane,
+                           &s.s_box, &s.t_proj, &s.t_axes, &s.g_axes, &s.g_frame, &s.g_cnt, &s.g_tris, &s.mat})
             retarget(*p, fs);
     }
     if (o.ris) retarget(o.ris->elem, fs);
@@ -366,6 +367,35 @@ rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const
     });
 }
 
+rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r, const float* sigma, void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto so = find(ctx, scene, 1);
+        if (!so) return fail(RT_ENOTFOUND, "unknown scene handle");
+        Scene& sc = *so->scene;
+        if (sc.n_tri > 0 && (!eps_r || !sigma)) return fail(RT_EINVAL, "null material array");
+        if (sc.n_tri == 0) return RT_OK;
+        std::vector<float> er((size_t)sc.n_tri), sg((size_t)sc.n_tri);
+        HIP_CHECK(hipMemcpy(er.data(), eps_r, sizeof(float) * er.size(), hipMemcpyDefault));
+        HIP_CHECK(hipMemcpy(sg.data(), sigma, sizeof(float) * sg.size(), hipMemcpyDefault));
+        std::vector<float> m(2 * (size_t)sc.n_tri);
+        for (int64_t t = 0; t < sc.n_tri; ++t) {
+            if (!(er[t] >= 1.0f) || !(sg[t] >= 0.0f) || !std::isfinite(er[t]) || !std::isfinite(sg[t]))
+                return fail(RT_EINVAL, "materials need eps_r >= 1 and sigma >= 0, finite");
+            m[2 * t] = er[t];
+            m[2 * t + 1] = sg[t];
+        }
+        hipStream_t st = (hipStream_t)stream;
+        if (sc.ready) HIP_CHECK(hipStreamWaitEvent(st, sc.ready, 0));
+        Scratch mat(ctx->c, sizeof(float) * m.size(), st);
+        HIP_CHECK(hipMemcpyAsync(mat.p, m.data(), mat.bytes, hipMemcpyHostToDevice, st));
+        HIP_CHECK(hipStreamSynchronize(st));   // the host staging buffer goes out of scope
+        sc.mat = std::move(mat);
+        if (sc.ready) HIP_CHECK(hipEventRecord(sc.ready, st));
+        return RT_OK;
+    });
+}
+
 rt_status rt_ris_create(rt_ctx ctx, const double* elem_xyz, int64_t M, const double centre[3], const double normal[3],
                         double dy, double dz, double elem_gain, double pattern_q, uint64_t* ris)
 {
@@ -412,7 +442,10 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
 {
     return guarded(ctx, [&]() -> rt_status {
         if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
-        if (params->flags & ~63u) return fail(RT_EINVAL, "unknown flag");
+        if (params->flags & ~255u) return fail(RT_EINVAL, "unknown flag");
+        if ((params->flags & 64u) && (params->flags & 128u)) return fail(RT_EINVAL, "Fresnel TE and TM both set");
+        if ((params->flags & 192u) && (params->flags & 16u))
+            return fail(RT_EINVAL, "the counting build has no Fresnel variant");
         if (params->max_order < 0 || params->max_order > RT_MAX_K)
             return fail(RT_EUNSUPPORTED, "max_order must be 0..3");
         if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
@@ -447,6 +480,11 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         fill_antenna(tc.rxa, rx->axis, rx->gain, rx->pattern, rx->param);
         tc.K = params->max_order;
         tc.flags = (int32_t)params->flags;
+        tc.fresnel = (params->flags & 64u) ? 1 : (params->flags & 128u) ? 2 : 0;
+        tc.pad = 0;
+        tc.sig_scale = 1.0 / (2.0 * 3.141592653589793 * params->freq_hz * 8.8541878128e-12);
+        if (tc.fresnel && so->scene->n_tri > 0 && !so->scene->mat.bytes)
+            return fail(RT_EINVAL, "Fresnel coefficients need the scene's materials (rt_scene_set_materials)");
         auto o = std::make_shared<Obj>();
         o->kind = 3;
         o->channel = std::make_unique<Channel>();

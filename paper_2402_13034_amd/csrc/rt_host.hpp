@@ -100,6 +100,7 @@ struct Scene {
     int32_t root = 0;
     int32_t max_depth = 0;
     Scratch tri4, nodes, node4, v64, refl, surf, s_ptr, s_tris, s_plane, s_box, t_proj, t_axes;
+    Scratch mat;   // float2 per triangle (eps_r, sigma), empty until set
     Scratch g_axes, g_frame, g_cnt, g_tris;
     SceneView view() const {
         SceneView v;
@@ -112,6 +113,7 @@ struct Scene {
         v.node4 = node4.as<float4>();
         v.v64 = v64.as<double>();
         v.refl = refl.as<float2>();
+        v.mat = mat.bytes ? mat.as<float2>() : nullptr;
         v.surf = surf.as<int32_t>();
         v.s_ptr = s_ptr.as<int32_t>();
         v.s_tris = s_tris.as<int32_t>();

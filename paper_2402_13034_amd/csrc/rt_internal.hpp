@@ -46,6 +46,7 @@ struct SceneView {
     const float4* node4;   // 8 per internal node of even depth (4-wide collapse), see RT_NODE4
     const double* v64;     // 9 per triangle (original order)
     const float2* refl;    // per triangle
+    const float2* mat;     // per triangle: relative permittivity, conductivity S/m (null: none set)
     const int32_t* surf;   // per triangle
     const int32_t* s_ptr;  // n_surf + 1
     const int32_t* s_tris; // triangles grouped by surface, ascending
@@ -88,6 +89,9 @@ struct TraceConst {
     Antenna rxa;
     int32_t K;
     int32_t flags;
+    int32_t fresnel;       // 0: fixed coefficients; 1 TE, 2 TM Fresnel coefficients of the materials
+    int32_t pad;
+    double sig_scale;      // 1 / (omega eps0): eps = eps_r - j sigma sig_scale
 };
 
 struct RisView {
@@ -1035,6 +1039,47 @@ __device__ __forceinline__ void phase_cs(double d, double lambda, float& cs, flo
     const float f = (float)(x - floor(x));
     cs = __builtin_amdgcn_cosf(f);
     sn = -__builtin_amdgcn_sinf(f);
+}
+
+// Fresnel reflection coefficient (Section II-B, specular reflection) of
+// triangle t's material for a wave arriving along d (FP64): TE (pol 1)
+//   (c - r) / (c + r), TM (pol 2) (eps c - r) / (eps c + r), r = sqrt(eps - 1 + c^2),
+// c = |d . n| / (|d| |n|), n = e1 x e2 from the FP64 vertices, eps = eps_r - j
+// sigma sig_scale, principal square root (stable form for either sign of
+// the real part).
+__device__ inline float2 fresnel_coef(const SceneView& s, int t, const double* d, int pol, double sig_scale)
+{
+#pragma clang fp contract(off)
+    const double* v = s.v64 + 9 * (int64_t)t;
+    const double ex = v[3] - v[0], ey = v[4] - v[1], ez = v[5] - v[2];
+    const double fx = v[6] - v[0], fy = v[7] - v[1], fz = v[8] - v[2];
+    const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+    const double dn = d[0] * nx + d[1] * ny + d[2] * nz;
+    const double c = fmin(fabs(dn) / (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * sqrt(nx * nx + ny * ny + nz * nz)),
+                          1.0);
+    const float2 m = s.mat[t];
+    const double er = (double)m.x, ei = -(double)m.y * sig_scale;
+    const double a = er - (1.0 - c * c), b = ei;
+    const double h = sqrt(a * a + b * b);
+    double rr, ri;
+    if (a >= 0.0) {
+        rr = sqrt(0.5 * (h + a));
+        ri = rr > 0.0 ? b / (2.0 * rr) : 0.0;
+    } else {
+        const double q = sqrt(0.5 * (h - a));
+        rr = fabs(b) / (2.0 * q);
+        ri = b < 0.0 ? -q : q;
+    }
+    double pr, pi, qr, qi;   // numerator p, denominator q
+    if (pol == 1) {
+        pr = c - rr; pi = -ri;
+        qr = c + rr; qi = ri;
+    } else {
+        pr = er * c - rr; pi = ei * c - ri;
+        qr = er * c + rr; qi = ei * c + ri;
+    }
+    const double qq = qr * qr + qi * qi;
+    return make_float2((float)((pr * qr + pi * qi) / qq), (float)((pi * qr - pr * qi) / qq));
 }
 
 // --------------------------------------------------------------------------

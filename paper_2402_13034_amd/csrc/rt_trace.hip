@@ -524,7 +524,13 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
 #pragma unroll
                 for (int j = 0; j < RT_MAX_K; ++j) {
                     if (j >= k) break;
-                    float2 Rc = s.refl[tri[j]];
+                    float2 Rc;
+                    if (tc.fresnel) {
+                        const double d[3] = {V[j + 1][0] - V[j][0], V[j + 1][1] - V[j][1], V[j + 1][2] - V[j][2]};
+                        Rc = fresnel_coef(s, tri[j], d, tc.fresnel, tc.sig_scale);
+                    } else {
+                        Rc = s.refl[tri[j]];
+                    }
                     float nr = ar * Rc.x - ai * Rc.y;
                     float ni = ar * Rc.y + ai * Rc.x;
                     ar = nr;
@@ -798,7 +804,13 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
 #pragma unroll
             for (int q = 0; q < RT_MAX_K; ++q) {
                 if (q >= k) break;
-                const float2 Rc = s.refl[tri[q]];
+                float2 Rc;
+                if (tc.fresnel) {
+                    const double d[3] = {V[q + 1][0] - V[q][0], V[q + 1][1] - V[q][1], V[q + 1][2] - V[q][2]};
+                    Rc = fresnel_coef(s, tri[q], d, tc.fresnel, tc.sig_scale);
+                } else {
+                    Rc = s.refl[tri[q]];
+                }
                 const float nr = ar * Rc.x - ai * Rc.y;
                 const float ni = ar * Rc.y + ai * Rc.x;
                 ar = nr;
@@ -891,7 +903,8 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 #define RT_RIS_WAVES_PER_SIMD 4   // register cap that measured fastest on the lab room
 #endif
 
-template <bool BRUTE, bool KEEP, int STK, bool CNT>
+// FRES: Fresnel coefficients of the materials (tc.fresnel) instead of the fixed ones
+template <bool BRUTE, bool KEEP, int STK, bool CNT, bool FRES>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
                                                const int32_t* useq, const uint64_t* order, int n_mchunk, float2* H,
@@ -1001,7 +1014,14 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
 #pragma unroll
                     for (int j = 0; j < RT_MAX_K; ++j) {
                         if (j >= k) break;
-                        float2 Rc = s.refl[tri[j]];
+                        float2 Rc;
+                        if (FRES) {
+                            double d[3];
+                            for (int q = 0; q < 3; ++q) d[q] = P[j][q] - (j == 0 ? E[q] : P[j > 0 ? j - 1 : 0][q]);
+                            Rc = fresnel_coef(s, tri[j], d, tc.fresnel, tc.sig_scale);
+                        } else {
+                            Rc = s.refl[tri[j]];
+                        }
                         float nr = ar * Rc.x - ai * Rc.y;
                         float ni = ar * Rc.y + ai * Rc.x;
                         ar = nr;
@@ -1396,6 +1416,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     const bool exhaustive = (a.tc.flags & 8) != 0;
     const bool count_work = (a.tc.flags & 16) != 0;
     const bool incoming = (a.tc.flags & 32) != 0;   // reflections Tx -> surfaces -> element
+    const bool fresnel = a.tc.fresnel != 0;
     const int stk = stack_depth_for(*a.scene, brute);
     const int64_t R = a.R;
     const int64_t M = a.ris ? a.ris->M : 0;
@@ -1565,19 +1586,19 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         tm.mark();   // 5
         if (threads > 0) {
             if (count_work && !brute && !keep_paths) {
-                SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true>), dim3(nblk(threads, RIS_B)),
+                SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false>), dim3(nblk(threads, RIS_B)),
                                                 dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                 uptr.as<int64_t>(), useq.as<int32_t>(), order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
                                                 ch.ris_valid.as<uint8_t>(), d_legs, d_work, d_ctr + 14));
             } else {
-                SEL_BOOL(brute, BR,
+                SEL_BOOL(fresnel, FR, SEL_BOOL(brute, BR,
                          SEL_BOOL(keep_paths, KP,
-                                  SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false>),
+                                  SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false, FR>),
                                                                   dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, st, sv,
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                                   uptr.as<int64_t>(), useq.as<int32_t>(),
                                                                   order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(), ch.ris_valid.as<uint8_t>(),
-                                                                  d_legs, d_work, d_ctr + 14))));
+                                                                  d_legs, d_work, d_ctr + 14)))));
             }
         }
         HIP_CHECK(hipGetLastError());

@@ -34,6 +34,8 @@ FLAG_BRUTE_FORCE = 4
 FLAG_EXHAUSTIVE = 8
 FLAG_COUNT_WORK = 16
 FLAG_RIS_INCOMING = 32
+FLAG_FRESNEL_TE = 64
+FLAG_FRESNEL_TM = 128
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
@@ -44,7 +46,7 @@ PREC_MFMA_F16X2 = 3
 ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
-    "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy",
+    "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials",
 )
 
 
@@ -127,6 +129,7 @@ def lib():
             "rt_ris_sum": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                             P, P, P]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
+            "rt_scene_set_materials": (ctypes.c_int32, [P, u64, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -205,6 +208,22 @@ class Context:
                                      int(T.shape[0]), arg(surf, np.int32), arg(refl_re, np.float32),
                                      arg(refl_im, np.float32), _stream_handle(stream), ctypes.byref(h)))
         return h.value
+
+    def scene_set_materials(self, scene: int, eps_r, sigma, stream=None) -> None:
+        """Per-triangle relative permittivity and conductivity (S/m) for the
+        Fresnel flags; NumPy (host) or torch device arrays."""
+        keep = []
+
+        def arg(x):
+            if hasattr(x, "data_ptr"):
+                keep.append(x)
+                return ctypes.c_void_p(x.data_ptr())
+            a = np.ascontiguousarray(x, np.float32)
+            keep.append(a)
+            return _ptr(a)
+
+        _check(lib().rt_scene_set_materials(self._h, ctypes.c_uint64(scene), arg(eps_r), arg(sigma),
+                                            _stream_handle(stream)))
 
     def ris_create(self, elems, centre, normal, dy, dz, gain, q) -> int:
         E = np.ascontiguousarray(elems, np.float64)
@@ -315,6 +334,8 @@ def upload_problem(ctx: Context, prob, stream=None):
     (scene handle, ris handle or 0)."""
     sc = prob.scene
     scene = ctx.scene_create(sc.V, sc.T, sc.surf, sc.refl_re, sc.refl_im, stream=stream)
+    if getattr(prob, "mat_eps_r", None) is not None:
+        ctx.scene_set_materials(scene, prob.mat_eps_r, prob.mat_sigma, stream=stream)
     ris = 0
     if prob.ris is not None:
         r = prob.ris
@@ -324,6 +345,9 @@ def upload_problem(ctx: Context, prob, stream=None):
 
 def trace_problem(ctx: Context, prob, scene: int, ris: int, flags: int = 0, n_rays: Optional[int] = None,
                   rx=None, stream=None):
+    """Trace a synthetic problem (its Fresnel choice, if any, adds the flag)."""
+    pol = getattr(prob, "fresnel", 0)
+    flags |= FLAG_FRESNEL_TE if pol == 1 else FLAG_FRESNEL_TM if pol == 2 else 0
     return ctx.trace(scene, ris, prob.tx_pos, prob.tx_ant.axis, prob.tx_power_w, prob.tx_ant.gain,
                      prob.tx_ant.pattern, prob.tx_ant.param, prob.rx_pos if rx is None else rx,
                      prob.rx_ant.axis, prob.rx_ant.gain, prob.rx_ant.pattern, prob.rx_ant.param, prob.freq,

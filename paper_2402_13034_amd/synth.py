@@ -343,6 +343,18 @@ def lab_room(seed: int = BASE_SEED + 1, n_rays: int = 1_000_000, order: int = 3,
                    order, n_rays, seed, gamma)
 
 
+def with_materials(prob: Problem, pol: int, seed: int = BASE_SEED + 9, eps_r=(2.0, 8.0), sigma=(0.0, 0.3)) -> Problem:
+    """The same problem with Fresnel reflection (pol 1 TE, 2 TM): one seeded
+    material per surface, relative permittivity U(eps_r), conductivity
+    U(sigma) S/m, copied to its triangles."""
+    rng = np.random.default_rng(seed)
+    ns = prob.scene.n_surf
+    er = rng.uniform(*eps_r, size=ns).astype(np.float32)
+    sg = rng.uniform(*sigma, size=ns).astype(np.float32)
+    return dataclasses.replace(prob, name=prob.name + ("_te" if pol == 1 else "_tm"), fresnel=pol,
+                               mat_eps_r=er[prob.scene.surf], mat_sigma=sg[prob.scene.surf])
+
+
 def wide_ris_room(seed: int = BASE_SEED + 5, n_rays: int = 20_000, order: int = 2, nx: int = 6,
                   ny: int = 5) -> Problem:
     """The lab room with a sparse 8 x 8 array (0.35 m pitch, 2.45 m across) on

@@ -168,6 +168,40 @@ def test_ris_incoming_reflections_brute_force(ctx):
     check_problem(ctx, synth.lab_room(nx=5, ny=4, order=2), n_rays=4000, brute=True, incoming=True)
 
 
+def test_fresnel_te_tiny_box(ctx):
+    check_problem(ctx, synth.with_materials(synth.tiny_box(), 1))
+
+
+def test_fresnel_tm_lab_room(ctx):
+    check_problem(ctx, synth.with_materials(synth.lab_room(nx=9, ny=7), 2), n_rays=20_000)
+
+
+def test_fresnel_tm_brute_force_with_incoming(ctx):
+    check_problem(ctx, synth.with_materials(synth.lab_room(nx=5, ny=4, order=2), 2), n_rays=4000, brute=True,
+                  incoming=True)
+
+
+def test_fresnel_paper_metal_with_incoming(ctx):
+    """Section III's metal (eps_r 1, sigma 1e7 S/m) on every wall, TE."""
+    p = synth.with_materials(synth.lab_room(nx=9, ny=7), 1, eps_r=(1.0, 1.0), sigma=(1e7, 1e7))
+    check_problem(ctx, p, n_rays=20_000, incoming=True)
+
+
+def test_fresnel_flag_errors(ctx):
+    from paper_2402_13034_amd import risrt
+    prob = synth.tiny_box()
+    scene, ris = risrt.upload_problem(ctx, prob)   # no materials set
+    for flags in (risrt.FLAG_FRESNEL_TE | risrt.FLAG_FRESNEL_TM, risrt.FLAG_FRESNEL_TE,
+                  risrt.FLAG_FRESNEL_TM | risrt.FLAG_COUNT_WORK):
+        with pytest.raises(risrt.RtError):
+            risrt.trace_problem(ctx, prob, scene, ris, flags=flags)
+    with pytest.raises(risrt.RtError):
+        ctx.scene_set_materials(scene, np.full(prob.scene.n_tri, 0.5, np.float32),
+                                np.zeros(prob.scene.n_tri, np.float32))
+    for h in (scene, ris):
+        ctx.destroy(h)
+
+
 def test_sparse_array_leg_walk_fallback(ctx):
     """Elements 0.35 m apart: the grouped leg walk of a slot outgrows its
     on-chip lists and walks leg by leg; results stay exact."""
