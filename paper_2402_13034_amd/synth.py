@@ -424,6 +424,56 @@ def random_box_room(rng, n_tri_target: int):
     return mb.build(), (L, W, H)
 
 
+def paper_room(reflective: bool = True, grid: str = "coarse", n_rays: int = 100_000,
+               seed: int = BASE_SEED + 11) -> Problem:
+    """Section III's scenario.  23.8 GHz, P_t = 10 dBm; a horn Tx (G_t = 19 dB,
+    cos^(G_t/2 - 1)) at t = (1.86 m, -36 deg, 90 deg) from the RIS centre,
+    aimed at it; a 127-element hexagonal RIS (d_y = d_z = 6.6 mm, element
+    pitch 6.6 mm, cos theta elements, G = 4 pi d_y d_z / lambda^2) at
+    u = (0, 0, 0.5) m facing +x; a lambda/4 monopole Rx (G_r = 0 dB) along +z;
+    the 0.9 x 0.05 x 1 m blocking panel at (1.55, -0.475, 0.5) m.  Reflective:
+    three metal walls (the sides y = -1.2, 1.2 m and the wall x = 2 m opposite
+    the RIS, 1 m high) and the panel, all of the paper's metal (eps_r = 1,
+    sigma = 1e7 S/m, TE Fresnel coefficients: the monopole's vertical field
+    lies across the plane of incidence on vertical walls), reflections up to
+    order 2; anechoic: the panel alone, order 0.  Receivers at z = 11.4 cm:
+    grid "coarse" 0.92 <= x <= 1.52, 0.02 <= y <= 0.92 m every 1 cm (61 x 91),
+    "fine" 1.1 <= x <= 1.3, 0.25 <= y <= 0.45 m every 2 mm (101 x 101),
+    "target" the single point r = (1.33, 0.23, 0.11) m the RIS is configured
+    for.  Gamma is left to the caller (on/off with amplitude 1.25)."""
+    f = 23.8e9
+    lam = C0 / f
+    u = np.array([0.0, 0.0, 0.5])
+    normal = np.array([1.0, 0.0, 0.0])
+    mb = MeshBuilder()
+    metal = complex(-1.0, 0.0)   # the fixed coefficient is not used (Fresnel)
+    if reflective:
+        mb.quad((0.0, -1.2, 0.0), (2.0, 0.0, 0.0), (0.0, 0.0, 1.0), 1, metal)   # y = -1.2
+        mb.quad((0.0, 1.2, 0.0), (2.0, 0.0, 0.0), (0.0, 0.0, 1.0), 1, metal)    # y = +1.2
+        mb.quad((2.0, -1.2, 0.0), (0.0, 2.4, 0.0), (0.0, 0.0, 1.0), 1, metal)   # x = 2
+    pc, ps = np.array([1.55, -0.475, 0.5]), np.array([0.9, 0.05, 1.0])
+    mb.box(tuple(pc - ps / 2), tuple(pc + ps / 2), 1, metal)
+    scene = mb.build()
+    elems = hex_ris(6, 6.6e-3, u, normal)
+    ris = Ris(elems, normal, u, 6.6e-3, 6.6e-3, 4.0 * math.pi * 6.6e-3 ** 2 / lam ** 2, 1.0)
+    tx = paper_spherical(u, 1.86, -36.0, 90.0)
+    gt = 10 ** 1.9
+    tx_ant = Antenna(unit(u - tx), gt, PAT_COSPOW, gt / 2.0 - 1.0)
+    rx_ant = Antenna(np.array([0.0, 0.0, 1.0]), 1.0, PAT_MONOPOLE, 0.25)
+    if grid == "coarse":
+        rx = rx_grid(0.92, 1.52, 61, 0.02, 0.92, 91, 0.114)
+    elif grid == "fine":
+        rx = rx_grid(1.1, 1.3, 101, 0.25, 0.45, 101, 0.114)
+    elif grid == "target":
+        rx = np.array([[1.33, 0.23, 0.11]])
+    else:
+        raise ValueError(grid)
+    nt = scene.n_tri
+    return Problem("paper_" + ("reflective" if reflective else "anechoic") + "_" + grid, scene, f, tx, 0.01,
+                   tx_ant, ris, rx, rx_ant, 2 if reflective else 0, n_rays, seed, None,
+                   fresnel=1, mat_eps_r=np.full(nt, 1.0, np.float32), mat_sigma=np.full(nt, 1e7, np.float32))
+
+
 def paper_spherical(u, r: float, phi_deg: float, theta_deg: float) -> np.ndarray:
     """A position given as (r, phi, theta) relative to the RIS centre u in
     the global axes (theta from +z, phi from +x), as used for the Tx and Rx

@@ -202,6 +202,58 @@ def test_fresnel_flag_errors(ctx):
         ctx.destroy(h)
 
 
+def test_paper_scene_reflective_parity(ctx):
+    """Section III's reflective scenario (metal walls, TE Fresnel, order 2,
+    10^5 rays) on every third receiver of the 1 cm map."""
+    p = synth.paper_room(reflective=True, grid="coarse")
+    idx = (np.arange(0, 91, 3)[:, None] * 61 + np.arange(0, 61, 3)[None, :]).ravel()
+    p.rx_pos = p.rx_pos[idx]
+    check_problem(ctx, p)
+
+
+def _paper_map_db(ctx, prob, g):
+    import torch
+    from paper_2402_13034_amd import risrt
+    scene, ris, ch, st = _run(ctx, prob, 0)
+    _, P = ctx.ris_sum(ch, torch.from_numpy(g.astype(np.complex64)[:, None]).cuda(),
+                       precision=risrt.PREC_VALU_F32, want_P=True)
+    torch.cuda.synchronize()
+    P = P.cpu().numpy()[:, 0].astype(np.float64)
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+    return 10 * np.log10(np.maximum(P, 1e-300) * 1e3), P
+
+
+def _paper_gpu_config(ctx, reflective):
+    from tests.ris_config import configure_on_off
+    scene, ris, ch, st = _run(ctx, synth.paper_room(reflective=reflective, grid="target"), 0)
+    _, H = ctx.channel_read(ch)
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+    return configure_on_off(H[0].astype(np.complex128))
+
+
+def test_paper_scene_maps(ctx):
+    """The full maps on the GPU show what Section IV reports: the anechoic
+    beam at -60 to -55 dBm near the Rx, and lambda/2 small-scale fading in
+    the reflective 2 mm map."""
+    from tests.ris_config import small_scale_period
+    g = _paper_gpu_config(ctx, False)
+    p = synth.paper_room(reflective=False, grid="coarse")
+    db, _ = _paper_map_db(ctx, p, g)
+    i = int(np.argmax(db))
+    _say("paper anechoic map: max %.2f dBm at %s" % (db[i], p.rx_pos[i]))
+    assert -60.0 <= db[i] <= -55.0
+    assert np.linalg.norm(p.rx_pos[i, :2] - [1.33, 0.23]) < 0.15
+    g = _paper_gpu_config(ctx, True)
+    p = synth.paper_room(reflective=True, grid="fine")
+    _, P = _paper_map_db(ctx, p, g)
+    per = small_scale_period(P.reshape(101, 101), 0.002)
+    lam = synth.C0 / p.freq
+    _say("paper reflective fine map: small-scale period %.4f m (lambda/2 %.4f m)" % (per, lam / 2))
+    assert abs(per / (lam / 2) - 1) < 0.15
+
+
 def test_sparse_array_leg_walk_fallback(ctx):
     """Elements 0.35 m apart: the grouped leg walk of a slot outgrows its
     on-chip lists and walks leg by leg; results stay exact."""

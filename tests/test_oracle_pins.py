@@ -492,6 +492,43 @@ def test_fresnel_single_wall_path_closed_form(pol):
 
 
 # ---------------------------------------------------------------------------
+# P11 / P12: the paper's scenario (Section III) against what Section IV reports
+# ---------------------------------------------------------------------------
+def _paper_config(reflective):
+    from tests.ris_config import configure_on_off
+    rt = O.trace(synth.paper_room(reflective=reflective, grid="target"), mode="exhaustive")
+    return configure_on_off(rt["H"][0])
+
+
+def test_paper_anechoic_beam_level():
+    """Anechoic simulation, RIS configured for r = (1.33, 0.23, 0.11) m: the
+    dominant beam is reported at about -60 to -55 dBm over a region of about
+    0.5 x 0.2 m, centred near the Rx."""
+    g = _paper_config(False)
+    p = synth.paper_room(reflective=False, grid="coarse")
+    r = O.trace(p, mode="exhaustive")
+    P = 10 * np.log10(np.abs(r["E_env"] + r["H"] @ g) ** 2 / (2 * ETA0) * 1e3)
+    i = int(np.argmax(P))
+    assert -60.0 <= P[i] <= -55.0, P[i]
+    assert np.linalg.norm(p.rx_pos[i, :2] - [1.33, 0.23]) < 0.15
+    area = (P > -60.0).sum() * 1e-4   # 1 cm x 1 cm samples
+    assert 0.05 < area < 0.2, area
+
+
+def test_paper_reflective_small_scale_fading_period():
+    """Reflective simulation, 2 mm map over 1.1-1.3 x 0.25-0.45 m: the
+    small-scale fading repeats about every lambda/2."""
+    from tests.ris_config import small_scale_period
+    g = _paper_config(True)
+    p = synth.paper_room(reflective=True, grid="fine")
+    r = O.trace(p, mode="exhaustive")
+    P = (np.abs(r["E_env"] + r["H"] @ g) ** 2).reshape(101, 101)
+    lam = O.C0 / p.freq
+    per = small_scale_period(P, 0.002)
+    assert abs(per / (lam / 2) - 1) < 0.15, (per, lam / 2)
+
+
+# ---------------------------------------------------------------------------
 # P7: SBR discovery finds what exhaustive search finds (tiny box)
 # ---------------------------------------------------------------------------
 def test_sbr_equals_exhaustive_tiny():
