@@ -82,7 +82,7 @@ def device_mesh(prob):
 
 def run_trace_bench(ctx, prob, steps, warmup):
     import torch
-    from paper_2402_13034_amd import risrt
+    from paper_2402_13034_amd import risrt, synth
     mesh = device_mesh(prob)
     rx = torch.from_numpy(prob.rx_pos).cuda()
     gamma = torch.from_numpy(prob.gamma.astype(np.complex64)).cuda()
@@ -151,9 +151,71 @@ def run_trace_bench(ctx, prob, steps, warmup):
                 "segments_per_step": in_stats[-1]["segments"], "n_in_seq": in_stats[-1]["n_in_seq"],
                 "n_in_paths": in_stats[-1]["n_in_paths"],
                 "Mray_segments_per_s": sum(x["segments"] for x in in_stats) / (t3 - t2) / 1e6}
+    # and with TM Fresnel coefficients of seeded materials (one per surface) instead of the fixed ones
+    pf = synth.with_materials(prob, 2)
+    ctx.scene_set_materials(scene, pf.mat_eps_r, pf.mat_sigma)
+    ch, _ = risrt.trace_problem(ctx, pf, scene, ris, rx=rx)   # warm-up
+    ctx.destroy(ch)
+    torch.cuda.synchronize()
+    gc.collect()
+    gc.disable()
+    try:
+        t4 = time.perf_counter()
+        f_stats = []
+        for _ in range(n_in):
+            ch, stf = risrt.trace_problem(ctx, pf, scene, ris, rx=rx)
+            ctx.ris_sum(ch, gamma, precision=risrt.PREC_VALU_F32, want_P=False, P_out=P_out)
+            ctx.destroy(ch)
+            f_stats.append(stf)
+        torch.cuda.synchronize()
+        t5 = time.perf_counter()
+    finally:
+        gc.enable()
+    fresnel = {"ms_per_step_without_scene_build": (t5 - t4) / n_in * 1e3, "steps": n_in,
+               "polarisation": "TM", "Mray_segments_per_s": sum(x["segments"] for x in f_stats) / (t5 - t4) / 1e6,
+               "k_ris_ms": sum(x["ms_stage"][5] for x in f_stats) / n_in}
     ctx.destroy(scene)
     ctx.destroy(ris)
-    return stats, t1 - t0, cst["ris_work"], incoming
+    return stats, t1 - t0, cst["ris_work"], {"ris_incoming_reflections": incoming, "fresnel_tm": fresnel}
+
+
+def run_paper_bench(ctx, reps=3):
+    """Section III's reflective scenario (metal walls, TE Fresnel, order 2):
+    the 2 mm map (101 x 101 receivers) and the 1 cm map (61 x 91), each a
+    whole trace (BVH build to H) plus the field of one configuration."""
+    import torch
+    from paper_2402_13034_amd import risrt, synth
+    out = {}
+    for grid in ("fine", "coarse"):
+        prob = synth.paper_room(reflective=True, grid=grid)
+        M = prob.ris.elems.shape[0]
+        g = torch.full((M, 1), 1.25 + 0j, dtype=torch.complex64, device="cuda")
+        rx = torch.from_numpy(prob.rx_pos).cuda()
+        sc = prob.scene
+        V, T, S = (torch.from_numpy(a).cuda() for a in (sc.V, sc.T, sc.surf))
+        rr, ri = (torch.from_numpy(a).cuda() for a in (sc.refl_re, sc.refl_im))
+        ris = ctx.ris_create(prob.ris.elems, prob.ris.centre, prob.ris.normal, prob.ris.dy, prob.ris.dz,
+                             prob.ris.gain, prob.ris.q)
+
+        def one():
+            scene = ctx.scene_create(V, T, S, rr, ri)
+            ctx.scene_set_materials(scene, prob.mat_eps_r, prob.mat_sigma)
+            ch, st = risrt.trace_problem(ctx, prob, scene, ris, rx=rx)
+            _, P = ctx.ris_sum(ch, g, precision=risrt.PREC_VALU_F32)
+            ctx.destroy(ch)
+            ctx.destroy(scene)
+            return st
+
+        one()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        sts = [one() for _ in range(reps)]
+        torch.cuda.synchronize()
+        dt = (time.perf_counter() - t0) / reps
+        ctx.destroy(ris)
+        out[grid] = {"receivers": int(prob.rx_pos.shape[0]), "ms_per_map": dt * 1e3,
+                     "segments_per_map": sts[-1]["segments"], "Mray_segments_per_s": sts[-1]["segments"] / dt / 1e6}
+    return out
 
 
 def run_gemm_bench(ctx, reps=5):
@@ -352,8 +414,10 @@ def main():
     ctx = risrt.Context(0)
     log("bench: lab room, %d triangles, M=%d, R=%d, K=%d, rays=%d" % (
         prob.scene.n_tri, prob.ris.elems.shape[0], prob.rx_pos.shape[0], prob.order, prob.n_rays))
-    stats, dt, work, incoming = run_trace_bench(ctx, prob, args.steps, args.warmup)
-    log("bench: with incoming reflections %s" % json.dumps(incoming))
+    stats, dt, work, variants = run_trace_bench(ctx, prob, args.steps, args.warmup)
+    log("bench: variants %s" % json.dumps(variants))
+    paper = run_paper_bench(ctx)
+    log("bench: paper scenario %s" % json.dumps(paper))
     segs = sum(s["segments"] for s in stats)
     value = segs / dt / 1e6
     ms_step = dt / args.steps * 1e3
@@ -402,7 +466,8 @@ def main():
                    "host_ms_scene_trace_sum_destroy": [round(float(np.mean([s["host_ms"][k] for s in stats])), 3)
                                                        for k in range(4)]},
         "roofline": roofline,
-        "ris_incoming_reflections": incoming,
+        "variants": variants,
+        "paper_scenario": paper,
         "ris_sum": gemm,
         "serving": serving,
         "latency_p50_ms": serving["p50_ms"] if serving else None,
