@@ -631,6 +631,26 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = 
     return out
 
 
+def cir(res, prob, gamma: np.ndarray, bin_s: float, n_bins: int) -> np.ndarray:
+    """Delay-binned channel impulse response of one configuration from a
+    ``trace`` result (direct incoming legs): bin b of receiver r sums the
+    complex amplitudes of its paths with unfolded length d, b = floor(d / L),
+    L = c bin_s; environment paths as traced, RIS paths of element m times
+    gamma[m]; paths past the last bin are left out."""
+    L = C0 * bin_s
+    R = prob.rx_pos.shape[0]
+    h = np.zeros((R, n_bins), np.complex128)
+    b = np.floor(res["env_len"] / L).astype(np.int64)
+    keep = b < n_bins
+    np.add.at(h, (res["env_rx"][keep], b[keep]), res["env_amp"][keep])
+    if prob.ris is not None and res["ris_amp"].size:
+        sl, m = res["ris_amp_idx"][:, 0], res["ris_amp_idx"][:, 1]
+        b = np.floor(res["ris_len"] / L).astype(np.int64)
+        keep = b < n_bins
+        np.add.at(h, (res["ris_slot_rx"][sl][keep], b[keep]), gamma[m[keep]] * res["ris_amp"][keep])
+    return h
+
+
 def ris_exact(prob, cands: np.ndarray):
     """The plain definition the centre-point heuristic approximates: for every
     element m, every sequence in ``cands`` is tried from m itself (no

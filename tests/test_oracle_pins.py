@@ -492,6 +492,44 @@ def test_fresnel_single_wall_path_closed_form(pol):
 
 
 # ---------------------------------------------------------------------------
+# Channel impulse response (delay bins of the paths)
+# ---------------------------------------------------------------------------
+def test_cir_one_wall_two_taps():
+    """One wall: the line-of-sight tap at |rx - tx| / c and the reflected tap
+    at the mirror distance, each with its closed-form amplitude; nothing else."""
+    mb = synth.MeshBuilder()
+    mb.quad((0.0, -5.0, -5.0), (0.0, 10.0, 0.0), (0.0, 0.0, 10.0), 1, complex(-0.6, 0.2))
+    scene = mb.build()
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    tx = np.array([1.3, 0.2, 0.1])
+    rx = np.array([[0.7, 2.9, -0.4]])
+    prob = synth.Problem("w", scene, 28e9, tx, 0.01, iso, None, rx, iso, 1, 16, 0)
+    r = O.trace(prob, mode="exhaustive")
+    bin_s = 1e-11
+    h = O.cir(r, prob, np.zeros(0), bin_s, 4096)
+    lam = O.C0 / 28e9
+    coef = complex(float(np.float32(-0.6)), float(np.float32(0.2)))
+    taps = {}
+    for d, c in ((np.linalg.norm(rx[0] - tx), 1.0), (np.linalg.norm(rx[0] - tx * np.array([-1.0, 1.0, 1.0])), coef)):
+        taps[int(d // (O.C0 * bin_s))] = math.sqrt(2 * ETA0 * 0.01) * c * lam / (4 * math.pi * d) * \
+            np.exp(-2j * math.pi * d / lam)
+    assert len(taps) == 2 and np.count_nonzero(h[0]) == 2
+    for b, a in taps.items():
+        assert abs(h[0, b] - a) < 1e-12 * abs(a)
+
+
+def test_cir_bins_sum_to_the_field():
+    """With every path inside the bins, the taps of a receiver add up to its
+    narrowband field E_env + H gamma."""
+    prob = synth.tiny_box()
+    r = O.trace(prob)
+    g = prob.gamma[:, 0]
+    h = O.cir(r, prob, g, 2e-10, 400)
+    E = r["E_env"] + r["H"] @ g
+    assert np.max(np.abs(h.sum(axis=1) - E)) < 1e-12 * np.max(np.abs(E))
+
+
+# ---------------------------------------------------------------------------
 # P11 / P12: the paper's scenario (Section III) against what Section IV reports
 # ---------------------------------------------------------------------------
 def _paper_config(reflective):
