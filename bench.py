@@ -174,9 +174,24 @@ def run_trace_bench(ctx, prob, steps, warmup):
     fresnel = {"ms_per_step_without_scene_build": (t5 - t4) / n_in * 1e3, "steps": n_in,
                "polarisation": "TM", "Mray_segments_per_s": sum(x["segments"] for x in f_stats) / (t5 - t4) / 1e6,
                "k_ris_ms": sum(x["ms_stage"][5] for x in f_stats) / n_in}
+    # impulse response of the configuration: 0.25 ns bins, 400 of them (every path of the room)
+    ch, stc = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_KEEP_CIR)
+    g0 = gamma[:, 0].contiguous()
+    ctx.cir(ch, g0, 2.5e-10, 400)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        h = ctx.cir(ch, g0, 2.5e-10, 400)
+    e1.record()
+    torch.cuda.synchronize()
+    cir = {"bins": 400, "bin_ns": 0.25, "ms": e0.elapsed_time(e1) / 3, "receivers": int(h.shape[0]),
+           "ris_paths_kept": int(stc["n_ris_slots"]) * prob.ris.elems.shape[0]}
+    ctx.destroy(ch)
     ctx.destroy(scene)
     ctx.destroy(ris)
-    return stats, t1 - t0, cst["ris_work"], {"ris_incoming_reflections": incoming, "fresnel_tm": fresnel}
+    return stats, t1 - t0, cst["ris_work"], {"ris_incoming_reflections": incoming, "fresnel_tm": fresnel,
+                                             "impulse_response": cir}
 
 
 def run_paper_bench(ctx, reps=3):

@@ -65,6 +65,9 @@ typedef int32_t rt_status;
                                   fixed coefficient; eps = eps_r - j sigma / (2 pi f eps0) */
 #define RT_FLAG_FRESNEL_TM 128u /* the same for the field in the plane of incidence; at most one of the
                                   two; not with RT_FLAG_COUNT_WORK */
+#define RT_FLAG_KEEP_CIR 256u  /* keep per-path delays and amplitudes for rt_cir (the RIS paths'
+                                  amplitude and unfolded length per slot and element: 16 B each);
+                                  not with RT_FLAG_RIS_INCOMING */
 #define RT_FLAG_RIS_INCOMING 32u /* the field reaching each element also by reflections
                                   Tx -> surfaces -> element (Section II-B, supporting
                                   reflections): image method per element for the Tx
@@ -238,6 +241,19 @@ rt_status rt_candidates_read(rt_ctx ctx, uint64_t channel, int32_t source, int32
 rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C, float gamma_scale,
                      int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out,
                      void* stream);
+
+/* Channel impulse response of one RIS configuration (the paths' delays,
+ * Section II-B / Fig. 3 context): cir[r, b] = sum of the complex amplitudes
+ * of the paths reaching receiver r with unfolded length d in
+ * [b L, (b + 1) L), L = c * bin_s (c = 299 792 458 m/s; bin = floor(d / L)):
+ * the environment paths as traced, and every RIS path of element m
+ * multiplied by gamma[m]; paths past the last bin are left out, so the bins
+ * sum to the narrowband field E = E_env + H gamma when none is.  gamma:
+ * complex [M], device; cir: device complex [R x n_bins]; 0 < n_bins <= 2^24.
+ * The channel must have been traced with RT_FLAG_KEEP_CIR (RT_EINVAL
+ * otherwise).  Enqueued on `stream`. */
+rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s, int64_t n_bins, float* cir,
+                 void* stream);
 
 /* Materials of a scene's triangles (original order) for the Fresnel
  * coefficients (RT_FLAG_FRESNEL_TE/TM; Section III's table gives metal as

@@ -276,7 +276,8 @@ void release_obj(rt_ctx ctx, Obj& o)
     if (o.channel) {
         Channel& ch = *o.channel;
         for (Scratch* p : {&ch.H, &ch.E_env, &ch.hits[0], &ch.hits[1], &ch.cand_keys[0], &ch.cand_keys[1], &ch.env,
-                           &ch.useq, &ch.ris_valid, &ch.a_hi, &ch.a_lo, &ch.a_sexp})
+                           &ch.useq, &ch.ris_valid, &ch.a_hi, &ch.a_lo, &ch.a_sexp, &ch.env_rstart, &ch.env_valid,
+                           &ch.env_amp, &ch.env_len, &ch.cir_amp, &ch.cir_len, &ch.cir_uptr})
             retarget(*p, fs);
     }
     if (o.scene && o.scene->ready) (void)hipEventDestroy(o.scene->ready);
@@ -442,7 +443,9 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
 {
     return guarded(ctx, [&]() -> rt_status {
         if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
-        if (params->flags & ~255u) return fail(RT_EINVAL, "unknown flag");
+        if (params->flags & ~511u) return fail(RT_EINVAL, "unknown flag");
+        if ((params->flags & 256u) && (params->flags & 32u))
+            return fail(RT_EINVAL, "the impulse response keeps the direct incoming leg only (no RT_FLAG_RIS_INCOMING)");
         if ((params->flags & 64u) && (params->flags & 128u)) return fail(RT_EINVAL, "Fresnel TE and TM both set");
         if ((params->flags & 192u) && (params->flags & 16u))
             return fail(RT_EINVAL, "the counting build has no Fresnel variant");
@@ -672,6 +675,30 @@ rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C
         std::lock_guard<std::mutex> lk(o->mu);
         if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
         ris_sum(ctx->c, ch, gamma, C, gamma_scale, gamma_is_real != 0, precision, E_out, P_out, st);
+        return RT_OK;
+    });
+}
+
+rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s, int64_t n_bins, float* cir_out,
+                 void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        Channel& ch = *o->channel;
+        if (!ch.keep_cir) return fail(RT_EINVAL, "the channel was not traced with RT_FLAG_KEEP_CIR");
+        if (!(bin_s > 0.0) || !std::isfinite(bin_s) || n_bins < 0 || n_bins > ((int64_t)1 << 24))
+            return fail(RT_EINVAL, "bad delay bins");
+        if (ch.R > 0 && n_bins > 0 && (!cir_out || !is_device_ptr(cir_out)))
+            return fail(RT_EINVAL, "the output must be device memory");
+        if (ch.R > 0 && ch.M > 0 && n_bins > 0 && (!gamma || !is_device_ptr(gamma)))
+            return fail(RT_EINVAL, "gamma must be device memory");
+        if (ch.R >= ((int64_t)1 << 31)) return fail(RT_EUNSUPPORTED, "too many receivers");
+        hipStream_t st = (hipStream_t)stream;
+        note_user(ctx, *o, st);
+        std::lock_guard<std::mutex> lk(o->mu);
+        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        cir(ctx->c, ch, gamma, bin_s, n_bins, cir_out, st);
         return RT_OK;
     });
 }

@@ -153,6 +153,13 @@ struct Channel {
     Scratch useq;       // int32 [n_u * 4]  (rx, s0, s1, s2)
     int64_t n_slots = 0;
     Scratch ris_valid;  // uint8 [n_slots * M]
+    // kept for the impulse response (RT_FLAG_KEEP_CIR): environment cells of
+    // every receiver (offsets, validity, amplitude, length) and, per RIS slot
+    // and element, amplitude (0: no path) and unfolded length; slot offsets
+    bool keep_cir = false;
+    int64_t env_cells = 0;
+    Scratch env_rstart, env_valid, env_amp, env_len;
+    Scratch cir_amp, cir_len, cir_uptr;
     // split of H, cached for matrix-core sums
     int split_kind = 0; // 0 none; bf16: 1 real-Gamma layout, 2 complex-Gamma layout; fp16: 3, 4
     Scratch a_hi, a_lo;
@@ -203,6 +210,8 @@ struct TraceOut {
     int64_t n_in_seq = 0, n_in_paths = 0;
 };
 void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st);
+// impulse response of one configuration from a channel traced with RT_FLAG_KEEP_CIR
+void cir(Ctx& c, const Channel& ch, const float* gamma, double bin_s, int64_t n_bins, float* out, hipStream_t st);
 
 // ---- RIS sum ----
 void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real,

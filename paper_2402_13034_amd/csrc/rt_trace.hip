@@ -908,8 +908,8 @@ template <bool BRUTE, bool KEEP, int STK, bool CNT, bool FRES>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
                                                const int32_t* useq, const uint64_t* order, int n_mchunk, float2* H,
-                                               uint8_t* rvalid, unsigned long long* segs, unsigned long long* work,
-                                               unsigned long long* fallbacks)
+                                               uint8_t* rvalid, float2* camp, double* clen, unsigned long long* segs,
+                                               unsigned long long* work, unsigned long long* fallbacks)
 {
     // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
     __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
@@ -936,6 +936,12 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
         const int mm = active ? m : 0;
         const double* e = rv.elem + 3 * mm;
         const double E[3] = {e[0], e[1], e[2]};
+        double dt_keep = 0.0;   // |E - Tx| as the direct leg's length (kept paths only)
+        if (KEEP) {
+#pragma clang fp contract(off)
+            const double v0 = E[0] - tc.tx[0], v1 = E[1] - tc.tx[1], v2 = E[2] - tc.tx[2];
+            dt_keep = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
+        }
         const TxmRec t = txm[mm];
         const double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
         const int64_t u0 = uptr[r], u1 = uptr[r + 1];
@@ -959,6 +965,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
             if (CNT && active) ++pairs;
             // phase 1 (FP64): image method, leg rays, length, amplitude
             float amp_r = 0.0f, amp_i = 0.0f;
+            double Dr_keep = 0.0;
             {
                 double P[RT_MAX_K][3];
                 int tri[RT_MAX_K] = {-1, -1, -1};
@@ -1009,6 +1016,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         lb[6 * 64] = (float)(L - RT_EPS);
                     }
                 }
+                if (KEEP) Dr_keep = Dr;
                 if (ok) {
                     float ar = 1.0f, ai = 0.0f;
 #pragma unroll
@@ -1072,7 +1080,14 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 acc_r += (double)amp_r;
                 acc_i += (double)amp_i;
             }
-            if (KEEP && active) rvalid[(u0 + r + sl) * rv.M + m] = ok ? 1 : 0;
+            if (KEEP && active) {
+                const int64_t cell = (u0 + r + sl) * rv.M + m;
+                if (rvalid) rvalid[cell] = ok ? 1 : 0;
+                if (camp) {   // per-path amplitude and unfolded length (d_t + D_r) for the impulse response
+                    camp[cell] = ok ? make_float2(amp_r, amp_i) : make_float2(0.0f, 0.0f);
+                    clen[cell] = dt_keep + Dr_keep;
+                }
+            }
         }
         if (active) H[r * rv.M + m] = make_float2((float)acc_r, (float)acc_i);
     }
@@ -1417,6 +1432,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     const bool count_work = (a.tc.flags & 16) != 0;
     const bool incoming = (a.tc.flags & 32) != 0;   // reflections Tx -> surfaces -> element
     const bool fresnel = a.tc.fresnel != 0;
+    const bool keep_cir = (a.tc.flags & 256) != 0;   // per-path delays and amplitudes for rt_cir
     const int stk = stack_depth_for(*a.scene, brute);
     const int64_t R = a.R;
     const int64_t M = a.ris ? a.ris->M : 0;
@@ -1534,6 +1550,13 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
                 HIP_CHECK(hipGetLastError());
             }
         }
+        if (keep_cir) {   // the environment paths of every receiver, in record order
+            ch.env_cells = ps.n;
+            ch.env_rstart = std::move(ps.rstart);
+            ch.env_valid = std::move(ps.valid);
+            ch.env_amp = std::move(ps.amp);
+            ch.env_len = std::move(ps.len);
+        }
     }
     // sequences valid from the RIS centre, grouped by receiver (centre branch)
     int64_t n_u = 0;
@@ -1559,7 +1582,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipGetLastError());
         HIP_CHECK(hipEventRecord(join.e, su));
         HIP_CHECK(hipStreamWaitEvent(st, join.e, 0));
-        if (keep_paths) n_u = read_i64(bu.d_cnt, st);
+        if (keep_paths || keep_cir) n_u = read_i64(bu.d_cnt, st);
     }
     tm.mark();   // 3
     tm.mark();   // 4
@@ -1572,6 +1595,10 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipStreamWaitEvent(st, in_ready.e, 0));   // the field reaching every element
         ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
         if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
+        if (keep_cir) {
+            ch.cir_amp = Scratch(c, sizeof(float2) * (size_t)((n_u + R) * M), st);
+            ch.cir_len = Scratch(c, sizeof(double) * (size_t)((n_u + R) * M), st);
+        }
         int n_mchunk = (int)((M + 63) / 64);
         int64_t waves = R * n_mchunk;
         int64_t threads = waves * 64;
@@ -1585,19 +1612,22 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         }
         tm.mark();   // 5
         if (threads > 0) {
-            if (count_work && !brute && !keep_paths) {
+            if (count_work && !brute && !keep_paths && !keep_cir) {
                 SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false>), dim3(nblk(threads, RIS_B)),
                                                 dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                 uptr.as<int64_t>(), useq.as<int32_t>(), order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
-                                                ch.ris_valid.as<uint8_t>(), d_legs, d_work, d_ctr + 14));
+                                                ch.ris_valid.as<uint8_t>(), (float2*)nullptr, (double*)nullptr, d_legs,
+                                                d_work, d_ctr + 14));
             } else {
                 SEL_BOOL(fresnel, FR, SEL_BOOL(brute, BR,
-                         SEL_BOOL(keep_paths, KP,
+                         SEL_BOOL(keep_paths || keep_cir, KP,
                                   SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false, FR>),
                                                                   dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, st, sv,
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                                   uptr.as<int64_t>(), useq.as<int32_t>(),
-                                                                  order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(), ch.ris_valid.as<uint8_t>(),
+                                                                  order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
+                                                                  keep_paths ? ch.ris_valid.as<uint8_t>() : nullptr,
+                                                                  ch.cir_amp.as<float2>(), ch.cir_len.as<double>(),
                                                                   d_legs, d_work, d_ctr + 14)))));
             }
         }
@@ -1607,6 +1637,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             ch.n_u = n_u;
             ch.useq = std::move(useq);
         }
+        if (keep_cir) ch.cir_uptr = std::move(uptr);
     }
     if (keep_paths) {
         ch.n_cand[0] = bt.cd.n;
@@ -1634,6 +1665,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     out.n_slots = a.ris ? h[5] + R : 0;
     ch.n_env = out.n_env;
     ch.n_slots = out.n_slots;
+    ch.keep_cir = keep_cir;
     for (int q = 0; q < 5; ++q) out.work[q] = h[8 + q];
     out.leg_walk_fallbacks = h[14];
     out.n_in_seq = incoming && a.ris ? h[16] : 0;
@@ -1655,6 +1687,82 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         out.ms[7] = el(0, 7);                  // total
     }
     ch.last_stream = st;
+}
+
+// --------------------------------------------------------------------------
+// Channel impulse response of one configuration (delay bins of width
+// L_bin / c): one workgroup per receiver.  The receiver's paths (environment
+// cells, then RIS slots and elements, in record order) pass through LDS in
+// chunks of 256, each thread computing one path's bin and gamma-weighted
+// amplitude; then thread t adds, in chunk order, the staged paths that fall
+// in its bins t, t + 256, ... (FP64), so every bin has one fixed summation
+// order.  Bin = floor(length / L_bin).
+// --------------------------------------------------------------------------
+constexpr int CIR_B = 256;
+__global__ __launch_bounds__(CIR_B) void k_cir(const int64_t* env_rstart, const uint8_t* env_valid,
+                                               const float2* env_amp, const double* env_len, const int64_t* uptr,
+                                               const float2* camp, const double* clen, int64_t M, const float2* gamma,
+                                               double l_bin, int64_t n_bins, float2* cir)
+{
+    __shared__ int64_t sbin[CIR_B];
+    __shared__ double sre[CIR_B], sim[CIR_B];
+    const int64_t r = blockIdx.x;
+    const int tid = threadIdx.x;
+    const int64_t e0 = env_rstart ? env_rstart[r] : 0, e1 = env_rstart ? env_rstart[r + 1] : 0;
+    const int64_t s0 = uptr ? uptr[r] + r : 0, s1 = uptr ? uptr[r + 1] + r + 1 : 0;
+    const int64_t n_env = e1 - e0, n_path = n_env + (s1 - s0) * M;
+    for (int64_t b0 = 0; b0 < n_bins; b0 += CIR_B) {
+        const int64_t b = b0 + tid;
+        double cr = 0.0, ci = 0.0;
+        for (int64_t p0 = 0; p0 < n_path; p0 += CIR_B) {
+            const int64_t p = p0 + tid;
+            int64_t bin = -1;
+            double ar = 0.0, ai = 0.0;
+            if (p < n_env) {
+                const int64_t j = e0 + p;
+                if (env_valid[j]) {
+                    const float2 a = env_amp[j];
+                    bin = (int64_t)floor(env_len[j] / l_bin);
+                    ar = a.x;
+                    ai = a.y;
+                }
+            } else if (p < n_path) {
+                const int64_t q = p - n_env, sl = s0 + q / M, m = q - (q / M) * M;
+                const float2 a = camp[sl * M + m];
+                if (a.x != 0.0f || a.y != 0.0f) {
+                    const float2 g = gamma[m];
+                    bin = (int64_t)floor(clen[sl * M + m] / l_bin);
+                    ar = (double)a.x * (double)g.x - (double)a.y * (double)g.y;
+                    ai = (double)a.x * (double)g.y + (double)a.y * (double)g.x;
+                }
+            }
+            sbin[tid] = bin;
+            sre[tid] = ar;
+            sim[tid] = ai;
+            __syncthreads();
+            const int cnt = (int)(n_path - p0 < CIR_B ? n_path - p0 : CIR_B);
+            for (int i = 0; i < cnt; ++i)
+                if (sbin[i] == b) {
+                    cr += sre[i];
+                    ci += sim[i];
+                }
+            __syncthreads();
+        }
+        if (b < n_bins) cir[r * n_bins + b] = make_float2((float)cr, (float)ci);
+    }
+}
+
+void cir(Ctx& c, const Channel& ch, const float* gamma, double bin_s, int64_t n_bins, float* out, hipStream_t st)
+{
+    (void)c;
+    if (ch.R == 0 || n_bins == 0) return;
+    const double l_bin = 299792458.0 * bin_s;
+    const bool ris = ch.M > 0 && ch.cir_uptr.bytes > 0;
+    hipLaunchKernelGGL(k_cir, dim3((unsigned)ch.R), dim3(CIR_B), 0, st, ch.env_cells > 0 ? ch.env_rstart.as<int64_t>() : nullptr,
+                       ch.env_valid.as<uint8_t>(), ch.env_amp.as<float2>(), ch.env_len.as<double>(),
+                       ris ? ch.cir_uptr.as<int64_t>() : nullptr, ch.cir_amp.as<float2>(), ch.cir_len.as<double>(),
+                       ris ? ch.M : 0, (const float2*)gamma, l_bin, n_bins, (float2*)out);
+    HIP_CHECK(hipGetLastError());
 }
 
 }  // namespace rt

@@ -36,6 +36,7 @@ FLAG_COUNT_WORK = 16
 FLAG_RIS_INCOMING = 32
 FLAG_FRESNEL_TE = 64
 FLAG_FRESNEL_TM = 128
+FLAG_KEEP_CIR = 256
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
@@ -46,7 +47,7 @@ PREC_MFMA_F16X2 = 3
 ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
-    "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials",
+    "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials", "rt_cir",
 )
 
 
@@ -130,6 +131,7 @@ def lib():
                                             P, P, P]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
             "rt_scene_set_materials": (ctypes.c_int32, [P, u64, P, P, P]),
+            "rt_cir": (ctypes.c_int32, [P, u64, P, ctypes.c_double, i64, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -308,6 +310,18 @@ class Context:
         return {"env": env, "useq": useq, "ris_valid": valid.astype(bool)}
 
     # ---- RIS sum ----
+    def cir(self, ch: int, gamma, bin_s: float, n_bins: int, stream=None):
+        """Delay-binned impulse response of one configuration (gamma: torch
+        complex64 device tensor [M]); returns a torch complex64 [R, n_bins]
+        device tensor.  The channel needs FLAG_KEEP_CIR."""
+        import torch
+        R = int(self.channel_info(ch)[0])
+        dev = gamma.device if hasattr(gamma, "device") else torch.device("cuda")
+        out = torch.zeros((R, n_bins), dtype=torch.complex64, device=dev)
+        _check(lib().rt_cir(self._h, ctypes.c_uint64(ch), ctypes.c_void_p(gamma.data_ptr()), float(bin_s),
+                            int(n_bins), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        return out
+
     def ris_sum(self, ch: int, gamma, scale: float = 1.0, gamma_is_real: bool = False,
                 precision: int = PREC_MFMA_BF16X2, want_E: bool = False, want_P: bool = True, stream=None,
                 E_out=None, P_out=None):

@@ -202,6 +202,36 @@ def test_fresnel_flag_errors(ctx):
         ctx.destroy(h)
 
 
+@pytest.mark.parametrize("case", ["tiny", "lab"])
+def test_cir_matches_oracle(ctx, case):
+    """Impulse response of one configuration: every delay bin against the
+    oracle's (null-aware bound on the bin's incoherent sum), and the bins of
+    each receiver add up to its narrowband field."""
+    import torch
+    from paper_2402_13034_amd import risrt
+    prob = synth.tiny_box() if case == "tiny" else synth.lab_room(nx=9, ny=7)
+    n_rays = None if case == "tiny" else 20_000
+    bin_s, n_bins = 2.5e-10, 400
+    scene, ris, ch, st = _run(ctx, prob, risrt.FLAG_KEEP_CIR, n_rays)
+    g = prob.gamma[:, 0]
+    h = ctx.cir(ch, torch.from_numpy(g.astype(np.complex64)).cuda(), bin_s, n_bins)
+    torch.cuda.synchronize()
+    h = h.cpu().numpy().astype(np.complex128)
+    E_env, H = ctx.channel_read(ch)
+    for o in (ch, scene, ris):
+        ctx.destroy(o)
+    ref = O.trace(prob, n_rays=n_rays)
+    h_ref = O.cir(ref, prob, g, bin_s, n_bins)
+    inc = O.cir({**ref, "env_amp": np.abs(ref["env_amp"]), "ris_amp": np.abs(ref["ris_amp"])}, prob,
+                np.abs(g), bin_s, n_bins).real
+    scale = np.maximum(np.abs(h_ref) ** 2, 1e-3 * inc ** 2)
+    ok = inc > 0
+    assert np.all(np.abs(h[~ok]) == 0)
+    assert np.max(np.abs(h[ok] - h_ref[ok]) ** 2 / scale[ok]) < 1e-4
+    E = E_env.astype(np.complex128) + H.astype(np.complex128) @ g
+    assert np.max(np.abs(h.sum(axis=1) - E)) < 1e-4 * np.max(np.abs(E))
+
+
 def test_paper_scene_reflective_parity(ctx):
     """Section III's reflective scenario (metal walls, TE Fresnel, order 2,
     10^5 rays) on every third receiver of the 1 cm map."""
