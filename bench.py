@@ -410,8 +410,8 @@ def main():
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: the path runs on a single device (see DESIGN.md for how it "
-              "would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU only: the path runs on a single device (receivers would shard "
+              "across GPUs without communication); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
     from paper_2402_13034_amd import risrt, synth

@@ -43,7 +43,7 @@ typedef int32_t rt_status;
 #define RT_EDEVICE (-3)      /* a HIP call failed */
 #define RT_EBUSY (-4)        /* handle in use */
 #define RT_ENOTFOUND (-5)    /* unknown or destroyed handle */
-#define RT_EUNSUPPORTED (-6) /* size or option outside what this build supports */
+#define RT_EUNSUPPORTED (-6) /* size or option outside what the library supports */
 
 /* antenna / element pattern kinds (power patterns, 1 at the maximum) */
 #define RT_PAT_ISO 0      /* F = 1 */
