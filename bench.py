@@ -80,7 +80,7 @@ def device_mesh(prob):
             torch.from_numpy(np.ascontiguousarray(sc.refl_im, np.float32)).cuda())
 
 
-def run_trace_bench(ctx, prob, steps, warmup):
+def run_trace_bench(ctx, prob, steps, warmup, variants=True):
     import torch
     from paper_2402_13034_amd import risrt, synth
     mesh = device_mesh(prob)
@@ -127,6 +127,10 @@ def run_trace_bench(ctx, prob, steps, warmup):
     scene = ctx.scene_create(*mesh)
     ch, cst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_COUNT_WORK)
     ctx.destroy(ch)
+    if not variants:
+        ctx.destroy(scene)
+        ctx.destroy(ris)
+        return stats, t1 - t0, cst["ris_work"], None
     # the same step with the reflections Tx -> surfaces -> element as well (its own line,
     # not the headline: the workload's channel has the direct incoming leg only)
     n_in = max(2, steps // 2)
@@ -406,6 +410,9 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--no-gemm", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-variants", action="store_true",
+                    help="skip the optional-feature lines (incoming reflections, Fresnel, impulse response, the "
+                         "paper's scenario)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -429,10 +436,12 @@ def main():
     ctx = risrt.Context(0)
     log("bench: lab room, %d triangles, M=%d, R=%d, K=%d, rays=%d" % (
         prob.scene.n_tri, prob.ris.elems.shape[0], prob.rx_pos.shape[0], prob.order, prob.n_rays))
-    stats, dt, work, variants = run_trace_bench(ctx, prob, args.steps, args.warmup)
-    log("bench: variants %s" % json.dumps(variants))
-    paper = run_paper_bench(ctx)
-    log("bench: paper scenario %s" % json.dumps(paper))
+    stats, dt, work, variants = run_trace_bench(ctx, prob, args.steps, args.warmup, not args.no_variants)
+    paper = None
+    if not args.no_variants:
+        log("bench: variants %s" % json.dumps(variants))
+        paper = run_paper_bench(ctx)
+        log("bench: paper scenario %s" % json.dumps(paper))
     segs = sum(s["segments"] for s in stats)
     value = segs / dt / 1e6
     ms_step = dt / args.steps * 1e3
