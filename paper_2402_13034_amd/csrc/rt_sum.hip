@@ -294,6 +294,105 @@ __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ A
         }
 }
 
+// Two-product split (H hi + lo against Gamma hi), larger tiles: 256 x 256 per
+// workgroup of 8 waves (2 x 4), each wave 128 x 64 = 4 x 2 blocks of 32 x 32,
+// so every A fragment read from LDS feeds two blocks and every B fragment
+// four.  K tiles of 32 are double-buffered in LDS (one barrier per tile): the
+// next tile's global loads are in flight while the current one is multiplied.
+constexpr int G2M = 256, G2N = 256, G2K = 32, G2L = G2K + 8;
+template <bool F16>
+__global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
+                                                     const uint16_t* __restrict__ Bhi, int64_t kp,
+                                                     const float2* __restrict__ Eenv, const int32_t* __restrict__ sexp,
+                                                     int64_t R, int64_t C, float scale, float2* Eout, float* Pout,
+                                                     int n_tiles_n)
+{
+    __shared__ __attribute__((aligned(16))) uint16_t sAh[2][G2M * G2L];
+    __shared__ __attribute__((aligned(16))) uint16_t sAl[2][G2M * G2L];
+    __shared__ __attribute__((aligned(16))) uint16_t sB[2][G2N * G2L];
+    const int tid = threadIdx.x;
+    const int wave = tid >> 6, lane = tid & 63;
+    const int64_t tile_m = blockIdx.x / n_tiles_n, tile_n = blockIdx.x % n_tiles_n;
+    const int64_t row0 = tile_m * G2M, col0 = tile_n * G2N;
+    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+
+    f32x16 acc[4][2];
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j)
+            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+
+    // each thread moves 16 bf16 (two 16-byte vectors) of a 256 x 32 tile of each operand
+    const int lrow = tid >> 1, lcol = (tid & 1) * 16;
+    const uint4* gAh = (const uint4*)(Ahi + (row0 + lrow) * kp + lcol);
+    const uint4* gAl = (const uint4*)(Alo + (row0 + lrow) * kp + lcol);
+    const uint4* gB = (const uint4*)(Bhi + (col0 + lrow) * kp + lcol);
+    const int64_t nk = kp / G2K;
+    uint4 rAh0 = gAh[0], rAh1 = gAh[1], rAl0 = gAl[0], rAl1 = gAl[1], rB0 = gB[0], rB1 = gB[1];
+    auto stage = [&](int buf) {
+        *(uint4*)&sAh[buf][lrow * G2L + lcol] = rAh0;
+        *(uint4*)&sAh[buf][lrow * G2L + lcol + 8] = rAh1;
+        *(uint4*)&sAl[buf][lrow * G2L + lcol] = rAl0;
+        *(uint4*)&sAl[buf][lrow * G2L + lcol + 8] = rAl1;
+        *(uint4*)&sB[buf][lrow * G2L + lcol] = rB0;
+        *(uint4*)&sB[buf][lrow * G2L + lcol + 8] = rB1;
+    };
+    auto fetch = [&](int64_t kt) {
+        const int64_t o = kt * G2K / 8;   // in uint4 units
+        rAh0 = gAh[o];
+        rAh1 = gAh[o + 1];
+        rAl0 = gAl[o];
+        rAl1 = gAl[o + 1];
+        rB0 = gB[o];
+        rB1 = gB[o + 1];
+    };
+    stage(0);
+    if (nk > 1) fetch(1);
+    __syncthreads();
+    for (int64_t kt = 0; kt < nk; ++kt) {
+        const int buf = (int)(kt & 1);
+        for (int ks = 0; ks < G2K; ks += 16) {
+            const int kofs = ks + (lane >> 5) * 8;
+            uint4 ah[4], al[4], bh[2];
+            for (int i = 0; i < 4; ++i) {
+                const int r = wm + i * 32 + (lane & 31);
+                ah[i] = *(const uint4*)&sAh[buf][r * G2L + kofs];
+                al[i] = *(const uint4*)&sAl[buf][r * G2L + kofs];
+            }
+            for (int j = 0; j < 2; ++j) {
+                const int cix = wn + j * 32 + (lane & 31);
+                bh[j] = *(const uint4*)&sB[buf][cix * G2L + kofs];
+            }
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma16<F16>((const uint16_t*)&ah[i], (const uint16_t*)&bh[j], acc[i][j]);
+            for (int i = 0; i < 4; ++i)
+                for (int j = 0; j < 2; ++j)
+                    acc[i][j] = mfma16<F16>((const uint16_t*)&al[i], (const uint16_t*)&bh[j], acc[i][j]);
+        }
+        if (kt + 1 < nk) {
+            stage(buf ^ 1);   // the other buffer: its last readers passed the previous barrier
+            if (kt + 2 < nk) fetch(kt + 2);
+        }
+        __syncthreads();
+    }
+    // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4)
+    for (int i = 0; i < 4; ++i)
+        for (int j = 0; j < 2; ++j) {
+            const int64_t c = col0 + wn + j * 32 + (lane & 31);
+            for (int e = 0; e < 16; e += 2) {
+                const int64_t row = row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
+                const int64_t r = row >> 1;
+                if (r >= R || c >= C) continue;
+                const float2 e0 = Eenv[r];
+                const float sr = F16 ? ldexpf(scale, -sexp[r]) : scale;   // exact: a power of two
+                const float er = e0.x + sr * acc[i][j][e];
+                const float ei = e0.y + sr * acc[i][j][e + 1];
+                if (Eout) Eout[r * C + c] = make_float2(er, ei);
+                if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
+            }
+        }
+}
+
 void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real, int precision,
              float* E_out, float* P_out, hipStream_t st)
 {
@@ -312,8 +411,8 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
     const int lay = gamma_real ? 1 : 2;
     const int64_t kd = gamma_real ? M : 2 * M;
     const int64_t kp = round_up(kd > 0 ? kd : 1, GBK);
-    const int64_t rows_p = round_up(2 * R, GBM);
-    const int64_t cols_p = round_up(C, GBN);
+    const int64_t rows_p = round_up(2 * R, G2M);   // a multiple of both tile heights
+    const int64_t cols_p = round_up(C, G2N);
     if (ch.split_kind == layout && ch.split_ev) HIP_CHECK(hipStreamWaitEvent(st, ch.split_ev, 0));
     if (ch.split_kind != layout) {
         ch.a_hi.release();
@@ -351,14 +450,18 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
         hipLaunchKernelGGL((k_sum_mfma<3, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
                            ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), blo.as<uint16_t>(), kp, ch.E_env.as<float2>(),
                            sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
-    else if (f16)
-        hipLaunchKernelGGL((k_sum_mfma<2, true>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
-                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), (const uint16_t*)nullptr, kp,
-                           ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
-    else
-        hipLaunchKernelGGL((k_sum_mfma<2, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
-                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), (const uint16_t*)nullptr, kp,
-                           ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
+    else {
+        const int n_tn2 = (int)(cols_p / G2N);
+        const int64_t n_tiles2 = (rows_p / G2M) * n_tn2;
+        if (f16)
+            hipLaunchKernelGGL((k_sum_mfma_2x<true>), dim3((unsigned)n_tiles2), dim3(512), 0, st, ch.a_hi.as<uint16_t>(),
+                               ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), kp, ch.E_env.as<float2>(), sexp, R, C, scale,
+                               (float2*)E_out, P_out, n_tn2);
+        else
+            hipLaunchKernelGGL((k_sum_mfma_2x<false>), dim3((unsigned)n_tiles2), dim3(512), 0, st,
+                               ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), kp,
+                               ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn2);
+    }
     HIP_CHECK(hipGetLastError());
 }
 
