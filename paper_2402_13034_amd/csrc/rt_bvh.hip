@@ -46,12 +46,12 @@ __device__ __forceinline__ unsigned wave_umax(unsigned v)
     return v;
 }
 
-// FP64 vertices, reflection coefficients, surface ids, centroids; bounds of
-// the centroids and of the vertices (order-preserving unsigned keys, reduced
-// per wave, one atomic per wave and value).
+// FP64 vertices and their 2-D projection, reflection coefficients, surface
+// ids, centroids; bounds of the centroids and of the vertices (order-preserving
+// unsigned keys, reduced per wave, one atomic per wave and value).
 __global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* surf_in, const float* rr,
                              const float* ri, int64_t nv, int64_t nt, double* v64, float2* refl,
-                             int32_t* surf, float4* cent, unsigned* bounds, int32_t* bad)
+                             int32_t* surf, float4* cent, unsigned* bounds, int32_t* bad, double* proj, int32_t* axes)
 {
     const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     const bool live = t < nt;
@@ -73,6 +73,7 @@ __global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* su
                 hi[k] = fmaxf(hi[k], x);
             }
         }
+        triangle_projection(v64 + 9 * t, proj + 6 * t, axes + t);
         refl[t] = make_float2(rr[t], ri[t]);
         surf[t] = surf_in[t];
         if (surf_in[t] < 0) atomicOr(bad, 4);
@@ -162,6 +163,7 @@ __global__ void k_karras(const uint64_t* keys, int64_t n, int32_t* child, int32_
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n - 1) return;
+    if (i == 0) parent_int[0] = -1;   // the root; every other node and every leaf gets its parent below
     int32_t cl, cr;
     lbvh_node(keys, n, i, &cl, &cr);
     if (cl < 0) parent_leaf[~cl] = (int32_t)i;
@@ -205,20 +207,6 @@ __global__ void k_refit(const int32_t* child, const int32_t* parent_int, const i
         __threadfence();
         p = parent_int[p];
     }
-}
-
-__global__ void k_depth(const int32_t* parent_int, const int32_t* parent_leaf, int64_t n, int32_t* maxd)
-{
-    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (i >= n) return;
-    int d = 0;
-    int32_t p = parent_leaf[i];
-    while (p >= 0 && p < n - 1 && d < 4096) {
-        ++d;
-        p = parent_int[p];
-    }
-    if (p != -1) d = 1 << 20;   // broken parent chain
-    atomicMax(maxd, d);
 }
 
 // Refit of a small tree in one workgroup, the leaf-to-root walk of the
@@ -284,14 +272,20 @@ __global__ __launch_bounds__(1024) void k_refit_small(const int32_t* child, cons
 
 // 4-wide nodes: every internal node of even depth lists its grandchildren
 // (a leaf child stands for itself).  Boxes are copied from the binary nodes.
+// Also the tree depth: the deepest leaf lies one below the deepest internal
+// node (a broken parent chain gives 2^20).
 __global__ void k_node4(const int32_t* child, const int32_t* parent_int, const float4* nodes, const float4* tri4,
-                        int64_t ni, float4* node4)
+                        int64_t ni, float4* node4, int32_t* maxd)
 {
-    int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (n >= ni) return;
+    const int64_t n = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const bool live = n < ni;
     int d = 0;
-    for (int32_t p = parent_int[n]; p >= 0 && p < ni && d < 4096; p = parent_int[p]) ++d;
-    if (d & 1) return;
+    int32_t p = live ? parent_int[n] : -1;
+    for (; p >= 0 && p < ni && d < 4096; p = parent_int[p]) ++d;
+    const unsigned dl = !live ? 0u : (p != -1 ? (1u << 20) : (unsigned)d + 1u);
+    const unsigned dm = wave_umax(dl);
+    if ((threadIdx.x & 63) == 0 && dm > 0) atomicMax(maxd, (int32_t)dm);
+    if (!live || (d & 1)) return;
     float lo[4][3], hi[4][3];
     int32_t ref[4];
     int cnt = 0;
@@ -336,13 +330,6 @@ __global__ void k_check_refit(const int32_t* flags, int64_t ni, int32_t* bad)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i < ni && flags[i] != 2) atomicOr(bad, 8);
-}
-
-__global__ void k_tri_proj(const double* v64, int64_t nt, double* proj, int32_t* axes)
-{
-    int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (t >= nt) return;
-    triangle_projection(v64 + 9 * t, proj + 6 * t, axes + t);
 }
 
 // surfaces
@@ -504,14 +491,28 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         return;
     }
     if (nt >= (int64_t)1 << 30) throw inval_error("too many triangles");
-    Scratch dV(c, sizeof(float) * 3 * (size_t)nv, st), dT(c, sizeof(int32_t) * 3 * (size_t)nt, st),
-        dS(c, sizeof(int32_t) * (size_t)nt, st), dR(c, sizeof(float) * (size_t)nt, st),
-        dI(c, sizeof(float) * (size_t)nt, st);
-    HIP_CHECK(hipMemcpyAsync(dV.p, V, dV.bytes, hipMemcpyDefault, st));
-    HIP_CHECK(hipMemcpyAsync(dT.p, T, dT.bytes, hipMemcpyDefault, st));
-    HIP_CHECK(hipMemcpyAsync(dS.p, surf, dS.bytes, hipMemcpyDefault, st));
-    HIP_CHECK(hipMemcpyAsync(dR.p, rr, dR.bytes, hipMemcpyDefault, st));
-    HIP_CHECK(hipMemcpyAsync(dI.p, ri, dI.bytes, hipMemcpyDefault, st));
+    // inputs in device memory are read in place (the build is complete before the call returns);
+    // host arrays are staged
+    auto on_device = [](const void* p) {
+        hipPointerAttribute_t at;
+        if (hipPointerGetAttributes(&at, p) != hipSuccess) {
+            (void)hipGetLastError();
+            return false;
+        }
+        return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
+    };
+    Scratch stage_buf[5];
+    auto input = [&](const void* p, size_t bytes, int slot) -> const void* {
+        if (bytes == 0 || on_device(p)) return p;
+        stage_buf[slot] = Scratch(c, bytes, st);
+        HIP_CHECK(hipMemcpyAsync(stage_buf[slot].p, p, bytes, hipMemcpyDefault, st));
+        return stage_buf[slot].p;
+    };
+    const float* dV = (const float*)input(V, sizeof(float) * 3 * (size_t)nv, 0);
+    const int32_t* dT = (const int32_t*)input(T, sizeof(int32_t) * 3 * (size_t)nt, 1);
+    const int32_t* dS = (const int32_t*)input(surf, sizeof(int32_t) * (size_t)nt, 2);
+    const float* dR = (const float*)input(rr, sizeof(float) * (size_t)nt, 3);
+    const float* dI = (const float*)input(ri, sizeof(float) * (size_t)nt, 4);
 
     s.v64 = Scratch(c, sizeof(double) * 9 * (size_t)nt, st);
     s.t_proj = Scratch(c, sizeof(double) * 6 * (size_t)nt, st);
@@ -530,22 +531,18 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     hipLaunchKernelGGL(k_ctl_init, dim3(1), dim3(64), 0, st, bounds);
     HIP_CHECK(hipGetLastError());
     const int B = 256;
-    hipLaunchKernelGGL(k_scene_prep, dim3(blocks_for(nt, B)), dim3(B), 0, st, dV.as<float>(), dT.as<int32_t>(),
-                       dS.as<int32_t>(), dR.as<float>(), dI.as<float>(), nv, nt, s.v64.as<double>(),
-                       s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad);
-    HIP_CHECK(hipGetLastError());
-    hipLaunchKernelGGL(k_tri_proj, dim3(blocks_for(nt, B)), dim3(B), 0, st, s.v64.as<double>(), nt,
+    hipLaunchKernelGGL(k_scene_prep, dim3(blocks_for(nt, B)), dim3(B), 0, st, dV, dT, dS, dR, dI, nv, nt,
+                       s.v64.as<double>(), s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad,
                        s.t_proj.as<double>(), s.t_axes.as<int32_t>());
     HIP_CHECK(hipGetLastError());
-    Scratch keys(c, sizeof(uint64_t) * (size_t)nt, st);
+    Scratch keys_raw(c, sizeof(uint64_t) * (size_t)nt, st), keys(c, sizeof(uint64_t) * (size_t)nt, st);
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, B)), dim3(B), 0, st, cent.as<float4>(), bounds, nt,
-                       keys.as<uint64_t>());
+                       keys_raw.as<uint64_t>());
     HIP_CHECK(hipGetLastError());
-    sort_u64(c, keys.as<uint64_t>(), nt, 62, st);
+    sort_u64_into(c, keys_raw.as<uint64_t>(), keys.as<uint64_t>(), nt, 62, st);
     Scratch lbox(c, sizeof(float) * 6 * (size_t)nt, st);
-    hipLaunchKernelGGL(k_leaves, dim3(blocks_for(nt, B)), dim3(B), 0, st, keys.as<uint64_t>(), dV.as<float>(),
-                       dT.as<int32_t>(), s.surf.as<int32_t>(), nv, nt, bounds, s.tri4.as<float4>(),
-                       lbox.as<float>());
+    hipLaunchKernelGGL(k_leaves, dim3(blocks_for(nt, B)), dim3(B), 0, st, keys.as<uint64_t>(), dV, dT,
+                       s.surf.as<int32_t>(), nv, nt, bounds, s.tri4.as<float4>(), lbox.as<float>());
     HIP_CHECK(hipGetLastError());
 
     if (nt >= 2) {
@@ -556,8 +553,6 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
             flags(c, sizeof(int32_t) * (size_t)ni, st);
         const bool small = nt <= RT_REFIT_SMALL;
         if (!small) HIP_CHECK(hipMemsetAsync(flags.p, 0, flags.bytes, st));
-        HIP_CHECK(hipMemsetAsync(pint.p, 0xff, pint.bytes, st));
-        HIP_CHECK(hipMemsetAsync(pleaf.p, 0xff, pleaf.bytes, st));
         hipLaunchKernelGGL(k_karras, dim3(blocks_for(ni, B)), dim3(B), 0, st, keys.as<uint64_t>(), nt,
                            child.as<int32_t>(), pint.as<int32_t>(), pleaf.as<int32_t>());
         HIP_CHECK(hipGetLastError());
@@ -571,10 +566,7 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         HIP_CHECK(hipGetLastError());
         s.node4 = Scratch(c, sizeof(float4) * 8 * (size_t)ni, st);
         hipLaunchKernelGGL(k_node4, dim3(blocks_for(ni, B)), dim3(B), 0, st, child.as<int32_t>(), pint.as<int32_t>(),
-                           s.nodes.as<float4>(), s.tri4.as<float4>(), ni, s.node4.as<float4>());
-        HIP_CHECK(hipGetLastError());
-        hipLaunchKernelGGL(k_depth, dim3(blocks_for(nt, B)), dim3(B), 0, st, pint.as<int32_t>(),
-                           pleaf.as<int32_t>(), nt, maxd);
+                           s.nodes.as<float4>(), s.tri4.as<float4>(), ni, s.node4.as<float4>(), maxd);
         HIP_CHECK(hipGetLastError());
         if (!small) {
             hipLaunchKernelGGL(k_check_refit, dim3(blocks_for(ni, B)), dim3(B), 0, st, flags.as<int32_t>(), ni, bad);
@@ -590,7 +582,11 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     hipLaunchKernelGGL(k_surf_keys, dim3(blocks_for(nt, B)), dim3(B), 0, st, s.surf.as<int32_t>(), nt,
                        skeys.as<uint64_t>(), nsurf, bad);
     HIP_CHECK(hipGetLastError());
-    sort_u64(c, skeys.as<uint64_t>(), nt, 64, st);
+    {
+        Scratch sorted(c, sizeof(uint64_t) * (size_t)nt, st);
+        sort_u64_into(c, skeys.as<uint64_t>(), sorted.as<uint64_t>(), nt, 64, st);
+        std::swap(skeys, sorted);
+    }
     s.s_ptr = Scratch(c, sizeof(int32_t) * (size_t)(nt + 1), st);
     s.s_tris = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
     s.s_plane = Scratch(c, sizeof(double) * 4 * (size_t)nt, st);

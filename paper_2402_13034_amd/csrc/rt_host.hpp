@@ -180,6 +180,7 @@ struct EnvRec {
 
 // ---- primitives (rocPRIM) ----
 void sort_u64(Ctx& c, uint64_t* keys, int64_t n, int end_bit, hipStream_t st);
+void sort_u64_into(Ctx& c, uint64_t* keys_in, uint64_t* keys_out, int64_t n, int end_bit, hipStream_t st);
 // unique of sorted keys; count written to device int64
 void unique_u64(Ctx& c, const uint64_t* in, uint64_t* out, int64_t n, int64_t* d_count, hipStream_t st);
 // exclusive scan of uint8 flags into int64 offsets; total written to d_total

@@ -7,6 +7,20 @@
 
 namespace rt {
 
+// keys_in sorted into keys_out (n >= 1; keys_in is left in an unspecified order)
+void sort_u64_into(Ctx& c, uint64_t* keys_in, uint64_t* keys_out, int64_t n, int end_bit, hipStream_t st)
+{
+    if (n == 1) {
+        HIP_CHECK(hipMemcpyAsync(keys_out, keys_in, sizeof(uint64_t), hipMemcpyDeviceToDevice, st));
+        return;
+    }
+    if (n <= 0) return;
+    size_t bytes = 0;
+    HIP_CHECK(rocprim::radix_sort_keys(nullptr, bytes, keys_in, keys_out, (size_t)n, 0, end_bit, st));
+    Scratch tmp(c, bytes, st);
+    HIP_CHECK(rocprim::radix_sort_keys(tmp.p, bytes, keys_in, keys_out, (size_t)n, 0, end_bit, st));
+}
+
 void sort_u64(Ctx& c, uint64_t* keys, int64_t n, int end_bit, hipStream_t st)
 {
     if (n <= 1) return;
