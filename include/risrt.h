@@ -169,7 +169,8 @@ rt_status rt_mem_info(rt_ctx ctx, uint64_t* in_use, uint64_t* budget);
  * triangles of one surface must be coplanar; ids 0..n_surf-1, each used), and
  * a complex reflection coefficient per triangle applied at every specular
  * bounce.  n_tri may be 0 (free space).  Builds the BVH on `stream`
- * (waits for it once, to check the tree depth). */
+ * (waits for it once, to check the tree depth; device arrays are read in
+ * place, host arrays staged, all before the call returns). */
 rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const int32_t* tri,
                           int64_t n_tri, const int32_t* surf, const float* refl_re,
                           const float* refl_im, void* stream, uint64_t* scene);
