@@ -1327,7 +1327,9 @@ static int64_t cand_count(Ctx& c, const Branch& br, bool exhaustive)
 static void cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch& br, int64_t n)
 {
     if (exhaustive) return;
-    sort_u64(c, br.keys.as<uint64_t>(), n, RT_KEY_BITS * a.tc.K, br.st);
+    Scratch sorted(c, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1), br.st);
+    sort_u64_into(c, br.keys.as<uint64_t>(), sorted.as<uint64_t>(), n, RT_KEY_BITS * a.tc.K, br.st);
+    br.keys = std::move(sorted);
     HIP_CHECK(hipMemsetAsync(br.d_app, 0, 2 * sizeof(unsigned long long), br.st));
 }
 
@@ -1483,31 +1485,33 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 1-3: candidates
     cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
     if (two) cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
-    int64_t n_tx = cand_count(c, bt, exhaustive);
-    int64_t n_u0 = two ? cand_count(c, bu, exhaustive) : 0;
-    // an overflow of a hash set: repeat phase A with the next level (the
-    // discovery segments were counted by the first pass)
+    // Each branch goes on as soon as its own count is back, so the Tx branch
+    // (launched first) does not wait for the centre branch's discovery.  An
+    // overflow of a hash set repeats phase A with the next level (the
+    // discovery segments were counted by the first pass).
     unsigned long long* d_dummy = d_ctr + 15;
-    while (n_tx < 0) {
-        bt.table_level += 1;
-        HIP_CHECK(hipMemsetAsync(bt.d_app, 0, 2 * sizeof(unsigned long long), bt.st));
-        cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_dummy);
-        n_tx = cand_count(c, bt, exhaustive);
-    }
-    while (n_u0 < 0) {
-        bu.table_level += 1;
-        HIP_CHECK(hipMemsetAsync(bu.d_app, 0, 2 * sizeof(unsigned long long), bu.st));
-        cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_dummy);
-        n_u0 = cand_count(c, bu, exhaustive);
-    }
+    auto count_of = [&](Branch& br) {
+        int64_t n = cand_count(c, br, exhaustive);
+        while (n < 0) {
+            br.table_level += 1;
+            HIP_CHECK(hipMemsetAsync(br.d_app, 0, 2 * sizeof(unsigned long long), br.st));
+            cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, br, d_dummy);
+            n = cand_count(c, br, exhaustive);
+        }
+        return n;
+    };
+    const int64_t n_tx = count_of(bt);
     cand_phase_b(c, a, exhaustive, bt, n_tx);
-    if (two) cand_phase_b(c, a, exhaustive, bu, n_u0);
-    out.n_cand_tx = n_tx;
-    out.n_cand_u = n_u0;
     tm.mark();   // 2
     // 4: geometry of every (receiver, candidate)
     geo_launch(c, sv, a, bt, n_tx);
-    if (two) geo_launch(c, sv, a, bu, n_u0);
+    const int64_t n_u0 = two ? count_of(bu) : 0;
+    if (two) {
+        cand_phase_b(c, a, exhaustive, bu, n_u0);
+        geo_launch(c, sv, a, bu, n_u0);
+    }
+    out.n_cand_tx = n_tx;
+    out.n_cand_u = n_u0;
     // the field reaching every element, on its own stream (forked here, launched
     // after the path kernels so that they go first)
     RisView rv{};
@@ -1520,10 +1524,10 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipEventRecord(in_fork.e, st));
         HIP_CHECK(hipStreamWaitEvent(side_in.s, in_fork.e, 0));
     }
-    const int64_t g_tx = read_i64(bt.ps.rstart.as<int64_t>() + R, st);
-    const int64_t g_u = two ? read_i64(bu.ps.rstart.as<int64_t>() + R, bu.st) : 0;
     // 5-6: legs and fields
+    const int64_t g_tx = read_i64(bt.ps.rstart.as<int64_t>() + R, st);
     paths_launch(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
+    const int64_t g_u = two ? read_i64(bu.ps.rstart.as<int64_t>() + R, bu.st) : 0;
     if (two) paths_launch(c, sv, stk, a, brute, false, bu, g_u, d_legs);
     if (a.ris) {
         ris_incident(c, sv, stk, a, brute, incoming, bt, rv, d_ctr, txm.as<TxmRec>(), side_in.s);
@@ -1605,10 +1609,11 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         if (R >= ((int64_t)1 << 32)) throw inval_error("too many receivers");
         Scratch order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), st);
         if (R > 0) {
+            Scratch cost(c, sizeof(uint64_t) * (size_t)R, st);
             hipLaunchKernelGGL(k_ris_order, dim3(nblk(R, 256)), dim3(256), 0, st, uptr.as<int64_t>(),
-                               useq.as<int32_t>(), R, order.as<uint64_t>());
+                               useq.as<int32_t>(), R, cost.as<uint64_t>());
             HIP_CHECK(hipGetLastError());
-            sort_u64(c, order.as<uint64_t>(), R, 52, st);
+            sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, st);
         }
         tm.mark();   // 5
         if (threads > 0) {
