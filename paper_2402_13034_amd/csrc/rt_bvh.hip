@@ -493,17 +493,9 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     if (nt >= (int64_t)1 << 30) throw inval_error("too many triangles");
     // inputs in device memory are read in place (the build is complete before the call returns);
     // host arrays are staged
-    auto on_device = [](const void* p) {
-        hipPointerAttribute_t at;
-        if (hipPointerGetAttributes(&at, p) != hipSuccess) {
-            (void)hipGetLastError();
-            return false;
-        }
-        return at.type == hipMemoryTypeDevice || at.type == hipMemoryTypeManaged;
-    };
     Scratch stage_buf[5];
     auto input = [&](const void* p, size_t bytes, int slot) -> const void* {
-        if (bytes == 0 || on_device(p)) return p;
+        if (bytes == 0 || is_device_ptr(p)) return p;
         stage_buf[slot] = Scratch(c, bytes, st);
         HIP_CHECK(hipMemcpyAsync(stage_buf[slot].p, p, bytes, hipMemcpyDefault, st));
         return stage_buf[slot].p;

@@ -241,17 +241,6 @@ void note_user(rt_ctx ctx, Obj& o, hipStream_t st)
     o.users.push_back(st);
 }
 
-bool is_device_ptr(const void* p)
-{
-    if (!p) return false;
-    hipPointerAttribute_t a;
-    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
-        (void)hipGetLastError();
-        return false;
-    }
-    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
-}
-
 void retarget(Scratch& s, hipStream_t st) { s.st = st; }
 
 // Release an object's memory once all work enqueued on its user streams is done.
@@ -491,9 +480,13 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         auto o = std::make_shared<Obj>();
         o->kind = 3;
         o->channel = std::make_unique<Channel>();
-        Scratch rxd(ctx->c, sizeof(double) * 3 * (size_t)R, st);
-        if (R > 0) HIP_CHECK(hipMemcpyAsync(rxd.p, rx_xyz, rxd.bytes, hipMemcpyDefault, st));
-        a.rx_dev = rxd.as<double>();
+        // receivers in device memory are read in place (the call waits for its work before it returns)
+        Scratch rxd;
+        if (R > 0 && !is_device_ptr(rx_xyz)) {
+            rxd = Scratch(ctx->c, sizeof(double) * 3 * (size_t)R, st);
+            HIP_CHECK(hipMemcpyAsync(rxd.p, rx_xyz, rxd.bytes, hipMemcpyDefault, st));
+        }
+        a.rx_dev = rxd.p ? rxd.as<double>() : rx_xyz;
         TraceOut out;
         trace(ctx->c, a, *o->channel, out, stats != nullptr, st);
         HIP_CHECK(hipEventCreateWithFlags(&o->channel->ready, hipEventDisableTiming));

@@ -179,6 +179,7 @@ struct EnvRec {
 };
 
 // ---- primitives (rocPRIM) ----
+bool is_device_ptr(const void* p);
 void sort_u64(Ctx& c, uint64_t* keys, int64_t n, int end_bit, hipStream_t st);
 void sort_u64_into(Ctx& c, uint64_t* keys_in, uint64_t* keys_out, int64_t n, int end_bit, hipStream_t st);
 // unique of sorted keys; count written to device int64

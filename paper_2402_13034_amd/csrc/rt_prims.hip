@@ -7,6 +7,18 @@
 
 namespace rt {
 
+// device (or managed) memory, as opposed to host memory, pinned or not
+bool is_device_ptr(const void* p)
+{
+    if (!p) return false;
+    hipPointerAttribute_t a;
+    if (hipPointerGetAttributes(&a, p) != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
 // keys_in sorted into keys_out (n >= 1; keys_in is left in an unspecified order)
 void sort_u64_into(Ctx& c, uint64_t* keys_in, uint64_t* keys_out, int64_t n, int end_bit, hipStream_t st)
 {
