@@ -323,6 +323,38 @@ def test_deterministic(ctx):
     assert res[0][1].tobytes() == res[1][1].tobytes()
 
 
+def test_device_inputs_read_in_place(ctx):
+    """Mesh and receivers handed over in device memory (read in place) give the
+    channel of the same arrays handed over from the host (staged), bit for bit;
+    a second, smaller problem follows so that reuse of cached buffers is covered."""
+    import torch
+    from paper_2402_13034_amd import risrt
+    for prob in (synth.lab_room(nx=16, ny=16), synth.tiny_box(seed=3)):
+        sc = prob.scene
+        _say("case device inputs, triangles", sc.n_tri, "receivers", prob.rx_pos.shape[0])
+        res = []
+        for on_device in (False, True):
+            if on_device:
+                arrs = [torch.from_numpy(np.ascontiguousarray(a, dt)).cuda()
+                        for a, dt in ((sc.V, np.float32), (sc.T, np.int32), (sc.surf, np.int32),
+                                      (sc.refl_re, np.float32), (sc.refl_im, np.float32))]
+                rx = torch.from_numpy(np.ascontiguousarray(prob.rx_pos, np.float64)).cuda()
+            else:
+                arrs = [sc.V, sc.T, sc.surf, sc.refl_re, sc.refl_im]
+                rx = None
+            scene = ctx.scene_create(*arrs)
+            r = prob.ris
+            ris = ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
+            ch, st = risrt.trace_problem(ctx, prob, scene, ris, n_rays=50_000, rx=rx,
+                                         flags=risrt.FLAG_KEEP_PATHS)
+            E, H = ctx.channel_read(ch)
+            res.append((E, H, ctx.paths_read(ch)["ris_valid"], st["n_cand_tx"], st["n_cand_u"]))
+            for h in (ch, scene, ris):
+                ctx.destroy(h)
+        for a, b in zip(res[0], res[1]):
+            assert np.array_equal(a, b)
+
+
 def test_free_space_and_single_element(ctx):
     """No geometry: Friis env path and direct RIS paths only."""
     lam = synth.C0 / 23.8e9
