@@ -19,9 +19,10 @@ static thread_local std::string g_err;
 // Blocks are rounded to a size class and, when released, kept in the
 // context's cache with the stream of their last use and an event recorded
 // there.  A request reuses a cached block of its class: at once on the same
-// stream (stream order), after a wait on the event on another stream.  New
-// blocks come from hipMalloc; cached blocks are returned to the device when
-// live + cached bytes would exceed the budget, and at shutdown.
+// stream (stream order) or once the event has completed, else after a wait
+// on the event on the requesting stream.  Events are pooled.  New blocks come
+// from hipMalloc; cached blocks are returned to the device when live + cached
+// bytes would exceed the budget, and at shutdown.
 static size_t size_class(size_t bytes)
 {
     if (bytes <= 256) return 256;
@@ -74,8 +75,14 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
             CachedBlock b = pick->second;
             c.cache.erase(pick);
             c.cached_bytes -= b.bytes;
-            if (b.st != st) (void)hipStreamWaitEvent(st, b.done, 0);
-            (void)hipEventDestroy(b.done);
+            if (b.st != st) {
+                const hipError_t q = hipEventQuery(b.done);
+                if (q != hipSuccess) {
+                    if (q != hipErrorNotReady) (void)hipGetLastError();
+                    (void)hipStreamWaitEvent(st, b.done, 0);
+                }
+            }
+            c.ev_pool.push_back(b.done);
             return b.p;
         }
         trim_cache_locked(c, cls);
@@ -99,15 +106,21 @@ void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
     b.p = p;
     b.bytes = cls;
     b.st = st;
-    if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess ||
-        hipEventRecord(b.done, st) != hipSuccess) {
+    std::lock_guard<std::mutex> lk(c.alloc_mu);
+    if (!c.ev_pool.empty()) {
+        b.done = c.ev_pool.back();
+        c.ev_pool.pop_back();
+    } else if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
+        b.done = nullptr;
+    }
+    if (!b.done || hipEventRecord(b.done, st) != hipSuccess) {
         (void)hipGetLastError();
+        if (b.done) (void)hipEventDestroy(b.done);
         (void)hipStreamSynchronize(st);
         (void)hipFree(p);
         c.in_use -= cls;
         return;
     }
-    std::lock_guard<std::mutex> lk(c.alloc_mu);
     c.cache.emplace(cls, b);
     c.cached_bytes += cls;
     c.in_use -= cls;
@@ -122,6 +135,8 @@ void release_cache(Ctx& c)
     }
     c.cache.clear();
     c.cached_bytes = 0;
+    for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
+    c.ev_pool.clear();
 }
 
 SideStream::SideStream(Ctx& ctx) : c(ctx)

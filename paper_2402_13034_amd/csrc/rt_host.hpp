@@ -40,6 +40,7 @@ struct Ctx {
     std::mutex alloc_mu;
     std::multimap<size_t, CachedBlock> cache;
     uint64_t cached_bytes = 0;
+    std::vector<hipEvent_t> ev_pool;   // events of reused blocks, recorded again by later releases
     // side streams lent to calls that fork work (default priority, non-blocking)
     std::mutex pool_mu;
     std::vector<hipStream_t> side_pool;

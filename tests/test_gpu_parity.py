@@ -382,6 +382,54 @@ def test_single_triangle_and_one_receiver(ctx):
     check_problem(ctx, prob)
 
 
+def test_degenerate_sizes(ctx):
+    """No RIS (E_env only, and a sum over no elements); no discovery rays
+    (only the direct paths); no receivers; no configurations."""
+    import dataclasses
+    import torch
+    from paper_2402_13034_amd import risrt
+    base = synth.tiny_box(order=2, n_rx=9)
+    eta2 = 2.0 * 120.0 * math.pi
+    # no RIS: the sum over zero elements is E_env for every configuration
+    prob = dataclasses.replace(base, ris=None, gamma=None)
+    check_problem(ctx, prob)
+    scene, ris, ch, st = _run(ctx, prob, 0)
+    assert ris == 0 and st["n_u_paths"] == 0 and st["n_ris_slots"] == 0
+    E_env, H = ctx.channel_read(ch)
+    assert H.shape == (9, 0)
+    g = torch.zeros((0, 3), dtype=torch.complex64, device="cuda")
+    for prec in (risrt.PREC_VALU_F32, risrt.PREC_MFMA_BF16X2):
+        E, P = ctx.ris_sum(ch, g, precision=prec, want_E=True)
+        E = E.cpu().numpy()
+        assert np.array_equal(E, np.repeat(E_env[:, None], 3, axis=1))
+        assert np.allclose(P.cpu().numpy(), np.abs(E) ** 2 / eta2, rtol=1e-6, atol=0)
+    for h in (ch, scene):
+        ctx.destroy(h)
+    # no discovery rays: order-0 candidates only
+    _say("case no rays")
+    check_problem(ctx, base, n_rays=0)
+    # no receivers
+    _say("case no receivers")
+    prob = dataclasses.replace(base, rx_pos=np.zeros((0, 3)))
+    scene, ris, ch, st = _run(ctx, prob, risrt.FLAG_KEEP_PATHS)
+    M = base.ris.elems.shape[0]
+    E_env, H = ctx.channel_read(ch)
+    assert E_env.shape == (0,) and H.shape == (0, M)
+    assert st["n_env_paths"] == 0 and st["n_ris_slots"] == 0
+    gamma = torch.from_numpy(np.ones((M, 2), np.complex64)).cuda()
+    E, P = ctx.ris_sum(ch, gamma, precision=risrt.PREC_MFMA_BF16X2, want_E=True)
+    assert tuple(E.shape) == (0, 2) and tuple(P.shape) == (0, 2)
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+    # no configurations
+    scene, ris, ch, st = _run(ctx, base, 0)
+    E, P = ctx.ris_sum(ch, torch.zeros((M, 0), dtype=torch.complex64, device="cuda"), want_E=True)
+    assert tuple(E.shape) == (9, 0) and tuple(P.shape) == (9, 0)
+    torch.cuda.synchronize()
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+
+
 def test_order0(ctx):
     check_problem(ctx, synth.tiny_box(order=0, n_rx=5))
 
