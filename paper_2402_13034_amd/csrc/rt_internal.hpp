@@ -810,21 +810,6 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
     return blocked;
 }
 
-// Leg test of leg_blocked for a whole wave (`need` masks lanes out).
-template <bool CNT>
-__device__ bool leg_blocked_wave(const SceneView& s, bool need, const double* A, const double* B, int sa, int sb,
-                                 int* wstack, WorkCount* wc)
-{
-#pragma clang fp contract(off)
-    double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
-    double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    float tmin = (float)RT_EPS;
-    float tmax = (float)(L - RT_EPS);
-    bool searching = need && (tmax > tmin);
-    return any_hit_wave<CNT>(s, searching, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
-                             (float)(w2 / L), tmin, tmax, sa, sb, wstack, wc);
-}
-
 // --------------------------------------------------------------------------
 // FP64 image method
 // --------------------------------------------------------------------------
