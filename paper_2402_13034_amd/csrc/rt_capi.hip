@@ -60,6 +60,8 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
                               std::to_string(c.budget) + " bytes)");
         if (c.in_use.compare_exchange_weak(cur, cur + cls)) break;
     }
+    CachedBlock b;
+    bool found = false;
     {
         std::lock_guard<std::mutex> lk(c.alloc_mu);
         auto range = c.cache.equal_range(cls);
@@ -72,20 +74,26 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
             if (pick == c.cache.end()) pick = it;
         }
         if (pick != c.cache.end()) {
-            CachedBlock b = pick->second;
+            b = pick->second;
             c.cache.erase(pick);
             c.cached_bytes -= b.bytes;
-            if (b.st != st) {
-                const hipError_t q = hipEventQuery(b.done);
-                if (q != hipSuccess) {
-                    if (q != hipErrorNotReady) (void)hipGetLastError();
-                    (void)hipStreamWaitEvent(st, b.done, 0);
-                }
-            }
-            c.ev_pool.push_back(b.done);
-            return b.p;
+            found = true;
+        } else {
+            trim_cache_locked(c, cls);
         }
-        trim_cache_locked(c, cls);
+    }
+    if (found) {
+        // the block is this caller's now; its event goes back to the pool after the wait is enqueued
+        if (b.st != st) {
+            const hipError_t q = hipEventQuery(b.done);
+            if (q != hipSuccess) {
+                if (q != hipErrorNotReady) (void)hipGetLastError();
+                (void)hipStreamWaitEvent(st, b.done, 0);
+            }
+        }
+        std::lock_guard<std::mutex> lk(c.alloc_mu);
+        c.ev_pool.push_back(b.done);
+        return b.p;
     }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, cls);
@@ -106,13 +114,14 @@ void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
     b.p = p;
     b.bytes = cls;
     b.st = st;
-    std::lock_guard<std::mutex> lk(c.alloc_mu);
-    if (!c.ev_pool.empty()) {
-        b.done = c.ev_pool.back();
-        c.ev_pool.pop_back();
-    } else if (hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) {
-        b.done = nullptr;
+    {
+        std::lock_guard<std::mutex> lk(c.alloc_mu);
+        if (!c.ev_pool.empty()) {
+            b.done = c.ev_pool.back();
+            c.ev_pool.pop_back();
+        }
     }
+    if (!b.done && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) b.done = nullptr;
     if (!b.done || hipEventRecord(b.done, st) != hipSuccess) {
         (void)hipGetLastError();
         if (b.done) (void)hipEventDestroy(b.done);
@@ -121,6 +130,7 @@ void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
         c.in_use -= cls;
         return;
     }
+    std::lock_guard<std::mutex> lk(c.alloc_mu);
     c.cache.emplace(cls, b);
     c.cached_bytes += cls;
     c.in_use -= cls;

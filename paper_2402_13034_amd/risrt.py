@@ -105,6 +105,12 @@ def lib():
     if _lib is None:
         if not os.path.exists(LIB_PATH):
             raise ImportError("librisrt.so is not built: run python -m paper_2402_13034_amd.build")
+        # torch (which supplies device memory and streams) is imported before the
+        # library starts the HIP runtime: imported afterwards, it finds no device
+        try:
+            import torch  # noqa: F401
+        except ImportError:
+            pass
         L = ctypes.CDLL(LIB_PATH)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64

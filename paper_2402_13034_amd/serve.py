@@ -93,6 +93,7 @@ class Server:
         self._lock = threading.Condition()
         self._queue: List[_Query] = []
         self._free_slots = list(range(n_slots))
+        torch.cuda.init()   # creating a stream does not initialise torch's device state by itself
         self._streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self._reserved = 0
         self._next_id = 0
