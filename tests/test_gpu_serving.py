@@ -101,3 +101,24 @@ def test_small_budget_admission(mix):
             f.result(timeout=120)
         assert ei.value.status == risrt.RT_ENOMEM
         s.close()
+
+
+def test_context_before_torch_in_a_fresh_process():
+    """A context opened before the caller touches torch: torch still finds the
+    device and a server (torch streams) runs a query."""
+    import os
+    import subprocess
+    import sys
+    code = (
+        "from paper_2402_13034_amd import risrt, serve\n"
+        "ctx = risrt.Context(0)\n"
+        "import torch\n"
+        "x = torch.zeros(4, device='cuda')\n"
+        "srv = serve.Server(ctx, n_slots=1)\n"
+        "torch.cuda.synchronize()\n"
+        "print('ok', float(x.sum()))\n"
+        "srv.close()\n"
+        "ctx.close()\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    r = subprocess.run([sys.executable, "-c", code], cwd=root, capture_output=True, text=True, timeout=180)
+    assert r.returncode == 0 and "ok 0.0" in r.stdout, r.stderr[-2000:]
