@@ -295,9 +295,9 @@ __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ A
 }
 
 // Two-product split (H hi + lo against Gamma hi), larger tiles: 256 x 256 per
-// workgroup of 8 waves (2 x 4), each wave 128 x 64 = 4 x 2 blocks of 32 x 32,
-// so every A fragment read from LDS feeds two blocks and every B fragment
-// four.  K tiles of 32 are double-buffered in LDS (one barrier per tile): the
+// workgroup of 8 waves (4 x 2), each wave 64 x 128 = 2 x 4 blocks of 32 x 32,
+// so every A fragment (hi and lo) read from LDS feeds four blocks and every B
+// fragment four (fewer LDS bytes per product than 128 x 64 with two A parts).  K tiles of 32 are double-buffered in LDS (one barrier per tile): the
 // next tile's global loads are in flight while the current one is multiplied.
 constexpr int G2M = 256, G2N = 256, G2K = 32, G2L = G2K + 8;
 template <bool F16>
@@ -314,11 +314,11 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
     const int wave = tid >> 6, lane = tid & 63;
     const int64_t tile_m = blockIdx.x / n_tiles_n, tile_n = blockIdx.x % n_tiles_n;
     const int64_t row0 = tile_m * G2M, col0 = tile_n * G2N;
-    const int wm = (wave >> 2) * 128, wn = (wave & 3) * 64;
+    const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
 
-    f32x16 acc[4][2];
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 2; ++j)
+    f32x16 acc[2][4];
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 4; ++j)
             for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
 
     // each thread moves 16 bf16 (two 16-byte vectors) of a 256 x 32 tile of each operand
@@ -352,21 +352,21 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
         const int buf = (int)(kt & 1);
         for (int ks = 0; ks < G2K; ks += 16) {
             const int kofs = ks + (lane >> 5) * 8;
-            uint4 ah[4], al[4], bh[2];
-            for (int i = 0; i < 4; ++i) {
+            uint4 ah[2], al[2], bh[4];
+            for (int i = 0; i < 2; ++i) {
                 const int r = wm + i * 32 + (lane & 31);
                 ah[i] = *(const uint4*)&sAh[buf][r * G2L + kofs];
                 al[i] = *(const uint4*)&sAl[buf][r * G2L + kofs];
             }
-            for (int j = 0; j < 2; ++j) {
+            for (int j = 0; j < 4; ++j) {
                 const int cix = wn + j * 32 + (lane & 31);
                 bh[j] = *(const uint4*)&sB[buf][cix * G2L + kofs];
             }
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 4; ++j)
                     acc[i][j] = mfma16<F16>((const uint16_t*)&ah[i], (const uint16_t*)&bh[j], acc[i][j]);
-            for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 2; ++j)
+            for (int i = 0; i < 2; ++i)
+                for (int j = 0; j < 4; ++j)
                     acc[i][j] = mfma16<F16>((const uint16_t*)&al[i], (const uint16_t*)&bh[j], acc[i][j]);
         }
         if (kt + 1 < nk) {
@@ -376,8 +376,8 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
         __syncthreads();
     }
     // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4)
-    for (int i = 0; i < 4; ++i)
-        for (int j = 0; j < 2; ++j) {
+    for (int i = 0; i < 2; ++i)
+        for (int j = 0; j < 4; ++j) {
             const int64_t c = col0 + wn + j * 32 + (lane & 31);
             for (int e = 0; e < 16; e += 2) {
                 const int64_t row = row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
