@@ -1696,64 +1696,128 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
 
 // --------------------------------------------------------------------------
 // Channel impulse response of one configuration (delay bins of width
-// L_bin / c): one workgroup per receiver.  The receiver's paths (environment
-// cells, then RIS slots and elements, in record order) pass through LDS in
-// chunks of 256, each thread computing one path's bin and gamma-weighted
-// amplitude; then thread t adds, in chunk order, the staged paths that fall
-// in its bins t, t + 256, ... (FP64), so every bin has one fixed summation
-// order.  Bin = floor(length / L_bin).
+// L_bin / c), bin = floor(length / L_bin): the gamma-weighted amplitudes of a
+// receiver's paths summed per bin.
 // --------------------------------------------------------------------------
 constexpr int CIR_B = 256;
+constexpr int CIR_G = 2048;   // bins per pass (two 64-bit LDS counters each)
+
+// The records of one receiver in order: its environment paths, then its RIS
+// paths slot by slot, element by element.  A thread visits records p, p +
+// CIR_B, ...; the (slot, element) of a RIS record advances by a fixed step.
+struct CirWalk {
+    int64_t n_env, s0, M, dsl, dm, sl = -1, m = 0;
+    __device__ void next(int64_t p)   // p = this thread's current record
+    {
+        if (sl >= 0) {
+            sl += dsl;
+            m += dm;
+            if (m >= M) {
+                m -= M;
+                ++sl;
+            }
+        } else if (p >= n_env && M > 0) {
+            const int64_t q = p - n_env;
+            sl = s0 + q / M;
+            m = q - (q / M) * M;
+        }
+    }
+};
+
+// Contribution of record p for configuration gamma: delay bin (-1: none or
+// outside the window; with BIN false only whether the record is a path) and
+// complex amplitude (FP64 of the FP32 inputs).
+template <bool BIN>
+__device__ __forceinline__ int64_t cir_term(int64_t p, const CirWalk& w, int64_t e0, int64_t n_path,
+                                            const uint8_t* env_valid, const float2* env_amp, const double* env_len,
+                                            const float2* camp, const double* clen, const float2* gamma,
+                                            double l_bin, int64_t n_bins, double& ar, double& ai)
+{
+    double bin = -1.0;
+    ar = 0.0;
+    ai = 0.0;
+    if (p < w.n_env) {
+        const int64_t j = e0 + p;
+        if (env_valid[j]) {
+            const float2 a = env_amp[j];
+            bin = BIN ? floor(env_len[j] / l_bin) : 0.0;
+            ar = a.x;
+            ai = a.y;
+        }
+    } else if (p < n_path) {
+        const int64_t cell = w.sl * w.M + w.m;
+        const float2 a = camp[cell];
+        if (a.x != 0.0f || a.y != 0.0f) {
+            const float2 g = gamma[w.m];
+            bin = BIN ? floor(clen[cell] / l_bin) : 0.0;
+            ar = (double)a.x * (double)g.x - (double)a.y * (double)g.y;
+            ai = (double)a.x * (double)g.y + (double)a.y * (double)g.x;
+        }
+    }
+    return bin >= 0.0 && bin < (double)n_bins ? (int64_t)bin : -1;
+}
+
+// One workgroup per receiver.  The bins are summed in fixed point: every
+// term is rounded to a multiple of 2^-S, where 2^S scales the receiver's sum
+// of |re| + |im| below 2^61, and added with 64-bit integer LDS atomics, so the
+// result does not depend on the order of the additions (deterministic) and
+// each term's rounding error is at most 2^-61 of that sum.
 __global__ __launch_bounds__(CIR_B) void k_cir(const int64_t* env_rstart, const uint8_t* env_valid,
                                                const float2* env_amp, const double* env_len, const int64_t* uptr,
                                                const float2* camp, const double* clen, int64_t M, const float2* gamma,
                                                double l_bin, int64_t n_bins, float2* cir)
 {
-    __shared__ int64_t sbin[CIR_B];
-    __shared__ double sre[CIR_B], sim[CIR_B];
+    __shared__ unsigned long long acc[2 * CIR_G];
+    __shared__ double red[CIR_B];
     const int64_t r = blockIdx.x;
     const int tid = threadIdx.x;
     const int64_t e0 = env_rstart ? env_rstart[r] : 0, e1 = env_rstart ? env_rstart[r + 1] : 0;
     const int64_t s0 = uptr ? uptr[r] + r : 0, s1 = uptr ? uptr[r + 1] + r + 1 : 0;
     const int64_t n_env = e1 - e0, n_path = n_env + (s1 - s0) * M;
-    for (int64_t b0 = 0; b0 < n_bins; b0 += CIR_B) {
-        const int64_t b = b0 + tid;
-        double cr = 0.0, ci = 0.0;
-        for (int64_t p0 = 0; p0 < n_path; p0 += CIR_B) {
-            const int64_t p = p0 + tid;
-            int64_t bin = -1;
-            double ar = 0.0, ai = 0.0;
-            if (p < n_env) {
-                const int64_t j = e0 + p;
-                if (env_valid[j]) {
-                    const float2 a = env_amp[j];
-                    bin = (int64_t)floor(env_len[j] / l_bin);
-                    ar = a.x;
-                    ai = a.y;
-                }
-            } else if (p < n_path) {
-                const int64_t q = p - n_env, sl = s0 + q / M, m = q - (q / M) * M;
-                const float2 a = camp[sl * M + m];
-                if (a.x != 0.0f || a.y != 0.0f) {
-                    const float2 g = gamma[m];
-                    bin = (int64_t)floor(clen[sl * M + m] / l_bin);
-                    ar = (double)a.x * (double)g.x - (double)a.y * (double)g.y;
-                    ai = (double)a.x * (double)g.y + (double)a.y * (double)g.x;
-                }
-            }
-            sbin[tid] = bin;
-            sre[tid] = ar;
-            sim[tid] = ai;
-            __syncthreads();
-            const int cnt = (int)(n_path - p0 < CIR_B ? n_path - p0 : CIR_B);
-            for (int i = 0; i < cnt; ++i)
-                if (sbin[i] == b) {
-                    cr += sre[i];
-                    ci += sim[i];
-                }
-            __syncthreads();
+    const int64_t dsl = M > 0 ? CIR_B / M : 0, dm = M > 0 ? CIR_B - dsl * M : 0;
+    // the scale: sum of |re| + |im| over the receiver's paths (inside the window or not), reduced in a
+    // fixed order
+    double sa = 0.0;
+    {
+        CirWalk w{n_env, s0, M, dsl, dm};
+        for (int64_t p = tid; p < n_path; p += CIR_B) {
+            w.next(p);
+            double ar, ai;
+            if (cir_term<false>(p, w, e0, n_path, env_valid, env_amp, env_len, camp, clen, gamma, l_bin, n_bins, ar,
+                                ai) >= 0)
+                sa += fabs(ar) + fabs(ai);
         }
-        if (b < n_bins) cir[r * n_bins + b] = make_float2((float)cr, (float)ci);
+    }
+    red[tid] = sa;
+    __syncthreads();
+    for (int h = CIR_B / 2; h > 0; h >>= 1) {
+        if (tid < h) red[tid] += red[tid + h];
+        __syncthreads();
+    }
+    const double total = red[0];
+    // total * 2^S < 2^61 (S kept in the range where 2^S is a finite double)
+    const int S = total > 0.0 ? min(1000, max(-1000, 60 - ilogb(total))) : 0;
+    const double scale = ldexp(1.0, S), unscale = ldexp(1.0, -S);
+    for (int64_t g0 = 0; g0 < n_bins; g0 += CIR_G) {
+        const int64_t gn = n_bins - g0 < CIR_G ? n_bins - g0 : CIR_G;
+        for (int64_t i = tid; i < 2 * gn; i += CIR_B) acc[i] = 0ull;
+        __syncthreads();
+        CirWalk w{n_env, s0, M, dsl, dm};
+        for (int64_t p = tid; p < n_path; p += CIR_B) {
+            w.next(p);
+            double ar, ai;
+            const int64_t bin =
+                cir_term<true>(p, w, e0, n_path, env_valid, env_amp, env_len, camp, clen, gamma, l_bin, n_bins, ar, ai);
+            if (bin >= g0 && bin < g0 + gn) {
+                atomicAdd(&acc[2 * (bin - g0)], (unsigned long long)(long long)rint(ar * scale));
+                atomicAdd(&acc[2 * (bin - g0) + 1], (unsigned long long)(long long)rint(ai * scale));
+            }
+        }
+        __syncthreads();
+        for (int64_t i = tid; i < gn; i += CIR_B)
+            cir[r * n_bins + g0 + i] = make_float2((float)((double)(long long)acc[2 * i] * unscale),
+                                                   (float)((double)(long long)acc[2 * i + 1] * unscale));
+        __syncthreads();
     }
 }
 
