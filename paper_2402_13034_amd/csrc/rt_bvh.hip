@@ -481,6 +481,31 @@ __global__ void k_ctl_init(unsigned* ctl)
     ctl[i] = v;
 }
 
+// unit normal of e1 x e2 per triangle (0 for a degenerate triangle)
+__global__ void k_unit_normals(const double* v64, int64_t nt, double* nrm)
+{
+    const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (t >= nt) return;
+    const double* v = v64 + 9 * t;
+    const double ex = v[3] - v[0], ey = v[4] - v[1], ez = v[5] - v[2];
+    const double fx = v[6] - v[0], fy = v[7] - v[1], fz = v[8] - v[2];
+    const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
+    const double l = sqrt(nx * nx + ny * ny + nz * nz);
+    const double il = l > 0.0 ? 1.0 / l : 0.0;
+    nrm[3 * t + 0] = nx * il;
+    nrm[3 * t + 1] = ny * il;
+    nrm[3 * t + 2] = nz * il;
+}
+
+void scene_normals(Ctx& c, Scene& s, hipStream_t st)
+{
+    if (s.n_tri == 0 || s.nrm.bytes) return;
+    s.nrm = Scratch(c, sizeof(double) * 3 * (size_t)s.n_tri, st);
+    hipLaunchKernelGGL(k_unit_normals, dim3(blocks_for(s.n_tri, 256)), dim3(256), 0, st, s.v64.as<double>(), s.n_tri,
+                       s.nrm.as<double>());
+    HIP_CHECK(hipGetLastError());
+}
+
 void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,
                  const int32_t* surf, const float* rr, const float* ri, hipStream_t st)
 {

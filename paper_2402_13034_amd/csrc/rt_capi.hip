@@ -283,7 +283,8 @@ void release_obj(rt_ctx ctx, Obj& o)
     if (o.scene) {
         Scene& s = *o.scene;
         for (Scratch* p : {&s.tri4, &s.nodes, &s.node4, &s.v64, &s.refl, &s.surf, &s.s_ptr, &s.s_tris, &s.s_plane,
-                           &s.s_box, &s.t_proj, &s.t_axes, &s.g_axes, &s.g_frame, &s.g_cnt, &s.g_tris, &s.mat})
+                           &s.s_box, &s.t_proj, &s.t_axes, &s.g_axes, &s.g_frame, &s.g_cnt, &s.g_tris, &s.mat,
+                           &s.nrm})
             retarget(*p, fs);
     }
     if (o.ris) retarget(o.ris->elem, fs);
@@ -406,6 +407,7 @@ rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r,
         HIP_CHECK(hipMemcpyAsync(mat.p, m.data(), mat.bytes, hipMemcpyHostToDevice, st));
         HIP_CHECK(hipStreamSynchronize(st));   // the host staging buffer goes out of scope
         sc.mat = std::move(mat);
+        scene_normals(ctx->c, sc, st);
         if (sc.ready) HIP_CHECK(hipEventRecord(sc.ready, st));
         return RT_OK;
     });

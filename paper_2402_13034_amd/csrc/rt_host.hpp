@@ -102,6 +102,7 @@ struct Scene {
     int32_t max_depth = 0;
     Scratch tri4, nodes, node4, v64, refl, surf, s_ptr, s_tris, s_plane, s_box, t_proj, t_axes;
     Scratch mat;   // float2 per triangle (eps_r, sigma), empty until set
+    Scratch nrm;   // 3 doubles per triangle: unit normal, computed with the materials
     Scratch g_axes, g_frame, g_cnt, g_tris;
     SceneView view() const {
         SceneView v;
@@ -115,6 +116,7 @@ struct Scene {
         v.v64 = v64.as<double>();
         v.refl = refl.as<float2>();
         v.mat = mat.bytes ? mat.as<float2>() : nullptr;
+        v.nrm = nrm.bytes ? nrm.as<double>() : nullptr;
         v.surf = surf.as<int32_t>();
         v.s_ptr = s_ptr.as<int32_t>();
         v.s_tris = s_tris.as<int32_t>();
@@ -194,6 +196,8 @@ void scan_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n, hipStream_t st
 // ---- scene build ----
 void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T, int64_t nt,
                  const int32_t* surf, const float* rr, const float* ri, hipStream_t st);
+// Unit normals of the scene's triangles (FP64) into s.nrm, on `st`.
+void scene_normals(Ctx& c, Scene& s, hipStream_t st);
 
 // ---- trace ----
 struct TraceArgs {

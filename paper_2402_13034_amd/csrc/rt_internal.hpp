@@ -47,6 +47,7 @@ struct SceneView {
     const double* v64;     // 9 per triangle (original order)
     const float2* refl;    // per triangle
     const float2* mat;     // per triangle: relative permittivity, conductivity S/m (null: none set)
+    const double* nrm;     // per triangle unit normal e1 x e2 / |e1 x e2| (FP64), set with the materials
     const int32_t* surf;   // per triangle
     const int32_t* s_ptr;  // n_surf + 1
     const int32_t* s_tris; // triangles grouped by surface, ascending
@@ -1029,19 +1030,16 @@ __device__ __forceinline__ void phase_cs(double d, double lambda, float& cs, flo
 // Fresnel reflection coefficient (Section II-B, specular reflection) of
 // triangle t's material for a wave arriving along d (FP64): TE (pol 1)
 //   (c - r) / (c + r), TM (pol 2) (eps c - r) / (eps c + r), r = sqrt(eps - 1 + c^2),
-// c = |d . n| / (|d| |n|), n = e1 x e2 from the FP64 vertices, eps = eps_r - j
+// c = |d . n| / |d| with n the unit normal of e1 x e2 from the FP64 vertices
+// (precomputed per triangle) and len = |d| from the caller, eps = eps_r - j
 // sigma sig_scale, principal square root (stable form for either sign of
 // the real part).
-__device__ inline float2 fresnel_coef(const SceneView& s, int t, const double* d, int pol, double sig_scale)
+__device__ inline float2 fresnel_coef(const SceneView& s, int t, const double* d, double len, int pol,
+                                     double sig_scale)
 {
 #pragma clang fp contract(off)
-    const double* v = s.v64 + 9 * (int64_t)t;
-    const double ex = v[3] - v[0], ey = v[4] - v[1], ez = v[5] - v[2];
-    const double fx = v[6] - v[0], fy = v[7] - v[1], fz = v[8] - v[2];
-    const double nx = ey * fz - ez * fy, ny = ez * fx - ex * fz, nz = ex * fy - ey * fx;
-    const double dn = d[0] * nx + d[1] * ny + d[2] * nz;
-    const double c = fmin(fabs(dn) / (sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]) * sqrt(nx * nx + ny * ny + nz * nz)),
-                          1.0);
+    const double* nv = s.nrm + 3 * (int64_t)t;
+    const double c = fmin(fabs(d[0] * nv[0] + d[1] * nv[1] + d[2] * nv[2]) / len, 1.0);   // len = |d|
     const float2 m = s.mat[t];
     const double er = (double)m.x, ei = -(double)m.y * sig_scale;
     const double a = er - (1.0 - c * c), b = ei;
@@ -1063,8 +1061,8 @@ __device__ inline float2 fresnel_coef(const SceneView& s, int t, const double* d
         pr = er * c - rr; pi = ei * c - ri;
         qr = er * c + rr; qi = ei * c + ri;
     }
-    const double qq = qr * qr + qi * qi;
-    return make_float2((float)((pr * qr + pi * qi) / qq), (float)((pi * qr - pr * qi) / qq));
+    const double iq = 1.0 / (qr * qr + qi * qi);
+    return make_float2((float)((pr * qr + pi * qi) * iq), (float)((pi * qr - pr * qi) * iq));
 }
 
 // --------------------------------------------------------------------------

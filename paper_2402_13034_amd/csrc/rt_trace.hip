@@ -514,10 +514,13 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
         for (int j = 0; j < RT_MAX_K; ++j) pr.tri[j] = j < k ? tri[j] : -1;
         recs[i] = pr;
         if (FIELD) {
-            double D = 0.0;
+            double D = 0.0, Lj[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int j = 0; j <= RT_MAX_K; ++j)
-                if (j <= k) D += seg_len(V[j], V[j + 1]);
+                if (j <= k) {
+                    Lj[j] = seg_len(V[j], V[j + 1]);
+                    D += Lj[j];
+                }
             float2 a = make_float2(0.0f, 0.0f);
             if (ok) {
                 float ar = 1.0f, ai = 0.0f;
@@ -527,7 +530,7 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                     float2 Rc;
                     if (tc.fresnel) {
                         const double d[3] = {V[j + 1][0] - V[j][0], V[j + 1][1] - V[j][1], V[j + 1][2] - V[j][2]};
-                        Rc = fresnel_coef(s, tri[j], d, tc.fresnel, tc.sig_scale);
+                        Rc = fresnel_coef(s, tri[j], d, Lj[j], tc.fresnel, tc.sig_scale);
                     } else {
                         Rc = s.refl[tri[j]];
                     }
@@ -796,10 +799,13 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
         }
         float2 a = make_float2(0.0f, 0.0f);
         if (ok) {
-            double D = 0.0;
+            double D = 0.0, Lq[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};
 #pragma unroll
             for (int q = 0; q <= RT_MAX_K; ++q)
-                if (q <= k) D += seg_len(V[q], V[q + 1]);
+                if (q <= k) {
+                    Lq[q] = seg_len(V[q], V[q + 1]);
+                    D += Lq[q];
+                }
             float ar = 1.0f, ai = 0.0f;
 #pragma unroll
             for (int q = 0; q < RT_MAX_K; ++q) {
@@ -807,7 +813,7 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
                 float2 Rc;
                 if (tc.fresnel) {
                     const double d[3] = {V[q + 1][0] - V[q][0], V[q + 1][1] - V[q][1], V[q + 1][2] - V[q][2]};
-                    Rc = fresnel_coef(s, tri[q], d, tc.fresnel, tc.sig_scale);
+                    Rc = fresnel_coef(s, tri[q], d, Lq[q], tc.fresnel, tc.sig_scale);
                 } else {
                     Rc = s.refl[tri[q]];
                 }
@@ -997,6 +1003,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                     ok = pattern_on(1, co) && pattern_on(tc.rxa.pattern, cr);
                 }
                 double Dr = 0.0;
+                double Lk[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};   // leg lengths (the Fresnel angles use them)
 #pragma unroll
                 for (int j = 0; j <= RT_MAX_K; ++j) {
                     if (j <= k) {
@@ -1005,6 +1012,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         const double* B = j == k ? X : P[j];
                         double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
                         double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
+                        if (FRES) Lk[j] = L;
                         Dr += L;
                         float* lb = &legbuf[wib][j][0][lane];
                         lb[0 * 64] = (float)A[0];
@@ -1026,7 +1034,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         if (FRES) {
                             double d[3];
                             for (int q = 0; q < 3; ++q) d[q] = P[j][q] - (j == 0 ? E[q] : P[j > 0 ? j - 1 : 0][q]);
-                            Rc = fresnel_coef(s, tri[j], d, tc.fresnel, tc.sig_scale);
+                            Rc = fresnel_coef(s, tri[j], d, Lk[j], tc.fresnel, tc.sig_scale);
                         } else {
                             Rc = s.refl[tri[j]];
                         }
