@@ -20,9 +20,10 @@ static thread_local std::string g_err;
 // context's cache with the stream of their last use and an event recorded
 // there.  A request reuses a cached block of its class: at once on the same
 // stream (stream order) or once the event has completed, else after a wait
-// on the event on the requesting stream.  Events are pooled.  New blocks come
-// from hipMalloc; cached blocks are returned to the device when live + cached
-// bytes would exceed the budget, and at shutdown.
+// on the event on the requesting stream.  Events are pooled; the blocks
+// released during one API call share one event per stream (FreeBatch).  New
+// blocks come from hipMalloc; cached blocks are returned to the device when
+// live + cached bytes would exceed the budget, and at shutdown.
 static size_t size_class(size_t bytes)
 {
     if (bytes <= 256) return 256;
@@ -35,6 +36,18 @@ static size_t size_class(size_t bytes)
     return (bytes + g - 1) / g * g;
 }
 
+// one cached block fewer uses event e: back to the pool (or destroyed) with its last block
+static void drop_event_ref_locked(Ctx& c, hipEvent_t e, bool keep)
+{
+    auto it = c.ev_refs.find(e);
+    if (it != c.ev_refs.end() && --it->second > 0) return;
+    if (it != c.ev_refs.end()) c.ev_refs.erase(it);
+    if (keep)
+        c.ev_pool.push_back(e);
+    else
+        (void)hipEventDestroy(e);
+}
+
 static void trim_cache_locked(Ctx& c, uint64_t need)
 {
     // drop cached blocks (largest first) until live + cached + need fits the budget
@@ -42,7 +55,7 @@ static void trim_cache_locked(Ctx& c, uint64_t need)
     HIP_CHECK(hipDeviceSynchronize());
     while (!c.cache.empty() && c.in_use.load() + c.cached_bytes + need > c.budget) {
         auto it = std::prev(c.cache.end());
-        (void)hipEventDestroy(it->second.done);
+        drop_event_ref_locked(c, it->second.done, false);
         (void)hipFree(it->second.p);
         c.cached_bytes -= it->second.bytes;
         c.cache.erase(it);
@@ -92,7 +105,7 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
             }
         }
         std::lock_guard<std::mutex> lk(c.alloc_mu);
-        c.ev_pool.push_back(b.done);
+        drop_event_ref_locked(c, b.done, true);
         return b.p;
     }
     void* p = nullptr;
@@ -106,45 +119,103 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
     return p;
 }
 
-void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
+static thread_local FreeBatch* tl_batch = nullptr;
+
+// a released block into the cache behind event e (already recorded on its stream)
+static void cache_block_locked(Ctx& c, void* p, size_t cls, hipStream_t st, hipEvent_t e)
 {
-    if (!p) return;
-    const size_t cls = size_class(bytes);
     CachedBlock b;
     b.p = p;
     b.bytes = cls;
     b.st = st;
+    b.done = e;
+    c.cache.emplace(cls, b);
+    ++c.ev_refs[e];
+}
+
+// an event from the pool, recorded on st (null if HIP refused)
+static hipEvent_t record_release(Ctx& c, hipStream_t st)
+{
+    hipEvent_t e = nullptr;
     {
         std::lock_guard<std::mutex> lk(c.alloc_mu);
         if (!c.ev_pool.empty()) {
-            b.done = c.ev_pool.back();
+            e = c.ev_pool.back();
             c.ev_pool.pop_back();
         }
     }
-    if (!b.done && hipEventCreateWithFlags(&b.done, hipEventDisableTiming) != hipSuccess) b.done = nullptr;
-    if (!b.done || hipEventRecord(b.done, st) != hipSuccess) {
-        (void)hipGetLastError();
-        if (b.done) (void)hipEventDestroy(b.done);
+    if (!e && hipEventCreateWithFlags(&e, hipEventDisableTiming) != hipSuccess) e = nullptr;
+    if (e && hipEventRecord(e, st) != hipSuccess) {
+        (void)hipEventDestroy(e);
+        e = nullptr;
+    }
+    if (!e) (void)hipGetLastError();
+    return e;
+}
+
+void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st)
+{
+    if (!p) return;
+    const size_t cls = size_class(bytes);
+    if (tl_batch && &tl_batch->c == &c) {
+        tl_batch->items.push_back({p, cls, st});
+        std::lock_guard<std::mutex> lk(c.alloc_mu);
+        c.cached_bytes += cls;   // counted as cached while it waits in the batch
+        c.in_use -= cls;
+        return;
+    }
+    hipEvent_t e = record_release(c, st);
+    if (!e) {
         (void)hipStreamSynchronize(st);
         (void)hipFree(p);
         c.in_use -= cls;
         return;
     }
     std::lock_guard<std::mutex> lk(c.alloc_mu);
-    c.cache.emplace(cls, b);
+    cache_block_locked(c, p, cls, st, e);
     c.cached_bytes += cls;
     c.in_use -= cls;
+}
+
+FreeBatch::FreeBatch(Ctx& ctx) : c(ctx), prev(tl_batch) { tl_batch = this; }
+
+FreeBatch::~FreeBatch()
+{
+    flush();
+    tl_batch = prev;
+}
+
+void FreeBatch::flush()
+{
+    size_t done = 0;
+    while (done < items.size()) {
+        const hipStream_t st = items[done].st;
+        hipEvent_t e = record_release(c, st);
+        std::lock_guard<std::mutex> lk(c.alloc_mu);
+        for (size_t i = done; i < items.size(); ++i) {
+            if (items[i].p == nullptr || items[i].st != st) continue;   // placed already, or another stream
+            if (e) {
+                cache_block_locked(c, items[i].p, items[i].cls, st, e);
+            } else {   // no event: wait for the stream and give the block back
+                (void)hipStreamSynchronize(st);
+                (void)hipFree(items[i].p);
+                c.cached_bytes -= items[i].cls;
+            }
+            items[i].p = nullptr;   // placed
+        }
+        while (done < items.size() && items[done].p == nullptr) ++done;
+    }
+    items.clear();
 }
 
 void release_cache(Ctx& c)
 {
     std::lock_guard<std::mutex> lk(c.alloc_mu);
-    for (auto& kv : c.cache) {
-        (void)hipEventDestroy(kv.second.done);
-        (void)hipFree(kv.second.p);
-    }
+    for (auto& kv : c.cache) (void)hipFree(kv.second.p);
     c.cache.clear();
     c.cached_bytes = 0;
+    for (auto& kv : c.ev_refs) (void)hipEventDestroy(kv.first);
+    c.ev_refs.clear();
     for (hipEvent_t e : c.ev_pool) (void)hipEventDestroy(e);
     c.ev_pool.clear();
 }
@@ -223,11 +294,13 @@ rt_status fail(rt_status s, const std::string& msg)
 }
 
 template <class F>
-rt_status guarded(rt_ctx ctx, F&& f)
+rt_status guarded(rt_ctx ctx, F&& f, bool batch_frees = true)
 {
     if (!ctx) return fail(RT_EINVAL, "null context");
     try {
         HIP_CHECK(hipSetDevice(ctx->c.device));
+        std::unique_ptr<FreeBatch> batch;
+        if (batch_frees) batch = std::make_unique<FreeBatch>(ctx->c);
         rt_status s = f();
         if (s == RT_OK) g_err.clear();
         return s;
@@ -348,7 +421,7 @@ rt_status rt_shutdown(rt_ctx ctx)
         for (hipStream_t s : ctx->c.side_all) (void)hipStreamDestroy(s);
         release_cache(ctx->c);
         return RT_OK;
-    });
+    }, false);
     delete ctx;
     return s;
 }

@@ -8,6 +8,7 @@
 #include <atomic>
 #include <map>
 #include <mutex>
+#include <unordered_map>
 #include <stdexcept>
 #include <string>
 #include <vector>
@@ -28,7 +29,7 @@ struct CachedBlock {
     void* p = nullptr;
     size_t bytes = 0;
     hipStream_t st = nullptr;   // stream of the last use
-    hipEvent_t done = nullptr;  // recorded on `st` when the block was released
+    hipEvent_t done = nullptr;  // recorded on `st` after the block was released (shared by a batch)
 };
 
 struct Ctx {
@@ -41,6 +42,7 @@ struct Ctx {
     std::multimap<size_t, CachedBlock> cache;
     uint64_t cached_bytes = 0;
     std::vector<hipEvent_t> ev_pool;   // events of reused blocks, recorded again by later releases
+    std::unordered_map<hipEvent_t, int> ev_refs;   // cached blocks per release event
     // side streams lent to calls that fork work (default priority, non-blocking)
     std::mutex pool_mu;
     std::vector<hipStream_t> side_pool;
@@ -68,6 +70,25 @@ struct SideStream {
 void* dalloc(Ctx& c, size_t bytes, hipStream_t st);
 void dfree(Ctx& c, void* p, size_t bytes, hipStream_t st);
 void release_cache(Ctx& c);
+
+// While one is alive on a thread, the blocks that thread releases to its
+// context wait in the batch; at its end one event per stream covers them all
+// (instead of one event per block).  Its streams must outlive it.
+struct FreeBatch {
+    struct Item {
+        void* p;
+        size_t cls;
+        hipStream_t st;
+    };
+    Ctx& c;
+    FreeBatch* prev;
+    std::vector<Item> items;
+    explicit FreeBatch(Ctx& ctx);
+    ~FreeBatch();
+    void flush();
+    FreeBatch(const FreeBatch&) = delete;
+    FreeBatch& operator=(const FreeBatch&) = delete;
+};
 
 // RAII scratch buffer on a stream.
 struct Scratch {
