@@ -68,6 +68,8 @@ typedef int32_t rt_status;
 #define RT_FLAG_KEEP_CIR 256u  /* keep per-path delays and amplitudes for rt_cir (the RIS paths'
                                   amplitude and unfolded length per slot and element: 16 B each);
                                   not with RT_FLAG_RIS_INCOMING */
+#define RT_FLAG_STAGE_TIMES 512u /* fill every rt_stats.ms_stage entry (events between the stages);
+                                   without it only ms_stage[5], the per-element kernel, is timed */
 #define RT_FLAG_RIS_INCOMING 32u /* the field reaching each element also by reflections
                                   Tx -> surfaces -> element (Section II-B, supporting
                                   reflections): image method per element for the Tx
@@ -118,7 +120,8 @@ typedef struct {
 } rt_params;
 
 /* Work counts and stage times of one rt_trace call (times only if requested,
- * which waits for the stream at the end of the call). */
+ * which waits for the stream at the end of the call; the stages other than
+ * the per-element kernel only with RT_FLAG_STAGE_TIMES). */
 typedef struct {
     int64_t segments;            /* all ray segments traced */
     int64_t discovery_segments;  /* discovery closest-hit segments */

@@ -532,7 +532,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
 {
     return guarded(ctx, [&]() -> rt_status {
         if (!tx || !rx || !params || !channel || R < 0 || (R > 0 && !rx_xyz)) return fail(RT_EINVAL, "bad trace arguments");
-        if (params->flags & ~511u) return fail(RT_EINVAL, "unknown flag");
+        if (params->flags & ~1023u) return fail(RT_EINVAL, "unknown flag");
         if ((params->flags & 256u) && (params->flags & 32u))
             return fail(RT_EINVAL, "the impulse response keeps the direct incoming leg only (no RT_FLAG_RIS_INCOMING)");
         if ((params->flags & 64u) && (params->flags & 128u)) return fail(RT_EINVAL, "Fresnel TE and TM both set");

@@ -1412,17 +1412,21 @@ static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
 struct StageTimer {
     bool on;
     hipStream_t st;
-    std::vector<hipEvent_t> ev;
-    StageTimer(bool o, hipStream_t s) : on(o), st(s) {}
-    void mark() {
-        if (!on) return;
-        hipEvent_t e;
-        HIP_CHECK(hipEventCreate(&e));
-        HIP_CHECK(hipEventRecord(e, st));
+    bool all;   // every stage, or only the marks that bracket the per-element kernel
+    std::vector<hipEvent_t> ev;   // per mark, null where not recorded
+    StageTimer(bool o, bool every, hipStream_t s) : on(o), st(s), all(every) {}
+    // every event is a marker the device processes between kernels: record only what is asked for
+    void mark(bool per_element = false) {
+        hipEvent_t e = nullptr;
+        if (on && (all || per_element)) {
+            HIP_CHECK(hipEventCreate(&e));
+            HIP_CHECK(hipEventRecord(e, st));
+        }
         ev.push_back(e);
     }
     ~StageTimer() {
-        for (auto e : ev) (void)hipEventDestroy(e);
+        for (auto e : ev)
+            if (e) (void)hipEventDestroy(e);
     }
 };
 
@@ -1449,7 +1453,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     ch.R = R;
     ch.M = M;
     ch.K = a.tc.K;
-    StageTimer tm(timing, st);
+    StageTimer tm(timing, (a.tc.flags & 512) != 0, st);
     tm.mark();   // 0
 
     // counters: [0] discovery segments, [1] leg segments, [2..4] Tx count / append / hash overflow,
@@ -1623,7 +1627,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             HIP_CHECK(hipGetLastError());
             sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, st);
         }
-        tm.mark();   // 5
+        tm.mark(true);   // 5
         if (threads > 0) {
             if (count_work && !brute && !keep_paths && !keep_cir) {
                 SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false>), dim3(nblk(threads, RIS_B)),
@@ -1645,7 +1649,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             }
         }
         HIP_CHECK(hipGetLastError());
-        tm.mark();   // 6
+        tm.mark(true);   // 6
         if (keep_paths) {
             ch.n_u = n_u;
             ch.useq = std::move(useq);
@@ -1687,7 +1691,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipStreamSynchronize(st));
         auto el = [&](int i, int j) {
             float ms = 0;
-            HIP_CHECK(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[j]));
+            if (tm.ev[i] && tm.ev[j]) HIP_CHECK(hipEventElapsedTime(&ms, tm.ev[i], tm.ev[j]));
             return ms;
         };
         out.ms[0] = el(0, 1);                  // setup

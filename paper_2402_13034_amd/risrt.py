@@ -37,6 +37,7 @@ FLAG_RIS_INCOMING = 32
 FLAG_FRESNEL_TE = 64
 FLAG_FRESNEL_TM = 128
 FLAG_KEEP_CIR = 256
+FLAG_STAGE_TIMES = 512
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1

@@ -323,6 +323,25 @@ def test_deterministic(ctx):
     assert res[0][1].tobytes() == res[1][1].tobytes()
 
 
+def test_stage_times_flag(ctx):
+    """Stage events only with FLAG_STAGE_TIMES (the per-element kernel is timed
+    either way); the channel does not depend on it."""
+    from paper_2402_13034_amd import risrt
+    prob = synth.lab_room(nx=8, ny=8)
+    out = []
+    for flags in (0, risrt.FLAG_STAGE_TIMES):
+        scene, ris, ch, st = _run(ctx, prob, flags, 20_000)
+        out.append((ctx.channel_read(ch), st["ms_stage"]))
+        for h in (ch, scene, ris):
+            ctx.destroy(h)
+    (E0, H0), ms0 = out[0]
+    (E1, H1), ms1 = out[1]
+    assert np.array_equal(E0, E1) and np.array_equal(H0, H1)
+    assert ms0[5] > 0 and ms1[5] > 0
+    assert ms0[1] == 0 and ms0[7] == 0
+    assert ms1[1] > 0 and ms1[7] >= ms1[5]
+
+
 def test_device_inputs_read_in_place(ctx):
     """Mesh and receivers handed over in device memory (read in place) give the
     channel of the same arrays handed over from the host (staged), bit for bit;
