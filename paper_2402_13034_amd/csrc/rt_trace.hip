@@ -1165,6 +1165,9 @@ struct Branch {
     // hash set: 0 sized from the last call's count, 1 the standard set,
     // 2 sized for every prefix being distinct (after overflows)
     int table_level = 0;
+    Scratch table;            // the hash set of the next phase A (cleared), cap slots
+    int64_t cap = 0;
+    uint64_t max_probe = 0;
     Scratch mask;             // geometric validity, R rows of n_words 32-bit words
     int64_t n_words = 0;
 };
@@ -1234,6 +1237,36 @@ static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
 // occupied slots compacted behind a leading 0 (the empty sequence); the
 // count is left in d_app[0] (overflow flag in d_app[1]).  Exhaustive mode:
 // every surface sequence, sorted and de-duplicated (count in d_cnt).
+// The hash set of a branch's phase A, allocated and cleared on `st`: probe
+// runs of at most 256 (an overflow makes the caller repeat with the next
+// level): first a set of at least 4x the last call's unique count, then 2^20
+// slots, then at least 2 x (keys + 1) slots, at most 2^24, with unbounded
+// probing.
+static void prepare_table(Ctx& c, const TraceArgs& a, Branch& br, hipStream_t st)
+{
+    const int64_t rows = br.hemi ? 2 * a.n_rays : a.n_rays;
+    const int64_t want = 2 * rows * a.tc.K + 2;
+    auto set_size = [want](int64_t limit) {
+        int64_t cap = 1024;
+        while (cap < want && cap < limit) cap <<= 1;
+        return cap;
+    };
+    int64_t cap = set_size(br.table_level == 2 ? ((int64_t)1 << 24) : ((int64_t)1 << 20));
+    if (br.table_level == 0) {
+        const int64_t h = c.cand_hint[br.which].load();
+        int64_t l = 1024;
+        while (h > 0 && l < 4 * h && l < cap) l <<= 1;
+        if (h > 0 && l < cap)
+            cap = set_size(l);
+        else
+            br.table_level = 1;   // no smaller set: an overflow goes straight to the last level
+    }
+    br.cap = cap;
+    br.max_probe = br.table_level == 2 ? (uint64_t)(cap - 1) : (uint64_t)255;
+    br.table = Scratch(c, sizeof(unsigned long long) * (size_t)cap, st);
+    HIP_CHECK(hipMemsetAsync(br.table.p, 0, br.table.bytes, st));
+}
+
 static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool exhaustive,
                          bool keep_hits, Channel& ch, Branch& br, unsigned long long* d_segs)
 {
@@ -1269,29 +1302,11 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         hipLaunchKernelGGL(k_fill_neg, dim3(nblk(rows * K, 256)), dim3(256), 0, st, hits.as<int32_t>(), rows * K);
         HIP_CHECK(hipGetLastError());
     }
-    // hash set filled by discovery, probe runs of at most 256 (an overflow makes
-    // the caller repeat with the next level): first a set of at least 4x the
-    // last call's unique count, then 2^20 slots, then at least 2 x (keys + 1)
-    // slots, at most 2^24, with unbounded probing
-    const int64_t want = 2 * rows * K + 2;
-    auto set_size = [want](int64_t limit) {
-        int64_t cap = 1024;
-        while (cap < want && cap < limit) cap <<= 1;
-        return cap;
-    };
-    int64_t cap = set_size(br.table_level == 2 ? ((int64_t)1 << 24) : ((int64_t)1 << 20));
-    if (br.table_level == 0) {
-        const int64_t h = c.cand_hint[br.which].load();
-        int64_t l = 1024;
-        while (h > 0 && l < 4 * h && l < cap) l <<= 1;
-        if (h > 0 && l < cap)
-            cap = set_size(l);
-        else
-            br.table_level = 1;   // no smaller set: an overflow goes straight to the last level
-    }
-    const uint64_t max_probe = br.table_level == 2 ? (uint64_t)(cap - 1) : (uint64_t)255;
-    Scratch table(c, sizeof(unsigned long long) * (size_t)cap, st);
-    HIP_CHECK(hipMemsetAsync(table.p, 0, table.bytes, st));
+    if (!br.table.p) prepare_table(c, a, br, st);
+    Scratch table = std::move(br.table);
+    table.st = st;   // released on the branch's stream after its last reader
+    const int64_t cap = br.cap;
+    const uint64_t max_probe = br.max_probe;
     if (rows > 0 && K > 0 && sv.n_tri > 0) {
         const int32_t *perm, *off;
         fib_tables(c, &perm, &off);
@@ -1491,6 +1506,14 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         bu.st = side.s;
         bu.d_cnt = (int64_t*)(d_ctr + 5);
         bu.d_app = d_ctr + 6;
+    }
+    // both hash sets are cleared here, ahead of either discovery (a clear queued
+    // behind the other branch's discovery waits for free compute units)
+    if (!exhaustive) {
+        prepare_table(c, a, bt, st);
+        if (two) prepare_table(c, a, bu, st);
+    }
+    if (two) {
         HIP_CHECK(hipEventRecord(fork.e, st));
         HIP_CHECK(hipStreamWaitEvent(bu.st, fork.e, 0));
     }
