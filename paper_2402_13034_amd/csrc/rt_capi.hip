@@ -119,6 +119,13 @@ void* dalloc(Ctx& c, size_t bytes, hipStream_t st)
     return p;
 }
 
+// Order `st` after an object's ready event; work on the stream that recorded
+// it is in order already (a wait would only add a marker to the stream).
+static void wait_ready(hipStream_t st, hipEvent_t ready, hipStream_t ready_st)
+{
+    if (ready && ready_st != st) HIP_CHECK(hipStreamWaitEvent(st, ready, 0));
+}
+
 static thread_local FreeBatch* tl_batch = nullptr;
 
 // a released block into the cache behind event e (already recorded on its stream)
@@ -450,6 +457,7 @@ rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const
         build_scene(ctx->c, *o->scene, vtx_xyz, n_vtx, tri, n_tri, surf, refl_re, refl_im, st);
         HIP_CHECK(hipEventCreateWithFlags(&o->scene->ready, hipEventDisableTiming));
         HIP_CHECK(hipEventRecord(o->scene->ready, st));
+        o->scene->ready_st = st;
         o->users.push_back(st);
         *scene = insert(ctx, o);
         return RT_OK;
@@ -475,13 +483,16 @@ rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r,
             m[2 * t + 1] = sg[t];
         }
         hipStream_t st = (hipStream_t)stream;
-        if (sc.ready) HIP_CHECK(hipStreamWaitEvent(st, sc.ready, 0));
+        wait_ready(st, sc.ready, sc.ready_st);
         Scratch mat(ctx->c, sizeof(float) * m.size(), st);
         HIP_CHECK(hipMemcpyAsync(mat.p, m.data(), mat.bytes, hipMemcpyHostToDevice, st));
         HIP_CHECK(hipStreamSynchronize(st));   // the host staging buffer goes out of scope
         sc.mat = std::move(mat);
         scene_normals(ctx->c, sc, st);
-        if (sc.ready) HIP_CHECK(hipEventRecord(sc.ready, st));
+        if (sc.ready) {
+            HIP_CHECK(hipEventRecord(sc.ready, st));
+            sc.ready_st = st;
+        }
         return RT_OK;
     });
 }
@@ -558,7 +569,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         hipStream_t st = (hipStream_t)stream;
         note_user(ctx, *so, st);
         if (ro) note_user(ctx, *ro, st);
-        if (so->scene->ready) HIP_CHECK(hipStreamWaitEvent(st, so->scene->ready, 0));
+        wait_ready(st, so->scene->ready, so->scene->ready_st);
         TraceArgs a;
         a.scene = so->scene.get();
         a.ris = ro ? ro->ris.get() : nullptr;
@@ -591,6 +602,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         trace(ctx->c, a, *o->channel, out, stats != nullptr, st);
         HIP_CHECK(hipEventCreateWithFlags(&o->channel->ready, hipEventDisableTiming));
         HIP_CHECK(hipEventRecord(o->channel->ready, st));
+        o->channel->ready_st = st;
         o->users.push_back(st);
         if (stats) {
             stats->segments = out.segments;
@@ -632,6 +644,7 @@ rt_status rt_channel_create(rt_ctx ctx, int64_t R, int64_t M, const float* E_env
         HIP_CHECK(hipStreamSynchronize(st));
         HIP_CHECK(hipEventCreateWithFlags(&ch.ready, hipEventDisableTiming));
         HIP_CHECK(hipEventRecord(ch.ready, st));
+        ch.ready_st = st;
         o->users.push_back(st);
         *channel = insert(ctx, o);
         return RT_OK;
@@ -659,7 +672,7 @@ rt_status rt_channel_read(rt_ctx ctx, uint64_t channel, float* E_env, float* H, 
         hipStream_t st = (hipStream_t)stream;
         note_user(ctx, *o, st);
         Channel& ch = *o->channel;
-        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        wait_ready(st, ch.ready, ch.ready_st);
         if (E_env && ch.R > 0) HIP_CHECK(hipMemcpyAsync(E_env, ch.E_env.p, ch.E_env.bytes, hipMemcpyDefault, st));
         if (H && ch.R * ch.M > 0) HIP_CHECK(hipMemcpyAsync(H, ch.H.p, ch.H.bytes, hipMemcpyDefault, st));
         HIP_CHECK(hipStreamSynchronize(st));
@@ -766,7 +779,7 @@ rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C
         hipStream_t st = (hipStream_t)stream;
         note_user(ctx, *o, st);
         std::lock_guard<std::mutex> lk(o->mu);
-        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        wait_ready(st, ch.ready, ch.ready_st);
         ris_sum(ctx->c, ch, gamma, C, gamma_scale, gamma_is_real != 0, precision, E_out, P_out, st);
         return RT_OK;
     });
@@ -790,7 +803,7 @@ rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s,
         hipStream_t st = (hipStream_t)stream;
         note_user(ctx, *o, st);
         std::lock_guard<std::mutex> lk(o->mu);
-        if (ch.ready) HIP_CHECK(hipStreamWaitEvent(st, ch.ready, 0));
+        wait_ready(st, ch.ready, ch.ready_st);
         cir(ctx->c, ch, gamma, bin_s, n_bins, cir_out, st);
         return RT_OK;
     });

@@ -118,6 +118,7 @@ struct Scratch {
 
 struct Scene {
     hipEvent_t ready = nullptr;   // recorded after the build
+    hipStream_t ready_st = nullptr;   // the stream `ready` was recorded on
     int64_t n_tri = 0, n_surf = 0;
     int32_t root = 0;
     int32_t max_depth = 0;
@@ -162,6 +163,7 @@ struct RisObj {
 
 struct Channel {
     hipEvent_t ready = nullptr;      // recorded when H / E_env are complete
+    hipStream_t ready_st = nullptr;  // the stream `ready` was recorded on
     hipEvent_t split_ev = nullptr;   // recorded after the split of H
     int64_t R = 0, M = 0, K = 0;
     Scratch H;          // float2 [R * M]
