@@ -343,9 +343,12 @@ __device__ __forceinline__ bool geo_path(const SceneView& s, const CandView& cv,
 
 // occupied slots of the hash set, appended per wave (order is fixed by the sort that follows)
 constexpr int TC_B = 256, TC_PT = 8;
+// The occupied slots appended to out[1..] (out[0] = 0: the order-0 key).
 __global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long* table, int64_t cap, uint64_t* out,
                                                         int64_t out_cap, unsigned long long* counter)
 {
+    if (blockIdx.x == 0 && threadIdx.x == 0) out[0] = 0ull;
+    out += 1;
     __shared__ uint64_t vals[TC_B * TC_PT];
     __shared__ int n;
     __shared__ unsigned long long base;
@@ -1325,9 +1328,8 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         ch.hits[br.which] = std::move(hits);
     }
     br.keys = Scratch(c, sizeof(uint64_t) * (size_t)(cap + 1), st);
-    HIP_CHECK(hipMemsetAsync(br.keys.p, 0, sizeof(uint64_t), st));
     hipLaunchKernelGGL(k_table_compact, dim3(nblk(cap, TC_B * TC_PT)), dim3(TC_B), 0, st, table.as<unsigned long long>(), cap,
-                       br.keys.as<uint64_t>() + 1, cap, br.d_app);
+                       br.keys.as<uint64_t>(), cap, br.d_app);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -1353,7 +1355,6 @@ static void cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch& br
     Scratch sorted(c, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1), br.st);
     sort_u64_into(c, br.keys.as<uint64_t>(), sorted.as<uint64_t>(), n, RT_KEY_BITS * a.tc.K, br.st);
     br.keys = std::move(sorted);
-    HIP_CHECK(hipMemsetAsync(br.d_app, 0, 2 * sizeof(unsigned long long), br.st));
 }
 
 // candidate images and the geometric test of every (receiver, candidate) cell
