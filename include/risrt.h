@@ -263,8 +263,10 @@ rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s,
  * coefficients (RT_FLAG_FRESNEL_TE/TM; Section III's table gives metal as
  * eps_r = 1, sigma = 1e7 S/m): relative permittivity eps_r >= 1 and
  * conductivity sigma >= 0 [S/m], host or device arrays of n_tri floats,
- * copied (the call waits for the copy).  Calling again replaces them for
- * later traces.  RT_EINVAL on a null array or an out-of-range value. */
+ * copied (the call waits for the copy); the first call also computes the
+ * triangles' unit normals the coefficients use (on `stream`).  Calling again
+ * replaces the materials for later traces.  RT_EINVAL on a null array or an
+ * out-of-range value. */
 rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r, const float* sigma,
                                  void* stream);
 
