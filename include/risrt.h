@@ -53,7 +53,8 @@ typedef int32_t rt_status;
 
 /* rt_params.flags */
 #define RT_FLAG_KEEP_HITS 1u   /* keep discovery hit lists (rt_hits_read) */
-#define RT_FLAG_KEEP_PATHS 2u  /* keep path lists (rt_paths_read) */
+#define RT_FLAG_KEEP_PATHS 2u  /* keep path lists (rt_paths_read) and the element paths' fields
+                                  (rt_ris_paths_read: 16 B per slot and element) */
 #define RT_FLAG_BRUTE_FORCE 4u /* test every triangle instead of walking the BVH */
 #define RT_FLAG_EXHAUSTIVE 8u  /* candidates = every surface sequence of order <= K
                                   (no discovery rays; small scenes only) */
@@ -229,6 +230,19 @@ rt_status rt_hits_read(rt_ctx ctx, uint64_t channel, int32_t source, int32_t* hi
 rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t cap_env,
                         int64_t* n_env, int32_t* useq, int64_t cap_u, int64_t* n_u,
                         uint8_t* ris_valid, int64_t cap_slots, int64_t* n_slots);
+
+/* Per-path RIS fields (RT_FLAG_KEEP_PATHS or RT_FLAG_KEEP_CIR), one cell
+ * per (slot, element) in the slot order of rt_paths_read's ris_valid
+ * (cell = slot * M + m): amp[2 cell .. 2 cell + 1] = complex amplitude of the
+ * element path at the receiver for Gamma_m = 1 (eq. (7) times eq. (8), with
+ * the reflection coefficients of its bounces; 0 where no path is emitted);
+ * length[cell] = its unfolded length, d_t + D_r for the direct incoming leg
+ * (eqs. (7)-(8)), D_r alone with RT_FLAG_RIS_INCOMING (the element's field
+ * then sums several incoming paths).  Either pointer may be NULL; host or
+ * device memory of cap_cells entries; *n_cells receives n_slots * M.
+ * RT_EINVAL if the channel kept no paths or cap_cells is too small.  Waits. */
+rt_status rt_ris_paths_read(rt_ctx ctx, uint64_t channel, float* amp, double* length, int64_t cap_cells,
+                           int64_t* n_cells);
 
 /* Candidate sequences (surface ids, -1 padded, 3 per row) found for source 0
  * (Tx) or 1 (RIS centre), in key order.  Waits. */

@@ -366,8 +366,12 @@ __global__ void k_surf_csr(const uint64_t* keys, int64_t nt, const int32_t* n_su
         for (int32_t q = s + 1; q <= n_surf; ++q) s_ptr[q] = (int32_t)nt;
 }
 
+// A surface's plane is that of its lowest-numbered triangle; every vertex of
+// the surface must lie within RT_EPS (0.1 mm) of it (bad |= 16), and that
+// triangle must not be degenerate (bad |= 32): the image method mirrors in
+// this one plane for the whole surface.
 __global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const double* v64, const int32_t* n_surf_p,
-                             double* s_plane, double* s_box)
+                             double* s_plane, double* s_box, int32_t* bad)
 {
     int s = blockIdx.x * blockDim.x + threadIdx.x;
     if (s >= *n_surf_p) return;
@@ -391,16 +395,25 @@ __global__ void k_surf_plane(const int32_t* s_ptr, const int32_t* s_tris, const 
     s_plane[4 * s + 0] = n0;
     s_plane[4 * s + 1] = n1;
     s_plane[4 * s + 2] = n2;
-    s_plane[4 * s + 3] = n0 * v[0] + n1 * v[1] + n2 * v[2];
+    const double dpl = n0 * v[0] + n1 * v[1] + n2 * v[2];
+    s_plane[4 * s + 3] = dpl;
+    const double nlen = sqrt(n0 * n0 + n1 * n1 + n2 * n2);
+    if (!(nlen > 0.0)) atomicOr(bad, 32);
+    const double tol = RT_EPS * nlen;
+    int off_plane = 0;
     double lo[3] = {1e300, 1e300, 1e300}, hi[3] = {-1e300, -1e300, -1e300};
     for (int j = s_ptr[s]; j < s_ptr[s + 1]; ++j) {
         const double* w = v64 + 9 * (int64_t)s_tris[j];
-        for (int a = 0; a < 3; ++a)
+        for (int a = 0; a < 3; ++a) {
             for (int k = 0; k < 3; ++k) {
                 lo[k] = fmin(lo[k], w[3 * a + k]);
                 hi[k] = fmax(hi[k], w[3 * a + k]);
             }
+            const double dist = n0 * w[3 * a] + n1 * w[3 * a + 1] + n2 * w[3 * a + 2] - dpl;
+            off_plane |= !(fabs(dist) <= tol);
+        }
     }
+    if (off_plane) atomicOr(bad, 16);
     for (int k = 0; k < 3; ++k) {
         s_box[6 * s + k] = lo[k] - 1e-9;
         s_box[6 * s + 3 + k] = hi[k] + 1e-9;
@@ -613,7 +626,7 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     HIP_CHECK(hipGetLastError());
     hipLaunchKernelGGL(k_surf_plane, dim3(blocks_for(nt, 64)), dim3(64), 0, st, s.s_ptr.as<int32_t>(),
                        s.s_tris.as<int32_t>(), s.v64.as<double>(), nsurf, s.s_plane.as<double>(),
-                       s.s_box.as<double>());
+                       s.s_box.as<double>(), bad);
     HIP_CHECK(hipGetLastError());
     s.g_axes = Scratch(c, sizeof(int32_t) * (size_t)nt, st);
     s.g_frame = Scratch(c, sizeof(double) * 4 * (size_t)nt, st);
@@ -635,6 +648,9 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     if (badv & 8) throw hip_error("BVH build produced an inconsistent tree");
     if (depth > RT_STACK - 1) throw inval_error("BVH deeper than the traversal stack");
     if (n_seen != n_surf) throw inval_error("surface ids must be 0..n_surf-1, each used");
+    if (badv & 32) throw inval_error("the lowest-numbered triangle of a surface is degenerate (no plane)");
+    if (badv & 16) throw inval_error("the triangles of a surface are not coplanar (a vertex lies more than "
+                                     "0.1 mm from the plane of the surface's first triangle)");
     s.max_depth = depth;
     s.n_surf = n_surf;
 }

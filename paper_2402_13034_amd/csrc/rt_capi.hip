@@ -379,6 +379,7 @@ void release_obj(rt_ctx ctx, Obj& o)
     if (o.channel) {
         if (o.channel->ready) (void)hipEventDestroy(o.channel->ready);
         if (o.channel->split_ev) (void)hipEventDestroy(o.channel->split_ev);
+        for (auto& rd : o.channel->split_readers) (void)hipEventDestroy(rd.second);
     }
     o.scene.reset();
     o.ris.reset();
@@ -734,6 +735,25 @@ rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t 
                 HIP_CHECK(hipMemcpy(ris_valid, ch.ris_valid.p, (size_t)(ch.n_slots * ch.M), hipMemcpyDefault));
             }
         }
+        return RT_OK;
+    });
+}
+
+rt_status rt_ris_paths_read(rt_ctx ctx, uint64_t channel, float* amp, double* length, int64_t cap_cells,
+                           int64_t* n_cells)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        Channel& ch = *o->channel;
+        if (ch.ready) HIP_CHECK(hipEventSynchronize(ch.ready));
+        const int64_t n = ch.n_slots * ch.M;
+        if (n_cells) *n_cells = n;
+        if (!amp && !length) return RT_OK;
+        if (n > 0 && !ch.cir_amp.p) return fail(RT_EINVAL, "paths not kept");
+        if (cap_cells < n) return fail(RT_EINVAL, "capacity too small");
+        if (n > 0 && amp) HIP_CHECK(hipMemcpy(amp, ch.cir_amp.p, sizeof(float2) * (size_t)n, hipMemcpyDefault));
+        if (n > 0 && length) HIP_CHECK(hipMemcpy(length, ch.cir_len.p, sizeof(double) * (size_t)n, hipMemcpyDefault));
         return RT_OK;
     });
 }

@@ -191,6 +191,10 @@ struct Channel {
     Scratch a_hi, a_lo;
     Scratch a_sexp;     // int32 [R]: fp16 split, per-receiver power-of-two scale exponents
     int64_t a_rows = 0, a_k = 0;
+    // every stream that has read the split, with an event recorded after its last
+    // read: a rebuild (new layout or format) waits on them all before it releases
+    // the old split, so no sum still running elsewhere reads a reused block
+    std::vector<std::pair<hipStream_t, hipEvent_t>> split_readers;
     hipStream_t last_stream = nullptr;
 };
 

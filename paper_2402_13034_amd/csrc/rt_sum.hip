@@ -415,6 +415,11 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
     const int64_t cols_p = round_up(C, G2N);
     if (ch.split_kind == layout && ch.split_ev) HIP_CHECK(hipStreamWaitEvent(st, ch.split_ev, 0));
     if (ch.split_kind != layout) {
+        // the old split may still be read by sums queued on other streams: this
+        // stream waits for all of them, then releases it in its own order
+        for (const auto& rd : ch.split_readers)
+            if (rd.first != st) HIP_CHECK(hipStreamWaitEvent(st, rd.second, 0));
+        for (Scratch* p : {&ch.a_hi, &ch.a_lo, &ch.a_sexp}) p->st = st;
         ch.a_hi.release();
         ch.a_lo.release();
         ch.a_hi = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
@@ -463,6 +468,16 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
                                ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn2);
     }
     HIP_CHECK(hipGetLastError());
+    // this stream has read the split up to here
+    hipEvent_t* ev = nullptr;
+    for (auto& rd : ch.split_readers)
+        if (rd.first == st) ev = &rd.second;
+    if (!ev) {
+        ch.split_readers.emplace_back(st, nullptr);
+        ev = &ch.split_readers.back().second;
+        HIP_CHECK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
+    }
+    HIP_CHECK(hipEventRecord(*ev, st));
 }
 
 }  // namespace rt

@@ -150,6 +150,8 @@ __global__ void k_fill_neg(int32_t* p, int64_t n)
 // capacity a power of two, linear probing; a probe run longer than max_probe
 // raises the overflow flag, and the caller repeats with a larger set).  A slot is read before the
 // compare-and-swap, so the many repeats of a key cost no atomics.
+// mix64 is the 64-bit finalizer (fmix64) of Austin Appleby's public-domain
+// MurmurHash3, constants as published.
 __device__ __forceinline__ uint64_t mix64(uint64_t x)
 {
     x ^= x >> 33;
@@ -945,8 +947,9 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
         const int mm = active ? m : 0;
         const double* e = rv.elem + 3 * mm;
         const double E[3] = {e[0], e[1], e[2]};
-        double dt_keep = 0.0;   // |E - Tx| as the direct leg's length (kept paths only)
-        if (KEEP) {
+        double dt_keep = 0.0;   // |E - Tx| as the direct leg's length (kept paths only; 0 with the
+                                // incoming reflections, whose element field sums several paths)
+        if (KEEP && !(tc.flags & 32)) {
 #pragma clang fp contract(off)
             const double v0 = E[0] - tc.tx[0], v1 = E[1] - tc.tx[1], v2 = E[2] - tc.tx[2];
             dt_keep = sqrt(v0 * v0 + v1 * v1 + v2 * v2);
@@ -1094,7 +1097,8 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
             if (KEEP && active) {
                 const int64_t cell = (u0 + r + sl) * rv.M + m;
                 if (rvalid) rvalid[cell] = ok ? 1 : 0;
-                if (camp) {   // per-path amplitude and unfolded length (d_t + D_r) for the impulse response
+                if (camp) {   // per-path amplitude and unfolded length (d_t + D_r; D_r alone with the incoming
+                              // reflections): impulse response and per-path read-back
                     camp[cell] = ok ? make_float2(amp_r, amp_i) : make_float2(0.0f, 0.0f);
                     clen[cell] = dt_keep + Dr_keep;
                 }
@@ -1635,7 +1639,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipStreamWaitEvent(st, in_ready.e, 0));   // the field reaching every element
         ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
         if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
-        if (keep_cir) {
+        if (keep_paths || keep_cir) {
             ch.cir_amp = Scratch(c, sizeof(float2) * (size_t)((n_u + R) * M), st);
             ch.cir_len = Scratch(c, sizeof(double) * (size_t)((n_u + R) * M), st);
         }

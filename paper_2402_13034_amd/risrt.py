@@ -39,6 +39,8 @@ FLAG_FRESNEL_TM = 128
 FLAG_KEEP_CIR = 256
 FLAG_STAGE_TIMES = 512
 
+MAX_ORDER = 3   # largest reflection order rt_trace accepts
+
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
 PREC_MFMA_BF16X3 = 2
@@ -49,6 +51,7 @@ ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
     "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials", "rt_cir",
+    "rt_ris_paths_read",
 )
 
 
@@ -134,6 +137,7 @@ def lib():
             "rt_hits_read": (ctypes.c_int32, [P, u64, ctypes.c_int32, P, i64, pi64]),
             "rt_paths_read": (ctypes.c_int32, [P, u64, P, i64, pi64, P, i64, pi64, P, i64, pi64]),
             "rt_candidates_read": (ctypes.c_int32, [P, u64, ctypes.c_int32, P, i64, pi64]),
+            "rt_ris_paths_read": (ctypes.c_int32, [P, u64, P, P, i64, pi64]),
             "rt_ris_sum": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                             P, P, P]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
@@ -169,6 +173,50 @@ def _stream_handle(stream):
     if isinstance(stream, int):
         return ctypes.c_void_p(stream)
     return ctypes.c_void_p(stream.cuda_stream)
+
+
+def _torch_stream(stream):
+    """The torch stream a call's work goes to (raw hipStream_t handles are
+    wrapped), so that outputs are allocated and temporaries kept in its order."""
+    import torch
+    if stream is None:
+        return torch.cuda.current_stream()
+    if isinstance(stream, int):
+        return torch.cuda.ExternalStream(stream)
+    return stream
+
+
+class _OnStream:
+    """Enqueue a library call on `stream` from torch's current stream: the
+    stream first waits for the current one (inputs written there are ready),
+    tensors allocated inside are ordered on `stream`, and tensors read by the
+    call are kept alive for it (record_stream) when the two streams differ."""
+
+    def __init__(self, stream):
+        import torch
+        self.s = _torch_stream(stream)
+        self.cur = torch.cuda.current_stream()
+        self.other = self.s.cuda_stream != self.cur.cuda_stream
+        self._ctx = torch.cuda.stream(self.s)
+
+    def __enter__(self):
+        if self.other:
+            self.s.wait_stream(self.cur)
+        self._ctx.__enter__()
+        return self
+
+    def __exit__(self, *a):
+        return self._ctx.__exit__(*a)
+
+    def keep(self, *tensors):
+        if self.other:
+            for t in tensors:
+                if t is not None:
+                    t.record_stream(self.s)
+
+    @property
+    def handle(self):
+        return ctypes.c_void_p(self.s.cuda_stream)
 
 
 def _v3(x):
@@ -316,6 +364,18 @@ class Context:
                                    _ptr(valid) if valid.size else None, ns.value, ctypes.byref(ns)))
         return {"env": env, "useq": useq, "ris_valid": valid.astype(bool)}
 
+    def ris_paths_read(self, ch: int):
+        """Per (slot, element) amplitude (complex64, 0 where no path) and
+        unfolded length of the element paths, [n_slots, M] each (the channel
+        needs FLAG_KEEP_PATHS or FLAG_KEEP_CIR)."""
+        R, M, _, ns = self.channel_info(ch)
+        n = ctypes.c_int64()
+        amp = np.zeros((ns, M), np.complex64)
+        length = np.zeros((ns, M), np.float64)
+        _check(lib().rt_ris_paths_read(self._h, ch, _ptr(amp) if amp.size else None,
+                                       _ptr(length) if length.size else None, amp.size, ctypes.byref(n)))
+        return amp, length
+
     # ---- RIS sum ----
     def cir(self, ch: int, gamma, bin_s: float, n_bins: int, stream=None):
         """Delay-binned impulse response of one configuration (gamma: torch
@@ -324,9 +384,12 @@ class Context:
         import torch
         R = int(self.channel_info(ch)[0])
         dev = gamma.device if hasattr(gamma, "device") else torch.device("cuda")
-        out = torch.zeros((R, n_bins), dtype=torch.complex64, device=dev)
-        _check(lib().rt_cir(self._h, ctypes.c_uint64(ch), ctypes.c_void_p(gamma.data_ptr()), float(bin_s),
-                            int(n_bins), ctypes.c_void_p(out.data_ptr()), _stream_handle(stream)))
+        with _OnStream(stream) as on:
+            g = gamma.contiguous()
+            out = torch.zeros((R, n_bins), dtype=torch.complex64, device=dev)   # cleared in the call's order
+            _check(lib().rt_cir(self._h, ctypes.c_uint64(ch), ctypes.c_void_p(g.data_ptr()), float(bin_s),
+                                int(n_bins), ctypes.c_void_p(out.data_ptr()), on.handle))
+            on.keep(gamma)
         return out
 
     def ris_sum(self, ch: int, gamma, scale: float = 1.0, gamma_is_real: bool = False,
@@ -337,16 +400,19 @@ class Context:
         import torch
         R, M, _, _ = self.channel_info(ch)
         C = int(gamma.shape[1])
-        g = gamma.contiguous()
-        dev = g.device
-        if want_E and E_out is None:
-            E_out = torch.empty((R, C), dtype=torch.complex64, device=dev)
-        if want_P and P_out is None:
-            P_out = torch.empty((R, C), dtype=torch.float32, device=dev)
-        _check(lib().rt_ris_sum(self._h, ch, ctypes.c_void_p(g.data_ptr()), C, float(scale), int(gamma_is_real),
-                                int(precision), ctypes.c_void_p(E_out.data_ptr()) if E_out is not None else None,
-                                ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None,
-                                _stream_handle(stream)))
+        given = (gamma, E_out, P_out)
+        with _OnStream(stream) as on:
+            g = gamma.contiguous()
+            dev = g.device
+            if want_E and E_out is None:
+                E_out = torch.empty((R, C), dtype=torch.complex64, device=dev)
+            if want_P and P_out is None:
+                P_out = torch.empty((R, C), dtype=torch.float32, device=dev)
+            _check(lib().rt_ris_sum(self._h, ch, ctypes.c_void_p(g.data_ptr()), C, float(scale),
+                                    int(gamma_is_real), int(precision),
+                                    ctypes.c_void_p(E_out.data_ptr()) if E_out is not None else None,
+                                    ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None, on.handle))
+            on.keep(*given)
         return E_out, P_out
 
 

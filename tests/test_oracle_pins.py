@@ -464,6 +464,86 @@ def test_fresnel_paper_metal_is_nearly_a_perfect_conductor():
         assert abs(O.fresnel(eps, math.cos(th), 2) - 1) < 3 * z / math.cos(th)
 
 
+def _conductor_problem(freq, sigma, eps_r=1.0):
+    return synth.Problem("m", synth.empty_scene(), freq, np.zeros(3), 0.01, None, None, np.zeros((1, 3)), None,
+                         1, 1, 0, fresnel=1, mat_eps_r=np.array([eps_r], np.float32),
+                         mat_sigma=np.array([sigma], np.float32))
+
+
+def leontovich_error(oracle_mod=O):
+    """Largest distance between the oracle's Fresnel coefficients of a good
+    conductor (eps_r = 1) and the surface-impedance (Leontovich) closed form.
+    A good conductor has intrinsic impedance Z_s = sqrt(j omega mu0 / sigma),
+    so with eta0 = sqrt(mu0 / eps0) the normalised impedance is
+    z = Z_s / eta0 = (1 + j) sqrt(omega eps0 / (2 sigma)), omega = 2 pi f, and
+    the transmitted wave leaves the surface along its normal, giving
+      TE: (z cos(theta) - 1) / (z cos(theta) + 1),
+      TM: (cos(theta) - z) / (cos(theta) + z)
+    (TM in the convention in which a perfect conductor gives +1).  The
+    neglected terms are of relative order omega eps0 / sigma (< 2e-7 here), so
+    the two agree to about 1e-10.  This fixes the 2 pi of omega and the sign
+    of the loss term of the permittivity independently of how the oracle
+    writes them (a loss term of the wrong sign flips Im z; a missing 2 pi
+    scales z by sqrt(2 pi))."""
+    worst = 0.0
+    for freq in (23.8e9, 28e9):
+        for sigma in (1e7, 5.8e7):
+            prob = _conductor_problem(freq, sigma)
+            eps = oracle_mod.material_eps(prob, np.array([0]))[0]
+            z = (1 + 1j) * math.sqrt(2 * math.pi * freq * O.EPS0 / (2 * sigma))
+            for th in (0.0, 0.3, 0.6, 0.9, 1.2):
+                c = math.cos(th)
+                te = (z * c - 1) / (z * c + 1)
+                tm = (c - z) / (c + z)
+                worst = max(worst, abs(oracle_mod.fresnel(eps, c, 1) - te), abs(oracle_mod.fresnel(eps, c, 2) - tm))
+    return worst
+
+
+def test_fresnel_good_conductor_surface_impedance():
+    assert leontovich_error() < 1e-9
+
+
+def test_good_conductor_absorptance_hagen_rubens():
+    """Power absorbed by a good conductor at normal incidence, 1 - |R|^2,
+    equals 4 Re z / |1 + z|^2 = 2 sqrt(2 omega eps0 / sigma) to first order in
+    z (the Hagen-Rubens relation); through the whole path: a one-wall
+    reflection at normal incidence on the paper's metal."""
+    mb = synth.MeshBuilder()
+    mb.quad((0.0, -5.0, -5.0), (0.0, 10.0, 0.0), (0.0, 0.0, 10.0), 1, complex(0.5, 0.0))
+    scene = mb.build()
+    iso = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
+    f, sigma = 23.8e9, 1e7
+    tx = np.array([1.0, 0.3, -0.2])
+    rx = np.array([[2.5, 0.3, -0.2]])   # on the wall normal through the Tx: normal incidence
+    prob = synth.Problem("w", scene, f, tx, 0.01, iso, None, rx, iso, 1, 16, 0, fresnel=1,
+                         mat_eps_r=np.ones(scene.n_tri, np.float32),
+                         mat_sigma=np.full(scene.n_tri, sigma, np.float32))
+    r = O.trace(prob, mode="exhaustive")
+    k1 = (r["env_seq"] >= 0).sum(axis=1) == 1
+    assert k1.sum() == 1
+    d = 3.5
+    lam = O.C0 / f
+    free = math.sqrt(2 * ETA0 * 0.01) * lam / (4 * math.pi * d)
+    refl = r["env_amp"][k1][0] / (free * np.exp(-2j * math.pi * d / lam))
+    x = 2 * math.pi * f * O.EPS0 / sigma
+    absorbed = 1 - abs(refl) ** 2
+    assert abs(absorbed / (2 * math.sqrt(2 * x)) - 1) < 1e-3   # first order in |z| ~ 4e-4
+    z = (1 + 1j) * math.sqrt(x / 2)
+    assert abs(refl - (z - 1) / (z + 1)) < 1e-9
+
+
+def test_lossy_permittivity_sixty_sigma_lambda():
+    """Textbook form of the loss term: Im(eps) = -sigma / (omega eps0)
+    = -60 sigma lambda (1 / (2 pi c eps0) = 59.96 ohm), negative for a lossy
+    medium under the e^{-j k d} convention."""
+    for f, er, sigma in ((28e9, 4.0, 0.5), (23.8e9, 2.5, 0.02), (5e9, 7.0, 0.1)):
+        eps = O.material_eps(_conductor_problem(f, sigma, er), np.array([0]))[0]
+        lam = O.C0 / f
+        assert abs(eps.real - er) < 1e-6
+        assert eps.imag < 0
+        assert abs(-eps.imag / (60 * sigma * lam) - 1) < 1e-3
+
+
 @pytest.mark.parametrize("pol", [1, 2])
 def test_fresnel_single_wall_path_closed_form(pol):
     """The order-1 path off one wall: free-space amplitude over the mirror
@@ -739,6 +819,19 @@ def test_planted_missing_outgoing_pattern_is_caught(monkeypatch):
     monkeypatch.setattr(O, "pattern", bad)
     err, *_ = tang_error(O)
     assert err > 1e-2
+
+
+@pytest.mark.parametrize("mistake", ["no_two_pi", "wrong_sign"])
+def test_planted_conductivity_mistakes_are_caught(monkeypatch, mistake):
+    def bad(prob, tris):
+        er = prob.mat_eps_r.astype(np.float64)[tris]
+        sg = prob.mat_sigma.astype(np.float64)[tris]
+        if mistake == "no_two_pi":
+            return er - 1j * sg / (prob.freq * O.EPS0)
+        return er + 1j * sg / (2.0 * math.pi * prob.freq * O.EPS0)
+
+    monkeypatch.setattr(O, "material_eps", bad)
+    assert leontovich_error(O) > 1e-5
 
 
 def test_planted_wrong_spreading_is_caught(monkeypatch):
