@@ -260,6 +260,24 @@ rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C
                      int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out,
                      void* stream);
 
+/* The coherent sum of rt_ris_sum (same arguments, same kernels, same
+ * results) for callers that cannot allocate device memory: code under HIP
+ * graph capture, tight serving loops, harnesses that forbid hipMalloc.  It
+ * allocates nothing: the split of H and Gamma goes to a static 64 MiB array
+ * that every device the library runs on holds until the process ends, and is
+ * rebuilt on every call (no cached split).  gamma, E_out and P_out are the
+ * caller's device memory as for rt_ris_sum.  Scratch needed: 2 (2R rounded up
+ * to 256) Kp + (1, or 2 for RT_PREC_MFMA_BF16X3) (C rounded up to 256) Kp
+ * bytes, times 2 for 16-bit values, plus 4R for RT_PREC_MFMA_F16X2, with
+ * Kp = M (real Gamma) or 2M (complex) rounded up to 32; a larger sum returns
+ * RT_EUNSUPPORTED (e.g. 4096 receivers x 1024 elements x 4096 real
+ * configurations fit; 16384 x 1024 do not).  RT_PREC_VALU_F32 uses no
+ * scratch.  Every call on one device shares that array: calls that overlap
+ * on the device (on different streams without an order between them) race
+ * and must be serialised by the caller. */
+rt_status rt_ris_sum_noalloc(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C, float gamma_scale,
+                            int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out, void* stream);
+
 /* Channel impulse response of one RIS configuration (the paths' delays,
  * Section II-B / Fig. 3 context): cir[r, b] = sum of the complex amplitudes
  * of the paths reaching receiver r with unfolded length d in

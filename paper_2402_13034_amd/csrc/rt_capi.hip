@@ -292,6 +292,13 @@ struct rt_ctx_s {
 
 static_assert(sizeof(EnvRec) == sizeof(rt_env_path), "path record layout");
 
+// Scratch of the allocation-free sum (rt_ris_sum_noalloc): a fixed array that
+// every device the library runs on holds until the process ends.  In host code
+// its name is only a stand-in; rt_init looks up this device's copy with
+// hipGetSymbolAddress and the calls pass that address to the kernels.
+#define RT_STATIC_SCRATCH_BYTES ((size_t)64 << 20)
+static __device__ __align__(256) unsigned char scratch[RT_STATIC_SCRATCH_BYTES];
+
 namespace {
 
 rt_status fail(rt_status s, const std::string& msg)
@@ -406,6 +413,15 @@ rt_status rt_init(int device, uint64_t mem_budget_bytes, rt_ctx* out)
         size_t fr = 0, tot = 0;
         HIP_CHECK(hipMemGetInfo(&fr, &tot));
         ctx->c.budget = mem_budget_bytes ? mem_budget_bytes : (uint64_t)(0.9 * (double)fr);
+        void* sp = nullptr;
+        const hipError_t se = hipGetSymbolAddress(&sp, HIP_SYMBOL(scratch));
+        if (se != hipSuccess || !sp) {
+            delete ctx;
+            return fail(RT_EDEVICE, std::string("hipGetSymbolAddress of the static scratch failed: ") +
+                                        hipGetErrorString(se));
+        }
+        ctx->c.static_scratch = sp;
+        ctx->c.static_scratch_bytes = RT_STATIC_SCRATCH_BYTES;
         HIP_CHECK(hipStreamCreateWithFlags(&ctx->free_stream, hipStreamNonBlocking));
         *out = ctx;
         g_err.clear();
@@ -803,6 +819,31 @@ rt_status rt_ris_sum(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C
         ris_sum(ctx->c, ch, gamma, C, gamma_scale, gamma_is_real != 0, precision, E_out, P_out, st);
         return RT_OK;
     });
+}
+
+rt_status rt_ris_sum_noalloc(rt_ctx ctx, uint64_t channel, const float* gamma, int64_t C, float gamma_scale,
+                            int32_t gamma_is_real, int32_t precision, float* E_out, float* P_out, void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, channel, 3);
+        if (!o) return fail(RT_ENOTFOUND, "unknown channel handle");
+        if (C < 0 || precision < 0 || precision > 3) return fail(RT_EINVAL, "bad configuration count or precision");
+        const Channel& ch = *o->channel;
+        if (C > 0 && ch.M > 0 && !is_device_ptr(gamma)) return fail(RT_EINVAL, "gamma must be device memory");
+        if ((E_out && !is_device_ptr(E_out)) || (P_out && !is_device_ptr(P_out)))
+            return fail(RT_EINVAL, "outputs must be device memory");
+        if (C > ((int64_t)1 << 31) - 1) return fail(RT_EUNSUPPORTED, "too many configurations");
+        const size_t need = ris_sum_scratch_bytes(ch.R, ch.M, C, gamma_is_real != 0, precision);
+        if (need > ctx->c.static_scratch_bytes)
+            return fail(RT_EUNSUPPORTED, "the sum needs " + std::to_string(need) + " bytes of scratch; the static "
+                                         "scratch holds " + std::to_string(ctx->c.static_scratch_bytes) +
+                                         " (use rt_ris_sum)");
+        hipStream_t st = (hipStream_t)stream;
+        note_user(ctx, *o, st);
+        wait_ready(st, ch.ready, ch.ready_st);
+        ris_sum_in(ch, gamma, C, gamma_scale, gamma_is_real != 0, precision, E_out, P_out, ctx->c.static_scratch, st);
+        return RT_OK;
+    }, false);
 }
 
 rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s, int64_t n_bins, float* cir_out,

@@ -54,6 +54,10 @@ struct Ctx {
     // unique candidate counts of the last call per branch (Tx, RIS centre):
     // the first hash set of the next call is sized from them
     std::atomic<int64_t> cand_hint[2] = {0, 0};
+    // device address of this device's copy of the library's static scratch array
+    // (the allocation-free sum); looked up once, when the context is opened
+    void* static_scratch = nullptr;
+    size_t static_scratch_bytes = 0;
 };
 
 // Borrow a side stream of the context for the lifetime of the object.
@@ -250,6 +254,11 @@ void cir(Ctx& c, const Channel& ch, const float* gamma, double bin_s, int64_t n_
 // ---- RIS sum ----
 void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real,
              int precision, float* E_out, float* P_out, hipStream_t st);
+// The same sum with its split buffers in caller-provided device memory (no
+// allocation, no cached split): bytes needed, and the sum itself.
+size_t ris_sum_scratch_bytes(int64_t R, int64_t M, int64_t C, bool gamma_real, int precision);
+void ris_sum_in(const Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real, int precision,
+                float* E_out, float* P_out, void* scratch, hipStream_t st);
 
 // pinned host staging for size read-backs
 int64_t read_i64(const int64_t* d, hipStream_t st);

@@ -393,6 +393,79 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
         }
 }
 
+// Shapes of the matrix-core product of one sum (the split buffers' sizes).
+struct SumShape {
+    bool f16, three;
+    int layout;      // cached split key: 1 / 2 bf16 real / complex Gamma, 3 / 4 fp16
+    int lay;         // 1 real, 2 complex Gamma
+    int64_t kp, rows_p, cols_p;
+};
+
+static SumShape sum_shape(int64_t R, int64_t M, int64_t C, bool gamma_real, int precision)
+{
+    SumShape sh;
+    sh.f16 = precision == 3;
+    sh.three = precision == 2;
+    sh.lay = gamma_real ? 1 : 2;
+    sh.layout = sh.lay + (sh.f16 ? 2 : 0);
+    const int64_t kd = gamma_real ? M : 2 * M;
+    sh.kp = round_up(kd > 0 ? kd : 1, GBK);
+    sh.rows_p = round_up(2 * R, G2M);   // a multiple of both tile heights
+    sh.cols_p = round_up(C, G2N);
+    return sh;
+}
+
+// Split of H into a_hi / a_lo (and the fp16 row scales), on `st`.
+static void launch_split_a(const Channel& ch, const SumShape& sh, uint16_t* a_hi, uint16_t* a_lo, int32_t* sexp,
+                           hipStream_t st)
+{
+    const int64_t R = ch.R, M = ch.M;
+    if (sh.f16) {
+        hipLaunchKernelGGL(k_row_scale, dim3(nblk(R, 4)), dim3(256), 0, st, ch.H.as<float2>(), R, M, sexp);
+        HIP_CHECK(hipGetLastError());
+    }
+    hipLaunchKernelGGL(k_split_A, dim3(nblk(sh.rows_p * sh.kp, 256)), dim3(256), 0, st, ch.H.as<float2>(), R, M,
+                       sh.lay, sh.rows_p, sh.kp, sh.f16 ? (const int32_t*)sexp : (const int32_t*)nullptr, a_hi, a_lo);
+    HIP_CHECK(hipGetLastError());
+}
+
+// Split of Gamma into b_hi (b_lo for three products) and the product itself, on `st`.
+static void launch_product(const Channel& ch, const SumShape& sh, const float2* G, int64_t C, float scale,
+                           const uint16_t* a_hi, const uint16_t* a_lo, const int32_t* sexp, uint16_t* b_hi,
+                           uint16_t* b_lo, float* E_out, float* P_out, hipStream_t st)
+{
+    const int64_t R = ch.R, M = ch.M, kp = sh.kp;
+    hipLaunchKernelGGL(k_split_B, dim3(nblk(sh.cols_p * kp, 256)), dim3(256), 0, st, G, M, C, sh.lay, sh.cols_p, kp,
+                       sh.f16, b_hi, sh.three ? b_lo : (uint16_t*)nullptr);
+    HIP_CHECK(hipGetLastError());
+    const int32_t* sx = sh.f16 ? sexp : nullptr;
+    if (sh.three) {
+        const int n_tn = (int)(sh.cols_p / GBN);
+        const int64_t n_tiles = (sh.rows_p / GBM) * n_tn;
+        hipLaunchKernelGGL((k_sum_mfma<3, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, a_hi, a_lo, b_hi, b_lo,
+                           kp, ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn);
+    } else {
+        const int n_tn2 = (int)(sh.cols_p / G2N);
+        const int64_t n_tiles2 = (sh.rows_p / G2M) * n_tn2;
+        if (sh.f16)
+            hipLaunchKernelGGL((k_sum_mfma_2x<true>), dim3((unsigned)n_tiles2), dim3(512), 0, st, a_hi, a_lo, b_hi, kp,
+                               ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn2);
+        else
+            hipLaunchKernelGGL((k_sum_mfma_2x<false>), dim3((unsigned)n_tiles2), dim3(512), 0, st, a_hi, a_lo, b_hi,
+                               kp, ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn2);
+    }
+    HIP_CHECK(hipGetLastError());
+}
+
+static void launch_valu(const Channel& ch, const float2* G, int64_t C, float scale, float* E_out, float* P_out,
+                        hipStream_t st)
+{
+    dim3 grid(nblk(C, VT), nblk(ch.R, VT));
+    hipLaunchKernelGGL(k_sum_valu, grid, dim3(256), 0, st, ch.H.as<float2>(), G, ch.E_env.as<float2>(), ch.R, ch.M, C,
+                       scale, (float2*)E_out, P_out);
+    HIP_CHECK(hipGetLastError());
+}
+
 void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real, int precision,
              float* E_out, float* P_out, hipStream_t st)
 {
@@ -400,21 +473,12 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
     const float2* G = (const float2*)gamma;
     if (R == 0 || C == 0) return;
     if (precision == 0) {
-        dim3 grid(nblk(C, VT), nblk(R, VT));
-        hipLaunchKernelGGL(k_sum_valu, grid, dim3(256), 0, st, ch.H.as<float2>(), G, ch.E_env.as<float2>(), R, M, C,
-                           scale, (float2*)E_out, P_out);
-        HIP_CHECK(hipGetLastError());
+        launch_valu(ch, G, C, scale, E_out, P_out, st);
         return;
     }
-    const bool f16 = precision == 3;
-    const int layout = (gamma_real ? 1 : 2) + (f16 ? 2 : 0);   // cached split: layout and number format
-    const int lay = gamma_real ? 1 : 2;
-    const int64_t kd = gamma_real ? M : 2 * M;
-    const int64_t kp = round_up(kd > 0 ? kd : 1, GBK);
-    const int64_t rows_p = round_up(2 * R, G2M);   // a multiple of both tile heights
-    const int64_t cols_p = round_up(C, G2N);
-    if (ch.split_kind == layout && ch.split_ev) HIP_CHECK(hipStreamWaitEvent(st, ch.split_ev, 0));
-    if (ch.split_kind != layout) {
+    const SumShape sh = sum_shape(R, M, C, gamma_real, precision);
+    if (ch.split_kind == sh.layout && ch.split_ev) HIP_CHECK(hipStreamWaitEvent(st, ch.split_ev, 0));
+    if (ch.split_kind != sh.layout) {
         // the old split may still be read by sums queued on other streams: this
         // stream waits for all of them, then releases it in its own order
         for (const auto& rd : ch.split_readers)
@@ -422,52 +486,22 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
         for (Scratch* p : {&ch.a_hi, &ch.a_lo, &ch.a_sexp}) p->st = st;
         ch.a_hi.release();
         ch.a_lo.release();
-        ch.a_hi = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
-        ch.a_lo = Scratch(c, sizeof(uint16_t) * (size_t)(rows_p * kp), st);
         ch.a_sexp.release();
-        if (f16) {
-            ch.a_sexp = Scratch(c, sizeof(int32_t) * (size_t)R, st);
-            hipLaunchKernelGGL(k_row_scale, dim3(nblk(R, 4)), dim3(256), 0, st, ch.H.as<float2>(), R, M,
-                               ch.a_sexp.as<int32_t>());
-            HIP_CHECK(hipGetLastError());
-        }
-        hipLaunchKernelGGL(k_split_A, dim3(nblk(rows_p * kp, 256)), dim3(256), 0, st, ch.H.as<float2>(), R, M, lay,
-                           rows_p, kp, f16 ? ch.a_sexp.as<int32_t>() : (const int32_t*)nullptr, ch.a_hi.as<uint16_t>(),
-                           ch.a_lo.as<uint16_t>());
-        HIP_CHECK(hipGetLastError());
-        ch.split_kind = layout;
-        ch.a_rows = rows_p;
-        ch.a_k = kp;
+        ch.a_hi = Scratch(c, sizeof(uint16_t) * (size_t)(sh.rows_p * sh.kp), st);
+        ch.a_lo = Scratch(c, sizeof(uint16_t) * (size_t)(sh.rows_p * sh.kp), st);
+        if (sh.f16) ch.a_sexp = Scratch(c, sizeof(int32_t) * (size_t)R, st);
+        launch_split_a(ch, sh, ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>(), ch.a_sexp.as<int32_t>(), st);
+        ch.split_kind = sh.layout;
+        ch.a_rows = sh.rows_p;
+        ch.a_k = sh.kp;
         if (!ch.split_ev) HIP_CHECK(hipEventCreateWithFlags(&ch.split_ev, hipEventDisableTiming));
         HIP_CHECK(hipEventRecord(ch.split_ev, st));
     }
-    const bool three = precision == 2;
-    Scratch bhi(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
+    Scratch bhi(c, sizeof(uint16_t) * (size_t)(sh.cols_p * sh.kp), st);
     Scratch blo;
-    if (three) blo = Scratch(c, sizeof(uint16_t) * (size_t)(cols_p * kp), st);
-    hipLaunchKernelGGL(k_split_B, dim3(nblk(cols_p * kp, 256)), dim3(256), 0, st, G, M, C, lay, cols_p, kp, f16,
-                       bhi.as<uint16_t>(), blo.as<uint16_t>());
-    HIP_CHECK(hipGetLastError());
-    const int n_tn = (int)(cols_p / GBN);
-    const int64_t n_tiles = (rows_p / GBM) * n_tn;
-    const int32_t* sexp = f16 ? ch.a_sexp.as<int32_t>() : nullptr;
-    if (three)
-        hipLaunchKernelGGL((k_sum_mfma<3, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, ch.a_hi.as<uint16_t>(),
-                           ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), blo.as<uint16_t>(), kp, ch.E_env.as<float2>(),
-                           sexp, R, C, scale, (float2*)E_out, P_out, n_tn);
-    else {
-        const int n_tn2 = (int)(cols_p / G2N);
-        const int64_t n_tiles2 = (rows_p / G2M) * n_tn2;
-        if (f16)
-            hipLaunchKernelGGL((k_sum_mfma_2x<true>), dim3((unsigned)n_tiles2), dim3(512), 0, st, ch.a_hi.as<uint16_t>(),
-                               ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), kp, ch.E_env.as<float2>(), sexp, R, C, scale,
-                               (float2*)E_out, P_out, n_tn2);
-        else
-            hipLaunchKernelGGL((k_sum_mfma_2x<false>), dim3((unsigned)n_tiles2), dim3(512), 0, st,
-                               ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>(), bhi.as<uint16_t>(), kp,
-                               ch.E_env.as<float2>(), sexp, R, C, scale, (float2*)E_out, P_out, n_tn2);
-    }
-    HIP_CHECK(hipGetLastError());
+    if (sh.three) blo = Scratch(c, sizeof(uint16_t) * (size_t)(sh.cols_p * sh.kp), st);
+    launch_product(ch, sh, G, C, scale, ch.a_hi.as<uint16_t>(), ch.a_lo.as<uint16_t>(), ch.a_sexp.as<int32_t>(),
+                   bhi.as<uint16_t>(), blo.as<uint16_t>(), E_out, P_out, st);
     // this stream has read the split up to here
     hipEvent_t* ev = nullptr;
     for (auto& rd : ch.split_readers)
@@ -478,6 +512,43 @@ void ris_sum(Ctx& c, Channel& ch, const float* gamma, int64_t C, float scale, bo
         HIP_CHECK(hipEventCreateWithFlags(ev, hipEventDisableTiming));
     }
     HIP_CHECK(hipEventRecord(*ev, st));
+}
+
+// The caller-provided scratch: [a_hi | a_lo | b_hi | b_lo | sexp], each part
+// starting on a 256-byte boundary.
+static inline size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+size_t ris_sum_scratch_bytes(int64_t R, int64_t M, int64_t C, bool gamma_real, int precision)
+{
+    if (precision == 0 || R == 0 || C == 0) return 0;
+    const SumShape sh = sum_shape(R, M, C, gamma_real, precision);
+    const size_t a = align256(sizeof(uint16_t) * (size_t)(sh.rows_p * sh.kp));
+    const size_t b = align256(sizeof(uint16_t) * (size_t)(sh.cols_p * sh.kp));
+    return 2 * a + (sh.three ? 2 : 1) * b + (sh.f16 ? align256(sizeof(int32_t) * (size_t)R) : 0);
+}
+
+void ris_sum_in(const Channel& ch, const float* gamma, int64_t C, float scale, bool gamma_real, int precision,
+                float* E_out, float* P_out, void* scratch, hipStream_t st)
+{
+    const int64_t R = ch.R, M = ch.M;
+    const float2* G = (const float2*)gamma;
+    if (R == 0 || C == 0) return;
+    if (precision == 0) {
+        launch_valu(ch, G, C, scale, E_out, P_out, st);
+        return;
+    }
+    const SumShape sh = sum_shape(R, M, C, gamma_real, precision);
+    const size_t a = align256(sizeof(uint16_t) * (size_t)(sh.rows_p * sh.kp));
+    const size_t b = align256(sizeof(uint16_t) * (size_t)(sh.cols_p * sh.kp));
+    char* base = (char*)scratch;
+    uint16_t* a_hi = (uint16_t*)base;
+    uint16_t* a_lo = (uint16_t*)(base + a);
+    uint16_t* b_hi = (uint16_t*)(base + 2 * a);
+    uint16_t* b_lo = sh.three ? (uint16_t*)(base + 2 * a + b) : nullptr;
+    int32_t* sexp = sh.f16 ? (int32_t*)(base + 2 * a + (sh.three ? 2 : 1) * b) : nullptr;
+    // every element of the split buffers (padding included) is written before it is read
+    launch_split_a(ch, sh, a_hi, a_lo, sexp, st);
+    launch_product(ch, sh, G, C, scale, a_hi, a_lo, sexp, b_hi, b_lo, E_out, P_out, st);
 }
 
 }  // namespace rt

@@ -51,7 +51,7 @@ ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
     "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials", "rt_cir",
-    "rt_ris_paths_read",
+    "rt_ris_paths_read", "rt_ris_sum_noalloc",
 )
 
 
@@ -140,6 +140,8 @@ def lib():
             "rt_ris_paths_read": (ctypes.c_int32, [P, u64, P, P, i64, pi64]),
             "rt_ris_sum": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32, ctypes.c_int32,
                                             P, P, P]),
+            "rt_ris_sum_noalloc": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32,
+                                                    ctypes.c_int32, P, P, P]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
             "rt_scene_set_materials": (ctypes.c_int32, [P, u64, P, P, P]),
             "rt_cir": (ctypes.c_int32, [P, u64, P, ctypes.c_double, i64, P, P]),
@@ -414,6 +416,23 @@ class Context:
                                     ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None, on.handle))
             on.keep(*given)
         return E_out, P_out
+
+
+def ris_sum_noalloc(ctx: Context, ch: int, gamma, E_out=None, P_out=None, scale: float = 1.0,
+                    gamma_is_real: bool = False, precision: int = PREC_MFMA_BF16X2, stream=None):
+    """rt_ris_sum_noalloc: the sum into caller-allocated outputs (torch device
+    tensors: E_out complex64 [R, C] and/or P_out float32 [R, C]) with the
+    library's static scratch; gamma must be a contiguous complex64 device
+    tensor [M, C].  Nothing is allocated here either."""
+    if E_out is None and P_out is None:
+        raise ValueError("give E_out and/or P_out")
+    if not gamma.is_contiguous():
+        raise ValueError("gamma must be contiguous")
+    _check(lib().rt_ris_sum_noalloc(ctx._h, ch, ctypes.c_void_p(gamma.data_ptr()), int(gamma.shape[1]),
+                                    float(scale), int(gamma_is_real), int(precision),
+                                    ctypes.c_void_p(E_out.data_ptr()) if E_out is not None else None,
+                                    ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None,
+                                    _stream_handle(stream)))
 
 
 def upload_problem(ctx: Context, prob, stream=None):
