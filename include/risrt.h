@@ -302,6 +302,19 @@ rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s,
 rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r, const float* sigma,
                                  void* stream);
 
+/* Sort n keys of `words` 64-bit words each (1 or 2; word 0 the least
+ * significant) in device memory, in place, by their bits [begin_bit,
+ * end_bit) (0 <= begin_bit <= end_bit <= 64 words), stably: keys equal on
+ * those bits keep their order.  With unique != 0, keys equal in every word
+ * are then kept once.  This is the primitive behind the de-duplication of
+ * the candidate surface sequences (packed 21 bits per surface; Section II-B
+ * searches the permutations of surfaces) and the Morton order of the BVH
+ * build.  *n_out (may be NULL) receives the number of keys left; the call
+ * waits for the stream.  RT_EINVAL on bad arguments or host memory,
+ * RT_EUNSUPPORTED for 2^32 keys or more. */
+rt_status rt_keys_sort(rt_ctx ctx, uint64_t* keys, int64_t n, int32_t words, int32_t begin_bit, int32_t end_bit,
+                       int32_t unique, int64_t* n_out, void* stream);
+
 /* Release a scene, RIS or channel. */
 rt_status rt_destroy(rt_ctx ctx, uint64_t handle);
 

@@ -24,6 +24,7 @@ scalar per-triangle reflection coefficient multiplies once per bounce.
 """
 from __future__ import annotations
 
+import contextlib
 import ctypes
 import itertools
 import math
@@ -45,26 +46,44 @@ PAT_MONOPOLE = 2
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "rt_oracle.c")
 _LIB_PATH = os.path.join(_HERE, "liboracle.so")
-_lib = None
+_LIB64_PATH = os.path.join(_HERE, "liboracle_fp64dec.so")
+_libs = {}
+_fp64 = False   # ray decisions in FP64 (the reference of the precision report), not the parity reading
 
 
-def build(force: bool = False) -> str:
-    """Compile the C part of the oracle (gcc, FP64/FP32 IEEE, no contraction)."""
-    if force or not os.path.exists(_LIB_PATH) or \
-            os.path.getmtime(_LIB_PATH) < os.path.getmtime(_SRC):
-        tmp = _LIB_PATH + ".tmp%d" % os.getpid()
+def build(force: bool = False, fp64_decisions: bool = False) -> str:
+    """Compile the C part of the oracle (gcc, FP64/FP32 IEEE, no contraction);
+    fp64_decisions: the variant that takes the ray decisions in FP64."""
+    path = _LIB64_PATH if fp64_decisions else _LIB_PATH
+    if force or not os.path.exists(path) or os.path.getmtime(path) < os.path.getmtime(_SRC):
+        tmp = path + ".tmp%d" % os.getpid()
         cmd = ["gcc", "-O2", "-std=c99", "-fPIC", "-shared", "-fopenmp",
                "-ffp-contract=off", "-fno-fast-math", "-o", tmp, _SRC, "-lm"]
+        if fp64_decisions:
+            cmd.insert(1, "-DOR_FP64_DECISIONS")
         subprocess.check_call(cmd)
-        os.replace(tmp, _LIB_PATH)
-    return _LIB_PATH
+        os.replace(tmp, path)
+    return path
+
+
+@contextlib.contextmanager
+def decisions_fp64():
+    """Within the block every oracle call takes its ray decisions (closest hit,
+    reflection, blocked leg) in FP64 instead of FP32."""
+    global _fp64
+    old = _fp64
+    _fp64 = True
+    try:
+        yield
+    finally:
+        _fp64 = old
 
 
 def lib():
-    global _lib
-    if _lib is None:
-        build()
-        L = ctypes.CDLL(_LIB_PATH)
+    L = _libs.get(_fp64)
+    if L is None:
+        path = build(fp64_decisions=_fp64)
+        L = ctypes.CDLL(path)
         P = ctypes.c_void_p
         i64 = ctypes.c_int64
         L.or_discover.restype = i64
@@ -83,8 +102,8 @@ def lib():
         L.or_leg_count.argtypes = []
         L.or_threads.restype = ctypes.c_int
         L.or_threads.argtypes = []
-        _lib = L
-    return _lib
+        _libs[_fp64] = L
+    return L
 
 
 def _p(a: np.ndarray):

@@ -25,6 +25,12 @@
  *   - image method, containment and side tests, lengths: FP64, no fused
  *     multiply-add.
  * Compile with -ffp-contract=off and without -ffast-math.
+ *
+ * Built with -DOR_FP64_DECISIONS the same ray decisions are taken in FP64
+ * instead (origin and direction not rounded to FP32): not the reading the
+ * parity tests use, but the reference that measures how many decisions the
+ * FP32 reading moves (hit lists, blocked legs, rays that escape a closed
+ * room).
  */
 #include <math.h>
 #include <omp.h>
@@ -33,6 +39,12 @@
 #include <string.h>
 
 #define OR_EPS 1e-4 /* metres: legs ignore hits within EPS of their ends */
+
+#ifdef OR_FP64_DECISIONS
+typedef double rfloat; /* precision of the ray decisions */
+#else
+typedef float rfloat;
+#endif
 
 static int64_t g_leg_count = 0; /* legs tested since the last or_leg_count() */
 
@@ -49,10 +61,10 @@ int64_t or_leg_count(void)
 }
 
 /* ----------------------------------------------------------------------- */
-/* FP32 ray / triangle test                                                 */
+/* Ray / triangle test (FP32, or FP64 with OR_FP64_DECISIONS)              */
 /* ----------------------------------------------------------------------- */
 typedef struct {
-    float v0[3], e1[3], e2[3];
+    rfloat v0[3], e1[3], e2[3];
 } tri32;
 
 static void make_tri32(const float* V, const int32_t* T, int64_t i, tri32* t)
@@ -62,35 +74,35 @@ static void make_tri32(const float* V, const int32_t* T, int64_t i, tri32* t)
     const float* c = V + 3 * (int64_t)T[3 * i + 2];
     for (int k = 0; k < 3; ++k) {
         t->v0[k] = a[k];
-        t->e1[k] = b[k] - a[k];
-        t->e2[k] = c[k] - a[k];
+        t->e1[k] = (rfloat)b[k] - (rfloat)a[k];
+        t->e2[k] = (rfloat)c[k] - (rfloat)a[k];
     }
 }
 
 /* Moller-Trumbore, two-sided.  Returns 1 and the parameter t if the ray
  * o + t d meets the closed triangle with tmin < t < tmax. */
-static int hit32(const float o[3], const float d[3], const tri32* tr, float tmin, float tmax,
-                 float* t_out)
+static int hit32(const rfloat o[3], const rfloat d[3], const tri32* tr, rfloat tmin, rfloat tmax,
+                 rfloat* t_out)
 {
-    const float* e1 = tr->e1;
-    const float* e2 = tr->e2;
-    float px = d[1] * e2[2] - d[2] * e2[1];
-    float py = d[2] * e2[0] - d[0] * e2[2];
-    float pz = d[0] * e2[1] - d[1] * e2[0];
-    float det = e1[0] * px + e1[1] * py + e1[2] * pz;
-    if (det == 0.0f) return 0;
-    float inv = 1.0f / det;
-    float sx = o[0] - tr->v0[0];
-    float sy = o[1] - tr->v0[1];
-    float sz = o[2] - tr->v0[2];
-    float u = (sx * px + sy * py + sz * pz) * inv;
-    if (!(u >= 0.0f && u <= 1.0f)) return 0;
-    float qx = sy * e1[2] - sz * e1[1];
-    float qy = sz * e1[0] - sx * e1[2];
-    float qz = sx * e1[1] - sy * e1[0];
-    float v = (d[0] * qx + d[1] * qy + d[2] * qz) * inv;
-    if (!(v >= 0.0f && u + v <= 1.0f)) return 0;
-    float t = (e2[0] * qx + e2[1] * qy + e2[2] * qz) * inv;
+    const rfloat* e1 = tr->e1;
+    const rfloat* e2 = tr->e2;
+    rfloat px = d[1] * e2[2] - d[2] * e2[1];
+    rfloat py = d[2] * e2[0] - d[0] * e2[2];
+    rfloat pz = d[0] * e2[1] - d[1] * e2[0];
+    rfloat det = e1[0] * px + e1[1] * py + e1[2] * pz;
+    if (det == (rfloat)0) return 0;
+    rfloat inv = (rfloat)1 / det;
+    rfloat sx = o[0] - tr->v0[0];
+    rfloat sy = o[1] - tr->v0[1];
+    rfloat sz = o[2] - tr->v0[2];
+    rfloat u = (sx * px + sy * py + sz * pz) * inv;
+    if (!(u >= (rfloat)0 && u <= (rfloat)1)) return 0;
+    rfloat qx = sy * e1[2] - sz * e1[1];
+    rfloat qy = sz * e1[0] - sx * e1[2];
+    rfloat qz = sx * e1[1] - sy * e1[0];
+    rfloat v = (d[0] * qx + d[1] * qy + d[2] * qz) * inv;
+    if (!(v >= (rfloat)0 && u + v <= (rfloat)1)) return 0;
+    rfloat t = (e2[0] * qx + e2[1] * qy + e2[2] * qz) * inv;
     if (!(t > tmin && t < tmax)) return 0;
     *t_out = t;
     return 1;
@@ -98,14 +110,14 @@ static int hit32(const float o[3], const float d[3], const tri32* tr, float tmin
 
 /* Closest hit over all triangles except `skip`; ties in t go to the lowest
  * triangle index. Returns -1 on a miss. */
-static int64_t closest32(const tri32* tris, int64_t nt, const float o[3], const float d[3],
-                         float tmin, int64_t skip, float* t_best)
+static int64_t closest32(const tri32* tris, int64_t nt, const rfloat o[3], const rfloat d[3],
+                         rfloat tmin, int64_t skip, rfloat* t_best)
 {
     int64_t best = -1;
-    float bt = INFINITY;
+    rfloat bt = INFINITY;
     for (int64_t i = 0; i < nt; ++i) {
         if (i == skip) continue;
-        float t;
+        rfloat t;
         if (hit32(o, d, &tris[i], tmin, INFINITY, &t)) {
             if (t < bt) {
                 bt = t;
@@ -119,16 +131,16 @@ static int64_t closest32(const tri32* tris, int64_t nt, const float o[3], const 
 
 /* Specular reflection of d off the plane of triangle tr:
  * n = e1 x e2 (not normalised), d' = d - (2 (d.n) / (n.n)) n. */
-static void reflect32(const tri32* tr, const float d[3], float out[3])
+static void reflect32(const tri32* tr, const rfloat d[3], rfloat out[3])
 {
-    const float* e1 = tr->e1;
-    const float* e2 = tr->e2;
-    float nx = e1[1] * e2[2] - e1[2] * e2[1];
-    float ny = e1[2] * e2[0] - e1[0] * e2[2];
-    float nz = e1[0] * e2[1] - e1[1] * e2[0];
-    float dn = d[0] * nx + d[1] * ny + d[2] * nz;
-    float nn = nx * nx + ny * ny + nz * nz;
-    float k = (2.0f * dn) / nn;
+    const rfloat* e1 = tr->e1;
+    const rfloat* e2 = tr->e2;
+    rfloat nx = e1[1] * e2[2] - e1[2] * e2[1];
+    rfloat ny = e1[2] * e2[0] - e1[0] * e2[2];
+    rfloat nz = e1[0] * e2[1] - e1[1] * e2[0];
+    rfloat dn = d[0] * nx + d[1] * ny + d[2] * nz;
+    rfloat nn = nx * nx + ny * ny + nz * nz;
+    rfloat k = ((rfloat)2 * dn) / nn;
     out[0] = d[0] - k * nx;
     out[1] = d[1] - k * ny;
     out[2] = d[2] - k * nz;
@@ -183,17 +195,17 @@ int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double s
         if (hemi) go = (d64[0] * hemi_n[0] + d64[1] * hemi_n[1] + d64[2] * hemi_n[2]) > 0.0;
         launched[i] = (uint8_t)go;
         if (!go) continue;
-        float o[3] = {(float)src[0], (float)src[1], (float)src[2]};
-        float d[3] = {(float)d64[0], (float)d64[1], (float)d64[2]};
+        rfloat o[3] = {(rfloat)src[0], (rfloat)src[1], (rfloat)src[2]};
+        rfloat d[3] = {(rfloat)d64[0], (rfloat)d64[1], (rfloat)d64[2]};
         int64_t skip = -1;
         for (int b = 0; b < K; ++b) {
-            float t;
+            rfloat t;
             segs += 1;
-            int64_t h = closest32(tris, nt, o, d, (float)OR_EPS, skip, &t);
+            int64_t h = closest32(tris, nt, o, d, (rfloat)OR_EPS, skip, &t);
             if (h < 0) break;
             hits[i * K + b] = (int32_t)h;
-            float p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
-            float r[3];
+            rfloat p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
+            rfloat r[3];
             reflect32(&tris[h], d, r);
             o[0] = p[0]; o[1] = p[1]; o[2] = p[2];
             d[0] = r[0]; d[1] = r[1]; d[2] = r[2];
@@ -205,7 +217,7 @@ int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double s
 }
 
 /* ----------------------------------------------------------------------- */
-/* Visibility of a leg (FP32 decision)                                      */
+/* Visibility of a leg (FP32 decision, or FP64 with OR_FP64_DECISIONS)     */
 /* ----------------------------------------------------------------------- */
 /* The leg A -> B (FP64 end points) is blocked if some triangle that is not
  * part of surface skip_a or skip_b (the surfaces its end points lie on, -1 for
@@ -216,16 +228,16 @@ static int leg_blocked(const tri32* tris, const int32_t* surf, int64_t nt, const
 {
     double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
     double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
-    float o[3] = {(float)A[0], (float)A[1], (float)A[2]};
-    float d[3] = {(float)(w0 / L), (float)(w1 / L), (float)(w2 / L)};
-    float tmin = (float)OR_EPS;
-    float tmax = (float)(L - OR_EPS);
+    rfloat o[3] = {(rfloat)A[0], (rfloat)A[1], (rfloat)A[2]};
+    rfloat d[3] = {(rfloat)(w0 / L), (rfloat)(w1 / L), (rfloat)(w2 / L)};
+    rfloat tmin = (rfloat)OR_EPS;
+    rfloat tmax = (rfloat)(L - OR_EPS);
 #pragma omp atomic
     g_leg_count += 1;
     if (!(tmax > tmin)) return 0;
     for (int64_t i = 0; i < nt; ++i) {
         if (surf[i] == skip_a || surf[i] == skip_b) continue;
-        float t;
+        rfloat t;
         if (hit32(o, d, &tris[i], tmin, tmax, &t)) return 1;
     }
     return 0;

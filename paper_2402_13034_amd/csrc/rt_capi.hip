@@ -870,6 +870,31 @@ rt_status rt_cir(rt_ctx ctx, uint64_t channel, const float* gamma, double bin_s,
     });
 }
 
+rt_status rt_keys_sort(rt_ctx ctx, uint64_t* keys, int64_t n, int32_t words, int32_t begin_bit, int32_t end_bit,
+                       int32_t unique, int64_t* n_out, void* stream)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        if (n < 0 || (words != 1 && words != 2) || begin_bit < 0 || end_bit > 64 * words || begin_bit > end_bit)
+            return fail(RT_EINVAL, "bad key count, width or bit range");
+        if (n > 0 && !is_device_ptr(keys)) return fail(RT_EINVAL, "keys must be device memory");
+        if (n >= ((int64_t)1 << 32)) return fail(RT_EUNSUPPORTED, "too many keys");
+        hipStream_t st = (hipStream_t)stream;
+        Scratch tmp(ctx->c, sizeof(uint64_t) * (size_t)words * (size_t)(n > 0 ? n : 1), st);
+        sort_keys(ctx->c, keys, tmp.as<uint64_t>(), n, words, begin_bit, end_bit, st);
+        int64_t count = n;
+        if (unique) {
+            Scratch cnt(ctx->c, sizeof(int64_t), st);
+            unique_keys(ctx->c, tmp.as<uint64_t>(), keys, n, words, cnt.as<int64_t>(), st);
+            count = read_i64(cnt.as<int64_t>(), st);
+        } else if (n > 0) {
+            HIP_CHECK(hipMemcpyAsync(keys, tmp.p, sizeof(uint64_t) * (size_t)words * (size_t)n,
+                                     hipMemcpyDeviceToDevice, st));
+        }
+        if (n_out) *n_out = count;
+        return RT_OK;
+    });
+}
+
 rt_status rt_destroy(rt_ctx ctx, uint64_t handle)
 {
     return guarded(ctx, [&]() -> rt_status {

@@ -212,8 +212,13 @@ struct EnvRec {
     float amp[2];
 };
 
-// ---- primitives (rocPRIM) ----
+// ---- primitives (rt_prims.hip) ----
 bool is_device_ptr(const void* p);
+// stable LSD radix sort of keys of `words` (1 or 2) 64-bit words on bits
+// [begin_bit, end_bit); `in` may be clobbered, in == out allowed
+void sort_keys(Ctx& c, uint64_t* in, uint64_t* out, int64_t n, int words, int begin_bit, int end_bit, hipStream_t st);
+// unique of sorted keys of `words` words; count written to device int64
+void unique_keys(Ctx& c, const uint64_t* in, uint64_t* out, int64_t n, int words, int64_t* d_count, hipStream_t st);
 void sort_u64(Ctx& c, uint64_t* keys, int64_t n, int end_bit, hipStream_t st);
 void sort_u64_into(Ctx& c, uint64_t* keys_in, uint64_t* keys_out, int64_t n, int end_bit, hipStream_t st);
 // unique of sorted keys; count written to device int64

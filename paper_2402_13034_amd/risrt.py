@@ -51,7 +51,7 @@ ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
     "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials", "rt_cir",
-    "rt_ris_paths_read", "rt_ris_sum_noalloc",
+    "rt_ris_paths_read", "rt_ris_sum_noalloc", "rt_keys_sort",
 )
 
 
@@ -142,6 +142,8 @@ def lib():
                                             P, P, P]),
             "rt_ris_sum_noalloc": (ctypes.c_int32, [P, u64, P, i64, ctypes.c_float, ctypes.c_int32,
                                                     ctypes.c_int32, P, P, P]),
+            "rt_keys_sort": (ctypes.c_int32, [P, P, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                              ctypes.c_int32, pi64, P]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
             "rt_scene_set_materials": (ctypes.c_int32, [P, u64, P, P, P]),
             "rt_cir": (ctypes.c_int32, [P, u64, P, ctypes.c_double, i64, P, P]),
@@ -365,6 +367,20 @@ class Context:
                                    _ptr(useq) if useq.size else None, nu.value, ctypes.byref(nu),
                                    _ptr(valid) if valid.size else None, ns.value, ctypes.byref(ns)))
         return {"env": env, "useq": useq, "ris_valid": valid.astype(bool)}
+
+    def keys_sort(self, keys, begin_bit: int = 0, end_bit: Optional[int] = None, unique: bool = False,
+                  stream=None) -> int:
+        """Sort a torch int64 device tensor of keys in place: shape [n] (one
+        word) or [n, 2] (word 0 least significant); returns the number of
+        keys left (all of them unless unique)."""
+        words = 1 if keys.dim() == 1 else int(keys.shape[1])
+        if not keys.is_contiguous():
+            raise ValueError("keys must be contiguous")
+        n_out = ctypes.c_int64()
+        _check(lib().rt_keys_sort(self._h, ctypes.c_void_p(keys.data_ptr()), int(keys.shape[0]), words,
+                                  int(begin_bit), int(64 * words if end_bit is None else end_bit), int(unique),
+                                  ctypes.byref(n_out), _stream_handle(stream)))
+        return n_out.value
 
     def ris_paths_read(self, ch: int):
         """Per (slot, element) amplitude (complex64, 0 where no path) and
