@@ -32,14 +32,21 @@ HBM_PEAK_GBS = 8000.0
 MFMA_BF16_PEAK_TFLOPS = 2500.0
 VECTOR_PEAK_TFLOPS = 78.6   # FP32 (non-packed FMA) = FP64 vector peak: 256 CU x 4 SIMD x 16 lanes x 2 x 2.4 GHz
 
-# Algorithmic flops of the per-element kernel's units of work (FMA = 2):
-#   BVH node visit: two slab tests, 6 FMA + 12 min/max each      -> 48
-#   ray/triangle test (FP32 Moller-Trumbore, see rt_internal.hpp) -> 50
-#   FP64 containment test (normal, projection, 3 edge functions)  -> 50
-#   (slot, element) pair: images, back-trace, side tests, patterns,
-#     lengths, phase, complex amplitude                            -> 150
-#   visibility leg set-up (length, direction, conversions)        -> 30
-FLOPS_PER = {"node": 48, "tri": 50, "contain": 50, "pair": 150, "leg": 30}
+# Algorithmic flops of the per-element kernel's units of work, the unit costs
+# the hot-path scope fixes for the traversal and the per-candidate FP64 work:
+#   BVH node visit (two slab tests)                                 -> 40
+#   ray/triangle test                                               -> 40
+#   (slot, element) pair: images, back-trace, containment, side
+#     tests, patterns, lengths, phase, amplitude, leg set-up (FP64)  -> 150 (the low end of 150-300)
+# Containment tests and leg set-ups are inside the pair's 150; the counting
+# build reports them separately.  The counts come from a counting instance
+# that walks the binary tree per leg (the method's LBVH walk); the timed
+# instance walks the tube of each slot's legs once, so `achieved` is the
+# method's algorithmic work per second, not the instructions executed: those
+# are in `valu_issue_share` (SQ counters of the timed instance).
+FLOPS_PER = {"node": 40, "tri": 40, "contain": 0, "pair": 150, "leg": 0}
+FLOPS_PER_PAIR_HIGH = 300
+SQ_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_ris_lab_room_sq_counters.json")
 KERNEL_SOURCES = ["paper_2402_13034_amd/csrc/rt_trace.hip", "paper_2402_13034_amd/csrc/rt_internal.hpp"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_ris_lab_room_hbm_counters.json")
 
@@ -64,6 +71,21 @@ def measured_traffic():
     if d.get("source_hash") != kernel_source_hash():
         return None
     return d.get("bytes_per_launch")
+
+
+def measured_valu_share():
+    """VALU issue share of the timed k_ris instance (VALU wave instructions x 4
+    cycles over 1024 SIMDs x launch time x clock) from the committed SQ
+    counters, if they were taken on the current kernel sources."""
+    try:
+        with open(SQ_COUNTERS_FILE) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("source_hash") != kernel_source_hash():
+        return None
+    return {"valu_issue_share": d.get("valu_issue_share"), "clock_ghz": d.get("clock_ghz"),
+            "valu_wave_insts": d.get("valu_wave_insts"), "launch_us": d.get("launch_us")}
 
 
 def log(*a):
@@ -201,6 +223,100 @@ def run_trace_bench(ctx, prob, steps, warmup, variants=True):
     ctx.destroy(ris)
     return stats, t1 - t0, cst["ris_work"], {"ris_incoming_reflections": incoming, "fresnel_tm": fresnel,
                                              "impulse_response": cir}
+
+
+# bytes of the discovery walk per unit (this library's layouts): a binary node
+# visit reads both child boxes and links (four float4, 64 B), a triangle test
+# reads (v0, id), (e1, surface), (e2, -) (48 B); per segment the ray (32 B) and
+# the hit (8 B) as the traversal roofline counts them
+DISC_BYTES = {"segment": 40, "node": 64, "tri": 48}
+
+
+def run_large_bench(ctx, reps=2):
+    """The large configuration: the office floor (about 1.08e6 triangles,
+    5064 surfaces), order 5, 1e7 discovery rays per source (1e8 discovery
+    segments), 256 x 256 receivers, 64 x 64 RIS; scene build, whole traces
+    (discovery to H), the stage and discovery-kernel times, the discovery
+    walk priced in algorithmic bytes (counting build) against HBM, and the
+    1024-configuration sum of its channel on the matrix cores."""
+    import torch
+    from paper_2402_13034_amd import risrt, synth
+    prob = synth.office_floor()
+    mesh = device_mesh(prob)
+    rx = torch.from_numpy(prob.rx_pos).cuda()
+    r = prob.ris
+    ris = ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    scene = ctx.scene_create(*mesh)
+    torch.cuda.synchronize()
+    build_ms = (time.perf_counter() - t0) * 1e3
+    info = ctx.scene_info(scene)
+    ch, _ = risrt.trace_problem(ctx, prob, scene, ris, rx=rx)   # warm-up
+    ctx.destroy(ch)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sts = []
+    for _ in range(reps):
+        ch, st = risrt.trace_problem(ctx, prob, scene, ris, rx=rx)
+        ctx.destroy(ch)
+        sts.append(st)
+    torch.cuda.synchronize()
+    dt = (time.perf_counter() - t0) / reps
+    stage = []
+    for _ in range(2):
+        ch, sst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_STAGE_TIMES)
+        ctx.destroy(ch)
+        stage.append(sst)
+    ch, cst = risrt.trace_problem(ctx, prob, scene, ris, rx=rx, flags=risrt.FLAG_COUNT_WORK)
+    ctx.destroy(ch)
+    ms_tx = float(np.mean([s_["ms_discovery"][0] for s_ in stage]))
+    ms_span = float(np.mean([s_["ms_discovery"][2] for s_ in stage]))
+    w = cst["discovery_work"]
+    units_tx = {"node": w[0], "tri": w[1], "segment": w[2]}
+    units_all = {"node": w[0] + w[3], "tri": w[1] + w[4], "segment": w[2] + w[5]}
+    bytes_tx = sum(DISC_BYTES[k] * v for k, v in units_tx.items())
+    bytes_all = sum(DISC_BYTES[k] * v for k, v in units_all.items())
+    ach_tx = bytes_tx / (ms_tx * 1e-3) / 1e9
+    ach_all = bytes_all / (ms_span * 1e-3) / 1e9
+    # the 1024-configuration sum of the channel (65536 receivers x 4096 elements)
+    ch, _ = risrt.trace_problem(ctx, prob, scene, ris, rx=rx)
+    R, M = prob.rx_pos.shape[0], prob.ris.elems.shape[0]
+    C = 1024
+    rng = np.random.default_rng(prob.seed + 9)
+    g = torch.from_numpy((rng.integers(0, 2, size=(M, C)) * 2 - 1).astype(np.complex64)).cuda()
+    P = torch.empty((R, C), dtype=torch.float32, device="cuda")
+    ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=risrt.PREC_MFMA_BF16X2, P_out=P)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(3):
+        ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=risrt.PREC_MFMA_BF16X2, P_out=P)
+    e1.record()
+    torch.cuda.synchronize()
+    ms_sum = e0.elapsed_time(e1) / 3
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+    segs = sts[-1]["segments"]
+    return {"workload": "office floor 40x20x3 m, 200 rooms, %d triangles / %d surfaces, order<=5, "
+                        "1e7 rays per source, 256x256 receivers at 1.2 m, 64x64 RIS" % (info["n_tri"], info["n_surf"]),
+            "scene_build_ms": build_ms, "bvh_depth": info["bvh_depth"], "scene_bytes": info["bytes"],
+            "ms_per_trace": dt * 1e3, "segments_per_trace": segs,
+            "discovery_segments": sts[-1]["discovery_segments"], "leg_segments": sts[-1]["leg_segments"],
+            "Mray_segments_per_s": segs / dt / 1e6,
+            "n_cand_tx": sts[-1]["n_cand_tx"], "n_cand_u": sts[-1]["n_cand_u"],
+            "n_env_paths": sts[-1]["n_env_paths"], "n_ris_slots": sts[-1]["n_ris_slots"],
+            "leg_walk_fallbacks": sts[-1]["leg_walk_fallbacks"],
+            "stage_ms": stage[-1]["ms_stage"], "discovery_kernel_ms": {"tx": ms_tx, "both_span": ms_span},
+            "roofline_discovery": {"kernel": "k_discover (Tx, 1e7 rays, order 5)", "bound": "hbm",
+                                   "achieved": ach_tx, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                                   "frac": ach_tx / HBM_PEAK_GBS, "traffic": None,
+                                   "work_per_launch": units_tx, "bytes_per_unit": DISC_BYTES,
+                                   "both_sources": {"achieved": ach_all, "frac": ach_all / HBM_PEAK_GBS,
+                                                    "work": units_all}},
+            "ris_sum_1024": {"ms": ms_sum, "shape": {"R": R, "M": M, "C": C},
+                             "tflops_complex_equiv": 8.0 * R * M * C / (ms_sum * 1e-3) / 1e12,
+                             "tflops_executed": 8.0 * R * M * C / (ms_sum * 1e-3) / 1e12}}
 
 
 def run_paper_bench(ctx, reps=3):
@@ -418,6 +534,8 @@ def main():
     ap.add_argument("--no-variants", action="store_true",
                     help="skip the optional-feature lines (incoming reflections, Fresnel, impulse response, the "
                          "paper's scenario)")
+    ap.add_argument("--no-large", action="store_true", help="skip the office-floor (order 5, 1e6 triangles) line")
+    ap.add_argument("--large-only", action="store_true", help="only the office-floor line (profiling)")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="MIB",
                     help="first run a plain device copy of MIB MiB (reference for HBM byte counters)")
     args = ap.parse_args()
@@ -439,6 +557,12 @@ def main():
         del src, dst
     prob = synth.lab_room()
     ctx = risrt.Context(0)
+    if args.large_only:
+        large = run_large_bench(ctx)
+        log("bench: large", json.dumps(large))
+        ctx.close()
+        print(json.dumps({"large_scene": large}))
+        return
     log("bench: lab room, %d triangles, M=%d, R=%d, K=%d, rays=%d" % (
         prob.scene.n_tri, prob.ris.elems.shape[0], prob.rx_pos.shape[0], prob.order, prob.n_rays))
     stats, dt, work, variants = run_trace_bench(ctx, prob, args.steps, args.warmup, not args.no_variants)
@@ -456,11 +580,19 @@ def main():
     units = dict(zip(["node", "tri", "contain", "pair", "leg"], work))
     flops = sum(FLOPS_PER[k] * units[k] for k in units)
     achieved = flops / (ris_ms * 1e-3) / 1e12
+    flops_high = flops + (FLOPS_PER_PAIR_HIGH - FLOPS_PER["pair"]) * units["pair"]
     roofline = {"kernel": "k_ris (per-element image method + visibility legs + field)", "bound": "alu",
                 "achieved": achieved, "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": achieved / VECTOR_PEAK_TFLOPS, "traffic": measured_traffic(),
-                "launch_ms": ris_ms, "work_per_launch": units, "flops_per_unit": FLOPS_PER}
+                "launch_ms": ris_ms, "work_per_launch": units, "flops_per_unit": FLOPS_PER,
+                "flops_per_launch": flops,
+                "frac_at_300_per_pair": flops_high / (ris_ms * 1e-3) / 1e12 / VECTOR_PEAK_TFLOPS,
+                "executed": measured_valu_share()}
     log("bench: k_ris %.3f ms, work %s -> %.2f TFLOP/s" % (ris_ms, units, achieved))
+    large = None
+    if not args.no_large:
+        large = run_large_bench(ctx)
+        log("bench: large", json.dumps(large))
     gemm = None
     if not args.no_gemm:
         gemm = run_gemm_bench(ctx)
@@ -497,6 +629,7 @@ def main():
         "roofline": roofline,
         "variants": variants,
         "paper_scenario": paper,
+        "large_scene": large,
         "ris_sum": gemm,
         "serving": serving,
         "latency_p50_ms": serving["p50_ms"] if serving else None,

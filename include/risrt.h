@@ -37,6 +37,8 @@ extern "C" {
 #endif
 
 typedef int32_t rt_status;
+
+#define RT_MAX_ORDER 5   /* largest reflection order K (Section II-B's order of the image method) */
 #define RT_OK 0
 #define RT_EINVAL (-1)       /* invalid argument */
 #define RT_ENOMEM (-2)       /* the context's memory budget would be exceeded */
@@ -58,8 +60,9 @@ typedef int32_t rt_status;
 #define RT_FLAG_BRUTE_FORCE 4u /* test every triangle instead of walking the BVH */
 #define RT_FLAG_EXHAUSTIVE 8u  /* candidates = every surface sequence of order <= K
                                   (no discovery rays; small scenes only) */
-#define RT_FLAG_COUNT_WORK 16u /* run the counting build of the per-element kernel and
-                                  report its work in rt_stats.ris_work (same results) */
+#define RT_FLAG_COUNT_WORK 16u /* run the counting builds of discovery and of the per-element
+                                  kernel and report their work in rt_stats.discovery_work and
+                                  rt_stats.ris_work (same results) */
 #define RT_FLAG_FRESNEL_TE 64u /* per bounce, the Fresnel coefficient (Section II-B) of the triangle's
                                   material (rt_scene_set_materials) at the incidence angle, for the
                                   field perpendicular to the plane of incidence, instead of the
@@ -110,7 +113,7 @@ typedef struct {
 } rt_rx;
 
 /* freq_hz: carrier (Table I).  max_order: K, reflections between the source
- * (Tx or RIS element) and the receiver, 0..3.  n_rays: discovery rays per
+ * (Tx or RIS element) and the receiver, 0..RT_MAX_ORDER.  n_rays: discovery rays per
  * source (the RIS-centre source launches into the half-space in front of the
  * RIS, about n_rays).  flags: RT_FLAG_*. */
 typedef struct {
@@ -142,15 +145,21 @@ typedef struct {
     int64_t n_in_seq;            /* RT_FLAG_RIS_INCOMING: Tx candidate sequences valid and unblocked
                                     from the Tx to the RIS centre (order >= 1) */
     int64_t n_in_paths;          /* RT_FLAG_RIS_INCOMING: emitted paths Tx -> surfaces -> element */
+    int64_t discovery_work[6];   /* with RT_FLAG_COUNT_WORK: binary BVH node visits, triangle tests and
+                                    segments of discovery from the Tx, then the same from the RIS
+                                    centre (each ray walks the tree on its own) */
+    float ms_discovery[3];       /* with RT_FLAG_STAGE_TIMES: the discovery kernel of the Tx, of the RIS
+                                    centre (events on their streams), and the span of both (they
+                                    overlap on two streams) */
 } rt_stats;
 
 /* Environment path record (RT_FLAG_KEEP_PATHS): Tx -> surfaces seq[0..k) ->
- * receiver rx, reflecting on triangles tri[0..k). */
+ * receiver rx, reflecting on triangles tri[0..k) (-1 from k on). */
 typedef struct {
     int32_t rx;
     int32_t order;
-    int32_t seq[3];
-    int32_t tri[3];
+    int32_t seq[RT_MAX_ORDER];
+    int32_t tri[RT_MAX_ORDER];
     double length;   /* unfolded path length [m] */
     float amp[2];    /* complex amplitude at the receiver (E field, V/m) */
 } rt_env_path;
@@ -178,6 +187,13 @@ rt_status rt_mem_info(rt_ctx ctx, uint64_t* in_use, uint64_t* budget);
 rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const int32_t* tri,
                           int64_t n_tri, const int32_t* surf, const float* refl_re,
                           const float* refl_im, void* stream, uint64_t* scene);
+
+/* Sizes of a scene: triangles, surfaces, the depth of its BVH (the longest
+ * root-to-leaf path of the binary tree; the traversal kernels keep 32 stack
+ * entries per lane below depth 31, else 64) and the device bytes it holds.
+ * Any pointer may be NULL. */
+rt_status rt_scene_info(rt_ctx ctx, uint64_t scene, int64_t* n_tri, int64_t* n_surf, int32_t* bvh_depth,
+                        uint64_t* bytes);
 
 /* RIS (Section II-A, Section III-C): M element centres (x, y, z), the RIS
  * centre u (the point the reflection search starts from, Section II-B), the
@@ -222,7 +238,8 @@ rt_status rt_hits_read(rt_ctx ctx, uint64_t channel, int32_t source, int32_t* hi
 /* Path lists (RT_FLAG_KEEP_PATHS), all in canonical (receiver, sequence key)
  * order, host memory.  Each pointer may be NULL; *_n receive the counts.
  *   env[cap_env]          environment paths;
- *   useq[cap_u * 4]       (rx, s0, s1, s2) sequences valid from the RIS centre;
+ *   useq[cap_u * (1 + RT_MAX_ORDER)]  (rx, s_0 .. s_4, -1 padded) sequences
+ *                         valid from the RIS centre;
  *   ris_valid[cap_slots * M] 1 if the element path of slot s, element m is
  *                         emitted; slots are receiver-major, the first slot
  *                         of a receiver is the direct path and the others
@@ -244,8 +261,10 @@ rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t 
 rt_status rt_ris_paths_read(rt_ctx ctx, uint64_t channel, float* amp, double* length, int64_t cap_cells,
                            int64_t* n_cells);
 
-/* Candidate sequences (surface ids, -1 padded, 3 per row) found for source 0
- * (Tx) or 1 (RIS centre), in key order.  Waits. */
+/* Candidate sequences (surface ids, -1 padded, RT_MAX_ORDER per row) found
+ * for source 0 (Tx) or 1 (RIS centre), in key order (the order of
+ * sum_j (s_j + 1) 2^(21 j) as an integer); cap in int32.  Kept with
+ * RT_FLAG_KEEP_PATHS or RT_FLAG_KEEP_HITS.  Waits. */
 rt_status rt_candidates_read(rt_ctx ctx, uint64_t channel, int32_t source, int32_t* seq, int64_t cap,
                              int64_t* n);
 

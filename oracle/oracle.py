@@ -66,6 +66,25 @@ def build(force: bool = False, fp64_decisions: bool = False) -> str:
     return path
 
 
+_accel = False   # median-split BVH instead of testing every triangle (same results)
+
+
+@contextlib.contextmanager
+def accelerated():
+    """Within the block the oracle's ray tests walk its own median-split BVH
+    (built once per scene) instead of testing every triangle: the same
+    decisions, for scenes too large for brute force."""
+    global _accel
+    old = _accel
+    _accel = True
+    try:
+        yield
+    finally:
+        _accel = old
+        for L in _libs.values():
+            L.or_set_accel(1 if _accel else 0)
+
+
 @contextlib.contextmanager
 def decisions_fp64():
     """Within the block every oracle call takes its ray decisions (closest hit,
@@ -102,7 +121,10 @@ def lib():
         L.or_leg_count.argtypes = []
         L.or_threads.restype = ctypes.c_int
         L.or_threads.argtypes = []
+        L.or_set_accel.restype = None
+        L.or_set_accel.argtypes = [ctypes.c_int]
         _libs[_fp64] = L
+    L.or_set_accel(1 if _accel else 0)
     return L
 
 
@@ -213,21 +235,33 @@ def candidates_from_hits(hits: np.ndarray, K: int) -> np.ndarray:
 
 
 def candidates_from_hits_np(hits: np.ndarray, K: int) -> np.ndarray:
-    """Same set as candidates_from_hits, via numpy.unique (large inputs)."""
+    """Same set as candidates_from_hits, via numpy (large inputs).  The key
+    sum (t_i + 1) 2^(21 i) is held as two 64-bit words (positions 0-2 and
+    3-4) and sorted by the high word, then the low one: the order of the
+    integer key."""
     h = hits.astype(np.int64)
-    keys = [np.zeros(1, np.uint64)]
+    lo = [np.zeros(1, np.uint64)]
+    hi = [np.zeros(1, np.uint64)]
     acc = np.zeros(h.shape[0], np.uint64)
+    acc1 = np.zeros(h.shape[0], np.uint64)
     alive = np.ones(h.shape[0], bool)
     for i in range(K):
         alive &= h[:, i] >= 0
-        acc = acc | (np.where(alive, h[:, i] + 1, 0).astype(np.uint64) << np.uint64(KEY_BITS * i))
-        keys.append(acc[alive])
-    u = np.unique(np.concatenate(keys))
-    out = np.full((u.size, K), -1, np.int32)
+        v = np.where(alive, h[:, i] + 1, 0).astype(np.uint64)
+        if i < 3:
+            acc = acc | (v << np.uint64(KEY_BITS * i))
+        else:
+            acc1 = acc1 | (v << np.uint64(KEY_BITS * (i - 3)))
+        lo.append(acc[alive])
+        hi.append(acc1[alive])
+    pairs = np.stack([np.concatenate(hi), np.concatenate(lo)], axis=1)
+    u = np.unique(pairs, axis=0)   # rows in lexicographic order: high word, then low word
+    out = np.full((u.shape[0], K), -1, np.int32)
     mask = np.uint64((1 << KEY_BITS) - 1)
     for i in range(K):
-        v = ((u >> np.uint64(KEY_BITS * i)) & mask).astype(np.int64)
-        prev = out[:, i - 1] >= 0 if i > 0 else np.ones(u.size, bool)
+        w = u[:, 1] if i < 3 else u[:, 0]
+        v = ((w >> np.uint64(KEY_BITS * (i if i < 3 else i - 3))) & mask).astype(np.int64)
+        prev = out[:, i - 1] >= 0 if i > 0 else np.ones(u.shape[0], bool)
         out[:, i] = np.where((v > 0) & prev, v - 1, -1)
     return out
 
@@ -549,7 +583,8 @@ def ris_amplitudes(prob, rx_idx, m_idx, tris, pts):
 # --------------------------------------------------------------------------
 # the whole path
 # --------------------------------------------------------------------------
-def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = False) -> Dict[str, np.ndarray]:
+def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = False,
+          hits=None) -> Dict[str, np.ndarray]:
     """Channel of one problem.
 
     mode = "sbr": candidate surface sequences from spherical-Fibonacci
@@ -561,6 +596,9 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = 
     ris_in: the field reaching each element also by reflections Tx ->
     surfaces -> m (``ris_incoming``; sequences of the Tx candidates valid at
     the RIS centre); otherwise by the direct leg alone.
+    hits: (Tx hit lists, RIS-centre hit lists) of an earlier ``discover`` of
+    the oracle with the same scene, sources and n_rays, reused instead of
+    tracing the discovery rays again (large scenes).
     """
     K = prob.order
     sc = prob.scene
@@ -569,12 +607,19 @@ def trace(prob, mode: str = "sbr", n_rays: Optional[int] = None, ris_in: bool = 
     out: Dict[str, np.ndarray] = {}
     segs = 0
     if mode == "sbr":
-        h_tx, _, s1 = discover(sc, prob.tx_pos, n, K)
+        if hits is not None:
+            h_tx, s1 = hits[0], 0
+        else:
+            h_tx, _, s1 = discover(sc, prob.tx_pos, n, K)
         out["hits_tx"] = h_tx
         c_tx = candidates_from_hits_np(surface_hits(sc, h_tx), K)
         segs += s1
         if prob.ris is not None:
-            h_u, launched_u, s2 = discover(sc, prob.ris.centre, n, K, hemi_normal=prob.ris.normal)
+            if hits is not None:
+                h_u, s2 = hits[1], 0
+                launched_u = (h_u >= 0).any(axis=1)
+            else:
+                h_u, launched_u, s2 = discover(sc, prob.ris.centre, n, K, hemi_normal=prob.ris.normal)
             out["hits_u"] = h_u
             out["launched_u"] = launched_u
             c_u = candidates_from_hits_np(surface_hits(sc, h_u), K)

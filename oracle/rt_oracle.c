@@ -154,6 +154,245 @@ static tri32* build_tris(const float* V, const int32_t* T, int64_t nt)
 }
 
 /* ----------------------------------------------------------------------- */
+/* Optional acceleration for large scenes: a median-split BVH               */
+/* ----------------------------------------------------------------------- */
+/* A binary tree of its own (split at the median centroid along the longest
+ * axis of the centroid bounds, up to 4 triangles per leaf; unlike the
+ * library's Morton-ordered LBVH), with FP64 boxes grown by 1e-4 m + 1e-5 |x|
+ * so that no triangle the FP32 test would hit is ever pruned.  Closest hit
+ * keeps the lowest (t, index) and any-hit stops at a hit: the results are
+ * those of the brute-force loops, in any traversal order.  Switched on with
+ * or_set_accel(1); built once per scene (recognised by a hash of its
+ * triangles) before the parallel loops that use it. */
+typedef struct {
+    double lo[3], hi[3];
+    int64_t left, right; /* children (internal node) */
+    int64_t first, count; /* triangle range in g_idx (leaf: count > 0) */
+} bvh_node;
+
+static int g_accel = 0;
+static bvh_node* g_nodes = NULL;
+static int64_t* g_idx = NULL;
+static int64_t g_nt = -1;
+static uint64_t g_hash = 0;
+
+void or_set_accel(int on) { g_accel = on; }
+
+static uint64_t tris_hash(const tri32* tris, int64_t nt)
+{
+    uint64_t h = 1469598103934665603ull; /* FNV-1a over the triangles' bytes */
+    const unsigned char* p = (const unsigned char*)tris;
+    size_t nb = sizeof(tri32) * (size_t)nt;
+    for (size_t i = 0; i < nb; ++i) {
+        h ^= p[i];
+        h *= 1099511628211ull;
+    }
+    return h;
+}
+
+static double* g_cent = NULL; /* centroids while building */
+static int g_axis = 0;
+static int cmp_cent(const void* a, const void* b)
+{
+    double ca = g_cent[3 * *(const int64_t*)a + g_axis], cb = g_cent[3 * *(const int64_t*)b + g_axis];
+    if (ca < cb) return -1;
+    if (ca > cb) return 1;
+    int64_t ia = *(const int64_t*)a, ib = *(const int64_t*)b;
+    return (ia > ib) - (ia < ib);
+}
+
+static void tri_bounds(const tri32* t, double lo[3], double hi[3])
+{
+    for (int k = 0; k < 3; ++k) {
+        double a = (double)t->v0[k], b = a + (double)t->e1[k], c = a + (double)t->e2[k];
+        lo[k] = fmin(a, fmin(b, c));
+        hi[k] = fmax(a, fmax(b, c));
+    }
+}
+
+static void bvh_build(const tri32* tris, int64_t nt)
+{
+    uint64_t h = tris_hash(tris, nt);
+    if (g_nodes && g_nt == nt && g_hash == h) return;
+    free(g_nodes);
+    free(g_idx);
+    g_nodes = (bvh_node*)malloc(sizeof(bvh_node) * (size_t)(2 * nt + 1));
+    g_idx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(nt > 0 ? nt : 1));
+    g_cent = (double*)malloc(sizeof(double) * 3 * (size_t)(nt > 0 ? nt : 1));
+    for (int64_t i = 0; i < nt; ++i) {
+        double lo[3], hi[3];
+        tri_bounds(&tris[i], lo, hi);
+        for (int k = 0; k < 3; ++k) g_cent[3 * i + k] = 0.5 * (lo[k] + hi[k]);
+        g_idx[i] = i;
+    }
+    int64_t n_nodes = 1;
+    int64_t* stack = (int64_t*)malloc(sizeof(int64_t) * 256);
+    int sp = 0;
+    g_nodes[0].first = 0;
+    g_nodes[0].count = nt;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        int64_t ni = stack[--sp];
+        bvh_node* nd = &g_nodes[ni];
+        int64_t f = nd->first, c = nd->count;
+        double clo[3] = {INFINITY, INFINITY, INFINITY}, chi[3] = {-INFINITY, -INFINITY, -INFINITY};
+        for (int k = 0; k < 3; ++k) {
+            nd->lo[k] = INFINITY;
+            nd->hi[k] = -INFINITY;
+        }
+        for (int64_t j = f; j < f + c; ++j) {
+            double lo[3], hi[3];
+            tri_bounds(&tris[g_idx[j]], lo, hi);
+            for (int k = 0; k < 3; ++k) {
+                nd->lo[k] = fmin(nd->lo[k], lo[k]);
+                nd->hi[k] = fmax(nd->hi[k], hi[k]);
+                clo[k] = fmin(clo[k], g_cent[3 * g_idx[j] + k]);
+                chi[k] = fmax(chi[k], g_cent[3 * g_idx[j] + k]);
+            }
+        }
+        for (int k = 0; k < 3; ++k) {
+            double m = 1e-4 + 1e-5 * fmax(fabs(nd->lo[k]), fabs(nd->hi[k]));
+            nd->lo[k] -= m;
+            nd->hi[k] += m;
+        }
+        if (c <= 4) {
+            nd->left = nd->right = -1;
+            continue;
+        }
+        int ax = 0;
+        for (int k = 1; k < 3; ++k)
+            if (chi[k] - clo[k] > chi[ax] - clo[ax]) ax = k;
+        g_axis = ax;
+        qsort(g_idx + f, (size_t)c, sizeof(int64_t), cmp_cent);
+        int64_t half = c / 2;
+        int64_t l = n_nodes++, r = n_nodes++;
+        nd = &g_nodes[ni];
+        nd->left = l;
+        nd->right = r;
+        g_nodes[l].first = f;
+        g_nodes[l].count = half;
+        g_nodes[r].first = f + half;
+        g_nodes[r].count = c - half;
+        nd->count = 0;
+        if (sp + 2 > 256) abort(); /* depth of a median split stays near log2(n) */
+        stack[sp++] = l;
+        stack[sp++] = r;
+    }
+    free(stack);
+    free(g_cent);
+    g_cent = NULL;
+    g_nt = nt;
+    g_hash = h;
+}
+
+/* entry distance of the ray into the node's box, or -1 if it misses it in [0, tmax] */
+static double box_entry(const bvh_node* nd, const double o[3], const double inv[3], double tmax)
+{
+    double t0 = 0.0, t1 = tmax;
+    for (int k = 0; k < 3; ++k) {
+        double a = (nd->lo[k] - o[k]) * inv[k], b = (nd->hi[k] - o[k]) * inv[k];
+        if (a > b) {
+            double x = a;
+            a = b;
+            b = x;
+        }
+        if (a != a) a = -INFINITY; /* 0 * inf: the ray runs inside the slab's plane */
+        if (b != b) b = INFINITY;
+        t0 = fmax(t0, a);
+        t1 = fmin(t1, b);
+    }
+    return t0 <= t1 ? t0 : -1.0;
+}
+
+/* Closest hit with the BVH; same result as closest32. */
+static int64_t closest_bvh(const tri32* tris, const rfloat o[3], const rfloat d[3], rfloat tmin, int64_t skip,
+                           rfloat* t_best)
+{
+    int64_t best = -1;
+    rfloat bt = INFINITY;
+    double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
+    double inv[3];
+    double dn = sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) inv[k] = 1.0 / (double)d[k];
+    int64_t stack[256];
+    double entry[256];
+    int sp = 0;
+    stack[sp] = 0;
+    entry[sp++] = box_entry(&g_nodes[0], od, inv, INFINITY);
+    while (sp > 0) {
+        --sp;
+        const bvh_node* nd = &g_nodes[stack[sp]];
+        /* boxes entered beyond the best hit so far (plus a slack far above the rounding) hold no closer one */
+        double lim = bt < INFINITY ? (double)bt + 1e-3 / (dn > 0 ? dn : 1.0) : INFINITY;
+        if (entry[sp] < 0.0 || entry[sp] > lim) continue;
+        if (nd->count > 0) {
+            for (int64_t j = nd->first; j < nd->first + nd->count; ++j) {
+                int64_t i = g_idx[j];
+                if (i == skip) continue;
+                rfloat t;
+                if (hit32(o, d, &tris[i], tmin, INFINITY, &t))
+                    if (t < bt || (t == bt && i < best)) {
+                        bt = t;
+                        best = i;
+                    }
+            }
+        } else {
+            /* the nearer child is popped first */
+            double el = box_entry(&g_nodes[nd->left], od, inv, lim), er = box_entry(&g_nodes[nd->right], od, inv, lim);
+            int64_t nl = nd->left, nr = nd->right;
+            if (el >= 0.0 && er >= 0.0 && er < el) {
+                double x = el;
+                el = er;
+                er = x;
+                int64_t y = nl;
+                nl = nr;
+                nr = y;
+            }
+            if (er >= 0.0) {
+                stack[sp] = nr;
+                entry[sp++] = er;
+            }
+            if (el >= 0.0) {
+                stack[sp] = nl;
+                entry[sp++] = el;
+            }
+        }
+    }
+    *t_best = bt;
+    return best;
+}
+
+/* Any hit with the BVH, skipping two surfaces; same result as the brute loop. */
+static int any_bvh(const tri32* tris, const int32_t* surf, const rfloat o[3], const rfloat d[3], rfloat tmin,
+                   rfloat tmax, int64_t skip_a, int64_t skip_b)
+{
+    double od[3] = {(double)o[0], (double)o[1], (double)o[2]};
+    double inv[3];
+    double dn = sqrt((double)d[0] * d[0] + (double)d[1] * d[1] + (double)d[2] * d[2]);
+    for (int k = 0; k < 3; ++k) inv[k] = 1.0 / (double)d[k];
+    double lim = (double)tmax + 1e-3 / (dn > 0 ? dn : 1.0);
+    int64_t stack[256];
+    int sp = 0;
+    stack[sp++] = 0;
+    while (sp > 0) {
+        const bvh_node* nd = &g_nodes[stack[--sp]];
+        if (box_entry(nd, od, inv, lim) < 0.0) continue;
+        if (nd->count > 0) {
+            for (int64_t j = nd->first; j < nd->first + nd->count; ++j) {
+                int64_t i = g_idx[j];
+                if (surf[i] == skip_a || surf[i] == skip_b) continue;
+                rfloat t;
+                if (hit32(o, d, &tris[i], tmin, tmax, &t)) return 1;
+            }
+        } else {
+            stack[sp++] = nd->left;
+            stack[sp++] = nd->right;
+        }
+    }
+    return 0;
+}
+
+/* ----------------------------------------------------------------------- */
 /* Discovery                                                                */
 /* ----------------------------------------------------------------------- */
 /* Spherical Fibonacci point i of n (FP64):
@@ -184,6 +423,8 @@ int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double s
                     const double hemi_n[3], int64_t n, int K, int32_t* hits, uint8_t* launched)
 {
     tri32* tris = build_tris(V, T, nt);
+    const int accel = g_accel && nt > 0;
+    if (accel) bvh_build(tris, nt);
     int64_t rows = hemi ? 2 * n : n;
     int64_t segs = 0;
 #pragma omp parallel for schedule(dynamic, 256) reduction(+ : segs)
@@ -201,7 +442,8 @@ int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double s
         for (int b = 0; b < K; ++b) {
             rfloat t;
             segs += 1;
-            int64_t h = closest32(tris, nt, o, d, (rfloat)OR_EPS, skip, &t);
+            int64_t h = accel ? closest_bvh(tris, o, d, (rfloat)OR_EPS, skip, &t)
+                              : closest32(tris, nt, o, d, (rfloat)OR_EPS, skip, &t);
             if (h < 0) break;
             hits[i * K + b] = (int32_t)h;
             rfloat p[3] = {o[0] + t * d[0], o[1] + t * d[1], o[2] + t * d[2]};
@@ -235,6 +477,7 @@ static int leg_blocked(const tri32* tris, const int32_t* surf, int64_t nt, const
 #pragma omp atomic
     g_leg_count += 1;
     if (!(tmax > tmin)) return 0;
+    if (g_accel && nt > 0) return any_bvh(tris, surf, o, d, tmin, tmax, skip_a, skip_b);
     for (int64_t i = 0; i < nt; ++i) {
         if (surf[i] == skip_a || surf[i] == skip_b) continue;
         rfloat t;
@@ -247,6 +490,7 @@ int or_leg_blocked(const float* V, const int32_t* T, const int32_t* surf, int64_
                    const double A[3], const double B[3], int64_t skip_a, int64_t skip_b)
 {
     tri32* tris = build_tris(V, T, nt);
+    if (g_accel && nt > 0) bvh_build(tris, nt);
     int r = leg_blocked(tris, surf, nt, A, B, skip_a, skip_b);
     free(tris);
     return r;
@@ -464,6 +708,7 @@ int64_t or_find_paths(const float* V, const int32_t* T, const int32_t* surf, int
                       int32_t* out_tri)
 {
     tri32* t32 = build_tris(V, T, nt);
+    if (g_accel && nt > 0) bvh_build(t32, nt);
     tri64* t64 = (tri64*)malloc(sizeof(tri64) * (size_t)(nt > 0 ? nt : 1));
     for (int64_t i = 0; i < nt; ++i) make_tri64(V, T, i, &t64[i]);
     surf_table st;
@@ -535,6 +780,7 @@ void or_ris_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t
                   int32_t* tri, uint8_t* txm_clear, const uint8_t* lit)
 {
     tri32* t32 = build_tris(V, T, nt);
+    if (g_accel && nt > 0) bvh_build(t32, nt);
     tri64* t64 = (tri64*)malloc(sizeof(tri64) * (size_t)(nt > 0 ? nt : 1));
     for (int64_t i = 0; i < nt; ++i) make_tri64(V, T, i, &t64[i]);
     surf_table st;

@@ -95,15 +95,21 @@ __global__ void k_scene_prep(const float* V, const int32_t* T, const int32_t* su
     }
 }
 
-__device__ __forceinline__ uint32_t expand10(uint32_t v)
+// spread the low 21 bits of v to every third bit of 63 (bit i -> bit 3 i)
+__device__ __forceinline__ uint64_t expand21(uint64_t v)
 {
-    v = (v * 0x00010001u) & 0xFF0000FFu;
-    v = (v * 0x00000101u) & 0x0F00F00Fu;
-    v = (v * 0x00000011u) & 0xC30C30C3u;
-    v = (v * 0x00000005u) & 0x49249249u;
+    v &= 0x1fffffull;
+    v = (v | v << 32) & 0x1f00000000ffffull;
+    v = (v | v << 16) & 0x1f0000ff0000ffull;
+    v = (v | v << 8) & 0x100f00f00f00f00full;
+    v = (v | v << 4) & 0x10c30c30c30c30c3ull;
+    v = (v | v << 2) & 0x1249249249249249ull;
     return v;
 }
 
+// Two-word sort keys: word 0 the triangle index, word 1 the 63-bit Morton code
+// of the centroid (21 bits per axis over the scene bounds); sorted on word 1,
+// stably, so equal codes stay in index order (the tie-break of the unique keys).
 __global__ void k_morton(const float4* cent, const unsigned* bounds, int64_t nt, uint64_t* keys)
 {
     int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -116,14 +122,14 @@ __global__ void k_morton(const float4* cent, const unsigned* bounds, int64_t nt,
     }
     float4 c = cent[t];
     float cc[3] = {c.x, c.y, c.z};
-    uint32_t q[3];
+    uint64_t q[3];
     for (int k = 0; k < 3; ++k) {
         float u = ext[k] > 0.0f ? (cc[k] - lo[k]) / ext[k] : 0.5f;
         u = fminf(fmaxf(u, 0.0f), 1.0f);
-        q[k] = (uint32_t)fminf(u * 1024.0f, 1023.0f);
+        q[k] = (uint64_t)fminf(u * 2097152.0f, 2097151.0f);
     }
-    uint32_t m = (expand10(q[0]) << 2) | (expand10(q[1]) << 1) | expand10(q[2]);
-    keys[t] = ((uint64_t)m << 32) | (uint64_t)t;
+    keys[2 * t] = (uint64_t)t;
+    keys[2 * t + 1] = (expand21(q[0]) << 2) | (expand21(q[1]) << 1) | expand21(q[2]);
 }
 
 struct Box6 {
@@ -142,7 +148,7 @@ __global__ void k_leaves(const uint64_t* keys, const float* V, const int32_t* T,
     float ext = 0.0f;
     for (int k = 0; k < 3; ++k) ext = fmaxf(ext, ord2f(bounds[9 + k]) - ord2f(bounds[6 + k]));
     const float pad = 1e-5f * ext + 1e-6f;
-    int32_t t = (int32_t)(keys[i] & 0xffffffffu);
+    int32_t t = (int32_t)keys[2 * i];   // word 0 of the sorted key: the triangle index
     const float* a = V + 3 * clamp_index(T[3 * t + 0], nv);
     const float* b = V + 3 * clamp_index(T[3 * t + 1], nv);
     const float* c = V + 3 * clamp_index(T[3 * t + 2], nv);
@@ -165,7 +171,7 @@ __global__ void k_karras(const uint64_t* keys, int64_t n, int32_t* child, int32_
     if (i >= n - 1) return;
     if (i == 0) parent_int[0] = -1;   // the root; every other node and every leaf gets its parent below
     int32_t cl, cr;
-    lbvh_node(keys, n, i, &cl, &cr);
+    lbvh_node<2>(keys, n, i, &cl, &cr);
     if (cl < 0) parent_leaf[~cl] = (int32_t)i;
     else parent_int[cl] = (int32_t)i;
     if (cr < 0) parent_leaf[~cr] = (int32_t)i;
@@ -528,7 +534,7 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
         s.root = 0;
         return;
     }
-    if (nt >= (int64_t)1 << 30) throw inval_error("too many triangles");
+    if (nt >= (int64_t)1 << 29) throw inval_error("too many triangles (at most 2^29 - 1)");
     // inputs in device memory are read in place (the build is complete before the call returns);
     // host arrays are staged
     Scratch stage_buf[5];
@@ -565,11 +571,11 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
                        s.v64.as<double>(), s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad,
                        s.t_proj.as<double>(), s.t_axes.as<int32_t>());
     HIP_CHECK(hipGetLastError());
-    Scratch keys_raw(c, sizeof(uint64_t) * (size_t)nt, st), keys(c, sizeof(uint64_t) * (size_t)nt, st);
+    Scratch keys_raw(c, 2 * sizeof(uint64_t) * (size_t)nt, st), keys(c, 2 * sizeof(uint64_t) * (size_t)nt, st);
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, B)), dim3(B), 0, st, cent.as<float4>(), bounds, nt,
                        keys_raw.as<uint64_t>());
     HIP_CHECK(hipGetLastError());
-    sort_u64_into(c, keys_raw.as<uint64_t>(), keys.as<uint64_t>(), nt, 62, st);
+    sort_keys(c, keys_raw.as<uint64_t>(), keys.as<uint64_t>(), nt, 2, 64, 127, st);
     Scratch lbox(c, sizeof(float) * 6 * (size_t)nt, st);
     hipLaunchKernelGGL(k_leaves, dim3(blocks_for(nt, B)), dim3(B), 0, st, keys.as<uint64_t>(), dV, dT,
                        s.surf.as<int32_t>(), nv, nt, bounds, s.tri4.as<float4>(), lbox.as<float>());

@@ -481,6 +481,28 @@ rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const
     });
 }
 
+rt_status rt_scene_info(rt_ctx ctx, uint64_t scene, int64_t* n_tri, int64_t* n_surf, int32_t* bvh_depth,
+                        uint64_t* bytes)
+{
+    return guarded(ctx, [&]() -> rt_status {
+        auto o = find(ctx, scene, 1);
+        if (!o) return fail(RT_ENOTFOUND, "unknown scene handle");
+        const Scene& sc = *o->scene;
+        if (n_tri) *n_tri = sc.n_tri;
+        if (n_surf) *n_surf = sc.n_surf;
+        if (bvh_depth) *bvh_depth = sc.max_depth;
+        if (bytes) {
+            uint64_t b = 0;
+            for (const Scratch* p : {&sc.tri4, &sc.nodes, &sc.node4, &sc.v64, &sc.refl, &sc.surf, &sc.s_ptr,
+                                     &sc.s_tris, &sc.s_plane, &sc.s_box, &sc.t_proj, &sc.t_axes, &sc.g_axes,
+                                     &sc.g_frame, &sc.g_cnt, &sc.g_tris, &sc.mat, &sc.nrm})
+                b += p->bytes;
+            *bytes = b;
+        }
+        return RT_OK;
+    });
+}
+
 rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r, const float* sigma, void* stream)
 {
     return guarded(ctx, [&]() -> rt_status {
@@ -567,7 +589,7 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         if ((params->flags & 192u) && (params->flags & 16u))
             return fail(RT_EINVAL, "the counting build has no Fresnel variant");
         if (params->max_order < 0 || params->max_order > RT_MAX_K)
-            return fail(RT_EUNSUPPORTED, "max_order must be 0..3");
+            return fail(RT_EUNSUPPORTED, "max_order must be 0.." + std::to_string(RT_MAX_K));
         if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
         if (R > ((int64_t)1 << 31) - 1) return fail(RT_EUNSUPPORTED, "too many receivers");
         for (int32_t p : {tx->pattern, rx->pattern})
@@ -635,6 +657,8 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
             stats->leg_walk_fallbacks = out.leg_walk_fallbacks;
             stats->n_in_seq = out.n_in_seq;
             stats->n_in_paths = out.n_in_paths;
+            for (int q = 0; q < 6; ++q) stats->discovery_work[q] = out.disc_work[q];
+            for (int q = 0; q < 3; ++q) stats->ms_discovery[q] = out.ms_disc[q];
         }
         *channel = insert(ctx, o);
         return RT_OK;
@@ -737,11 +761,15 @@ rt_status rt_paths_read(rt_ctx ctx, uint64_t channel, rt_env_path* env, int64_t 
             if (cap_u < ch.n_u) return fail(RT_EINVAL, "capacity too small");
             if (ch.n_u) {
                 if (!ch.useq.p) return fail(RT_EINVAL, "paths not kept");
-                // internal rows: rx, s0..s2, t0..t2, 0
-                std::vector<int32_t> rows((size_t)(8 * ch.n_u));
+                // internal rows: rx, s_0..s_{KM-1}, triangles, 0; out: rx, s_0..s_4 (-1 padded)
+                const int us = ch.useq_stride, km = (us - 2) / 2;
+                std::vector<int32_t> rows((size_t)(us * ch.n_u));
                 HIP_CHECK(hipMemcpy(rows.data(), ch.useq.p, sizeof(int32_t) * rows.size(), hipMemcpyDefault));
-                for (int64_t i = 0; i < ch.n_u; ++i)
-                    for (int j = 0; j < 4; ++j) useq[4 * i + j] = rows[8 * i + j];
+                for (int64_t i = 0; i < ch.n_u; ++i) {
+                    useq[(1 + RT_MAX_K) * i] = rows[us * i];
+                    for (int j = 0; j < RT_MAX_K; ++j)
+                        useq[(1 + RT_MAX_K) * i + 1 + j] = j < km ? rows[us * i + 1 + j] : -1;
+                }
             }
         }
         if (ris_valid) {
@@ -786,14 +814,17 @@ rt_status rt_candidates_read(rt_ctx ctx, uint64_t channel, int32_t source, int32
         if (n) *n = nc;
         if (seq) {
             if (!ch.cand_keys[source].p && nc > 0) return fail(RT_EINVAL, "candidates not kept");
-            if (cap < 3 * nc) return fail(RT_EINVAL, "capacity too small");
-            std::vector<uint64_t> keys((size_t)nc);
-            if (nc) HIP_CHECK(hipMemcpy(keys.data(), ch.cand_keys[source].p, sizeof(uint64_t) * (size_t)nc, hipMemcpyDefault));
+            if (cap < RT_MAX_K * nc) return fail(RT_EINVAL, "capacity too small");
+            const int w = ch.key_words;
+            std::vector<uint64_t> keys((size_t)(w * nc));
+            if (nc) HIP_CHECK(hipMemcpy(keys.data(), ch.cand_keys[source].p, sizeof(uint64_t) * keys.size(), hipMemcpyDefault));
             for (int64_t i = 0; i < nc; ++i)
-                for (int j = 0; j < 3; ++j) {
-                    uint64_t v = (keys[i] >> (RT_KEY_BITS * j)) & ((1ull << RT_KEY_BITS) - 1);
-                    bool alive = v != 0 && (j == 0 || seq[3 * i + j - 1] >= 0);
-                    seq[3 * i + j] = alive ? (int32_t)v - 1 : -1;
+                for (int j = 0; j < RT_MAX_K; ++j) {
+                    // surfaces 0-2 in word 0, 3-4 in word 1 (two-word keys), 21 bits each
+                    const uint64_t word = j < 3 ? keys[w * i] : (w == 2 ? keys[w * i + 1] : 0ull);
+                    const uint64_t v = (word >> (RT_KEY_BITS * (j < 3 ? j : j - 3))) & ((1ull << RT_KEY_BITS) - 1);
+                    const bool alive = v != 0 && (j == 0 || seq[RT_MAX_K * i + j - 1] >= 0);
+                    seq[RT_MAX_K * i + j] = alive ? (int32_t)v - 1 : -1;
                 }
         }
         return RT_OK;

@@ -176,11 +176,13 @@ struct Channel {
     int64_t n_hits_rows[2] = {0, 0};
     Scratch hits[2];    // int32 [rows * K]
     int64_t n_cand[2] = {0, 0};
-    Scratch cand_keys[2];  // uint64 [n_cand]
+    Scratch cand_keys[2];  // uint64 [n_cand * key_words]
     int64_t n_env = 0;
     Scratch env;        // rt_env_path-like records (device EnvRec)
     int64_t n_u = 0;
-    Scratch useq;       // int32 [n_u * 4]  (rx, s0, s1, s2)
+    Scratch useq;       // int32 rows of useq_stride: rx, surfaces s_0..s_{KM-1}, triangles, 0
+    int useq_stride = 8;
+    int key_words = 1;  // 64-bit words per candidate key (2 for orders 4 and 5)
     int64_t n_slots = 0;
     Scratch ris_valid;  // uint8 [n_slots * M]
     // kept for the impulse response (RT_FLAG_KEEP_CIR): environment cells of
@@ -206,8 +208,8 @@ struct Channel {
 struct EnvRec {
     int32_t rx;
     int32_t order;
-    int32_t seq[3];
-    int32_t tri[3];
+    int32_t seq[RT_MAX_K];
+    int32_t tri[RT_MAX_K];
     double length;
     float amp[2];
 };
@@ -251,6 +253,8 @@ struct TraceOut {
     int64_t work[5] = {0, 0, 0, 0, 0};
     int64_t leg_walk_fallbacks = 0;
     int64_t n_in_seq = 0, n_in_paths = 0;
+    int64_t disc_work[6] = {0, 0, 0, 0, 0, 0};
+    float ms_disc[3] = {0.0f, 0.0f, 0.0f};
 };
 void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st);
 // impulse response of one configuration from a channel traced with RT_FLAG_KEEP_CIR

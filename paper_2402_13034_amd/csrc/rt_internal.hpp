@@ -15,7 +15,8 @@
 #include <stdexcept>
 #include <string>
 
-#define RT_MAX_K 3
+#define RT_MAX_K 5            // largest reflection order (keys of two 64-bit words above 3)
+#define RT_KM_SMALL 3        // orders up to this use one-word keys and the smaller kernel instances
 #define RT_STACK 64          // BVH traversal stack entries per lane (LDS)
 #define RT_EPS 1e-4          // metres: legs and bounces ignore hits closer than this
 #define RT_KEY_BITS 21
@@ -196,10 +197,11 @@ __device__ __forceinline__ bool slab(const RayBox& r, float4 lo, float4 hi, floa
 // Closest hit: lowest (t, triangle id) among triangles other than skip_tri
 // with tmin < t < tmax.  Returns the leaf slot or -1.  `stack` points at this
 // lane's column of an LDS array laid out [RT_STACK][stride].
-template <bool BRUTE>
+// CNT: count the binary nodes visited and the triangles tested in *wc.
+template <bool BRUTE, bool CNT = false>
 __device__ int closest_hit(const SceneView& s, float ox, float oy, float oz, float dx, float dy,
                            float dz, float tmin, int skip_tri, int* stack, int stride, float& t_best,
-                           int& id_best)
+                           int& id_best, WorkCount* wc = nullptr)
 {
     t_best = __builtin_inff();
     id_best = 0x7fffffff;
@@ -226,6 +228,7 @@ __device__ int closest_hit(const SceneView& s, float ox, float oy, float oz, flo
     int node = s.root;
     while (true) {
         if (node >= 0) {
+            if (CNT) wc->nodes++;
             const float4* nd = s.nodes + 4 * node;
             float4 n0 = nd[0], n1 = nd[1], n2 = nd[2], n3 = nd[3];
             float tl, tr;
@@ -248,6 +251,7 @@ __device__ int closest_hit(const SceneView& s, float ox, float oy, float oz, flo
             }
         } else {
             int i = ~node;
+            if (CNT) wc->tris++;
             float4 a = s.tri4[3 * i], b = s.tri4[3 * i + 1], c = s.tri4[3 * i + 2];
             int id = __float_as_int(a.w);
             float t;
@@ -640,8 +644,8 @@ __device__ __forceinline__ float wave_max(float v)
 }
 
 // All legs of one slot at once: one tube per leg, frontier and candidate
-// entries tagged with their leg (2 bits), so the wave walks the levels of
-// the tree once for up to RT_MAX_K + 1 legs.
+// entries tagged with their leg (3 bits above a 29-bit node or slot index),
+// so the wave walks the levels of the tree once for up to KM + 1 legs.
 // lb: the wave's leg rays in LDS, [leg][7][64] = ox, oy, oz, dx, dy, dz, tmax;
 // tube: 8 floats per leg in LDS; front: 2 x RT_TUBE_FRONT ints, cand:
 // RT_TUBE_CAND ints, wstack: RT_STACK4 ints (fallback), all per wave;
@@ -650,18 +654,46 @@ __device__ __forceinline__ float wave_max(float v)
 // RT_TUBE_FELL_BACK if the lists overflowed and the legs were walked one by
 // one.
 #define RT_TUBE_FELL_BACK 256u
+#define RT_TUBE_TAG_SHIFT 29
+#define RT_TUBE_IDX_MASK 0x1fffffffu
+// a frontier or candidate entry: node or leaf slot index (< 2^29) and leg j (3 bits), as int
+__device__ __forceinline__ int tube_entry(int idx, int j)
+{
+    return (int)((unsigned)idx | ((unsigned)j << RT_TUBE_TAG_SHIFT));
+}
+// surface at the start (a) or end (b) of leg j of a slot of order k (-1: a
+// source or receiver), selected by value (j differs between lanes)
+template <int KM>
+__device__ __forceinline__ int leg_surface_a(const int* seq, int j)
+{
+    int v = -1;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) v = (j == q + 1) ? seq[q] : v;
+    return v;
+}
+template <int KM>
+__device__ __forceinline__ int leg_surface_b(const int* seq, int j, int k)
+{
+    int v = -1;
+#pragma unroll
+    for (int q = 0; q < KM; ++q) v = (j == q && j != k) ? seq[q] : v;
+    return v;
+}
+
+template <int KM>
 __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool ok, int k, const int* seq,
                                                       const float* lb, float* tube, int* front, int* cand,
                                                       int* wstack)
 {
-    static_assert(RT_MAX_K + 1 <= 4, "two bits of leg index");
+    static_assert(KM + 1 <= 8, "three bits of leg index");
     const int lane = threadIdx.x & 63;
     const float tmin = (float)RT_EPS;
     unsigned blocked = 0;
     if (s.n_tri == 0 || __ballot(ok) == 0ull) return 0;
+    const unsigned exact = 1u << 16;   // a tube radius not representable: exact walk
     unsigned live = 0;   // legs with a searching lane (uniform)
 #pragma unroll
-    for (int j = 0; j <= RT_MAX_K; ++j) {
+    for (int j = 0; j <= KM; ++j) {
         if (j > k) break;
         const float* r0 = lb + j * 7 * 64 + lane;
         const float ox = r0[0], oy = r0[64], oz = r0[128], dx = r0[192], dy = r0[256], dz = r0[320], tmax = r0[384];
@@ -699,7 +731,7 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
             crb.oiy = cay * crb.iy;
             crb.oiz = caz * crb.iz;
         }
-        if (!(r < 1e30f)) live |= 16u;   // not representable: exact walk below
+        if (!(r < 1e30f)) live |= exact;   // not representable: exact walk below
         if (lane == 0) {
             float* t = tube + 8 * j;
             t[0] = crb.ix;
@@ -713,19 +745,19 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
     }
     if (live == 0) return 0;
     int nc = 0;
-    bool overflow = (live & 16u) != 0;
+    bool overflow = (live & exact) != 0;
     if (!overflow) {
         if (s.root < 0) {
             for (int j = 0; j <= k; ++j)
                 if (live & (1u << j)) {
-                    if (lane == 0) cand[nc] = (~s.root) | (j << 30);
+                    if (lane == 0) cand[nc] = tube_entry(~s.root, j);
                     ++nc;
                 }
         } else {
             int nf = 0, cur = 0;
             for (int j = 0; j <= k; ++j)
                 if (live & (1u << j)) {
-                    if (lane == 0) front[nf] = s.root | (j << 30);
+                    if (lane == 0) front[nf] = tube_entry(s.root, j);
                     ++nf;
                 }
             while (nf > 0) {
@@ -736,7 +768,7 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
                     const int slot = base + (lane >> 2), e = lane & 3;
                     const bool valid = slot < nf;
                     const unsigned v = valid ? (unsigned)fin[slot] : 0u;
-                    const int n = (int)(v & 0x3fffffffu), j = (int)(v >> 30);
+                    const int n = (int)(v & RT_TUBE_IDX_MASK), j = (int)(v >> RT_TUBE_TAG_SHIFT);
                     const float* t = tube + 8 * j;
                     RayBox crb;
                     crb.ix = t[0];
@@ -750,8 +782,8 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
                     const int ref = __float_as_int(q[24 + e]);
                     // a leaf of one of the leg's end-point surfaces is never a candidate of that leg
                     const int lsf = __float_as_int(q[28 + e]);
-                    const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
-                    const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
+                    const int sa = leg_surface_a<KM>(seq, j);
+                    const int sb = leg_surface_b<KM>(seq, j, k);
                     const bool skip = lsf >= 0 && (lsf == sa || lsf == sb);
                     const bool hit = valid && ref != RT_NODE4_EMPTY && !skip &&
                                      slab1(q[e] - r, q[4 + e] + r, q[8 + e] - r, q[12 + e] + r, q[16 + e] - r,
@@ -761,11 +793,11 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
                     const unsigned long long ml = __ballot(hit && ref < 0);
                     if (hit && ref >= 0) {
                         const int idx = nn + __popcll(mi & lt);
-                        if (idx < RT_TUBE_FRONT) fout[idx] = ref | (j << 30);
+                        if (idx < RT_TUBE_FRONT) fout[idx] = tube_entry(ref, j);
                     }
                     if (hit && ref < 0) {
                         const int idx = nc + __popcll(ml & lt);
-                        if (idx < RT_TUBE_CAND) cand[idx] = (~ref) | (j << 30);
+                        if (idx < RT_TUBE_CAND) cand[idx] = tube_entry(~ref, j);
                     }
                     nn += __popcll(mi);
                     nc += __popcll(ml);
@@ -795,7 +827,7 @@ __device__ __forceinline__ unsigned legs_blocked_tube(const SceneView& s, bool o
     }
     for (int i = 0; i < nc; ++i) {
         const unsigned v = (unsigned)__builtin_amdgcn_readfirstlane(cand[i]);
-        const int slot = (int)(v & 0x3fffffffu), j = (int)(v >> 30);
+        const int slot = (int)(v & RT_TUBE_IDX_MASK), j = (int)(v >> RT_TUBE_TAG_SHIFT);
         const float4 a = s.tri4[3 * slot], b = s.tri4[3 * slot + 1], c = s.tri4[3 * slot + 2];
         const int sf = __float_as_int(b.w);
         const int sa = j == 0 ? -1 : seq[j - 1];
@@ -942,14 +974,16 @@ __device__ __forceinline__ void mirror(const double* pl, const double* p, double
 
 // Back-trace from X through images I[1..k] (I[0] = source S) over surfaces
 // seq; on success fills P[0..k) and tri[0..k).  The loops run over the
-// compile-time bound with constant indices so the arrays stay in registers.
+// compile-time bound KM >= k with constant indices so the arrays stay in
+// registers.
+template <int KM>
 __device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k, const double (*I)[3],
                                        const double* X, double (*P)[3], int* tri)
 {
 #pragma clang fp contract(off)
     double Q[3] = {X[0], X[1], X[2]};
 #pragma unroll
-    for (int i = RT_MAX_K; i >= 1; --i) {
+    for (int i = KM; i >= 1; --i) {
         if (i > k) continue;
         const double* pl = s.s_plane + 4 * seq[i - 1];
         double w0 = Q[0] - I[i][0], w1 = Q[1] - I[i][1], w2 = Q[2] - I[i][2];
@@ -965,13 +999,13 @@ __device__ inline bool image_backtrace(const SceneView& s, const int* seq, int k
         Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
     }
 #pragma unroll
-    for (int i = 0; i < RT_MAX_K; ++i) {
+    for (int i = 0; i < KM; ++i) {
         if (i >= k) break;
         const double* pl = s.s_plane + 4 * seq[i];
         double prev[3], next[3];
         for (int q = 0; q < 3; ++q) {
             prev[q] = i == 0 ? I[0][q] : P[i > 0 ? i - 1 : 0][q];
-            next[q] = (i == k - 1 || i + 1 >= RT_MAX_K) ? X[q] : P[i + 1 < RT_MAX_K ? i + 1 : 0][q];
+            next[q] = (i == k - 1 || i + 1 >= KM) ? X[q] : P[i + 1 < KM ? i + 1 : 0][q];
         }
         double a = plane_side(pl, prev);
         double b = plane_side(pl, next);

@@ -7,7 +7,9 @@
 //                hit + specular bounce up to K times (stand-in for the
 //                analytic first stage of the hybrid tracer, Section II).
 //  2. dedupe     every prefix of every hit list, mapped to surfaces, packed
-//                into a 64-bit key (21 bits per surface); sort + unique.
+//                21 bits per surface into a key of one 64-bit word (orders
+//                up to 3) or two (orders 4 and 5: surfaces 0-2 in word 0,
+//                3-4 in word 1); hash set, then sort (+ unique for two words).
 //  3. images     per candidate: images of the source in the surfaces' planes.
 //  4. paths      per (receiver, candidate): image-method back-trace, surface
 //                containment and side tests (FP64); the valid cells are
@@ -25,6 +27,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstring>
+#include <memory>
 #include <utility>
 #include <vector>
 
@@ -179,24 +182,59 @@ __device__ __forceinline__ void hash_insert(unsigned long long* table, uint64_t 
     atomicOr(overflow, 1);
 }
 
+// Two-word keys (orders 4 and 5): a slot is two words, word 0 (never 0 for a
+// key: it holds the first surface) claimed by compare-and-swap, then word 1
+// published with bit 63 set (0 = not yet written).  A lane that finds word 0
+// equal to its key's but word 1 not (yet) equal probes on and may insert the
+// key a second time; the sort that follows removes such duplicates, so a key
+// is never lost and never kept twice.
+#define RT_W1_SET (1ull << 63)
+__device__ __forceinline__ void hash_insert2(unsigned long long* table, uint64_t mask, uint64_t max_probe,
+                                             uint64_t k0, uint64_t k1, int* overflow)
+{
+    const unsigned long long w1 = (unsigned long long)(k1 | RT_W1_SET);
+    uint64_t h = mix64(k0 ^ mix64(k1)) & mask;
+    for (uint64_t probe = 0; probe <= max_probe; ++probe) {
+        unsigned long long cur = table[2 * h];
+        if (cur == 0ull) {
+            const unsigned long long prev = atomicCAS(&table[2 * h], 0ull, (unsigned long long)k0);
+            if (prev == 0ull) {
+                atomicExch(&table[2 * h + 1], w1);
+                return;
+            }
+            cur = prev;
+        }
+        if (cur == k0 && table[2 * h + 1] == w1) return;
+        h = (h + 1) & mask;
+    }
+    atomicOr(overflow, 1);
+}
+
 // Discovery over the direction-sorted ray list; every prefix of every hit
 // list (as surface ids) goes into the hash set.  Neighbouring lanes trace
 // neighbouring directions, so a lane skips a key equal to its left
-// neighbour's (one of them inserts it).
-template <bool BRUTE, int STK>
+// neighbour's (one of them inserts it).  KM: the largest order of the
+// instance (K <= KM); keys of orders above 3 have two words.
+// CNT: the counting build: each lane walks the binary tree on its own (the
+// method's per-ray LBVH walk, same hits) and the node visits, triangle tests
+// and segments are added to work[0..2].
+template <bool BRUTE, int STK, int KM, bool CNT>
 __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, double sy, double sz,
                                                      const int32_t* perm, const int32_t* off, int64_t rows,
                                                      int hemi, double hx, double hy, double hz, int K,
                                                      int32_t* hits, unsigned long long* segs,
                                                      unsigned long long* table, uint64_t mask, uint64_t max_probe,
-                                                     int* overflow)
+                                                     int* overflow, unsigned long long* work)
 {
-    static_assert(RT_MAX_K == 3, "three key registers");
-    // per-lane stacks for the brute-force build, one stack per wave for the wave walk
-    __shared__ int stack[BRUTE ? 1 : RT_STACK4 * (DISC_B / 64)];
+    constexpr int W = KM > RT_KM_SMALL ? 2 : 1;
+    // per-lane stacks for the brute-force build and the counting build, one stack per wave for the wave walk
+    __shared__ int stack[BRUTE ? 1 : (CNT ? STK * DISC_B : RT_STACK4 * (DISC_B / 64))];
+    WorkCount wc;
     int64_t t = (int64_t)blockIdx.x * DISC_B + threadIdx.x;
     unsigned nseg = 0;
-    uint64_t keys[RT_MAX_K] = {0, 0, 0};
+    uint64_t keys[KM], keys1[KM];   // key of each prefix: word 0, word 1
+#pragma unroll
+    for (int q = 0; q < KM; ++q) keys[q] = keys1[q] = 0ull;
     const int64_t ch = t / RT_FIB_CHUNK;
     const int64_t i = ch * RT_FIB_CHUNK + perm[(off[ch] + (int)(t % RT_FIB_CHUNK)) % RT_FIB_CHUNK];
     // the bounce loop runs for the whole wave; a lane drops out when its ray escapes
@@ -210,8 +248,10 @@ __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, dou
     float ox = (float)sx, oy = (float)sy, oz = (float)sz;
     float dx = (float)d64[0], dy = (float)d64[1], dz = (float)d64[2];
     int skip = -1;
-    uint64_t acc = 0;
-    int hid[RT_MAX_K] = {-1, -1, -1};   // hit ids, stored after the walk (no store between the walk's loads)
+    uint64_t acc = 0, acc1 = 0;
+    int hid[KM];   // hit ids, stored after the walk (no store between the walk's loads)
+#pragma unroll
+    for (int q = 0; q < KM; ++q) hid[q] = -1;
     int* wst = stack + (BRUTE ? 0 : __builtin_amdgcn_readfirstlane(threadIdx.x >> 6) * RT_STACK4);
     for (int b = 0; b < K; ++b) {
         if (__ballot(alive) == 0ull) break;
@@ -221,18 +261,26 @@ __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, dou
         int slot;
         if (BRUTE)
             slot = alive ? closest_hit<true>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, nullptr, 0, tt, id) : -1;
+        else if (CNT)
+            slot = alive ? closest_hit<false, true>(s, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip,
+                                                    stack + threadIdx.x, DISC_B, tt, id, &wc)
+                         : -1;
         else
             slot = closest_hit_wave4(s, alive, ox, oy, oz, dx, dy, dz, (float)RT_EPS, skip, wst, tt, id);
         alive = alive && slot >= 0;
         if (alive) {
-            hid[0] = b == 0 ? id : hid[0];
-            hid[1] = b == 1 ? id : hid[1];
-            hid[2] = b == 2 ? id : hid[2];
-            acc |= (uint64_t)(__float_as_int(s.tri4[3 * slot + 1].w) + 1) << (RT_KEY_BITS * b);
-            // constant indices only, so the keys stay in registers
-            keys[0] = b == 0 ? acc : keys[0];
-            keys[1] = b == 1 ? acc : keys[1];
-            keys[2] = b == 2 ? acc : keys[2];
+            const uint64_t field = (uint64_t)(__float_as_int(s.tri4[3 * slot + 1].w) + 1);
+            if (W == 1 || b < 3)
+                acc |= field << (RT_KEY_BITS * b);
+            else
+                acc1 |= field << (RT_KEY_BITS * (b - 3));
+            // constant indices only, so the ids and keys stay in registers
+#pragma unroll
+            for (int q = 0; q < KM; ++q) {
+                hid[q] = b == q ? id : hid[q];
+                keys[q] = b == q ? acc : keys[q];
+                if (W == 2) keys1[q] = b == q ? acc1 : keys1[q];
+            }
             float px = ox + tt * dx, py = oy + tt * dy, pz = oz + tt * dz;
             reflect32(s.tri4[3 * slot + 1], s.tri4[3 * slot + 2], dx, dy, dz);
             ox = px;
@@ -242,20 +290,35 @@ __global__ __launch_bounds__(DISC_B) void k_discover(SceneView s, double sx, dou
         }
     }
     if (hits && alive0)
-        for (int b = 0; b < K; ++b) hits[i * K + b] = hid[b < RT_MAX_K ? b : 0];
 #pragma unroll
-    for (int b = 0; b < RT_MAX_K; ++b) {
+        for (int b = 0; b < KM; ++b)
+            if (b < K) hits[i * K + b] = hid[b];
+#pragma unroll
+    for (int b = 0; b < KM; ++b) {
         const uint64_t left = __shfl_up(keys[b], 1, 64);
-        const bool first = (threadIdx.x & 63) == 0 || left != keys[b];
-        if (b < K && keys[b] != 0ull && first) hash_insert(table, mask, max_probe, keys[b], overflow);
+        const uint64_t left1 = W == 2 ? __shfl_up(keys1[b], 1, 64) : 0ull;
+        const bool first = (threadIdx.x & 63) == 0 || left != keys[b] || (W == 2 && left1 != keys1[b]);
+        if (b < K && keys[b] != 0ull && first) {
+            if (W == 1)
+                hash_insert(table, mask, max_probe, keys[b], overflow);
+            else
+                hash_insert2(table, mask, max_probe, keys[b], keys1[b], overflow);
+        }
     }
     wave_count_add(segs, nseg);
+    if (CNT) {
+        wave_count_add(work + 0, wc.nodes);
+        wave_count_add(work + 1, wc.tris);
+        wave_count_add(work + 2, nseg);
+    }
 }
 
 // --------------------------------------------------------------------------
 // 2. candidate keys: surface ids + 1, 21 bits per bounce; 0 = none
 // --------------------------------------------------------------------------
-// every sequence of <= K surfaces without immediate repeat, as keys (0 for skipped)
+// every sequence of <= K surfaces without immediate repeat, as keys of W
+// words (0 for skipped)
+template <int W>
 __global__ void k_exhaustive_keys(int64_t n_surf, int K, int64_t total, uint64_t* keys)
 {
     int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -269,7 +332,7 @@ __global__ void k_exhaustive_keys(int64_t n_surf, int K, int64_t total, uint64_t
         ++k;
     }
     int64_t r = idx - base;
-    uint64_t key = 0;
+    uint64_t key = 0, key1 = 0;
     int prev = -1;
     bool ok = true;
     for (int j = 0; j < k; ++j) {
@@ -277,31 +340,49 @@ __global__ void k_exhaustive_keys(int64_t n_surf, int K, int64_t total, uint64_t
         r /= n_surf;
         if (sidx == prev) ok = false;
         prev = sidx;
-        key |= (uint64_t)(sidx + 1) << (RT_KEY_BITS * j);
+        if (j < 3)
+            key |= (uint64_t)(sidx + 1) << (RT_KEY_BITS * j);
+        else
+            key1 |= (uint64_t)(sidx + 1) << (RT_KEY_BITS * (j - 3));
     }
-    keys[idx] = ok ? key : 0ull;
+    keys[W * idx] = ok ? key : 0ull;
+    if (W == 2) keys[W * idx + 1] = ok ? key1 : 0ull;
+}
+
+// surface id (or -1) of position j of a key of W words
+template <int W>
+__device__ __forceinline__ int key_surface(const uint64_t* key, int j)
+{
+    const uint64_t w = (W == 2 && j >= 3) ? key[1] : key[0];
+    const int sh = RT_KEY_BITS * (j >= 3 ? j - 3 : j);
+    const uint64_t v = (w >> sh) & ((1ull << RT_KEY_BITS) - 1);
+    return v ? (int)v - 1 : -1;
 }
 
 // --------------------------------------------------------------------------
 // 3. candidates: decode keys, images of the source
 // --------------------------------------------------------------------------
+// per candidate: order, KM surface ids (-1 padded), KM images (3 doubles each)
+template <int KM>
 __global__ void k_cand_prep(const uint64_t* keys, int64_t n, SceneView s, double sx, double sy, double sz,
                             int32_t* ck, int32_t* cseq, double* cimg)
 {
+    constexpr int W = KM > RT_KM_SMALL ? 2 : 1;
     int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (c >= n) return;
-    uint64_t key = keys[c];
+    const uint64_t* key = keys + W * c;
     int k = 0;
-    int seq[RT_MAX_K];
-    for (int j = 0; j < RT_MAX_K; ++j) {
-        uint64_t v = (key >> (RT_KEY_BITS * j)) & ((1ull << RT_KEY_BITS) - 1);
-        seq[j] = v ? (int)v - 1 : -1;
-        if (v && k == j) k = j + 1;
+    int seq[KM];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        seq[j] = key_surface<W>(key, j);
+        if (seq[j] >= 0 && k == j) k = j + 1;
     }
     ck[c] = k;
     double I[3] = {sx, sy, sz};
-    for (int j = 0; j < RT_MAX_K; ++j) {
-        cseq[3 * c + j] = seq[j];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        cseq[KM * c + j] = seq[j];
         if (j < k) {
             double o[3];
             mirror(s.s_plane + 4 * seq[j], I, o);
@@ -309,9 +390,9 @@ __global__ void k_cand_prep(const uint64_t* keys, int64_t n, SceneView s, double
             I[1] = o[1];
             I[2] = o[2];
         }
-        cimg[9 * c + 3 * j + 0] = I[0];
-        cimg[9 * c + 3 * j + 1] = I[1];
-        cimg[9 * c + 3 * j + 2] = I[2];
+        cimg[3 * KM * c + 3 * j + 0] = I[0];
+        cimg[3 * KM * c + 3 * j + 1] = I[1];
+        cimg[3 * KM * c + 3 * j + 2] = I[2];
     }
 }
 
@@ -325,20 +406,22 @@ struct CandView {
     int64_t n;
 };
 
+template <int KM>
 __device__ __forceinline__ bool geo_path(const SceneView& s, const CandView& cv, int64_t c, const double* S,
                                          const double* X, double (*P)[3], int* tri, int& k)
 {
     k = cv.k[c];
-    int seq[RT_MAX_K];
-    double I[RT_MAX_K + 1][3];
+    int seq[KM];
+    double I[KM + 1][3];
     I[0][0] = S[0];
     I[0][1] = S[1];
     I[0][2] = S[2];
-    for (int j = 0; j < RT_MAX_K; ++j) {
-        seq[j] = cv.seq[3 * c + j];
-        for (int q = 0; q < 3; ++q) I[j + 1][q] = cv.img[9 * c + 3 * j + q];
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        seq[j] = cv.seq[KM * c + j];
+        for (int q = 0; q < 3; ++q) I[j + 1][q] = cv.img[3 * KM * c + 3 * j + q];
     }
-    return image_backtrace(s, seq, k, I, X, P, tri);
+    return image_backtrace<KM>(s, seq, k, I, X, P, tri);
 }
 
 
@@ -366,6 +449,39 @@ __global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long
     app.flush(out, out_cap, counter);
 }
 
+// The same for two-word slots (word 1 loses its written bit): the block
+// gathers slot indices, then copies both words.
+__global__ __launch_bounds__(TC_B) void k_table_compact2(const unsigned long long* table, int64_t cap, uint64_t* out,
+                                                         int64_t out_cap, unsigned long long* counter)
+{
+    if (blockIdx.x == 0 && threadIdx.x == 0) {
+        out[0] = 0ull;
+        out[1] = 0ull;
+    }
+    out += 2;
+    __shared__ uint64_t idx[TC_B * TC_PT];
+    __shared__ int n;
+    __shared__ unsigned long long base;
+    if (threadIdx.x == 0) n = 0;
+    __syncthreads();
+    for (int j = 0; j < TC_PT; ++j) {
+        const int64_t i = ((int64_t)blockIdx.x * TC_PT + j) * TC_B + threadIdx.x;
+        if (i < cap && table[2 * i] != 0ull) idx[atomicAdd(&n, 1)] = (uint64_t)i;
+    }
+    __syncthreads();
+    const int cnt = n;
+    if (threadIdx.x == 0) base = cnt > 0 ? atomicAdd(counter, (unsigned long long)cnt) : 0ull;
+    __syncthreads();
+    for (int t = threadIdx.x; t < cnt; t += TC_B) {
+        const unsigned long long o = base + (unsigned long long)t;
+        if (o < (unsigned long long)out_cap) {
+            const uint64_t i = idx[t];
+            out[2 * o] = table[2 * i];
+            out[2 * o + 1] = table[2 * i + 1] & ~RT_W1_SET;
+        }
+    }
+}
+
 // One wave takes GEO_CPW candidates for 64 consecutive receivers, so the
 // candidate's surfaces, planes and triangles are wave-uniform (scalar loads,
 // no divergence in the loops over a surface's triangles).  A block covers 32
@@ -373,6 +489,7 @@ __global__ __launch_bounds__(TC_B) void k_table_compact(const unsigned long long
 // (mask[r * n_words + w], bit b = candidate 32 w + b).
 // grid: x = word (group of 32 candidates), y = block of 64 receivers
 constexpr int GEO_B = 256, GEO_CPW = 8;
+template <int KM>
 __global__ __launch_bounds__(GEO_B) void k_geo_mask(SceneView s, CandView cv, double sx, double sy, double sz,
                                                     const double* rx, int64_t R, int64_t n_words, uint32_t* mask)
 {
@@ -389,10 +506,10 @@ __global__ __launch_bounds__(GEO_B) void k_geo_mask(SceneView s, CandView cv, do
         for (int j = 0; j < GEO_CPW; ++j) {
             const int64_t c = c0 + j;
             if (c >= cv.n) break;
-            double P[RT_MAX_K][3];
-            int tri[RT_MAX_K];
+            double P[KM][3];
+            int tri[KM];
             int k;
-            if (geo_path(s, cv, c, S, X, P, tri, k)) bits |= 1u << j;
+            if (geo_path<KM>(s, cv, c, S, X, P, tri, k)) bits |= 1u << j;
         }
     }
     part[wib][lane] = bits << (GEO_CPW * wib);
@@ -447,10 +564,39 @@ __global__ void k_cell_emit(const uint32_t* mask, int64_t R, int64_t n_words, in
 // --------------------------------------------------------------------------
 constexpr int LEG_B = 128;
 
+template <int KM>
 struct PathRec {
     int32_t rx, cand, k;
-    int32_t tri[RT_MAX_K];
+    int32_t tri[KM];
 };
+
+// Path points by value, constant indices only: V[0] = S, V[j] = P[j - 1] for
+// j <= k, X from k + 1 on (so leg j runs from V[j] to V[j + 1]).
+template <int KM>
+__device__ __forceinline__ void path_points(const double* S, const double (*P)[3], const double* X, int k,
+                                            double (*V)[3])
+{
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        V[0][q] = S[q];
+#pragma unroll
+        for (int j = 1; j <= KM; ++j) V[j][q] = k >= j ? P[j - 1][q] : X[q];
+        V[KM + 1][q] = X[q];
+    }
+}
+
+// the point before X on the path (S for a direct path), by value
+template <int KM>
+__device__ __forceinline__ void last_point(const double* S, const double (*P)[3], int k, double* L)
+{
+#pragma unroll
+    for (int q = 0; q < 3; ++q) {
+        double v = S[q];
+#pragma unroll
+        for (int j = 1; j <= KM; ++j) v = k == j ? P[j - 1][q] : v;
+        L[q] = v;
+    }
+}
 
 __device__ __forceinline__ double seg_len(const double* a, const double* b)
 {
@@ -458,10 +604,10 @@ __device__ __forceinline__ double seg_len(const double* a, const double* b)
     return sqrt(w0 * w0 + w1 * w1 + w2 * w2);
 }
 
-template <bool BRUTE, bool FIELD, int STK>
+template <bool BRUTE, bool FIELD, int STK, int KM>
 __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, TraceConst tc, double sx, double sy,
                                                  double sz, const double* rx, const uint64_t* cells, int64_t n,
-                                                 uint8_t* valid, float2* amp, double* len, PathRec* recs,
+                                                 uint8_t* valid, float2* amp, double* len, PathRec<KM>* recs,
                                                  unsigned long long* segs)
 {
     __shared__ int stack[STK * LEG_B];
@@ -472,27 +618,21 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
         const int64_t r = (int64_t)(cell / (uint64_t)cv.n), c = (int64_t)(cell - (uint64_t)r * cv.n);
         double S[3] = {sx, sy, sz};
         double X[3] = {rx[3 * r], rx[3 * r + 1], rx[3 * r + 2]};
-        double P[RT_MAX_K][3];
-        int tri[RT_MAX_K] = {-1, -1, -1};
+        double P[KM][3];
+        int tri[KM];
+#pragma unroll
+        for (int j = 0; j < KM; ++j) tri[j] = -1;
         int k;
-        bool ok = geo_path(s, cv, c, S, X, P, tri, k);
+        bool ok = geo_path<KM>(s, cv, c, S, X, P, tri, k);
         float Ft = 1.0f, Fr = 1.0f;
-        // path points by value, constant indices only: V[0] = S, V[1..k] = P, V[k+1] = X
-        static_assert(RT_MAX_K == 3, "selections below list every order");
-        double V[RT_MAX_K + 2][3];
-        for (int q = 0; q < 3; ++q) {
-            V[0][q] = S[q];
-            V[1][q] = k >= 1 ? P[0][q] : X[q];
-            V[2][q] = k >= 2 ? P[1][q] : X[q];
-            V[3][q] = k >= 3 ? P[2][q] : X[q];
-            V[4][q] = X[q];
-        }
+        double V[KM + 2][3];
+        path_points<KM>(S, P, X, k, V);
         if (FIELD && ok) {
-            double v1[3], vl[3];
+            double v1[3], vl[3], L[3];
+            last_point<KM>(S, P, k, L);
             for (int q = 0; q < 3; ++q) {
                 v1[q] = V[1][q] - S[q];
-                const double lq = k == 0 ? S[q] : k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
-                vl[q] = lq - X[q];
+                vl[q] = L[q] - X[q];
             }
             const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
             const double cr = cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm);
@@ -500,37 +640,41 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
             Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);
             ok = pattern_on(tc.txa.pattern, ct) && pattern_on(tc.rxa.pattern, cr);
         }
-        int sq[RT_MAX_K];
-        for (int j = 0; j < RT_MAX_K; ++j) sq[j] = cv.seq[3 * c + j];
+        int sq[KM];
 #pragma unroll
-        for (int j = 0; j <= RT_MAX_K; ++j) {
+        for (int j = 0; j < KM; ++j) sq[j] = cv.seq[KM * c + j];
+#pragma unroll
+        for (int j = 0; j <= KM; ++j) {
             if (j > k || !ok) break;
             // leg j runs from V[j] to V[j + 1] (V[j + 1] = X when j = k)
             const int sa = j == 0 ? -1 : sq[j > 0 ? j - 1 : 0];
-            const int sb = j == k ? -1 : sq[j < RT_MAX_K ? j : 0];
+            const int sb = j == k ? -1 : sq[j < KM ? j : 0];
             ++nseg;
             if (leg_blocked<BRUTE>(s, V[j], V[j + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
         }
         valid[i] = ok ? 1 : 0;
-        PathRec pr;
+        PathRec<KM> pr;
         pr.rx = (int32_t)r;
         pr.cand = (int32_t)c;
         pr.k = k;
-        for (int j = 0; j < RT_MAX_K; ++j) pr.tri[j] = j < k ? tri[j] : -1;
+#pragma unroll
+        for (int j = 0; j < KM; ++j) pr.tri[j] = j < k ? tri[j] : -1;
         recs[i] = pr;
         if (FIELD) {
-            double D = 0.0, Lj[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};
+            double D = 0.0, Lj[KM + 1];
 #pragma unroll
-            for (int j = 0; j <= RT_MAX_K; ++j)
+            for (int j = 0; j <= KM; ++j) {
+                Lj[j] = 0.0;
                 if (j <= k) {
                     Lj[j] = seg_len(V[j], V[j + 1]);
                     D += Lj[j];
                 }
+            }
             float2 a = make_float2(0.0f, 0.0f);
             if (ok) {
                 float ar = 1.0f, ai = 0.0f;
 #pragma unroll
-                for (int j = 0; j < RT_MAX_K; ++j) {
+                for (int j = 0; j < KM; ++j) {
                     if (j >= k) break;
                     float2 Rc;
                     if (tc.fresnel) {
@@ -583,17 +727,24 @@ __global__ __launch_bounds__(ENV_B) void k_env_reduce(const int64_t* rstart, int
 }
 
 // keep valid records: env path records for read-back
-__global__ void k_env_compact(const PathRec* recs, CandView cv, const uint8_t* valid, const int64_t* off2,
+template <int KM>
+__global__ void k_env_compact(const PathRec<KM>* recs, CandView cv, const uint8_t* valid, const int64_t* off2,
                               const float2* amp, const double* len, int64_t n, EnvRec* out)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !valid[i]) return;
-    const PathRec& pr = recs[i];
+    const PathRec<KM>& pr = recs[i];
     EnvRec e;
     e.rx = pr.rx;
     e.order = pr.k;
-    for (int j = 0; j < 3; ++j) {
-        e.seq[j] = cv.seq[3 * pr.cand + j];
+#pragma unroll
+    for (int j = 0; j < RT_MAX_K; ++j) {
+        e.seq[j] = -1;
+        e.tri[j] = -1;
+    }
+#pragma unroll
+    for (int j = 0; j < KM; ++j) {
+        e.seq[j] = cv.seq[KM * pr.cand + j];
         e.tri[j] = pr.tri[j];
     }
     e.length = len[i];
@@ -603,26 +754,32 @@ __global__ void k_env_compact(const PathRec* recs, CandView cv, const uint8_t* v
 }
 
 // valid centre sequences of order >= 1
-__global__ void k_u_flags(const PathRec* recs, const uint8_t* valid, int64_t n, uint8_t* f2)
+template <int KM>
+__global__ void k_u_flags(const PathRec<KM>* recs, const uint8_t* valid, int64_t n, uint8_t* f2)
 {
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n) return;
     f2[i] = (valid[i] && recs[i].k >= 1) ? 1 : 0;
 }
 
-// rows of 8 ints: rx, surfaces s0..s2, triangles t0..t2 reached from the centre, 0
-__global__ void k_u_compact(const PathRec* recs, CandView cv, const uint8_t* f2, const int64_t* off2, int64_t n,
+// Rows of useq_stride(KM) = 2 KM + 2 ints: rx, surfaces s_0..s_{KM-1},
+// triangles t_0..t_{KM-1} reached from the centre, 0.
+constexpr int useq_stride(int KM) { return 2 * KM + 2; }
+
+template <int KM>
+__global__ void k_u_compact(const PathRec<KM>* recs, CandView cv, const uint8_t* f2, const int64_t* off2, int64_t n,
                             int32_t* useq)
 {
+    constexpr int US = useq_stride(KM);
     int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i >= n || !f2[i]) return;
     int64_t o = off2[i];
-    useq[8 * o + 0] = recs[i].rx;
-    for (int j = 0; j < 3; ++j) {
-        useq[8 * o + 1 + j] = cv.seq[3 * recs[i].cand + j];
-        useq[8 * o + 4 + j] = recs[i].tri[j];
+    useq[US * o + 0] = recs[i].rx;
+    for (int j = 0; j < KM; ++j) {
+        useq[US * o + 1 + j] = cv.seq[KM * recs[i].cand + j];
+        useq[US * o + 1 + KM + j] = recs[i].tri[j];
     }
-    useq[8 * o + 7] = 0;
+    useq[US * o + US - 1] = 0;
 }
 
 __global__ void k_uptr_dev(const int64_t* rstart, int64_t n_rec, const int64_t* off2, const int64_t* total2,
@@ -637,14 +794,16 @@ __global__ void k_uptr_dev(const int64_t* rstart, int64_t n_rec, const int64_t* 
 // Launch order of the per-element kernel, heaviest receiver first (the
 // longest waves start first and short ones fill the tail): key = inverted
 // cost (slots weighted by legs, 20 bits) above the receiver index.
+template <int KM>
 __global__ void k_ris_order(const int64_t* uptr, const int32_t* useq, int64_t R, uint64_t* keys)
 {
     const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (r >= R) return;
     int64_t cost = 1;   // the direct slot: one leg
     for (int64_t u = uptr[r]; u < uptr[r + 1]; ++u) {
-        const int32_t* row = useq + 8 * u;
-        cost += 2 + (row[2] >= 0) + (row[3] >= 0);   // k + 1 legs, k >= 1
+        const int32_t* row = useq + useq_stride(KM) * u;
+        cost += 2;   // k + 1 legs, k >= 1
+        for (int j = 1; j < KM; ++j) cost += row[1 + j] >= 0;
     }
     const uint64_t c = (uint64_t)(cost < 0xFFFFF ? cost : 0xFFFFF);
     keys[r] = ((0xFFFFFull - c) << 32) | (uint64_t)r;
@@ -704,7 +863,7 @@ __global__ __launch_bounds__(64) void k_txm(SceneView s, TraceConst tc, RisView 
 // method from the Tx to the RIS, restricted like the out side to the
 // sequences valid from the Tx to the RIS centre u.
 // 1) per Tx candidate of order >= 1: valid and unblocked from the Tx to u?
-template <bool BRUTE, int STK>
+template <bool BRUTE, int STK, int KM>
 __global__ __launch_bounds__(LEG_B) void k_in_centre(SceneView s, CandView cv, double sx, double sy, double sz,
                                                      double ux, double uy, double uz, uint8_t* ok_out,
                                                      unsigned long long* segs)
@@ -715,25 +874,20 @@ __global__ __launch_bounds__(LEG_B) void k_in_centre(SceneView s, CandView cv, d
     if (c < cv.n) {
         const double S[3] = {sx, sy, sz};
         const double X[3] = {ux, uy, uz};
-        double P[RT_MAX_K][3];
-        int tri[RT_MAX_K] = {-1, -1, -1};
+        double P[KM][3];
+        int tri[KM];
         int k = 0;
-        bool ok = cv.k[c] >= 1 && geo_path(s, cv, c, S, X, P, tri, k);
-        double V[RT_MAX_K + 2][3];
-        for (int q = 0; q < 3; ++q) {
-            V[0][q] = S[q];
-            V[1][q] = k >= 1 ? P[0][q] : X[q];
-            V[2][q] = k >= 2 ? P[1][q] : X[q];
-            V[3][q] = k >= 3 ? P[2][q] : X[q];
-            V[4][q] = X[q];
-        }
-        int sq[RT_MAX_K];
-        for (int j = 0; j < RT_MAX_K; ++j) sq[j] = cv.seq[3 * c + j];
+        bool ok = cv.k[c] >= 1 && geo_path<KM>(s, cv, c, S, X, P, tri, k);
+        double V[KM + 2][3];
+        path_points<KM>(S, P, X, k, V);
+        int sq[KM];
 #pragma unroll
-        for (int j = 0; j <= RT_MAX_K; ++j) {
+        for (int j = 0; j < KM; ++j) sq[j] = cv.seq[KM * c + j];
+#pragma unroll
+        for (int j = 0; j <= KM; ++j) {
             if (j > k || !ok) break;
             const int sa = j == 0 ? -1 : sq[j > 0 ? j - 1 : 0];
-            const int sb = j == k ? -1 : sq[j < RT_MAX_K ? j : 0];
+            const int sb = j == k ? -1 : sq[j < KM ? j : 0];
             ++nseg;
             if (leg_blocked<BRUTE>(s, V[j], V[j + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
         }
@@ -750,7 +904,7 @@ __global__ void k_in_list(const uint8_t* ok, const int64_t* off, int64_t n, int3
 
 // 2) per (sequence j of the list, element m): the path Tx -> seq -> m, its legs
 // and its contribution to T_m (zero if not emitted); *n_in = list length
-template <bool BRUTE, int STK>
+template <bool BRUTE, int STK, int KM>
 __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, TraceConst tc, RisView rv,
                                                    const int32_t* list, const int64_t* n_in, float2* contrib,
                                                    uint8_t* emitted_out, unsigned long long* segs,
@@ -766,25 +920,19 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
         const int64_t c = list[j];
         const double S[3] = {tc.tx[0], tc.tx[1], tc.tx[2]};
         const double X[3] = {rv.elem[3 * m], rv.elem[3 * m + 1], rv.elem[3 * m + 2]};
-        double P[RT_MAX_K][3];
-        int tri[RT_MAX_K] = {-1, -1, -1};
+        double P[KM][3];
+        int tri[KM];
         int k = 0;
-        bool ok = geo_path(s, cv, c, S, X, P, tri, k);
-        double V[RT_MAX_K + 2][3];
-        for (int q = 0; q < 3; ++q) {
-            V[0][q] = S[q];
-            V[1][q] = k >= 1 ? P[0][q] : X[q];
-            V[2][q] = k >= 2 ? P[1][q] : X[q];
-            V[3][q] = k >= 3 ? P[2][q] : X[q];
-            V[4][q] = X[q];
-        }
+        bool ok = geo_path<KM>(s, cv, c, S, X, P, tri, k);
+        double V[KM + 2][3];
+        path_points<KM>(S, P, X, k, V);
         float Ft = 0.0f, Fin = 0.0f;
         if (ok) {
-            double v1[3], back[3];
+            double v1[3], back[3], L[3];
+            last_point<KM>(S, P, k, L);
             for (int q = 0; q < 3; ++q) {
                 v1[q] = V[1][q] - S[q];
-                const double lq = k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
-                back[q] = lq - X[q];
+                back[q] = L[q] - X[q];
             }
             const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
             const double ci = cos_between(back, rv.normal, rv.normal_norm);
@@ -792,28 +940,31 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
             Fin = pattern_amp(1, rv.q, ci);
             ok = pattern_on(tc.txa.pattern, ct) && pattern_on(1, ci);
         }
-        int sq[RT_MAX_K];
-        for (int q = 0; q < RT_MAX_K; ++q) sq[q] = cv.seq[3 * c + q];
+        int sq[KM];
 #pragma unroll
-        for (int q = 0; q <= RT_MAX_K; ++q) {
+        for (int q = 0; q < KM; ++q) sq[q] = cv.seq[KM * c + q];
+#pragma unroll
+        for (int q = 0; q <= KM; ++q) {
             if (q > k || !ok) break;
             const int sa = q == 0 ? -1 : sq[q > 0 ? q - 1 : 0];
-            const int sb = q == k ? -1 : sq[q < RT_MAX_K ? q : 0];
+            const int sb = q == k ? -1 : sq[q < KM ? q : 0];
             ++nseg;
             if (leg_blocked<BRUTE>(s, V[q], V[q + 1], sa, sb, stack + threadIdx.x, LEG_B)) ok = false;
         }
         float2 a = make_float2(0.0f, 0.0f);
         if (ok) {
-            double D = 0.0, Lq[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};
+            double D = 0.0, Lq[KM + 1];
 #pragma unroll
-            for (int q = 0; q <= RT_MAX_K; ++q)
+            for (int q = 0; q <= KM; ++q) {
+                Lq[q] = 0.0;
                 if (q <= k) {
                     Lq[q] = seg_len(V[q], V[q + 1]);
                     D += Lq[q];
                 }
+            }
             float ar = 1.0f, ai = 0.0f;
 #pragma unroll
-            for (int q = 0; q < RT_MAX_K; ++q) {
+            for (int q = 0; q < KM; ++q) {
                 if (q >= k) break;
                 float2 Rc;
                 if (tc.fresnel) {
@@ -867,7 +1018,7 @@ constexpr int RIS_B = 128;
 // Back-trace like image_backtrace, but each reflection first tries the
 // triangle the RIS-centre path used (hint); a point on a surface lies in
 // exactly one of its triangles, so the result is the same as a full search.
-template <bool CNT>
+template <bool CNT, int KM>
 __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, const int* hint, int k,
                                             const double (*I)[3], const double* X, double (*P)[3], int* tri,
                                             WorkCount* wc)
@@ -875,7 +1026,7 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 #pragma clang fp contract(off)
     double Q[3] = {X[0], X[1], X[2]};
 #pragma unroll
-    for (int i = RT_MAX_K; i >= 1; --i) {
+    for (int i = KM; i >= 1; --i) {
         if (i > k) continue;
         const double* pl = s.s_plane + 4 * seq[i - 1];
         double w0 = Q[0] - I[i][0], w1 = Q[1] - I[i][1], w2 = Q[2] - I[i][2];
@@ -893,13 +1044,13 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
         Q[0] = p[0]; Q[1] = p[1]; Q[2] = p[2];
     }
 #pragma unroll
-    for (int i = 0; i < RT_MAX_K; ++i) {
+    for (int i = 0; i < KM; ++i) {
         if (i >= k) break;
         const double* pl = s.s_plane + 4 * seq[i];
         double prev[3], next[3];
         for (int q = 0; q < 3; ++q) {
             prev[q] = i == 0 ? I[0][q] : P[i > 0 ? i - 1 : 0][q];
-            next[q] = (i == k - 1 || i + 1 >= RT_MAX_K) ? X[q] : P[i + 1 < RT_MAX_K ? i + 1 : 0][q];
+            next[q] = (i == k - 1 || i + 1 >= KM) ? X[q] : P[i + 1 < KM ? i + 1 : 0][q];
         }
         double a = plane_side(pl, prev);
         double b = plane_side(pl, next);
@@ -915,7 +1066,7 @@ __device__ inline bool image_backtrace_hint(const SceneView& s, const int* seq, 
 #endif
 
 // FRES: Fresnel coefficients of the materials (tc.fresnel) instead of the fixed ones
-template <bool BRUTE, bool KEEP, int STK, bool CNT, bool FRES>
+template <bool BRUTE, bool KEEP, int STK, bool CNT, bool FRES, int KM>
 __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView s, TraceConst tc, RisView rv, const TxmRec* txm,
                                                const double* rx, int64_t R, const int64_t* uptr,
                                                const int32_t* useq, const uint64_t* order, int n_mchunk, float2* H,
@@ -925,11 +1076,12 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
     // one traversal stack per wave (the 4-wide walk needs RT_STACK4 >= STK entries)
     __shared__ int wstack[RT_STACK4 * (RIS_B / 64)];
     // the rays of a slot's legs wait in LDS while earlier legs are walked (fewer live registers)
-    __shared__ float legbuf[RIS_B / 64][RT_MAX_K + 1][7][64];
+    __shared__ float legbuf[RIS_B / 64][KM + 1][7][64];
     // per-wave frontier and candidate lists of the tube walk
     __shared__ int tfront[RIS_B / 64][2 * RT_TUBE_FRONT];
     __shared__ int tcand[RIS_B / 64][RT_TUBE_CAND];
-    __shared__ float ttube[RIS_B / 64][8 * (RT_MAX_K + 1)];
+    __shared__ float ttube[RIS_B / 64][8 * (KM + 1)];
+    constexpr int US = useq_stride(KM);
     static_assert(RT_STACK4 >= STK, "wave stack");
     WorkCount wc;
     unsigned pairs = 0;
@@ -962,14 +1114,16 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
 #pragma unroll 1
         for (int64_t sl = 0; sl < nsl; ++sl) {
             // the slot's sequence is the same for every lane of the wave
-            int seq[RT_MAX_K] = {-1, -1, -1};
-            int hint[RT_MAX_K] = {-1, -1, -1};
+            int seq[KM], hint[KM];
+#pragma unroll
+            for (int j = 0; j < KM; ++j) seq[j] = hint[j] = -1;
             int k = 0;
             if (sl > 0) {
-                const int32_t* row = useq + 8 * (u0 + sl - 1);
-                for (int j = 0; j < RT_MAX_K; ++j) {
+                const int32_t* row = useq + US * (u0 + sl - 1);
+#pragma unroll
+                for (int j = 0; j < KM; ++j) {
                     seq[j] = row[1 + j];
-                    hint[j] = row[4 + j];
+                    hint[j] = row[1 + KM + j];
                     if (seq[j] >= 0) k = j + 1;
                 }
             }
@@ -979,27 +1133,26 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
             float amp_r = 0.0f, amp_i = 0.0f;
             double Dr_keep = 0.0;
             {
-                double P[RT_MAX_K][3];
-                int tri[RT_MAX_K] = {-1, -1, -1};
+                double P[KM][3];
+                int tri[KM];
+#pragma unroll
+                for (int j = 0; j < KM; ++j) tri[j] = -1;
                 {
-                    double I[RT_MAX_K + 1][3];
+                    double I[KM + 1][3];
                     I[0][0] = E[0];
                     I[0][1] = E[1];
                     I[0][2] = E[2];
 #pragma unroll
-                    for (int j = 0; j < RT_MAX_K; ++j)
+                    for (int j = 0; j < KM; ++j)
                         if (j < k) mirror(s.s_plane + 4 * seq[j], I[j], I[j + 1]);
-                    if (ok) ok = image_backtrace_hint<CNT>(s, seq, hint, k, I, X, P, tri, &wc);
+                    if (ok) ok = image_backtrace_hint<CNT, KM>(s, seq, hint, k, I, X, P, tri, &wc);
                 }
                 float Fout = 0.0f, Fr = 0.0f;
                 if (ok) {
                     // first and last path points, selected by value (constant indices)
-                    static_assert(RT_MAX_K == 3, "selection below lists every order");
                     double f[3], l[3];
-                    for (int q = 0; q < 3; ++q) {
-                        f[q] = k ? P[0][q] : X[q];
-                        l[q] = k == 0 ? E[q] : k == 1 ? P[0][q] : k == 2 ? P[1][q] : P[2][q];
-                    }
+                    last_point<KM>(E, P, k, l);
+                    for (int q = 0; q < 3; ++q) f[q] = k ? P[0][q] : X[q];
                     double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
                     double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
                     const double co = cos_between(v1, rv.normal, rv.normal_norm);
@@ -1009,9 +1162,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                     ok = pattern_on(1, co) && pattern_on(tc.rxa.pattern, cr);
                 }
                 double Dr = 0.0;
-                double Lk[RT_MAX_K + 1] = {0.0, 0.0, 0.0, 0.0};   // leg lengths (the Fresnel angles use them)
+                double Lk[KM + 1];   // leg lengths (the Fresnel angles use them)
 #pragma unroll
-                for (int j = 0; j <= RT_MAX_K; ++j) {
+                for (int j = 0; j <= KM; ++j) {
+                    Lk[j] = 0.0;
                     if (j <= k) {
 #pragma clang fp contract(off)
                         const double* A = j == 0 ? E : P[j - 1];
@@ -1034,7 +1188,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 if (ok) {
                     float ar = 1.0f, ai = 0.0f;
 #pragma unroll
-                    for (int j = 0; j < RT_MAX_K; ++j) {
+                    for (int j = 0; j < KM; ++j) {
                         if (j >= k) break;
                         float2 Rc;
                         if (FRES) {
@@ -1064,8 +1218,8 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
             if (BRUTE || CNT) {
 #pragma unroll 1
                 for (int j = 0; j <= k; ++j) {
-                    const int sa = j == 0 ? -1 : (j == 1 ? seq[0] : (j == 2 ? seq[1] : seq[2]));
-                    const int sb = j == k ? -1 : (j == 0 ? seq[0] : (j == 1 ? seq[1] : seq[2]));
+                    const int sa = leg_surface_a<KM>(seq, j);
+                    const int sb = leg_surface_b<KM>(seq, j, k);
                     const float* lb = &legbuf[wib][j][0][lane];
                     const float ox = lb[0 * 64], oy = lb[1 * 64], oz = lb[2 * 64];
                     const float dx = lb[3 * 64], dy = lb[4 * 64], dz = lb[5 * 64];
@@ -1083,7 +1237,7 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                 }
             } else {
                 // every leg at once; legs are counted as the sequential test would (up to the first blocked one)
-                const unsigned res = legs_blocked_tube(s, ok, k, seq, &legbuf[wib][0][0][0], ttube[wib],
+                const unsigned res = legs_blocked_tube<KM>(s, ok, k, seq, &legbuf[wib][0][0][0], ttube[wib],
                                                        tfront[wib], tcand[wib], my_stack);
                 n_fallback += (res & RT_TUBE_FELL_BACK) ? 1u : 0u;   // same on every lane
                 const unsigned bl = res & ~RT_TUBE_FELL_BACK;
@@ -1177,6 +1331,8 @@ struct Branch {
     uint64_t max_probe = 0;
     Scratch mask;             // geometric validity, R rows of n_words 32-bit words
     int64_t n_words = 0;
+    unsigned long long* d_work = nullptr;   // counting build: node visits, triangle tests of discovery
+    hipEvent_t ev_disc[2] = {nullptr, nullptr};   // around the discovery kernel (stage times only)
 };
 
 // RIS description for the kernels
@@ -1203,6 +1359,7 @@ static RisView make_ris_view(const TraceArgs& a)
 // leg, and with `incoming` the reflections Tx -> surfaces -> element for the
 // Tx candidates valid at the RIS centre.  Launched on stream si (beside the
 // path kernels); its scratch lives on si.
+template <int KM>
 static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool incoming,
                          const Branch& bt, const RisView& rv, unsigned long long* d_ctr, TxmRec* txm, hipStream_t si)
 {
@@ -1219,7 +1376,7 @@ static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         in_list(c, sizeof(int32_t) * (size_t)nc, si);
     int64_t* d_nin = (int64_t*)(d_ctr + 16);
     SEL_BOOL(brute, BR,
-             SEL_STK(stk, hipLaunchKernelGGL((k_in_centre<BR, STK>), dim3(nblk(nc, LEG_B)), dim3(LEG_B), 0, si, sv,
+             SEL_STK(stk, hipLaunchKernelGGL((k_in_centre<BR, STK, KM>), dim3(nblk(nc, LEG_B)), dim3(LEG_B), 0, si, sv,
                                              bt.cd.view(), a.tc.tx[0], a.tc.tx[1], a.tc.tx[2], rv.centre[0],
                                              rv.centre[1], rv.centre[2], in_ok.as<uint8_t>(), d_legs)));
     HIP_CHECK(hipGetLastError());
@@ -1231,7 +1388,7 @@ static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     if (nc > ((int64_t)1 << 40) / M) throw inval_error("candidates x elements too large");
     Scratch contrib(c, sizeof(float2) * (size_t)(nc * M), si), emitted(c, (size_t)(nc * M), si);
     SEL_BOOL(brute, BR,
-             SEL_STK(stk, hipLaunchKernelGGL((k_in_elem<BR, STK>), dim3(nblk(nc * M, LEG_B)), dim3(LEG_B), 0, si, sv,
+             SEL_STK(stk, hipLaunchKernelGGL((k_in_elem<BR, STK, KM>), dim3(nblk(nc * M, LEG_B)), dim3(LEG_B), 0, si, sv,
                                              bt.cd.view(), a.tc, rv, in_list.as<int32_t>(), d_nin,
                                              contrib.as<float2>(), emitted.as<uint8_t>(), d_legs, d_ctr + 17)));
     HIP_CHECK(hipGetLastError());
@@ -1240,6 +1397,11 @@ static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     HIP_CHECK(hipGetLastError());
 }
 
+// 64-bit words per candidate key: one up to order 3, two for orders 4 and 5
+static inline int key_words(int K) { return K > RT_KM_SMALL ? 2 : 1; }
+// end of the key bits: 21 per surface, orders above 3 continue in word 1
+static inline int key_end_bit(int K) { return K > RT_KM_SMALL ? 64 + RT_KEY_BITS * (K - 3) : RT_KEY_BITS * K; }
+
 // Phase A of the candidates: discovery rays, prefix keys into a hash set,
 // occupied slots compacted behind a leading 0 (the empty sequence); the
 // count is left in d_app[0] (overflow flag in d_app[1]).  Exhaustive mode:
@@ -1247,7 +1409,7 @@ static void ris_incident(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
 // The hash set of a branch's phase A, allocated and cleared on `st`: probe
 // runs of at most 256 (an overflow makes the caller repeat with the next
 // level): first a set of at least 4x the last call's unique count, then 2^20
-// slots, then at least 2 x (keys + 1) slots, at most 2^24, with unbounded
+// slots, then at least 2 x (keys + 1) slots, at most 2^27, with unbounded
 // probing.
 static void prepare_table(Ctx& c, const TraceArgs& a, Branch& br, hipStream_t st)
 {
@@ -1258,7 +1420,7 @@ static void prepare_table(Ctx& c, const TraceArgs& a, Branch& br, hipStream_t st
         while (cap < want && cap < limit) cap <<= 1;
         return cap;
     };
-    int64_t cap = set_size(br.table_level == 2 ? ((int64_t)1 << 24) : ((int64_t)1 << 20));
+    int64_t cap = set_size(br.table_level == 2 ? ((int64_t)1 << 27) : ((int64_t)1 << 20));
     if (br.table_level == 0) {
         const int64_t h = c.cand_hint[br.which].load();
         int64_t l = 1024;
@@ -1270,14 +1432,16 @@ static void prepare_table(Ctx& c, const TraceArgs& a, Branch& br, hipStream_t st
     }
     br.cap = cap;
     br.max_probe = br.table_level == 2 ? (uint64_t)(cap - 1) : (uint64_t)255;
-    br.table = Scratch(c, sizeof(unsigned long long) * (size_t)cap, st);
+    br.table = Scratch(c, sizeof(unsigned long long) * (size_t)key_words(a.tc.K) * (size_t)cap, st);
     HIP_CHECK(hipMemsetAsync(br.table.p, 0, br.table.bytes, st));
 }
 
+template <int KM>
 static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool exhaustive,
                          bool keep_hits, Channel& ch, Branch& br, unsigned long long* d_segs)
 {
     const int K = a.tc.K;
+    constexpr int W = KM > RT_KM_SMALL ? 2 : 1;
     hipStream_t st = br.st;
     if (exhaustive) {
         int64_t ns = sv.n_surf;
@@ -1288,15 +1452,15 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
             if (total > (int64_t)1 << 26) throw inval_error("exhaustive candidate set too large");
         }
         int64_t nkeys = total + 1;
-        Scratch keys(c, sizeof(uint64_t) * (size_t)nkeys, st);
+        Scratch keys(c, sizeof(uint64_t) * W * (size_t)nkeys, st), sorted(c, sizeof(uint64_t) * W * (size_t)nkeys, st);
         HIP_CHECK(hipMemsetAsync(keys.p, 0, keys.bytes, st));
         if (total > 0)
-            hipLaunchKernelGGL(k_exhaustive_keys, dim3(nblk(total, 256)), dim3(256), 0, st, ns, K, total,
+            hipLaunchKernelGGL(k_exhaustive_keys<W>, dim3(nblk(total, 256)), dim3(256), 0, st, ns, K, total,
                                keys.as<uint64_t>());
         HIP_CHECK(hipGetLastError());
-        sort_u64(c, keys.as<uint64_t>(), nkeys, RT_KEY_BITS * K, st);
-        br.keys = Scratch(c, sizeof(uint64_t) * (size_t)nkeys, st);
-        unique_u64(c, keys.as<uint64_t>(), br.keys.as<uint64_t>(), nkeys, br.d_cnt, st);
+        sort_keys(c, keys.as<uint64_t>(), sorted.as<uint64_t>(), nkeys, W, 0, key_end_bit(K), st);
+        br.keys = Scratch(c, sizeof(uint64_t) * W * (size_t)nkeys, st);
+        unique_keys(c, sorted.as<uint64_t>(), br.keys.as<uint64_t>(), nkeys, W, br.d_cnt, st);
         return;
     }
     const double* src = br.src;
@@ -1318,22 +1482,29 @@ static void cand_phase_a(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
         const int32_t *perm, *off;
         fib_tables(c, &perm, &off);
         const int64_t n_launch = (rows + RT_FIB_CHUNK - 1) / RT_FIB_CHUNK * RT_FIB_CHUNK;
-        SEL_BOOL(brute, BR,
-                 SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK>), dim3(nblk(n_launch, DISC_B)), dim3(DISC_B),
-                                                 0, st, sv, src[0], src[1], src[2], perm, off, rows, hemi_n ? 1 : 0,
-                                                 hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0,
-                                                 hemi_n ? hemi_n[2] : 0.0, K, keep_hits ? hits.as<int32_t>() : nullptr, d_segs,
-                                                 table.as<unsigned long long>(), (uint64_t)(cap - 1), max_probe,
-                                                 (int*)(br.d_app + 1))));
+        const bool count = (a.tc.flags & 16) != 0 && !brute;
+        if (br.ev_disc[0]) HIP_CHECK(hipEventRecord(br.ev_disc[0], st));
+        SEL_BOOL(brute, BR, SEL_BOOL(count, CN,
+                 SEL_STK(stk, hipLaunchKernelGGL((k_discover<BR, STK, KM, CN>), dim3(nblk(n_launch, DISC_B)),
+                                                 dim3(DISC_B), 0, st, sv, src[0], src[1], src[2], perm, off, rows,
+                                                 hemi_n ? 1 : 0, hemi_n ? hemi_n[0] : 0.0, hemi_n ? hemi_n[1] : 0.0,
+                                                 hemi_n ? hemi_n[2] : 0.0, K, keep_hits ? hits.as<int32_t>() : nullptr,
+                                                 d_segs, table.as<unsigned long long>(), (uint64_t)(cap - 1), max_probe,
+                                                 (int*)(br.d_app + 1), br.d_work))));
         HIP_CHECK(hipGetLastError());
+        if (br.ev_disc[1]) HIP_CHECK(hipEventRecord(br.ev_disc[1], st));
     }
     if (keep_hits) {
         ch.n_hits_rows[br.which] = rows;
         ch.hits[br.which] = std::move(hits);
     }
-    br.keys = Scratch(c, sizeof(uint64_t) * (size_t)(cap + 1), st);
-    hipLaunchKernelGGL(k_table_compact, dim3(nblk(cap, TC_B * TC_PT)), dim3(TC_B), 0, st, table.as<unsigned long long>(), cap,
-                       br.keys.as<uint64_t>(), cap, br.d_app);
+    br.keys = Scratch(c, sizeof(uint64_t) * W * (size_t)(cap + 1), st);
+    if (W == 1)
+        hipLaunchKernelGGL(k_table_compact, dim3(nblk(cap, TC_B * TC_PT)), dim3(TC_B), 0, st,
+                           table.as<unsigned long long>(), cap, br.keys.as<uint64_t>(), cap, br.d_app);
+    else
+        hipLaunchKernelGGL(k_table_compact2, dim3(nblk(cap, TC_B * TC_PT)), dim3(TC_B), 0, st,
+                           table.as<unsigned long long>(), cap, br.keys.as<uint64_t>(), cap, br.d_app);
     HIP_CHECK(hipGetLastError());
 }
 
@@ -1353,15 +1524,28 @@ static int64_t cand_count(Ctx& c, const Branch& br, bool exhaustive)
 }
 
 // Phase B: the unique keys in key order (the canonical candidate order).
-static void cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch& br, int64_t n)
+// Returns their number: n for one-word keys (the hash set holds each once);
+// two-word keys may have been inserted twice (see hash_insert2), so they are
+// de-duplicated after the sort and counted again (one more size read-back).
+static int64_t cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch& br, int64_t n)
 {
-    if (exhaustive) return;
-    Scratch sorted(c, sizeof(uint64_t) * (size_t)(n > 0 ? n : 1), br.st);
-    sort_u64_into(c, br.keys.as<uint64_t>(), sorted.as<uint64_t>(), n, RT_KEY_BITS * a.tc.K, br.st);
-    br.keys = std::move(sorted);
+    if (exhaustive) return n;
+    const int W = key_words(a.tc.K);
+    Scratch sorted(c, sizeof(uint64_t) * W * (size_t)(n > 0 ? n : 1), br.st);
+    sort_keys(c, br.keys.as<uint64_t>(), sorted.as<uint64_t>(), n, W, 0, key_end_bit(a.tc.K), br.st);
+    if (W == 1) {
+        br.keys = std::move(sorted);
+        return n;
+    }
+    br.keys = Scratch(c, sizeof(uint64_t) * W * (size_t)(n > 0 ? n : 1), br.st);
+    unique_keys(c, sorted.as<uint64_t>(), br.keys.as<uint64_t>(), n, W, br.d_cnt, br.st);
+    const int64_t nu = read_i64(br.d_cnt, br.st);
+    c.cand_hint[br.which].store(nu);
+    return nu;
 }
 
 // candidate images and the geometric test of every (receiver, candidate) cell
+template <int KM>
 static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& br, int64_t n_cand)
 {
     hipStream_t st = br.st;
@@ -1369,9 +1553,9 @@ static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& 
     cd.n = n_cand;
     cd.keys = std::move(br.keys);
     cd.k = Scratch(c, sizeof(int32_t) * (size_t)n_cand, st);
-    cd.seq = Scratch(c, sizeof(int32_t) * 3 * (size_t)n_cand, st);
-    cd.img = Scratch(c, sizeof(double) * 9 * (size_t)n_cand, st);
-    hipLaunchKernelGGL(k_cand_prep, dim3(nblk(n_cand, 128)), dim3(128), 0, st, cd.keys.as<uint64_t>(), n_cand, sv,
+    cd.seq = Scratch(c, sizeof(int32_t) * KM * (size_t)n_cand, st);
+    cd.img = Scratch(c, sizeof(double) * 3 * KM * (size_t)n_cand, st);
+    hipLaunchKernelGGL(k_cand_prep<KM>, dim3(nblk(n_cand, 128)), dim3(128), 0, st, cd.keys.as<uint64_t>(), n_cand, sv,
                        br.src[0], br.src[1], br.src[2], cd.k.as<int32_t>(), cd.seq.as<int32_t>(),
                        cd.img.as<double>());
     HIP_CHECK(hipGetLastError());
@@ -1382,7 +1566,7 @@ static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& 
     br.n_words = n_words;
     br.mask = Scratch(c, sizeof(uint32_t) * (size_t)(R * n_words), st);
     if (R * n_words > 0) {
-        hipLaunchKernelGGL(k_geo_mask, dim3((unsigned)n_words, nblk(R, 64)), dim3(GEO_B), 0, st, sv, cd.view(),
+        hipLaunchKernelGGL(k_geo_mask<KM>, dim3((unsigned)n_words, nblk(R, 64)), dim3(GEO_B), 0, st, sv, cd.view(),
                            br.src[0], br.src[1], br.src[2], a.rx_dev, R, n_words, br.mask.as<uint32_t>());
         HIP_CHECK(hipGetLastError());
     }
@@ -1396,6 +1580,7 @@ static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& 
 }
 
 // the valid cells in (receiver, candidate) order, legs and field of each path
+template <int KM>
 static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& a, bool brute, bool field,
                          Branch& br, int64_t n, unsigned long long* d_segs)
 {
@@ -1411,7 +1596,7 @@ static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     }
     br.mask.release();
     ps.valid = Scratch(c, (size_t)(n > 0 ? n : 1), st);
-    ps.recs = Scratch(c, sizeof(PathRec) * (size_t)(n > 0 ? n : 1), st);
+    ps.recs = Scratch(c, sizeof(PathRec<KM>) * (size_t)(n > 0 ? n : 1), st);
     if (field) {
         ps.amp = Scratch(c, sizeof(float2) * (size_t)(n > 0 ? n : 1), st);
         ps.len = Scratch(c, sizeof(double) * (size_t)(n > 0 ? n : 1), st);
@@ -1421,11 +1606,11 @@ static void paths_launch(Ctx& c, const SceneView& sv, int stk, const TraceArgs& 
     const double* src = br.src;
     SEL_BOOL(brute, BR,
              SEL_BOOL(field, FI,
-                      SEL_STK(stk, hipLaunchKernelGGL((k_paths<BR, FI, STK>), dim3(nblk(n, LEG_B)), dim3(LEG_B), 0,
+                      SEL_STK(stk, hipLaunchKernelGGL((k_paths<BR, FI, STK, KM>), dim3(nblk(n, LEG_B)), dim3(LEG_B), 0,
                                                       st, sv, cv, a.tc, src[0], src[1], src[2], a.rx_dev,
                                                       ps.cells.as<uint64_t>(), n, ps.valid.as<uint8_t>(),
                                                       ps.amp.as<float2>(), ps.len.as<double>(),
-                                                      ps.recs.as<PathRec>(), d_segs))));
+                                                      ps.recs.as<PathRec<KM>>(), d_segs))));
     HIP_CHECK(hipGetLastError());
 }
 
@@ -1454,9 +1639,21 @@ struct Event {
     hipEvent_t e = nullptr;
     Event() { HIP_CHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming)); }
     ~Event() { (void)hipEventDestroy(e); }
+    Event(const Event&) = delete;
+    Event& operator=(const Event&) = delete;
 };
 
-void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st)
+// events that can time the kernels between them
+struct TimedEvent {
+    hipEvent_t e = nullptr;
+    TimedEvent() { HIP_CHECK(hipEventCreate(&e)); }
+    ~TimedEvent() { (void)hipEventDestroy(e); }
+    TimedEvent(const TimedEvent&) = delete;
+    TimedEvent& operator=(const TimedEvent&) = delete;
+};
+
+template <int KM>
+static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st)
 {
     const SceneView sv = a.scene->view();
     const bool brute = (a.tc.flags & 4) != 0;
@@ -1483,8 +1680,9 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     // 0 discovery segments, 1 legs, 2-4 Tx branch counts, 5-7 centre branch counts,
     // 8-12 work, 13 env paths, 14 leg-walk fallbacks, 15 dummy segments,
     // 16 incoming sequences, 17 incoming element paths
-    Scratch ctr(c, 8 * 18, st);
-    HIP_CHECK(hipMemsetAsync(ctr.p, 0, 8 * 18, st));
+    // 18-20, 21-23: node visits, triangle tests, segments of the counting discovery build (Tx, centre)
+    Scratch ctr(c, 8 * 24, st);
+    HIP_CHECK(hipMemsetAsync(ctr.p, 0, 8 * 24, st));
     unsigned long long* d_ctr = ctr.as<unsigned long long>();
     unsigned long long* d_disc = d_ctr;
     unsigned long long* d_legs = d_ctr + 1;
@@ -1501,6 +1699,13 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     bt.st = st;
     bt.d_cnt = (int64_t*)(d_ctr + 2);
     bt.d_app = d_ctr + 3;
+    bt.d_work = d_ctr + 18;
+    const bool time_disc = timing && (a.tc.flags & 512) != 0;
+    std::unique_ptr<TimedEvent[]> ev_d(time_disc ? new TimedEvent[4] : nullptr);   // created only when asked for
+    if (time_disc) {
+        bt.ev_disc[0] = ev_d[0].e;
+        bt.ev_disc[1] = ev_d[1].e;
+    }
     const bool two = a.ris != nullptr;
     Event fork, join;
     SideStream side(c);   // returned to the pool after the join below
@@ -1511,6 +1716,11 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         bu.st = side.s;
         bu.d_cnt = (int64_t*)(d_ctr + 5);
         bu.d_app = d_ctr + 6;
+        bu.d_work = d_ctr + 21;
+        if (time_disc) {
+            bu.ev_disc[0] = ev_d[2].e;
+            bu.ev_disc[1] = ev_d[3].e;
+        }
     }
     // both hash sets are cleared here, ahead of either discovery (a clear queued
     // behind the other branch's discovery waits for free compute units)
@@ -1523,8 +1733,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         HIP_CHECK(hipStreamWaitEvent(bu.st, fork.e, 0));
     }
     // 1-3: candidates
-    cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
-    if (two) cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
+    cand_phase_a<KM>(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
+    if (two) cand_phase_a<KM>(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
     // Each branch goes on as soon as its own count is back, so the Tx branch
     // (launched first) does not wait for the centre branch's discovery.  An
     // overflow of a hash set repeats phase A with the next level (the
@@ -1535,21 +1745,17 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         while (n < 0) {
             br.table_level += 1;
             HIP_CHECK(hipMemsetAsync(br.d_app, 0, 2 * sizeof(unsigned long long), br.st));
-            cand_phase_a(c, sv, stk, a, brute, exhaustive, keep_hits, ch, br, d_dummy);
+            cand_phase_a<KM>(c, sv, stk, a, brute, exhaustive, keep_hits, ch, br, d_dummy);
             n = cand_count(c, br, exhaustive);
         }
         return n;
     };
-    const int64_t n_tx = count_of(bt);
-    cand_phase_b(c, a, exhaustive, bt, n_tx);
+    const int64_t n_tx = cand_phase_b(c, a, exhaustive, bt, count_of(bt));
     tm.mark();   // 2
     // 4: geometry of every (receiver, candidate)
-    geo_launch(c, sv, a, bt, n_tx);
-    const int64_t n_u0 = two ? count_of(bu) : 0;
-    if (two) {
-        cand_phase_b(c, a, exhaustive, bu, n_u0);
-        geo_launch(c, sv, a, bu, n_u0);
-    }
+    geo_launch<KM>(c, sv, a, bt, n_tx);
+    const int64_t n_u0 = two ? cand_phase_b(c, a, exhaustive, bu, count_of(bu)) : 0;
+    if (two) geo_launch<KM>(c, sv, a, bu, n_u0);
     out.n_cand_tx = n_tx;
     out.n_cand_u = n_u0;
     // the field reaching every element, on its own stream (forked here, launched
@@ -1566,11 +1772,11 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     }
     // 5-6: legs and fields
     const int64_t g_tx = read_i64(bt.ps.rstart.as<int64_t>() + R, st);
-    paths_launch(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
+    paths_launch<KM>(c, sv, stk, a, brute, true, bt, g_tx, d_legs);
     const int64_t g_u = two ? read_i64(bu.ps.rstart.as<int64_t>() + R, bu.st) : 0;
-    if (two) paths_launch(c, sv, stk, a, brute, false, bu, g_u, d_legs);
+    if (two) paths_launch<KM>(c, sv, stk, a, brute, false, bu, g_u, d_legs);
     if (a.ris) {
-        ris_incident(c, sv, stk, a, brute, incoming, bt, rv, d_ctr, txm.as<TxmRec>(), side_in.s);
+        ris_incident<KM>(c, sv, stk, a, brute, incoming, bt, rv, d_ctr, txm.as<TxmRec>(), side_in.s);
         HIP_CHECK(hipEventRecord(in_ready.e, side_in.s));
     }
 
@@ -1588,7 +1794,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             const int64_t n_env = read_i64((const int64_t*)(d_ctr + 13), st);
             ch.env = Scratch(c, sizeof(EnvRec) * (size_t)n_env, st);
             if (ps.n > 0) {
-                hipLaunchKernelGGL(k_env_compact, dim3(nblk(ps.n, 128)), dim3(128), 0, st, ps.recs.as<PathRec>(),
+                hipLaunchKernelGGL(k_env_compact<KM>, dim3(nblk(ps.n, 128)), dim3(128), 0, st, ps.recs.as<PathRec<KM>>(),
                                    bt.cd.view(), ps.valid.as<uint8_t>(), off2.as<int64_t>(), ps.amp.as<float2>(),
                                    ps.len.as<double>(), ps.n, ch.env.as<EnvRec>());
                 HIP_CHECK(hipGetLastError());
@@ -1609,15 +1815,15 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         hipStream_t su = bu.st;
         Scratch f2(c, (size_t)(ps.n > 0 ? ps.n : 1), su), off2(c, sizeof(int64_t) * (size_t)(ps.n > 0 ? ps.n : 1), su);
         if (ps.n > 0) {
-            hipLaunchKernelGGL(k_u_flags, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec>(),
+            hipLaunchKernelGGL(k_u_flags<KM>, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec<KM>>(),
                                ps.valid.as<uint8_t>(), ps.n, f2.as<uint8_t>());
             HIP_CHECK(hipGetLastError());
         }
         scan_flags(c, f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, bu.d_cnt, su);
         // rows for every geometric path (an upper bound of the valid ones)
-        useq = Scratch(c, sizeof(int32_t) * 8 * (size_t)(ps.n > 0 ? ps.n : 1), su);
+        useq = Scratch(c, sizeof(int32_t) * useq_stride(KM) * (size_t)(ps.n > 0 ? ps.n : 1), su);
         if (ps.n > 0) {
-            hipLaunchKernelGGL(k_u_compact, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec>(),
+            hipLaunchKernelGGL(k_u_compact<KM>, dim3(nblk(ps.n, 256)), dim3(256), 0, su, ps.recs.as<PathRec<KM>>(),
                                bu.cd.view(), f2.as<uint8_t>(), off2.as<int64_t>(), ps.n, useq.as<int32_t>());
             HIP_CHECK(hipGetLastError());
         }
@@ -1650,7 +1856,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         Scratch order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), st);
         if (R > 0) {
             Scratch cost(c, sizeof(uint64_t) * (size_t)R, st);
-            hipLaunchKernelGGL(k_ris_order, dim3(nblk(R, 256)), dim3(256), 0, st, uptr.as<int64_t>(),
+            hipLaunchKernelGGL(k_ris_order<KM>, dim3(nblk(R, 256)), dim3(256), 0, st, uptr.as<int64_t>(),
                                useq.as<int32_t>(), R, cost.as<uint64_t>());
             HIP_CHECK(hipGetLastError());
             sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, st);
@@ -1658,7 +1864,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         tm.mark(true);   // 5
         if (threads > 0) {
             if (count_work && !brute && !keep_paths && !keep_cir) {
-                SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false>), dim3(nblk(threads, RIS_B)),
+                SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false, KM>), dim3(nblk(threads, RIS_B)),
                                                 dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                 uptr.as<int64_t>(), useq.as<int32_t>(), order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
                                                 ch.ris_valid.as<uint8_t>(), (float2*)nullptr, (double*)nullptr, d_legs,
@@ -1666,7 +1872,7 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             } else {
                 SEL_BOOL(fresnel, FR, SEL_BOOL(brute, BR,
                          SEL_BOOL(keep_paths || keep_cir, KP,
-                                  SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false, FR>),
+                                  SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false, FR, KM>),
                                                                   dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, st, sv,
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                                   uptr.as<int64_t>(), useq.as<int32_t>(),
@@ -1684,7 +1890,9 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         }
         if (keep_cir) ch.cir_uptr = std::move(uptr);
     }
-    if (keep_paths) {
+    ch.key_words = key_words(a.tc.K);
+    ch.useq_stride = useq_stride(KM);
+    if (keep_paths || keep_hits) {   // the candidate keys are small: kept with either flag
         ch.n_cand[0] = bt.cd.n;
         ch.cand_keys[0] = std::move(bt.cd.keys);
         if (two) {
@@ -1699,8 +1907,8 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
             p->st = st;
         if (!keep_paths) useq.st = st;
     }
-    int64_t h[18];
-    read_i64s((const int64_t*)d_ctr, h, 18, st);
+    int64_t h[24];
+    read_i64s((const int64_t*)d_ctr, h, 24, st);
     tm.mark();   // 7
     out.disc_segments = h[0];
     out.leg_segments = h[1];
@@ -1715,6 +1923,30 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
     out.leg_walk_fallbacks = h[14];
     out.n_in_seq = incoming && a.ris ? h[16] : 0;
     out.n_in_paths = incoming && a.ris ? h[17] : 0;
+    for (int q = 0; q < 6; ++q) out.disc_work[q] = h[18 + q];
+    if (time_disc) {   // the repeats of phase A after a hash-set overflow are not timed separately
+        HIP_CHECK(hipStreamSynchronize(st));
+        auto el = [&](int i, int j) {
+            float ms = 0.0f;
+            if (hipEventElapsedTime(&ms, ev_d[i].e, ev_d[j].e) != hipSuccess) {
+                (void)hipGetLastError();
+                return -1.0f;
+            }
+            return ms;
+        };
+        out.ms_disc[0] = fmaxf(el(0, 1), 0.0f);
+        if (two) {
+            out.ms_disc[1] = fmaxf(el(2, 3), 0.0f);
+            // span of both launches: from the earlier start to the later end (the two streams overlap)
+            const float start_gap = el(0, 2);   // > 0: the Tx launch started first
+            const float t_first = start_gap >= 0.0f ? 0.0f : -start_gap;
+            const float end_tx = t_first + out.ms_disc[0];
+            const float end_u = (start_gap >= 0.0f ? start_gap : 0.0f) + out.ms_disc[1];
+            out.ms_disc[2] = fmaxf(end_tx, end_u);
+        } else {
+            out.ms_disc[2] = out.ms_disc[0];
+        }
+    }
     if (timing) {
         HIP_CHECK(hipStreamSynchronize(st));
         auto el = [&](int i, int j) {
@@ -1732,6 +1964,14 @@ void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, 
         out.ms[7] = el(0, 7);                  // total
     }
     ch.last_stream = st;
+}
+
+void trace(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, bool timing, hipStream_t st)
+{
+    if (a.tc.K <= RT_KM_SMALL)
+        trace_km<RT_KM_SMALL>(c, a, ch, out, timing, st);
+    else
+        trace_km<RT_MAX_K>(c, a, ch, out, timing, st);
 }
 
 // --------------------------------------------------------------------------

@@ -39,7 +39,7 @@ FLAG_FRESNEL_TM = 128
 FLAG_KEEP_CIR = 256
 FLAG_STAGE_TIMES = 512
 
-MAX_ORDER = 3   # largest reflection order rt_trace accepts
+MAX_ORDER = 5   # largest reflection order rt_trace accepts (RT_MAX_ORDER)
 
 PREC_VALU_F32 = 0
 PREC_MFMA_BF16X2 = 1
@@ -51,7 +51,7 @@ ENTRY_POINTS = (
     "rt_last_error", "rt_init", "rt_shutdown", "rt_mem_info", "rt_scene_create", "rt_ris_create",
     "rt_trace", "rt_channel_create", "rt_channel_info", "rt_channel_read", "rt_hits_read",
     "rt_paths_read", "rt_candidates_read", "rt_ris_sum", "rt_destroy", "rt_scene_set_materials", "rt_cir",
-    "rt_ris_paths_read", "rt_ris_sum_noalloc", "rt_keys_sort",
+    "rt_ris_paths_read", "rt_ris_sum_noalloc", "rt_keys_sort", "rt_scene_info",
 )
 
 
@@ -76,21 +76,23 @@ class RtStats(ctypes.Structure):
                 ("n_env_paths", ctypes.c_int64), ("n_u_paths", ctypes.c_int64), ("n_ris_slots", ctypes.c_int64),
                 ("ms_stage", ctypes.c_float * 8), ("ris_work", ctypes.c_int64 * 5),
                 ("leg_walk_fallbacks", ctypes.c_int64), ("n_in_seq", ctypes.c_int64),
-                ("n_in_paths", ctypes.c_int64)]
+                ("n_in_paths", ctypes.c_int64), ("discovery_work", ctypes.c_int64 * 6),
+                ("ms_discovery", ctypes.c_float * 3)]
 
     def as_dict(self):
-        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in ("ms_stage", "ris_work")}
-        d["ms_stage"] = list(self.ms_stage)
-        d["ris_work"] = list(self.ris_work)
+        arrays = ("ms_stage", "ris_work", "discovery_work", "ms_discovery")
+        d = {f: getattr(self, f) for f, _ in self._fields_ if f not in arrays}
+        for f in arrays:
+            d[f] = list(getattr(self, f))
         return d
 
 
 class RtEnvPath(ctypes.Structure):
-    _fields_ = [("rx", ctypes.c_int32), ("order", ctypes.c_int32), ("seq", ctypes.c_int32 * 3),
-                ("tri", ctypes.c_int32 * 3), ("length", ctypes.c_double), ("amp", ctypes.c_float * 2)]
+    _fields_ = [("rx", ctypes.c_int32), ("order", ctypes.c_int32), ("seq", ctypes.c_int32 * MAX_ORDER),
+                ("tri", ctypes.c_int32 * MAX_ORDER), ("length", ctypes.c_double), ("amp", ctypes.c_float * 2)]
 
 
-ENV_DTYPE = np.dtype([("rx", "<i4"), ("order", "<i4"), ("seq", "<i4", 3), ("tri", "<i4", 3),
+ENV_DTYPE = np.dtype([("rx", "<i4"), ("order", "<i4"), ("seq", "<i4", MAX_ORDER), ("tri", "<i4", MAX_ORDER),
                       ("length", "<f8"), ("amp", "<f4", 2)])
 assert ENV_DTYPE.itemsize == ctypes.sizeof(RtEnvPath)
 
@@ -144,6 +146,7 @@ def lib():
                                                     ctypes.c_int32, P, P, P]),
             "rt_keys_sort": (ctypes.c_int32, [P, P, i64, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
                                               ctypes.c_int32, pi64, P]),
+            "rt_scene_info": (ctypes.c_int32, [P, u64, pi64, pi64, ctypes.POINTER(ctypes.c_int32), pu64]),
             "rt_destroy": (ctypes.c_int32, [P, u64]),
             "rt_scene_set_materials": (ctypes.c_int32, [P, u64, P, P, P]),
             "rt_cir": (ctypes.c_int32, [P, u64, P, ctypes.c_double, i64, P, P]),
@@ -270,6 +273,13 @@ class Context:
                                      arg(refl_im, np.float32), _stream_handle(stream), ctypes.byref(h)))
         return h.value
 
+    def scene_info(self, scene: int) -> dict:
+        nt, ns, b = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_uint64()
+        d = ctypes.c_int32()
+        _check(lib().rt_scene_info(self._h, ctypes.c_uint64(scene), ctypes.byref(nt), ctypes.byref(ns),
+                                   ctypes.byref(d), ctypes.byref(b)))
+        return {"n_tri": nt.value, "n_surf": ns.value, "bvh_depth": d.value, "bytes": b.value}
+
     def scene_set_materials(self, scene: int, eps_r, sigma, stream=None) -> None:
         """Per-triangle relative permittivity and conductivity (S/m) for the
         Fresnel flags; NumPy (host) or torch device arrays."""
@@ -351,7 +361,7 @@ class Context:
     def candidates_read(self, ch: int, source: int):
         n = ctypes.c_int64()
         _check(lib().rt_candidates_read(self._h, ch, source, None, 0, ctypes.byref(n)))
-        out = np.zeros((n.value, 3), np.int32)
+        out = np.zeros((n.value, MAX_ORDER), np.int32)
         _check(lib().rt_candidates_read(self._h, ch, source, _ptr(out), out.size, ctypes.byref(n)))
         return out
 
@@ -361,7 +371,7 @@ class Context:
         _check(lib().rt_paths_read(self._h, ch, None, 0, ctypes.byref(ne), None, 0, ctypes.byref(nu), None, 0,
                                    ctypes.byref(ns)))
         env = np.zeros(ne.value, ENV_DTYPE)
-        useq = np.zeros((nu.value, 4), np.int32)
+        useq = np.zeros((nu.value, 1 + MAX_ORDER), np.int32)
         valid = np.zeros((ns.value, M), np.uint8)
         _check(lib().rt_paths_read(self._h, ch, _ptr(env) if env.size else None, ne.value, ctypes.byref(ne),
                                    _ptr(useq) if useq.size else None, nu.value, ctypes.byref(nu),

@@ -483,3 +483,181 @@ def paper_spherical(u, r: float, phi_deg: float, theta_deg: float) -> np.ndarray
     u = np.asarray(u, np.float64)
     return u + r * np.array([math.sin(th) * math.cos(ph), math.sin(th) * math.sin(ph),
                              math.cos(th)])
+
+
+# --------------------------------------------------------------------------
+# large scene: an office floor
+# --------------------------------------------------------------------------
+def _face_grid(p0, pu, pv, nu: int, nv: int):
+    """Vertices and triangles of the rectangle p0 + a pu + b pv, a, b in
+    [0, 1], cut into nu x nv quads, each split along its (0,0)-(1,1)
+    diagonal (vertices shared inside the face).  Returns float64 vertices
+    [(nu+1)(nv+1), 3] and int64 triangles [2 nu nv, 3] (local indices)."""
+    a = np.arange(nu + 1) / nu
+    b = np.arange(nv + 1) / nv
+    V = (np.asarray(p0, np.float64)[None, None, :] + a[:, None, None] * np.asarray(pu, np.float64)
+         + b[None, :, None] * np.asarray(pv, np.float64)).reshape(-1, 3)
+    i, j = np.meshgrid(np.arange(nu), np.arange(nv), indexing="ij")
+    c00 = (i * (nv + 1) + j).ravel()
+    c10 = ((i + 1) * (nv + 1) + j).ravel()
+    c11 = ((i + 1) * (nv + 1) + j + 1).ravel()
+    c01 = (i * (nv + 1) + j + 1).ravel()
+    T = np.stack([np.stack([c00, c10, c11], 1), np.stack([c00, c11, c01], 1)], 1).reshape(-1, 3)
+    return V, T
+
+
+class FastMesh:
+    """Mesh accumulated face by face with numpy (one surface per face, one
+    reflection coefficient per object): for scenes of 10^5-10^6 triangles."""
+
+    def __init__(self) -> None:
+        self.V, self.T, self.surf, self.coef = [], [], [], []
+        self.nv = 0
+        self.ns = 0
+
+    def face(self, p0, pu, pv, size_u: float, size_v: float, cell: float, coef: complex) -> None:
+        nu = max(1, int(round(size_u / cell)))
+        nv = max(1, int(round(size_v / cell)))
+        V, T = _face_grid(p0, pu, pv, nu, nv)
+        self.V.append(V)
+        self.T.append(T + self.nv)
+        self.surf.append(np.full(T.shape[0], self.ns, np.int32))
+        self.coef.append(np.full(T.shape[0], coef, np.complex128))
+        self.nv += V.shape[0]
+        self.ns += 1
+
+    def box(self, lo, hi, cell: float, coef: complex, bottom: bool = False, top: bool = False) -> None:
+        x0, y0, z0 = lo
+        x1, y1, z1 = hi
+        dx, dy, dz = x1 - x0, y1 - y0, z1 - z0
+        self.face((x0, y0, z0), (0, dy, 0), (0, 0, dz), dy, dz, cell, coef)   # x = x0
+        self.face((x1, y0, z0), (0, dy, 0), (0, 0, dz), dy, dz, cell, coef)   # x = x1
+        self.face((x0, y0, z0), (dx, 0, 0), (0, 0, dz), dx, dz, cell, coef)   # y = y0
+        self.face((x0, y1, z0), (dx, 0, 0), (0, 0, dz), dx, dz, cell, coef)   # y = y1
+        if bottom:
+            self.face((x0, y0, z0), (dx, 0, 0), (0, dy, 0), dx, dy, cell, coef)
+        if top:
+            self.face((x0, y0, z1), (dx, 0, 0), (0, dy, 0), dx, dy, cell, coef)
+
+    def build(self) -> Scene:
+        c = np.concatenate(self.coef)
+        return Scene(np.concatenate(self.V).astype(np.float32), np.concatenate(self.T).astype(np.int32),
+                     c.real.astype(np.float32), c.imag.astype(np.float32), np.concatenate(self.surf))
+
+
+def office_floor_scene(rng, nx: int = 20, ny: int = 10, room: float = 2.0, height: float = 3.0,
+                       wall: float = 0.1, door: float = 0.8, p_door: float = 0.6, clutter: int = 2,
+                       cell_wall: float = 0.18, cell_floor: float = 0.1, cell_clutter: float = 0.08,
+                       coef=(0.2, 0.8)) -> Scene:
+    """An office floor of nx x ny rooms of room x room metres (40 x 20 x 3 m
+    for the defaults), like SURVEY's large configuration: floor and ceiling
+    tiles per room; partitions between neighbouring rooms as wall-thick boxes
+    from floor to ceiling, a seeded fraction of them with a door gap (two
+    boxes); the outer walls as boxes; `clutter` furniture boxes per room
+    (desks and cabinets, bottom face omitted).  Faces are meshed with square
+    cells of about cell_* metres; each face is one surface; reflection
+    coefficient U(coef) per object."""
+    fm = FastMesh()
+    L, W = nx * room, ny * room
+
+    def cf():
+        return complex(rng.uniform(*coef))
+
+    for i in range(nx):
+        for j in range(ny):
+            x0, y0 = i * room, j * room
+            fm.face((x0, y0, 0.0), (room, 0, 0), (0, room, 0), room, room, cell_floor, cf())       # floor tile
+            fm.face((x0, y0, height), (room, 0, 0), (0, room, 0), room, room, cell_floor, cf())    # ceiling tile
+    h = wall / 2
+
+    def partition(p_lo, p_hi, along_x: bool, with_door: bool):
+        c = cf()
+        if along_x:   # wall along x at y = p_lo[1]
+            (xa, y), (xb, _) = p_lo, p_hi
+            segs = [(xa, xb)] if not with_door else [(xa, (xa + xb - door) / 2), ((xa + xb + door) / 2, xb)]
+            for a, b in segs:
+                fm.box((a, y - h, 0.0), (b, y + h, height), cell_wall, c)
+        else:         # wall along y at x = p_lo[0]
+            (x, ya), (_, yb) = p_lo, p_hi
+            segs = [(ya, yb)] if not with_door else [(ya, (ya + yb - door) / 2), ((ya + yb + door) / 2, yb)]
+            for a, b in segs:
+                fm.box((x - h, a, 0.0), (x + h, b, height), cell_wall, c)
+
+    # inner partitions (door gaps seeded) and the outer walls (closed)
+    for i in range(1, nx):
+        for j in range(ny):
+            partition((i * room, j * room + h), (i * room, (j + 1) * room - h), False, rng.uniform() < p_door)
+    for j in range(1, ny):
+        for i in range(nx):
+            partition((i * room + h, j * room), ((i + 1) * room - h, j * room), True, rng.uniform() < p_door)
+    for j in range(ny):
+        partition((0.0, j * room + h), (0.0, (j + 1) * room - h), False, False)
+        partition((L, j * room + h), (L, (j + 1) * room - h), False, False)
+    for i in range(nx):
+        partition((i * room + h, 0.0), ((i + 1) * room - h, 0.0), True, False)
+        partition((i * room + h, W), ((i + 1) * room - h, W), True, False)
+    # clutter: desks and cabinets, kept 0.3 m off the walls
+    for i in range(nx):
+        for j in range(ny):
+            for _ in range(clutter):
+                w, d = rng.uniform(0.4, 1.2), rng.uniform(0.3, 0.8)
+                hh = rng.uniform(0.7, 1.8)
+                x0 = i * room + rng.uniform(0.3, room - 0.3 - w)
+                y0 = j * room + rng.uniform(0.3, room - 0.3 - d)
+                fm.box((x0, y0, 0.0), (x0 + w, y0 + d, hh), cell_clutter, cf(), top=True)
+    return fm.build()
+
+
+def office_floor(seed: int = BASE_SEED + 4, n_rays: int = 10_000_000, order: int = 5, n_rx: int = 256,
+                 n_side: int = 64, rx_region=None, n_cfg: int = 1, **scene_kw) -> Problem:
+    """SURVEY's large configuration: the office floor (about 10^6 triangles
+    with the defaults), 28 GHz, a 64 x 64 square RIS (lambda/2) 1 mm in front
+    of the partition wall x = 10 m of room (4, 4) facing -x, a horn Tx
+    (cos^8, G_t = 18) in that room aimed at the RIS centre, an n_rx x n_rx
+    isotropic receiver grid at 1.2 m over the floor (or over rx_region =
+    (x0, x1, y0, y1)), reflections up to `order`, n_rays discovery rays per
+    source."""
+    rng = np.random.default_rng(seed)
+    freq = 28e9
+    lam = C0 / freq
+    scene = office_floor_scene(rng, **scene_kw)
+    normal = np.array([-1.0, 0.0, 0.0])
+    centre = np.array([10.0 - 0.05 - 0.001, 9.0, 1.5])
+    elems = square_ris(n_side, n_side, lam / 2, centre, normal)
+    ris = Ris(elems, normal, centre, lam / 2, lam / 2, math.pi, 3.0)
+    tx = np.array([8.35, 8.35, 2.5])
+    x0, x1, y0, y1 = rx_region if rx_region is not None else (0.15, 39.85, 0.15, 19.85)
+    rx = rx_grid(x0, x1, n_rx, y0, y1, n_rx, 1.2, 3e-4, rng)
+    gamma = gamma_binary(elems.shape[0], n_cfg, 0.9, rng)
+    return Problem("office_floor", scene, freq, tx, 0.01,
+                   Antenna(unit(centre - tx), 18.0, PAT_COSPOW, 8.0), ris, rx,
+                   Antenna(np.array([0.0, 0.0, 1.0]), 1.0, PAT_ISO, 0.0),
+                   order, n_rays, seed, gamma)
+
+
+def deep_tree_room(seed: int = BASE_SEED + 6, n_rays: int = 20_000, order: int = 2, chain: int = 48,
+                   nx: int = 6, ny: int = 5) -> Problem:
+    """The lab room (bounds [0, 6] x [0, 5] x [0, 3] m) with a chain of tiny
+    triangles (1 um, each a surface of its own) near its corner (0, 0, 0):
+    element i has its centroid at the centre of the Morton cell whose 63-bit
+    code is 2^(62 - i), i.e. one axis at (2^(20 - i//3) + 1/2) ext / 2^21 and
+    the other two at ext / 2^22.  No other triangle comes within a few cm of
+    the corner, so below the first few levels every level of the Morton order
+    splits off one chain element and the BVH is about `chain` levels deeper
+    than the room's own: the traversal kernels' 64-entry-stack instances."""
+    rng = np.random.default_rng(seed)
+    base = lab_room(seed=BASE_SEED + 1, n_rays=n_rays, order=order, nx=nx, ny=ny)
+    ext = np.array([6.0, 5.0, 3.0])
+    V, T = [], []
+    for i in range(chain):
+        q = np.zeros(3)
+        q[i % 3] = 2.0 ** (20 - i // 3)
+        c = (q + 0.5) * ext / 2.0 ** 21
+        d = 1e-6
+        V.extend([c + [d, 0.0, 0.0], c + [-0.5 * d, 0.866 * d, 0.0], c + [-0.5 * d, -0.866 * d, 0.0]])
+        T.append([3 * i, 3 * i + 1, 3 * i + 2])
+    coef = rng.uniform(0.3, 0.7, size=chain).astype(np.float32)
+    tiny = Scene(np.asarray(V, np.float32), np.asarray(T, np.int32), coef, np.zeros(chain, np.float32),
+                 np.arange(chain, dtype=np.int32))
+    scene = concat_scenes(base.scene, tiny)
+    return dataclasses.replace(base, name="deep_tree_room", scene=scene)

@@ -1,6 +1,8 @@
 // Host check of the LBVH node construction used by the build kernel:
-// for sorted unique keys, every internal node except the root and every leaf
-// has exactly one parent, and every node's leaves form a contiguous range.
+// for sorted unique keys (one word, or two words as the build uses them:
+// triangle index in word 0, Morton code in word 1), every internal node
+// except the root and every leaf has exactly one parent, and every node's
+// leaves form a contiguous range.
 #include <stdint.h>
 #include <stdio.h>
 #include <stdlib.h>
@@ -11,15 +13,23 @@
 
 #include "../../paper_2402_13034_amd/csrc/rt_lbvh_core.hpp"
 
-static int check(std::vector<uint64_t> keys)
+// keys: W words per key; sorted and made unique here (lexicographic from the top word)
+template <int W>
+static int check(std::vector<uint64_t> flat)
 {
-    std::sort(keys.begin(), keys.end());
-    keys.erase(std::unique(keys.begin(), keys.end()), keys.end());
-    int64_t n = (int64_t)keys.size();
+    std::vector<std::vector<uint64_t>> rows(flat.size() / W);
+    for (size_t i = 0; i < rows.size(); ++i)
+        for (int w = W - 1; w >= 0; --w) rows[i].push_back(flat[W * i + w]);   // most significant first
+    std::sort(rows.begin(), rows.end());
+    rows.erase(std::unique(rows.begin(), rows.end()), rows.end());
+    std::vector<uint64_t> keys;
+    for (auto& r : rows)
+        for (int w = W - 1; w >= 0; --w) keys.push_back(r[w]);   // back to word 0 first
+    int64_t n = (int64_t)rows.size();
     if (n < 2) return 0;
     std::vector<int32_t> cl(n - 1), cr(n - 1), pin(n - 1, 0), pleaf(n, 0);
     for (int64_t i = 0; i < n - 1; ++i) {
-        rt::lbvh_node(keys.data(), n, i, &cl[i], &cr[i]);
+        rt::lbvh_node<W>(keys.data(), n, i, &cl[i], &cr[i]);
         for (int32_t c : {cl[i], cr[i]}) {
             if (c < 0) {
                 if (~c >= n) return 1;
@@ -64,15 +74,19 @@ int main()
     int fails = 0;
     for (int trial = 0; trial < 40; ++trial) {
         int64_t n = 2 + (int64_t)(rng() % (trial < 20 ? 50 : 100000));
-        std::vector<uint64_t> keys(n);
+        std::vector<uint64_t> keys(n), keys2(2 * n);
         int dup_bits = (int)(rng() % 30);
+        int dup_bits2 = (int)(rng() % 63);
         for (int64_t i = 0; i < n; ++i) {
             uint64_t m = (rng() & 0x3fffffffull) >> dup_bits << dup_bits;   // many equal Morton codes
             keys[i] = (m << 32) | (uint64_t)i;
+            keys2[2 * i] = (uint64_t)i;                                        // index, then a 63-bit code
+            keys2[2 * i + 1] = (rng() & 0x7fffffffffffffffull) >> dup_bits2 << dup_bits2;
         }
-        int r = check(keys);
-        if (r) {
-            printf("FAIL trial %d n=%lld code %d\n", trial, (long long)n, r);
+        int r = check<1>(keys);
+        int r2 = check<2>(keys2);
+        if (r || r2) {
+            printf("FAIL trial %d n=%lld code %d / %d\n", trial, (long long)n, r, r2);
             fails++;
         }
     }

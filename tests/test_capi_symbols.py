@@ -31,9 +31,9 @@ def test_library_exports_every_declared_symbol():
 
 def test_env_record_layout_matches_header():
     from paper_2402_13034_amd import risrt
-    assert ctypes.sizeof(risrt.RtEnvPath) == 48
-    assert risrt.ENV_DTYPE.itemsize == 48
-    assert ctypes.sizeof(risrt.RtStats) == 8 * 8 + 8 * 4 + 5 * 8 + 3 * 8
+    assert ctypes.sizeof(risrt.RtEnvPath) == 64
+    assert risrt.ENV_DTYPE.itemsize == 64
+    assert ctypes.sizeof(risrt.RtStats) == 8 * 8 + 8 * 4 + 5 * 8 + 3 * 8 + 6 * 8 + 3 * 4 + 4   # padded to 8
 
 
 def test_last_error_callable_without_device():

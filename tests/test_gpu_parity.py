@@ -147,6 +147,38 @@ def test_tiny_box_order3_ragged(ctx):
     check_problem(ctx, synth.tiny_box(order=3, n_rx=37, n_rays=3001))
 
 
+@pytest.mark.parametrize("K", [4, 5])
+def test_tiny_box_high_order(ctx, K):
+    """Orders 4 and 5: two-word candidate keys and the order-5 kernel
+    instances; BVH and brute force."""
+    prob = synth.tiny_box(order=K, n_rx=19, n_rays=3001)
+    st = check_problem(ctx, prob)
+    # discovery finds a subset of the box lattice's 129 (order <= 4) or 231 (<= 5) paths per receiver
+    lattice = 19 * (129 if K == 4 else 231)
+    assert 0.95 * lattice <= st["n_env_paths"] <= lattice
+    check_problem(ctx, prob, brute=True)
+
+
+def test_tiny_box_order5_exhaustive_and_incoming(ctx):
+    from paper_2402_13034_amd import risrt
+    prob = synth.tiny_box(order=5, n_rx=7)
+    scene, ris, ch, st = _run(ctx, prob, risrt.FLAG_KEEP_PATHS | risrt.FLAG_EXHAUSTIVE)
+    ref = O.trace(prob, mode="exhaustive")
+    assert np.array_equal(ctx.candidates_read(ch, 0)[:, :5], ref["cand_tx"])
+    E, H = ctx.channel_read(ch)
+    R, M = H.shape
+    sl, mm = ref["ris_amp_idx"][:, 0], ref["ris_amp_idx"][:, 1]
+    _close_complex(H, ref["H"], _incoherent((ref["ris_slot_rx"][sl], mm), ref["ris_amp"], (R, M)))
+    assert np.array_equal(ctx.paths_read(ch)["ris_valid"], ref["ris_valid"])
+    for h in (ch, scene, ris):
+        ctx.destroy(h)
+    check_problem(ctx, synth.with_materials(synth.tiny_box(order=4, n_rx=9), 2), incoming=True)
+
+
+def test_lab_room_order4_reduced(ctx):
+    check_problem(ctx, synth.lab_room(nx=5, ny=4, order=4), n_rays=20_000)
+
+
 def test_lab_room_reduced(ctx):
     check_problem(ctx, synth.lab_room(nx=9, ny=7), n_rays=20_000)
 
@@ -310,6 +342,23 @@ def test_sparse_array_leg_walk_fallback(ctx):
     on-chip lists and walks leg by leg; results stay exact."""
     st = check_problem(ctx, synth.wide_ris_room())
     assert st["leg_walk_fallbacks"] > 0
+
+
+def test_deep_tree_stack64(ctx):
+    """A BVH deeper than 31 levels (a chain of tiny triangles nested towards a
+    corner): the traversal kernels take their 64-entry-stack instances, and
+    every result still matches the oracle and the brute-force walk."""
+    prob = synth.deep_tree_room()
+    from paper_2402_13034_amd import risrt
+    scene, ris = risrt.upload_problem(ctx, prob)
+    info = ctx.scene_info(scene)
+    _say("deep tree: depth", info["bvh_depth"], "triangles", info["n_tri"])
+    assert info["bvh_depth"] >= 31 and info["n_tri"] == prob.scene.n_tri
+    for h in (scene, ris):
+        ctx.destroy(h)
+    check_problem(ctx, prob)
+    check_problem(ctx, prob, incoming=True)
+    check_problem(ctx, prob, brute=True)
 
 
 @pytest.mark.parametrize("sub", [3, 5])

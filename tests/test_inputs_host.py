@@ -35,6 +35,8 @@ def _check_scene(sc):
     lambda: synth.precision_problem(n_cfg=1).scene,
     lambda: synth.paper_room(reflective=True).scene,
     lambda: synth.paper_room(reflective=False).scene,
+    lambda: synth.deep_tree_room().scene,
+    lambda: synth.office_floor(n_rx=2).scene,
 ])
 def test_generated_scenes_meet_the_input_contract(make):
     _check_scene(make())

@@ -51,3 +51,20 @@ def test_escape_count_helper():
     hits = np.array([[1, 2, 3], [1, -1, -1], [-1, -1, -1], [4, 5, -1]], np.int32)
     assert reports.escapes(hits, 3) == 3
     assert reports.escapes(hits, 3, np.array([True, True, False, False])) == 1
+
+
+def test_oracle_bvh_equals_brute_force():
+    """The oracle's median-split BVH (for scenes too large for brute force)
+    takes exactly the brute-force decisions: hit lists of both sources,
+    candidates, paths, element-path validity and fields on the lab room."""
+    prob = synth.lab_room(nx=6, ny=5)
+    a = O.trace(prob, n_rays=60_000)
+    with O.accelerated():
+        b = O.trace(prob, n_rays=60_000)
+    for k in ("hits_tx", "hits_u", "cand_tx", "cand_u", "env_rx", "env_seq", "env_tri", "u_seq", "ris_valid"):
+        assert np.array_equal(a[k], b[k]), k
+    assert np.array_equal(a["H"], b["H"]) and np.array_equal(a["E_env"], b["E_env"])
+    # a trace that reuses the oracle's own hit lists gives the same channel
+    with O.accelerated():
+        c = O.trace(prob, n_rays=60_000, hits=(a["hits_tx"], a["hits_u"]))
+    assert np.array_equal(a["H"], c["H"]) and np.array_equal(a["cand_u"], c["cand_u"])

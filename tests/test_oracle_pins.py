@@ -253,7 +253,7 @@ def lattice_ris(prob, L, R0):
     return H, counts
 
 
-@pytest.mark.parametrize("K", [1, 2, 3])
+@pytest.mark.parametrize("K", [1, 2, 3, 4, 5])
 def test_box_lattice_env(K):
     prob, L, R0 = _box_problem(K)
     r = O.trace(prob, mode="exhaustive")
@@ -264,9 +264,10 @@ def test_box_lattice_env(K):
 
 
 def test_box_lattice_counts_isotropic():
-    """Orders 0..3: 1 + sum(4k^2 + 2) = 1/7/25/63 environment paths and, for
-    an element on a wall, sum(2k^2 + 2k + 1) = 1/6/19/44 element paths."""
-    for K, env_n, ris_n in [(1, 7, 6), (2, 25, 19), (3, 63, 44)]:
+    """Orders 0..5: 1 + sum(4k^2 + 2) = 1/7/25/63/129/231 environment paths
+    and, for an element on a wall, sum(2k^2 + 2k + 1) = 1/6/19/44/85/146
+    element paths."""
+    for K, env_n, ris_n in [(1, 7, 6), (2, 25, 19), (3, 63, 44), (4, 129, 85), (5, 231, 146)]:
         prob, L, R0 = _box_problem(K, n_rx=3, tx_horn=False)
         prob.rx_ant = synth.Antenna(np.array([0.0, 0.0, 1.0]), 1.0, synth.PAT_ISO, 0.0)
         r = O.trace(prob, mode="exhaustive")
@@ -722,18 +723,29 @@ def test_fill_rule_one_owner():
 # ---------------------------------------------------------------------------
 # P9 / P10: dedupe and the RIS sum against library routines
 # ---------------------------------------------------------------------------
-def test_dedupe_matches_python_set():
-    rng = np.random.default_rng(5)
-    hits = rng.integers(-1, 40, size=(3000, 3)).astype(np.int32)
+@pytest.mark.parametrize("K", [1, 3, 4, 5])
+def test_dedupe_matches_python_set(K):
+    rng = np.random.default_rng(5 + K)
+    hits = rng.integers(-1, 40, size=(3000, K)).astype(np.int32)
     # a miss ends the hit list
     for i in range(hits.shape[0]):
-        k = np.argmax(hits[i] < 0) if (hits[i] < 0).any() else 3
+        k = np.argmax(hits[i] < 0) if (hits[i] < 0).any() else K
         hits[i, k:] = -1
-    a = O.candidates_from_hits(hits, 3)
-    b = O.candidates_from_hits_np(hits, 3)
+    a = O.candidates_from_hits(hits, K)
+    b = O.candidates_from_hits_np(hits, K)
     assert np.array_equal(a, b)
     keys = [O.seq_key(r) for r in a]
     assert keys == sorted(set(keys))
+    # the same set as Python's set() of the prefixes, in sorted() order of their keys
+    ref = {0}
+    for row in hits:
+        acc = 0
+        for i, t in enumerate(row):
+            if t < 0:
+                break
+            acc += (int(t) + 1) << (21 * i)
+            ref.add(acc)
+    assert keys == sorted(ref)
 
 
 def test_ris_sum_matches_loop():
