@@ -1621,11 +1621,11 @@ struct StageTimer {
     std::vector<hipEvent_t> ev;   // per mark, null where not recorded
     StageTimer(bool o, bool every, hipStream_t s) : on(o), st(s), all(every) {}
     // every event is a marker the device processes between kernels: record only what is asked for
-    void mark(bool per_element = false) {
+    void mark(bool per_element = false, hipStream_t on_stream = nullptr) {
         hipEvent_t e = nullptr;
         if (on && (all || per_element)) {
             HIP_CHECK(hipEventCreate(&e));
-            HIP_CHECK(hipEventRecord(e, st));
+            HIP_CHECK(hipEventRecord(e, on_stream ? on_stream : st));
         }
         ev.push_back(e);
     }
@@ -1830,42 +1830,45 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
         hipLaunchKernelGGL(k_uptr_dev, dim3(nblk(R + 1, 128)), dim3(128), 0, su, ps.rstart.as<int64_t>(), ps.n,
                            off2.as<int64_t>(), bu.d_cnt, R, uptr.as<int64_t>());
         HIP_CHECK(hipGetLastError());
-        HIP_CHECK(hipEventRecord(join.e, su));
-        HIP_CHECK(hipStreamWaitEvent(st, join.e, 0));
-        if (keep_paths || keep_cir) n_u = read_i64(bu.d_cnt, st);
+        if (keep_paths || keep_cir) n_u = read_i64(bu.d_cnt, su);
     }
-    tm.mark();   // 3
+    tm.mark();   // 3: the Tx branch's legs and field are queued on the caller's stream
     tm.mark();   // 4
 
+    // The per-element kernel needs only the centre branch (its sequences per
+    // receiver) and the field reaching the elements: it runs on the centre
+    // branch's stream, beside the Tx branch's legs and field on the caller's
+    // stream; the caller's stream joins it below.
+    const hipStream_t sr = two ? bu.st : st;
     if (!a.ris) {
         ch.H = Scratch(c, 0, st);
         tm.mark();
         tm.mark();
     } else {
-        HIP_CHECK(hipStreamWaitEvent(st, in_ready.e, 0));   // the field reaching every element
-        ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), st);
-        if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), st);
+        HIP_CHECK(hipStreamWaitEvent(sr, in_ready.e, 0));   // the field reaching every element
+        ch.H = Scratch(c, sizeof(float2) * (size_t)(R * M), sr);
+        if (keep_paths) ch.ris_valid = Scratch(c, (size_t)((n_u + R) * M), sr);
         if (keep_paths || keep_cir) {
-            ch.cir_amp = Scratch(c, sizeof(float2) * (size_t)((n_u + R) * M), st);
-            ch.cir_len = Scratch(c, sizeof(double) * (size_t)((n_u + R) * M), st);
+            ch.cir_amp = Scratch(c, sizeof(float2) * (size_t)((n_u + R) * M), sr);
+            ch.cir_len = Scratch(c, sizeof(double) * (size_t)((n_u + R) * M), sr);
         }
         int n_mchunk = (int)((M + 63) / 64);
         int64_t waves = R * n_mchunk;
         int64_t threads = waves * 64;
         if (R >= ((int64_t)1 << 32)) throw inval_error("too many receivers");
-        Scratch order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), st);
+        Scratch order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), sr);
         if (R > 0) {
-            Scratch cost(c, sizeof(uint64_t) * (size_t)R, st);
-            hipLaunchKernelGGL(k_ris_order<KM>, dim3(nblk(R, 256)), dim3(256), 0, st, uptr.as<int64_t>(),
+            Scratch cost(c, sizeof(uint64_t) * (size_t)R, sr);
+            hipLaunchKernelGGL(k_ris_order<KM>, dim3(nblk(R, 256)), dim3(256), 0, sr, uptr.as<int64_t>(),
                                useq.as<int32_t>(), R, cost.as<uint64_t>());
             HIP_CHECK(hipGetLastError());
-            sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, st);
+            sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, sr);
         }
-        tm.mark(true);   // 5
+        tm.mark(true, sr);   // 5
         if (threads > 0) {
             if (count_work && !brute && !keep_paths && !keep_cir) {
                 SEL_STK(stk, hipLaunchKernelGGL((k_ris<false, false, STK, true, false, KM>), dim3(nblk(threads, RIS_B)),
-                                                dim3(RIS_B), 0, st, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
+                                                dim3(RIS_B), 0, sr, sv, a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                 uptr.as<int64_t>(), useq.as<int32_t>(), order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
                                                 ch.ris_valid.as<uint8_t>(), (float2*)nullptr, (double*)nullptr, d_legs,
                                                 d_work, d_ctr + 14));
@@ -1873,7 +1876,7 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
                 SEL_BOOL(fresnel, FR, SEL_BOOL(brute, BR,
                          SEL_BOOL(keep_paths || keep_cir, KP,
                                   SEL_STK(stk, hipLaunchKernelGGL((k_ris<BR, KP, STK, false, FR, KM>),
-                                                                  dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, st, sv,
+                                                                  dim3(nblk(threads, RIS_B)), dim3(RIS_B), 0, sr, sv,
                                                                   a.tc, rv, txm.as<TxmRec>(), a.rx_dev, R,
                                                                   uptr.as<int64_t>(), useq.as<int32_t>(),
                                                                   order.as<uint64_t>(), n_mchunk, ch.H.as<float2>(),
@@ -1883,12 +1886,16 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
             }
         }
         HIP_CHECK(hipGetLastError());
-        tm.mark(true);   // 6
+        tm.mark(true, sr);   // 6
         if (keep_paths) {
             ch.n_u = n_u;
             ch.useq = std::move(useq);
         }
         if (keep_cir) ch.cir_uptr = std::move(uptr);
+    }
+    if (two) {   // the caller's stream joins the centre branch (and the per-element kernel)
+        HIP_CHECK(hipEventRecord(join.e, sr));
+        HIP_CHECK(hipStreamWaitEvent(st, join.e, 0));
     }
     ch.key_words = key_words(a.tc.K);
     ch.useq_stride = useq_stride(KM);
@@ -1957,10 +1964,10 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
         out.ms[0] = el(0, 1);                  // setup
         out.ms[1] = el(1, 2);                  // discovery + dedupe (both sources)
         out.ms[2] = 0.0f;
-        out.ms[3] = el(2, 3);                  // images, paths, legs, fields of both sources
+        out.ms[3] = el(2, 3);                  // Tx branch: images, paths, legs, field
         out.ms[4] = 0.0f;
-        out.ms[5] = a.ris ? el(5, 6) : 0.0f;   // per-element kernel (k_ris) alone
-        out.ms[6] = a.ris ? el(4, 5) : 0.0f;   // Tx -> element legs
+        out.ms[5] = a.ris ? el(5, 6) : 0.0f;   // per-element kernel (k_ris) alone, on its stream
+        out.ms[6] = a.ris ? el(2, 5) : 0.0f;   // from the candidates to the start of the per-element kernel
         out.ms[7] = el(0, 7);                  // total
     }
     ch.last_stream = st;
