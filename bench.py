@@ -358,7 +358,7 @@ def run_paper_bench(ctx, reps=3):
     return out
 
 
-def run_gemm_bench(ctx, reps=5):
+def run_gemm_bench(ctx, reps=20, warm=20):
     """Many-configuration RIS sum on the matrix cores: channel from the box
     room with a 32 x 32 RIS and 128 x 128 receivers, 4096 random +-1
     configurations (Gamma = 0.9 s)."""
@@ -385,7 +385,9 @@ def run_gemm_bench(ctx, reps=5):
     rows_t = torch.from_numpy(rows).cuda()
     for name, prec in (("bf16x2", risrt.PREC_MFMA_BF16X2), ("f16x2", risrt.PREC_MFMA_F16X2),
                        ("valu_f32", risrt.PREC_VALU_F32)):
-        ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=prec, P_out=P)
+        # warm-up long enough for the clocks to settle under matrix-core load (~10 ms)
+        for _ in range(warm if prec != risrt.PREC_VALU_F32 else 1):
+            ctx.ris_sum(ch, g, scale=0.9, gamma_is_real=True, precision=prec, P_out=P)
         torch.cuda.synchronize()
         n = reps if prec != risrt.PREC_VALU_F32 else 2
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)

@@ -13,6 +13,7 @@
 //   largest magnitude into [2^14, 2^15) (fp16 has 5 exponent bits: unscaled
 //   fields of 1e-6 V/m would be subnormal); the epilogue multiplies by 2^-s_r.
 //   The epilogue adds E_env, scales, and writes E and/or P.
+#include <algorithm>
 #include <cstring>
 
 #include "rt_host.hpp"
@@ -148,27 +149,42 @@ __global__ void k_split_A(const float2* H, int64_t R, int64_t M, int layout, int
     Alo[idx] = bf16_rne(v - bf16_to_f(hi));
 }
 
-// Bt [cols_p x kp] (k fastest)
-__global__ void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int64_t cols_p, int64_t kp, bool f16,
-                          uint16_t* Bhi, uint16_t* Blo)
+// Bt [cols_p x kp] (k fastest) from Gamma [M x C] (c fastest): a 64 x 64
+// transpose through LDS per workgroup, so both the reads (along c) and the
+// writes (along k) are contiguous
+constexpr int SBT = 64;
+__global__ __launch_bounds__(256) void k_split_B(const float2* G, int64_t M, int64_t C, int layout, int64_t cols_p,
+                                                 int64_t kp, bool f16, uint16_t* Bhi, uint16_t* Blo)
 {
-    int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (idx >= cols_p * kp) return;
-    int64_t c = idx / kp, k = idx - c * kp;
-    float v = 0.0f;
-    if (c < C) {
-        if (k < M) v = G[k * C + c].x;
-        else if (layout == 2 && k < 2 * M) v = G[(k - M) * C + c].y;
+    __shared__ float tile[SBT][SBT + 1];
+    const int64_t c0 = (int64_t)blockIdx.x * SBT, k0 = (int64_t)blockIdx.y * SBT;
+    for (int i = threadIdx.x; i < SBT * SBT; i += 256) {
+        const int kk = i / SBT, cc = i % SBT;
+        const int64_t k = k0 + kk, c = c0 + cc;
+        float v = 0.0f;
+        if (c < C) {
+            if (k < M) v = G[k * C + c].x;
+            else if (layout == 2 && k < 2 * M) v = G[(k - M) * C + c].y;
+        }
+        tile[kk][cc] = v;
     }
-    if (f16) {
-        const uint16_t hi = f16_rne(v);
-        Bhi[idx] = hi;
-        if (Blo) Blo[idx] = f16_rne(v - f16_to_f(hi));
-        return;
+    __syncthreads();
+    for (int i = threadIdx.x; i < SBT * SBT; i += 256) {
+        const int cc = i / SBT, kk = i % SBT;
+        const int64_t k = k0 + kk, c = c0 + cc;
+        if (c >= cols_p || k >= kp) continue;
+        const float v = tile[kk][cc];
+        const int64_t idx = c * kp + k;
+        if (f16) {
+            const uint16_t hi = f16_rne(v);
+            Bhi[idx] = hi;
+            if (Blo) Blo[idx] = f16_rne(v - f16_to_f(hi));
+        } else {
+            const uint16_t hi = bf16_rne(v);
+            Bhi[idx] = hi;
+            if (Blo) Blo[idx] = bf16_rne(v - bf16_to_f(hi));
+        }
     }
-    uint16_t hi = bf16_rne(v);
-    Bhi[idx] = hi;
-    if (Blo) Blo[idx] = bf16_rne(v - bf16_to_f(hi));
 }
 
 // --------------------------------------------------------------------------
@@ -294,103 +310,226 @@ __global__ __launch_bounds__(256) void k_sum_mfma(const uint16_t* __restrict__ A
         }
 }
 
-// Two-product split (H hi + lo against Gamma hi), larger tiles: 256 x 256 per
-// workgroup of 8 waves (4 x 2), each wave 64 x 128 = 2 x 4 blocks of 32 x 32,
-// so every A fragment (hi and lo) read from LDS feeds four blocks and every B
-// fragment four (fewer LDS bytes per product than 128 x 64 with two A parts).  K tiles of 32 are double-buffered in LDS (one barrier per tile): the
-// next tile's global loads are in flight while the current one is multiplied.
-constexpr int G2M = 256, G2N = 256, G2K = 32, G2L = G2K + 8;
+// Two-product split (H hi + lo against Gamma hi) on 256 x 256 tiles: 8 waves
+// (4 x 2), each 64 x 128 outputs = 2 x 4 blocks of 32 x 32, so every A
+// fragment (hi and lo) read from LDS feeds four blocks and every B fragment four.
+//
+// Operand tiles of K = 32 come straight from global memory into LDS
+// (buffer_load_dwordx4 ... lds: no staging registers), three stages deep, so
+// two tiles are in flight while one is multiplied.  An LDS row is 64 bytes
+// (four 16-byte chunks); chunk c of row r sits at position c ^ swz(r), which
+// keeps both the 64-lane fragment reads and the direct loads free of bank
+// conflicts.  Within a tile the second half (k 16..31) is read from LDS while
+// the first half's products run, and the next tile's first half is read right
+// after the barrier, while the second half's products run.
+//
+// Persistent: one workgroup per CU walks tiles t = blockIdx.x + i * gridDim.x;
+// the next tile's three stages are loaded during this tile's epilogue.
+// XCD-aware order (gh > 0): workgroups are placed on the 8 XCDs round-robin
+// by index, so tile t is given to XCD t % 8; each XCD owns a band of n_tm / 8
+// tile rows and walks it in groups of gh tile rows, column by column, which
+// keeps the A rows and B columns its CUs share in that XCD's L2.
+constexpr int G2M = 256, G2N = 256, G2K = 32;
+constexpr int G2R = 32;                 // LDS row length (elements)
+constexpr int G2OP = G2M * G2R;         // elements of one operand tile in LDS
+constexpr int G2_STAGE_WAIT_1 = 0x0076;   // s_waitcnt vmcnt(6) lgkmcnt(0): one later tile's loads may fly
+constexpr int G2_STAGE_WAIT_0 = 0x0070;   // s_waitcnt vmcnt(0) lgkmcnt(0)
+constexpr int G2_STAGE_WAIT_2 = 0x007C;   // s_waitcnt vmcnt(12) lgkmcnt(0): two later tiles' loads may fly
+typedef __attribute__((address_space(3))) void lds_void;
+
+__device__ __forceinline__ int g2_swz(int r) { return ((r >> 1) ^ (r >> 2)) & 3; }
+
+// a barrier after an explicit wait: the direct loads are counted by vmcnt only,
+// so the wait names how many of this wave's later loads may still be in flight
+#define G2_SYNC(WAIT)                          \
+    do {                                       \
+        __builtin_amdgcn_s_waitcnt(WAIT);      \
+        asm volatile("" ::: "memory");         \
+        __builtin_amdgcn_s_barrier();          \
+        asm volatile("" ::: "memory");         \
+    } while (0)
+
 template <bool F16>
 __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict__ Ahi, const uint16_t* __restrict__ Alo,
                                                      const uint16_t* __restrict__ Bhi, int64_t kp,
                                                      const float2* __restrict__ Eenv, const int32_t* __restrict__ sexp,
                                                      int64_t R, int64_t C, float scale, float2* Eout, float* Pout,
-                                                     int n_tiles_n)
+                                                     int n_tm, int n_tn, int gh)
 {
-    __shared__ __attribute__((aligned(16))) uint16_t sAh[2][G2M * G2L];
-    __shared__ __attribute__((aligned(16))) uint16_t sAl[2][G2M * G2L];
-    __shared__ __attribute__((aligned(16))) uint16_t sB[2][G2N * G2L];
+    // three stages, each [A hi | A lo | B] of 256 rows x 32; separate arrays so
+    // that a read of one stage never waits for the direct loads into another
+    __shared__ __attribute__((aligned(1024))) uint16_t st0[3 * G2OP];
+    __shared__ __attribute__((aligned(1024))) uint16_t st1[3 * G2OP];
+    __shared__ __attribute__((aligned(1024))) uint16_t st2[3 * G2OP];
     const int tid = threadIdx.x;
     const int wave = tid >> 6, lane = tid & 63;
-    const int64_t tile_m = blockIdx.x / n_tiles_n, tile_n = blockIdx.x % n_tiles_n;
-    const int64_t row0 = tile_m * G2M, col0 = tile_n * G2N;
     const int wm = (wave >> 1) * 64, wn = (wave & 1) * 128;
-
-    f32x16 acc[2][4];
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 4; ++j)
-            for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
-
-    // each thread moves 16 bf16 (two 16-byte vectors) of a 256 x 32 tile of each operand
-    const int lrow = tid >> 1, lcol = (tid & 1) * 16;
-    const uint4* gAh = (const uint4*)(Ahi + (row0 + lrow) * kp + lcol);
-    const uint4* gAl = (const uint4*)(Alo + (row0 + lrow) * kp + lcol);
-    const uint4* gB = (const uint4*)(Bhi + (col0 + lrow) * kp + lcol);
+    const int T = n_tm * n_tn;
     const int64_t nk = kp / G2K;
-    uint4 rAh0 = gAh[0], rAh1 = gAh[1], rAl0 = gAl[0], rAl1 = gAl[1], rB0 = gB[0], rB1 = gB[1];
-    auto stage = [&](int buf) {
-        *(uint4*)&sAh[buf][lrow * G2L + lcol] = rAh0;
-        *(uint4*)&sAh[buf][lrow * G2L + lcol + 8] = rAh1;
-        *(uint4*)&sAl[buf][lrow * G2L + lcol] = rAl0;
-        *(uint4*)&sAl[buf][lrow * G2L + lcol + 8] = rAl1;
-        *(uint4*)&sB[buf][lrow * G2L + lcol] = rB0;
-        *(uint4*)&sB[buf][lrow * G2L + lcol + 8] = rB1;
-    };
-    auto fetch = [&](int64_t kt) {
-        const int64_t o = kt * G2K / 8;   // in uint4 units
-        rAh0 = gAh[o];
-        rAh1 = gAh[o + 1];
-        rAl0 = gAl[o];
-        rAl1 = gAl[o + 1];
-        rB0 = gB[o];
-        rB1 = gB[o + 1];
-    };
-    stage(0);
-    if (nk > 1) fetch(1);
-    __syncthreads();
-    for (int64_t kt = 0; kt < nk; ++kt) {
-        const int buf = (int)(kt & 1);
-        for (int ks = 0; ks < G2K; ks += 16) {
-            const int kofs = ks + (lane >> 5) * 8;
-            uint4 ah[2], al[2], bh[4];
-            for (int i = 0; i < 2; ++i) {
-                const int r = wm + i * 32 + (lane & 31);
-                ah[i] = *(const uint4*)&sAh[buf][r * G2L + kofs];
-                al[i] = *(const uint4*)&sAl[buf][r * G2L + kofs];
-            }
-            for (int j = 0; j < 4; ++j) {
-                const int cix = wn + j * 32 + (lane & 31);
-                bh[j] = *(const uint4*)&sB[buf][cix * G2L + kofs];
-            }
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = mfma16<F16>((const uint16_t*)&ah[i], (const uint16_t*)&bh[j], acc[i][j]);
-            for (int i = 0; i < 2; ++i)
-                for (int j = 0; j < 4; ++j)
-                    acc[i][j] = mfma16<F16>((const uint16_t*)&al[i], (const uint16_t*)&bh[j], acc[i][j]);
+    auto tile_of = [&](int t, int& tm, int& tn) {
+        if (gh == 0) {
+            tm = t / n_tn;
+            tn = t % n_tn;
+        } else {
+            const int x = t & 7, l = t >> 3;
+            const int g = l / (gh * n_tn), q = l % (gh * n_tn);
+            tm = x * (n_tm >> 3) + g * gh + q % gh;
+            tn = q / gh;
         }
-        if (kt + 1 < nk) {
-            stage(buf ^ 1);   // the other buffer: its last readers passed the previous barrier
-            if (kt + 2 < nk) fetch(kt + 2);
-        }
-        __syncthreads();
+    };
+    // this lane's two 16-byte chunks of each operand tile: LDS chunk
+    // p = wave * 128 + q * 64 + lane holds row p / 4, logical chunk (p % 4) ^ swz(row)
+    int voff[2];
+    for (int q = 0; q < 2; ++q) {
+        const int p = wave * 128 + q * 64 + lane;
+        const int r = p >> 2, c = (p & 3) ^ g2_swz(p >> 2);
+        voff[q] = (int)((r * kp + c * 8) * 2);
     }
-    // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4)
-    for (int i = 0; i < 2; ++i)
-        for (int j = 0; j < 4; ++j) {
-            const int64_t c = col0 + wn + j * 32 + (lane & 31);
-            for (int e = 0; e < 16; e += 2) {
-                const int64_t row = row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4);
-                const int64_t r = row >> 1;
-                if (r >= R || c >= C) continue;
-                const float2 e0 = Eenv[r];
-                const float sr = F16 ? ldexpf(scale, -sexp[r]) : scale;   // exact: a power of two
-                const float er = e0.x + sr * acc[i][j][e];
-                const float ei = e0.y + sr * acc[i][j][e + 1];
-                if (Eout) Eout[r * C + c] = make_float2(er, ei);
-                if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
-            }
+    const int tile_bytes = (int)(G2M * kp * 2);   // 256 rows of either operand
+    __amdgpu_buffer_rsrc_t rAh, rAl, rB;
+    auto set_tile = [&](int t) {
+        int tm, tn;
+        tile_of(t, tm, tn);
+        rAh = __builtin_amdgcn_make_buffer_rsrc((void*)(Ahi + (int64_t)tm * G2M * kp), (short)0, tile_bytes, 0x00020000);
+        rAl = __builtin_amdgcn_make_buffer_rsrc((void*)(Alo + (int64_t)tm * G2M * kp), (short)0, tile_bytes, 0x00020000);
+        rB = __builtin_amdgcn_make_buffer_rsrc((void*)(Bhi + (int64_t)tn * G2N * kp), (short)0, tile_bytes, 0x00020000);
+    };
+    auto issue = [&](uint16_t* base, int64_t kt) {
+        const int ko = (int)(kt * G2K * 2);
+        for (int q = 0; q < 2; ++q) {
+            const int lo = (wave * 128 + q * 64) * 8;
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rAh, (lds_void*)(base + lo), 16, voff[q], ko, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rAl, (lds_void*)(base + G2OP + lo), 16, voff[q], ko, 0, 0);
+            __builtin_amdgcn_raw_ptr_buffer_load_lds(rB, (lds_void*)(base + 2 * G2OP + lo), 16, voff[q], ko, 0, 0);
         }
+    };
+    f32x16 acc[2][4];
+    uint4 xh[2], xl[2], xb[4], yh[2], yl[2], yb[4];
+    // fragments of k half ks (0 or 16) of the tile in `base`
+    auto frag = [&](const uint16_t* base, int ks, uint4* h, uint4* l, uint4* bb) {
+        const int c = (ks >> 3) + (lane >> 5);
+        for (int i = 0; i < 2; ++i) {
+            const int r = wm + i * 32 + (lane & 31);
+            const int o = r * G2R + ((c ^ g2_swz(r)) * 8);
+            h[i] = *(const uint4*)&base[o];
+            l[i] = *(const uint4*)&base[G2OP + o];
+        }
+        for (int j = 0; j < 4; ++j) {
+            const int r = wn + j * 32 + (lane & 31);
+            bb[j] = *(const uint4*)&base[2 * G2OP + r * G2R + ((c ^ g2_swz(r)) * 8)];
+        }
+    };
+    auto mma = [&](const uint4* h, const uint4* l, const uint4* bb) {
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<F16>((const uint16_t*)&h[i], (const uint16_t*)&bb[j], acc[i][j]);
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 4; ++j) acc[i][j] = mfma16<F16>((const uint16_t*)&l[i], (const uint16_t*)&bb[j], acc[i][j]);
+    };
+    // Tile kt from stage `cur`; the next tile's first half from stage `nxt`.
+    // Every body issues exactly one tile's loads (past the last tile: the last
+    // tile again, never read), so the same wait, one later tile in flight,
+    // holds everywhere and the compiler's own waits stay exact.
+    // The scheduling fences keep each phase whole: one half's reads are all in
+    // flight while the other half's products issue.
+    auto body = [&](uint16_t* cur, const uint16_t* nxt, int64_t kt) {
+        frag(cur, 16, yh, yl, yb);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(xh, xl, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        G2_SYNC(G2_STAGE_WAIT_1);                      // tile kt + 1 landed in every wave
+        issue(cur, kt + 3 < nk ? kt + 3 : nk - 1);     // every wave has read tile kt
+        frag(nxt, 0, xh, xl, xb);
+        __builtin_amdgcn_sched_barrier(0);
+        mma(yh, yl, yb);
+        __builtin_amdgcn_sched_barrier(0);
+    };
+    auto issue3 = [&]() {
+        issue(st0, 0);
+        issue(st1, nk > 1 ? 1 : nk - 1);
+        issue(st2, nk > 2 ? 2 : nk - 1);
+    };
+
+    int t = blockIdx.x;
+    if (t >= T) return;
+    set_tile(t);
+    issue3();
+    for (; t < T; t += gridDim.x) {
+        int tm, tn;
+        tile_of(t, tm, tn);
+        const int64_t row0 = (int64_t)tm * G2M, col0 = (int64_t)tn * G2N;
+        for (int i = 0; i < 2; ++i)
+            for (int j = 0; j < 4; ++j)
+                for (int e = 0; e < 16; ++e) acc[i][j][e] = 0.0f;
+        G2_SYNC(G2_STAGE_WAIT_2);   // tile 0 landed
+        frag(st0, 0, xh, xl, xb);
+        int64_t kt = 0;
+        for (; kt + 3 <= nk; kt += 3) {
+            body(st0, st1, kt);
+            body(st1, st2, kt + 1);
+            body(st2, st0, kt + 2);
+        }
+        if (kt < nk) body(st0, st1, kt);
+        if (kt + 1 < nk) body(st1, st2, kt + 1);
+        G2_SYNC(G2_STAGE_WAIT_0);   // the repeated loads landed and every LDS read is done
+        // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4),
+        // receiver = row / 2.  E_env and the row scales are loaded first, then the
+        // next tile's stages
+        float2 ev[2][4][2];
+        float sv[2][4][2];
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int eb = 0; eb < 4; ++eb)
+#pragma unroll
+                for (int h = 0; h < 2; ++h) {
+                    int64_t r = (row0 + wm + i * 32 + 8 * eb + 4 * (lane >> 5) + 2 * h) >> 1;
+                    r = r < R ? r : R - 1;
+                    ev[i][eb][h] = Eenv[r];
+                    sv[i][eb][h] = F16 ? ldexpf(scale, -sexp[r]) : scale;   // exact: a power of two
+                }
+        asm volatile("" ::: "memory");
+        const int t2 = t + (int)gridDim.x;
+        if (t2 < T) {
+            set_tile(t2);
+            issue3();
+        }
+#pragma unroll
+        for (int i = 0; i < 2; ++i)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const int64_t c = col0 + wn + j * 32 + (lane & 31);
+#pragma unroll
+                for (int e = 0; e < 16; e += 2) {
+                    const int64_t r = (row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4)) >> 1;
+                    if (r >= R || c >= C) continue;
+                    const float2 e0 = ev[i][e / 4][(e % 4) / 2];
+                    const float sr = sv[i][e / 4][(e % 4) / 2];
+                    const float er = e0.x + sr * acc[i][j][e];
+                    const float ei = e0.y + sr * acc[i][j][e + 1];
+                    if (Eout) Eout[r * C + c] = make_float2(er, ei);
+                    if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
+                }
+            }
+    }
+}
+#undef G2_SYNC
+
+// XCD-aware group height of the two-product kernel: tile rows per group, 0 for row-major order
+static int g2_group_rows(int n_tm)
+{
+    if (n_tm % 8) return 0;
+    const int band = n_tm / 8;
+    for (int g : {8, 4, 2, 1})
+        if (band % g == 0) return g;
+    return 0;
+}
+
+static int cu_count()
+{
+    int dev = 0, n = 0;
+    if (hipGetDevice(&dev) != hipSuccess) return 256;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) return 256;
+    return n;
 }
 
 // Shapes of the matrix-core product of one sum (the split buffers' sizes).
@@ -435,7 +574,7 @@ static void launch_product(const Channel& ch, const SumShape& sh, const float2* 
                            uint16_t* b_lo, float* E_out, float* P_out, hipStream_t st)
 {
     const int64_t R = ch.R, M = ch.M, kp = sh.kp;
-    hipLaunchKernelGGL(k_split_B, dim3(nblk(sh.cols_p * kp, 256)), dim3(256), 0, st, G, M, C, sh.lay, sh.cols_p, kp,
+    hipLaunchKernelGGL(k_split_B, dim3(nblk(sh.cols_p, SBT), nblk(kp, SBT)), dim3(256), 0, st, G, M, C, sh.lay, sh.cols_p, kp,
                        sh.f16, b_hi, sh.three ? b_lo : (uint16_t*)nullptr);
     HIP_CHECK(hipGetLastError());
     const int32_t* sx = sh.f16 ? sexp : nullptr;
@@ -445,14 +584,18 @@ static void launch_product(const Channel& ch, const SumShape& sh, const float2* 
         hipLaunchKernelGGL((k_sum_mfma<3, false>), dim3((unsigned)n_tiles), dim3(256), 0, st, a_hi, a_lo, b_hi, b_lo,
                            kp, ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn);
     } else {
-        const int n_tn2 = (int)(sh.cols_p / G2N);
-        const int64_t n_tiles2 = (sh.rows_p / G2M) * n_tn2;
+        const int n_tm = (int)(sh.rows_p / G2M), n_tn = (int)(sh.cols_p / G2N);
+        const int64_t n_tiles = (int64_t)n_tm * n_tn;
+        if (n_tiles >= ((int64_t)1 << 31) || (int64_t)G2M * kp * 2 >= ((int64_t)1 << 31))
+            throw inval_error("sum too large for the matrix-core tiles");
+        const int gh = g2_group_rows(n_tm);
+        const unsigned grid = (unsigned)std::min<int64_t>(n_tiles, cu_count());   // one workgroup per CU
         if (sh.f16)
-            hipLaunchKernelGGL((k_sum_mfma_2x<true>), dim3((unsigned)n_tiles2), dim3(512), 0, st, a_hi, a_lo, b_hi, kp,
-                               ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn2);
+            hipLaunchKernelGGL((k_sum_mfma_2x<true>), dim3(grid), dim3(512), 0, st, a_hi, a_lo, b_hi, kp,
+                               ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tm, n_tn, gh);
         else
-            hipLaunchKernelGGL((k_sum_mfma_2x<false>), dim3((unsigned)n_tiles2), dim3(512), 0, st, a_hi, a_lo, b_hi,
-                               kp, ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tn2);
+            hipLaunchKernelGGL((k_sum_mfma_2x<false>), dim3(grid), dim3(512), 0, st, a_hi, a_lo, b_hi, kp,
+                               ch.E_env.as<float2>(), sx, R, C, scale, (float2*)E_out, P_out, n_tm, n_tn, gh);
     }
     HIP_CHECK(hipGetLastError());
 }
