@@ -190,6 +190,8 @@ void scan_i64(Ctx& c, const int64_t* in, int64_t* out, int64_t n, hipStream_t st
 constexpr int SMALL_T = 1024;                    // threads (16 waves)
 constexpr int SMALL_WORDS = 8192;                // 64-bit words per LDS buffer (64 KiB)
 
+// A pass over a digit that every key shares is the identity (the sort is
+// stable): the bits that vary (OR ^ AND over all keys) decide which passes run.
 template <int W>
 __global__ __launch_bounds__(SMALL_T) void k_sort_small(const uint64_t* in, uint64_t* out, int n, int begin, int end)
 {
@@ -197,10 +199,48 @@ __global__ __launch_bounds__(SMALL_T) void k_sort_small(const uint64_t* in, uint
     __shared__ unsigned wc[SMALL_T / 64][256];   // per wave and digit: count, then start
     __shared__ unsigned hist[256];
     __shared__ unsigned wsum[4];
+    __shared__ uint64_t wor[SMALL_T / 64][W], wand[SMALL_T / 64][W];
     const int t = (int)threadIdx.x, wave = t >> 6;
-    for (int i = t; i < n * W; i += SMALL_T) buf[0][i] = in[i];
+    uint64_t vo[W], va[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        vo[j] = 0ull;
+        va[j] = ~0ull;
+    }
+    for (int i = t; i < n; i += SMALL_T) {
+#pragma unroll
+        for (int j = 0; j < W; ++j) {
+            const uint64_t v = in[i * W + j];
+            buf[0][i * W + j] = v;
+            vo[j] |= v;
+            va[j] &= v;
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        for (int o = 32; o > 0; o >>= 1) {
+            vo[j] |= (uint64_t)__shfl_xor((long long)vo[j], o, 64);
+            va[j] &= (uint64_t)__shfl_xor((long long)va[j], o, 64);
+        }
+        if ((t & 63) == 0) {
+            wor[wave][j] = vo[j];
+            wand[wave][j] = va[j];
+        }
+    }
+    __syncthreads();
+    uint64_t vary[W];
+#pragma unroll
+    for (int j = 0; j < W; ++j) {
+        uint64_t o = 0ull, a = ~0ull;
+        for (int w = 0; w < SMALL_T / 64; ++w) {
+            o |= wor[w][j];
+            a &= wand[w][j];
+        }
+        vary[j] = n > 0 ? (o ^ a) : 0ull;
+    }
     int src = 0;
     for (int shift = begin; shift < end; shift += 8) {
+        if (key_digit<W>(vary, shift, end) == 0u) continue;   // same on every thread
         if (t < 256) hist[t] = 0;
         __syncthreads();
         for (int i = t; i < n; i += SMALL_T) {

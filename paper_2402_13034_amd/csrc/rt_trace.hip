@@ -1862,7 +1862,8 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
             hipLaunchKernelGGL(k_ris_order<KM>, dim3(nblk(R, 256)), dim3(256), 0, sr, uptr.as<int64_t>(),
                                useq.as<int32_t>(), R, cost.as<uint64_t>());
             HIP_CHECK(hipGetLastError());
-            sort_u64_into(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 52, sr);
+            // the keys come in receiver order and the sort is stable: the cost bits decide alone
+            sort_keys(c, cost.as<uint64_t>(), order.as<uint64_t>(), R, 1, 32, 52, sr);
         }
         tm.mark(true, sr);   // 5
         if (threads > 0) {

@@ -16,7 +16,10 @@ answer is the received power map P [R x C] (eqs. (9)-(10)).
   its own column of Gamma, so a result is bit-identical alone and in a mix.
 * A query that does not fit the budget waits; one that cannot fit even alone
   fails with the library's RT_ENOMEM instead of blocking the queue.
-* Latency = completion time - submission time (host clock), per query.
+* Latency = completion time - submission time (host clock), per query, kept
+  apart for cache hits and misses (a miss: the deployment's channel was not
+  cached when its batch started, so the batch traced it or waited for the
+  slot that did).
 """
 from __future__ import annotations
 
@@ -73,14 +76,16 @@ def deployment_from_problem(key: str, scene_key: str, ris_key: str, prob) -> Dep
 
 
 class Server:
-    def __init__(self, ctx: risrt.Context, n_slots: int = 4, max_cols: int = 4096, cache_frac: float = 0.6):
+    def __init__(self, ctx: risrt.Context, n_slots: int = 4, max_cols: int = 4096, cache_frac: float = 0.6,
+                 cache_bytes: Optional[int] = None):
         import torch
         self.ctx = ctx
         self.n_slots = n_slots
         self.max_cols = max_cols
         self._torch = torch
         self._budget = ctx.mem_info()[1]
-        self._cache_limit = int(cache_frac * self._budget)
+        # channels are evicted (least recently used first) beyond this many bytes
+        self._cache_limit = int(cache_bytes) if cache_bytes is not None else int(cache_frac * self._budget)
         self._scenes_host: Dict[str, object] = {}
         self._ris_host: Dict[str, object] = {}
         self._deps: Dict[str, Deployment] = {}
@@ -99,7 +104,9 @@ class Server:
         self._next_id = 0
         self._running = True
         self.latencies: List[float] = []
+        self.missed: List[bool] = []   # per latency: the query's batch found no cached channel
         self.n_traces = 0
+        self.n_evictions = 0
         self.n_batches = 0
         self.n_cols = 0
         self.cache_hits = 0
@@ -164,11 +171,23 @@ class Server:
         self._scene_h.clear()
         self._ris_h.clear()
 
+    def clear_latencies(self) -> None:
+        with self._lock:
+            self.latencies.clear()
+            self.missed.clear()
+
     def stats(self) -> dict:
-        lat = np.asarray(self.latencies) * 1e3
-        return {"queries": int(lat.size), "p50_ms": float(np.percentile(lat, 50)) if lat.size else None,
-                "p99_ms": float(np.percentile(lat, 99)) if lat.size else None,
-                "mean_ms": float(lat.mean()) if lat.size else None, "traces": self.n_traces,
+        with self._lock:
+            lat = np.asarray(self.latencies) * 1e3
+            miss = np.asarray(self.missed, bool)
+
+        def pct(x, q):
+            return float(np.percentile(x, q)) if x.size else None
+        return {"queries": int(lat.size), "p50_ms": pct(lat, 50), "p99_ms": pct(lat, 99),
+                "mean_ms": float(lat.mean()) if lat.size else None,
+                "hits": int((~miss).sum()), "hit_p50_ms": pct(lat[~miss], 50), "hit_p99_ms": pct(lat[~miss], 99),
+                "misses": int(miss.sum()), "miss_p50_ms": pct(lat[miss], 50), "miss_p99_ms": pct(lat[miss], 99),
+                "traces": self.n_traces, "evictions": self.n_evictions,
                 "batches": self.n_batches, "columns": self.n_cols, "channel_cache_hits": self.cache_hits,
                 "admission_waits": self.admission_waits, "errors": self._errors}
 
@@ -236,14 +255,18 @@ class Server:
                 self._ris_h[key] = self.ctx.ris_create(r.elems, r.centre, r.normal, r.dy, r.dz, r.gain, r.q)
             return self._ris_h[key]
 
-    def _channel(self, dep: Deployment, stream) -> int:
+    def _channel(self, dep: Deployment, stream):
+        """(channel handle, missed): missed when the channel was not cached as
+        the call began (this call traced it, or waited for the one that did)."""
+        with self._lock:
+            missed = dep.key not in self._chan
         with self._key_locks["chan:" + dep.key]:
             with self._lock:
                 if dep.key in self._chan:
                     self._chan.move_to_end(dep.key)
                     self._in_use[dep.key] += 1
                     self.cache_hits += 1
-                    return self._chan[dep.key]
+                    return self._chan[dep.key], missed
             self._evict(dep.key)
             scene = self._scene(dep.scene_key, stream)
             ris = self._ris(dep.ris_key)
@@ -257,7 +280,7 @@ class Server:
                 self._chan_bytes[dep.key] = R * M * 8 * 3 + R * 8
                 self._in_use[dep.key] += 1
                 self.n_traces += 1
-            return ch
+            return ch, True
 
     def _evict(self, keep: str) -> None:
         with self._lock:
@@ -269,6 +292,7 @@ class Server:
                 if k != keep and self._in_use[k] == 0:
                     victims.append((k, self._chan.pop(k)))
                     total -= self._chan_bytes.pop(k)
+                    self.n_evictions += 1
         for _, h in victims:
             self.ctx.destroy(h)
 
@@ -279,7 +303,7 @@ class Server:
         held = False
         try:
             with torch.cuda.stream(stream):
-                ch = self._channel(dep, stream)
+                ch, missed = self._channel(dep, stream)
                 held = True
                 # the batch's columns are gathered straight into pinned memory and uploaded on the slot's stream
                 M = batch[0].gamma.shape[0]
@@ -301,12 +325,15 @@ class Server:
                 Ph = Pt.numpy()
             t = time.perf_counter()
             c0 = 0
+            lats = []
             for q in batch:
                 c = q.gamma.shape[1]
                 q.future.set_result(Ph[:, c0:c0 + c])
                 c0 += c
-                self.latencies.append(t - q.t_submit)
+                lats.append(t - q.t_submit)
             with self._lock:
+                self.latencies.extend(lats)
+                self.missed.extend([missed] * len(lats))
                 self.n_batches += 1
                 self.n_cols += cols
         except risrt.RtError as e:

@@ -80,3 +80,27 @@ def test_sort_bit_range_one_word(ctx):
     field = (keys >> np.uint64(8)) & np.uint64((1 << 32) - 1)
     got = _gpu(ctx, keys, begin_bit=8, end_bit=40)
     assert np.array_equal(got, keys[np.argsort(field, kind="stable")])
+
+
+@pytest.mark.parametrize("n", [2, 1000, 8192])
+def test_sort_skips_shared_digits_stably(ctx, n):
+    """Keys whose 8-bit digits are partly the same in every key (those passes
+    are skipped), all-equal keys, and the receiver-order keys of the
+    per-element kernel (cost above bit 32, the index below, sorted on the
+    cost bits alone): stable results equal to NumPy's."""
+    rng = np.random.default_rng(7 + n)
+    _say("case sort shared digits n", n)
+    keys = (np.uint64(0xAB) << np.uint64(56)) | (rng.integers(0, 256, size=n).astype(np.uint64) << np.uint64(16)) \
+        | np.uint64(0x3C00)
+    keys = keys | np.arange(n, dtype=np.uint64) % np.uint64(3)   # low digit varies a little
+    assert np.array_equal(_gpu(ctx, keys), np.sort(keys))
+    same = np.full(n, np.uint64(0x1234_5678_9ABC_DEF0))
+    assert np.array_equal(_gpu(ctx, same), same)
+    cost = rng.integers(1, 40, size=n).astype(np.uint64)
+    rk = ((np.uint64(0xFFFFF) - cost) << np.uint64(32)) | np.arange(n, dtype=np.uint64)
+    got = _gpu(ctx, rk, begin_bit=32, end_bit=52)
+    assert np.array_equal(got, rk[np.argsort(rk >> np.uint64(32), kind="stable")])
+    assert np.array_equal(got, np.sort(rk))   # the same order as a sort of every bit
+    two = np.stack([np.arange(n, dtype=np.uint64), np.full(n, np.uint64(5))], axis=1)
+    got = _gpu(ctx, two, begin_bit=0, end_bit=128).reshape(-1, 2)
+    assert np.array_equal(got, two)

@@ -19,10 +19,10 @@ def mix():
     return scenes, riss, deps
 
 
-def _server(ctx, mix, n_slots):
+def _server(ctx, mix, n_slots, cache_bytes=None):
     from paper_2402_13034_amd import serve
     scenes, riss, deps = mix
-    s = serve.Server(ctx, n_slots=n_slots)
+    s = serve.Server(ctx, n_slots=n_slots, cache_bytes=cache_bytes)
     for k, v in scenes.items():
         s.add_scene(k, v)
     for k, v in riss.items():
@@ -53,6 +53,35 @@ def test_alone_equals_mix(mix):
     assert st["queries"] == len(qs) and st["errors"] == 0
     assert st["batches"] <= len(qs)
     assert st["p99_ms"] >= st["p50_ms"] > 0
+
+
+def test_evictions_retrace_bit_identical(mix):
+    """A channel cache that holds one deployment's channel: a stream over four
+    deployments evicts and traces again, and every answer is bit-identical to
+    the one of a server whose cache holds them all; the misses (queries whose
+    batch traced or waited for a trace) are counted and timed apart from the
+    hits."""
+    from paper_2402_13034_amd import risrt, serve, workloads
+    scenes, riss, deps = mix
+    qs = workloads.query_stream(deps, riss, 48, seed=21, max_cols=16, zipf_a=0.5)
+    one = max(workloads.channel_bytes(d, riss) for d in deps)
+    with risrt.Context(0) as ctx:
+        big = _server(ctx, mix, 2)
+        ref = [f.result(timeout=120) for f in serve.run_poisson(big, qs, rate_hz=3000.0, seed=4)]
+        st_big = big.stats()
+        big.close()
+        small = _server(ctx, mix, 2, cache_bytes=one)
+        got = [f.result(timeout=120) for f in serve.run_poisson(small, qs, rate_hz=3000.0, seed=4)]
+        st = small.stats()
+        small.close()
+    for a, b in zip(ref, got):
+        assert a.tobytes() == b.tobytes()
+    assert st["errors"] == 0 and st["queries"] == len(qs)
+    assert st_big["traces"] <= len(deps) and st_big["evictions"] == 0
+    assert st["evictions"] > 0 and st["traces"] > st_big["traces"]
+    assert st["misses"] >= st["traces"] - 1 and st["hits"] + st["misses"] == len(qs)
+    assert st["miss_p50_ms"] is not None and st["miss_p99_ms"] >= st["miss_p50_ms"] > 0
+    assert st["hits"] == 0 or st["hit_p99_ms"] >= st["hit_p50_ms"] > 0
 
 
 def test_mix_matches_oracle_channel(mix):

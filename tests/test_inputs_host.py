@@ -46,3 +46,21 @@ def test_serving_scenes_meet_the_input_contract():
     scenes, _, _ = workloads.serving_mix()
     for sc in scenes.values():
         _check_scene(sc)
+
+
+def test_full_serving_mix_spans_the_configuration():
+    """The full serving mix: 16 rooms of 1k-200k triangles meeting the input
+    contract; RIS sizes from 37 to 4096 elements, grids from 16^2 to 256^2,
+    orders 1-3; no deployment above 2^24 receivers x elements."""
+    scenes, riss, deps = workloads.serving_mix_c4()
+    assert len(scenes) == 16 and len(deps) == 32
+    tris = [sc.n_tri for sc in scenes.values()]
+    assert 1_000 <= min(tris) and max(tris) <= 200_000
+    for sc in scenes.values():
+        _check_scene(sc)
+    R = [d.rx_pos.shape[0] for d in deps]
+    M = [riss[d.ris_key].elems.shape[0] for d in deps]
+    assert max(R) == 256 * 256 and min(R) >= 16 * 16
+    assert max(M) == 4096 and min(M) >= 37
+    assert {d.order for d in deps} <= {1, 2, 3}
+    assert all(r * m <= 1 << 24 for r, m in zip(R, M))
