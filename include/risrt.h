@@ -181,7 +181,8 @@ rt_status rt_mem_info(rt_ctx ctx, uint64_t* in_use, uint64_t* budget);
  * wall or a face: the "surfaces" whose permutations Section II-B searches;
  * triangles of one surface must be coplanar; ids 0..n_surf-1, each used), and
  * a complex reflection coefficient per triangle applied at every specular
- * bounce.  n_tri may be 0 (free space).  Builds the BVH on `stream`
+ * bounce.  n_tri may be 0 (free space); at most 2^29 - 1 triangles and
+ * 2^21 - 1 surfaces (RT_EINVAL beyond).  Builds the BVH on `stream`
  * (waits for it once, to check the tree depth; device arrays are read in
  * place, host arrays staged, all before the call returns). */
 rt_status rt_scene_create(rt_ctx ctx, const float* vtx_xyz, int64_t n_vtx, const int32_t* tri,

@@ -654,6 +654,8 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     if (badv & 8) throw hip_error("BVH build produced an inconsistent tree");
     if (depth > RT_STACK - 1) throw inval_error("BVH deeper than the traversal stack");
     if (n_seen != n_surf) throw inval_error("surface ids must be 0..n_surf-1, each used");
+    if (n_surf > (1 << RT_KEY_BITS) - 1)   // a candidate key holds surface id + 1 in 21 bits
+        throw inval_error("at most 2^21 - 1 surfaces");
     if (badv & 32) throw inval_error("the lowest-numbered triangle of a surface is degenerate (no plane)");
     if (badv & 16) throw inval_error("the triangles of a surface are not coplanar (a vertex lies more than "
                                      "0.1 mm from the plane of the surface's first triangle)");
