@@ -1,5 +1,6 @@
 // C ABI of the risrt library: contexts, handles, memory budget, argument
 // checks, and the calls declared in include/risrt.h.
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -374,7 +375,10 @@ void release_obj(rt_ctx ctx, Obj& o)
                            &s.nrm})
             retarget(*p, fs);
     }
-    if (o.ris) retarget(o.ris->elem, fs);
+    if (o.ris) {
+        retarget(o.ris->elem, fs);
+        retarget(o.ris->order, fs);
+    }
     if (o.channel) {
         Channel& ch = *o.channel;
         for (Scratch* p : {&ch.H, &ch.E_env, &ch.hits[0], &ch.hits[1], &ch.cand_keys[0], &ch.cand_keys[1], &ch.env,
@@ -536,6 +540,53 @@ rt_status rt_scene_set_materials(rt_ctx ctx, uint64_t scene, const float* eps_r,
     });
 }
 
+// Elements sorted by the Morton code of their coordinates in the RIS plane
+// (16 bits per axis over the elements' extent; equal codes keep their index
+// order).  Consecutive runs of 64 are compact patches of the surface (8 x 8
+// blocks of a square array), so the legs a wave of the per-element kernel
+// tests together lie in a thin tube; the order changes no result.
+static std::vector<int32_t> element_order(const std::vector<double>& xyz, const double c[3], const double n[3])
+{
+    const size_t M = xyz.size() / 3;
+    // in-plane axes: a = n x up (up = z, or x for a horizontal RIS), b = n x a
+    const double up[3] = {fabs(n[2]) > 0.9 ? 1.0 : 0.0, 0.0, fabs(n[2]) > 0.9 ? 0.0 : 1.0};
+    double a[3] = {n[1] * up[2] - n[2] * up[1], n[2] * up[0] - n[0] * up[2], n[0] * up[1] - n[1] * up[0]};
+    const double al = sqrt(a[0] * a[0] + a[1] * a[1] + a[2] * a[2]);
+    for (double& v : a) v /= al;
+    const double b[3] = {n[1] * a[2] - n[2] * a[1], n[2] * a[0] - n[0] * a[2], n[0] * a[1] - n[1] * a[0]};
+    std::vector<double> u(M), v(M);
+    double u0 = 1e300, u1 = -1e300, v0 = 1e300, v1 = -1e300;
+    for (size_t i = 0; i < M; ++i) {
+        const double d[3] = {xyz[3 * i] - c[0], xyz[3 * i + 1] - c[1], xyz[3 * i + 2] - c[2]};
+        u[i] = d[0] * a[0] + d[1] * a[1] + d[2] * a[2];
+        v[i] = d[0] * b[0] + d[1] * b[1] + d[2] * b[2];
+        u0 = fmin(u0, u[i]);
+        u1 = fmax(u1, u[i]);
+        v0 = fmin(v0, v[i]);
+        v1 = fmax(v1, v[i]);
+    }
+    auto quant = [](double x, double lo, double hi) -> uint32_t {
+        if (!(hi > lo)) return 0u;
+        const double t = (x - lo) / (hi - lo) * 65535.0;
+        return (uint32_t)fmin(fmax(t + 0.5, 0.0), 65535.0);
+    };
+    auto spread = [](uint32_t x) -> uint64_t {   // 16 bits to the even positions of 32
+        uint64_t y = x & 0xFFFFu;
+        y = (y | (y << 8)) & 0x00FF00FFull;
+        y = (y | (y << 4)) & 0x0F0F0F0Full;
+        y = (y | (y << 2)) & 0x33333333ull;
+        y = (y | (y << 1)) & 0x55555555ull;
+        return y;
+    };
+    std::vector<std::pair<uint64_t, int32_t>> key(M);
+    for (size_t i = 0; i < M; ++i)
+        key[i] = {spread(quant(u[i], u0, u1)) | (spread(quant(v[i], v0, v1)) << 1), (int32_t)i};
+    std::sort(key.begin(), key.end());
+    std::vector<int32_t> ord(M);
+    for (size_t i = 0; i < M; ++i) ord[i] = key[i].second;
+    return ord;
+}
+
 rt_status rt_ris_create(rt_ctx ctx, const double* elem_xyz, int64_t M, const double centre[3], const double normal[3],
                         double dy, double dz, double elem_gain, double pattern_q, uint64_t* ris)
 {
@@ -560,6 +611,13 @@ rt_status rt_ris_create(rt_ctx ctx, const double* elem_xyz, int64_t M, const dou
         r.q = pattern_q;
         r.elem = Scratch(ctx->c, sizeof(double) * 3 * (size_t)M, nullptr);
         HIP_CHECK(hipMemcpyAsync(r.elem.p, elem_xyz, r.elem.bytes, hipMemcpyDefault, nullptr));
+        // the order the per-element kernel takes the elements in, 64 per wave
+        std::vector<double> xyz((size_t)3 * M);
+        HIP_CHECK(hipMemcpyAsync(xyz.data(), r.elem.p, r.elem.bytes, hipMemcpyDeviceToHost, nullptr));
+        HIP_CHECK(hipStreamSynchronize(nullptr));
+        const std::vector<int32_t> ord = element_order(xyz, r.centre, r.normal);
+        r.order = Scratch(ctx->c, sizeof(int32_t) * (size_t)M, nullptr);
+        HIP_CHECK(hipMemcpyAsync(r.order.p, ord.data(), r.order.bytes, hipMemcpyHostToDevice, nullptr));
         HIP_CHECK(hipStreamSynchronize(nullptr));
         o->users.push_back(nullptr);
         *ris = insert(ctx, o);

@@ -163,6 +163,7 @@ struct RisObj {
     double centre[3], normal[3];
     double dy = 0, dz = 0, gain = 0, q = 1;
     Scratch elem;   // double [M * 3]
+    Scratch order;  // int32 [M]: the elements in Morton order of their in-plane coordinates
 };
 
 struct Channel {

@@ -100,6 +100,7 @@ struct RisView {
     int32_t M;
     int32_t pad;
     const double* elem;    // 3 per element
+    const int32_t* order;  // elements in the order the per-element kernel groups them (64 per wave)
     double centre[3];
     double normal[3];      // unit
     double normal_norm;    // |normal| in FP64

@@ -1094,9 +1094,12 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
     if (w < R * n_mchunk) {
         const int64_t wr = w / n_mchunk;
         const int64_t r = (int64_t)(order[wr] & 0xFFFFFFFFull);
-        const int m = (int)(w - wr * n_mchunk) * 64 + lane;
-        const bool active = m < rv.M;
-        const int mm = active ? m : 0;
+        // the wave's 64 elements are neighbours on the RIS (Morton order of their
+        // in-plane coordinates), so the legs of a slot stay in a thin tube
+        const int mi = (int)(w - wr * n_mchunk) * 64 + lane;
+        const bool active = mi < rv.M;
+        const int mm = active ? rv.order[mi] : 0;
+        const int m = mm;
         const double* e = rv.elem + 3 * mm;
         const double E[3] = {e[0], e[1], e[2]};
         double dt_keep = 0.0;   // |E - Tx| as the direct leg's length (kept paths only; 0 with the
@@ -1342,6 +1345,7 @@ static RisView make_ris_view(const TraceArgs& a)
     rv.M = (int32_t)a.ris->M;
     rv.pad = 0;
     rv.elem = a.ris->elem.as<double>();
+    rv.order = a.ris->order.as<int32_t>();
     for (int q = 0; q < 3; ++q) {
         rv.centre[q] = a.ris->centre[q];
         rv.normal[q] = a.ris->normal[q];
