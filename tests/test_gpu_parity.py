@@ -573,7 +573,10 @@ def test_ris_sum_valu(ctx, R, M, C, real):
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
 @pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (300, 1024, 257, True),
-                                        (64, 1024, 128, False)])
+                                        (64, 1024, 128, False),
+                                        # one K tile; three (a multiple of the three LDS stages); eight tile
+                                        # rows (the XCD-aware order with groups of one row) and six K tiles
+                                        (50, 20, 7, True), (96, 96, 300, True), (1024, 96, 300, False)])
 def test_ris_sum_mfma(ctx, R, M, C, real, prec):
     E, P, E_ref, P_ref, P_inc = _gemm_case(ctx, R, M, C, real, prec)
     sel = P_ref >= 1e-3 * P_inc
