@@ -8,6 +8,7 @@ there is no fallback: loading fails loudly without it.
 from __future__ import annotations
 
 import ctypes
+import json
 import os
 from typing import Optional
 
@@ -459,6 +460,53 @@ def ris_sum_noalloc(ctx: Context, ch: int, gamma, E_out=None, P_out=None, scale:
                                     ctypes.c_void_p(E_out.data_ptr()) if E_out is not None else None,
                                     ctypes.c_void_p(P_out.data_ptr()) if P_out is not None else None,
                                     _stream_handle(stream)))
+
+
+CHANNEL_FILE_VERSION = 1
+
+
+def channel_save(ctx: Context, ch: int, path: str, **meta) -> str:
+    """Write a channel to an ``.npz`` file: E_env complex64 [R], H complex64
+    [R, M] (receiver-major, as rt_channel_read gives them) and a JSON string of
+    the keyword arguments (deployment parameters, say).  Nothing in the file is
+    pickled.  Returns the path written (numpy adds ``.npz`` if it is missing)."""
+    E, H = ctx.channel_read(ch)
+    doc = dict(meta, version=CHANNEL_FILE_VERSION, R=int(H.shape[0]), M=int(H.shape[1]))
+    if not path.endswith(".npz"):
+        path += ".npz"
+    np.savez(path, E_env=E, H=H, meta=np.array(json.dumps(doc, sort_keys=True)))
+    return path
+
+
+def read_channel_file(path: str):
+    """(E_env, H, meta) of a file written by channel_save, checked: complex64
+    arrays, E_env [R] and H [R, M] with the R and M the metadata states, all
+    finite.  Raises ValueError on anything else."""
+    with np.load(path, allow_pickle=False) as f:
+        for k in ("E_env", "H", "meta"):
+            if k not in f.files:
+                raise ValueError("%s: no %s array" % (path, k))
+        E, H, raw = f["E_env"], f["H"], f["meta"]
+    if raw.shape != () or raw.dtype.kind != "U":
+        raise ValueError("%s: meta is not a string" % path)
+    meta = json.loads(str(raw))
+    if meta.get("version") != CHANNEL_FILE_VERSION:
+        raise ValueError("%s: channel file version %r" % (path, meta.get("version")))
+    if E.dtype != np.complex64 or H.dtype != np.complex64:
+        raise ValueError("%s: arrays must be complex64" % path)
+    if E.ndim != 1 or H.ndim != 2 or H.shape[0] != E.shape[0] or (meta.get("R"), meta.get("M")) != H.shape:
+        raise ValueError("%s: shapes E_env %s, H %s do not match R, M = %s, %s"
+                         % (path, E.shape, H.shape, meta.get("R"), meta.get("M")))
+    if not (np.isfinite(E.view(np.float32)).all() and np.isfinite(H.view(np.float32)).all()):
+        raise ValueError("%s: non-finite values" % path)
+    return E, H, meta
+
+
+def channel_load(ctx: Context, path: str, stream=None):
+    """Channel handle (rt_channel_create) and metadata of a file written by
+    channel_save."""
+    E, H, meta = read_channel_file(path)
+    return ctx.channel_create(E, H, stream=stream), meta
 
 
 def upload_problem(ctx: Context, prob, stream=None):

@@ -20,11 +20,20 @@ answer is the received power map P [R x C] (eqs. (9)-(10)).
   apart for cache hits and misses (a miss: the deployment's channel was not
   cached when its batch started, so the batch traced it or waited for the
   slot that did).
+* With ``log`` (a path or a text stream) every answered query adds one JSON
+  line: latency, queueing time, columns, its batch, hit or miss, the segments
+  its batch traced and the bytes of its answer.
+* A channel can be exported to an ``.npz`` file and imported into another
+  server's cache (a warm start: the deployment is then served without
+  tracing).
 """
 from __future__ import annotations
 
 import collections
 import dataclasses
+import hashlib
+import io
+import json
 import queue
 import threading
 import time
@@ -77,8 +86,12 @@ def deployment_from_problem(key: str, scene_key: str, ris_key: str, prob) -> Dep
 
 class Server:
     def __init__(self, ctx: risrt.Context, n_slots: int = 4, max_cols: int = 4096, cache_frac: float = 0.6,
-                 cache_bytes: Optional[int] = None):
+                 cache_bytes: Optional[int] = None, log=None):
         import torch
+        # per-query JSON lines: a path (appended to) or an open text stream
+        self._log_own = isinstance(log, str)
+        self._log: Optional[io.TextIOBase] = open(log, "a") if self._log_own else log
+        self._log_lock = threading.Lock()
         self.ctx = ctx
         self.n_slots = n_slots
         self.max_cols = max_cols
@@ -170,6 +183,56 @@ class Server:
         self._chan.clear()
         self._scene_h.clear()
         self._ris_h.clear()
+        if self._log is not None:
+            self._log.flush()
+            if self._log_own:
+                self._log.close()
+            self._log = None
+
+    # ---------------- channel export / import ----------------
+    def export_channel(self, dep_key: str, path: str) -> str:
+        """Write the deployment's channel (traced first if it is not cached)
+        to an ``.npz`` file with the deployment's parameters as metadata.
+        Returns the path written."""
+        dep = self._deps[dep_key]
+        stream = self._torch.cuda.Stream()
+        ch, _, _ = self._channel(dep, stream)
+        try:
+            return risrt.channel_save(self.ctx, ch, path, **_dep_meta(dep))
+        finally:
+            with self._lock:
+                self._in_use[dep_key] -= 1
+
+    def import_channel(self, dep_key: str, path: str) -> None:
+        """Put a channel file written by export_channel (or
+        risrt.channel_save) into the cache as the deployment's channel.  Its R
+        and M must be the deployment's; if its metadata names deployment
+        parameters, they must be the deployment's too."""
+        dep = self._deps[dep_key]
+        E, H, meta = risrt.read_channel_file(path)
+        M = self._ris_host[dep.ris_key].elems.shape[0]
+        if H.shape != (dep.rx_pos.shape[0], M):
+            raise ValueError("channel %s is %s, deployment %s needs (%d, %d)"
+                             % (path, H.shape, dep_key, dep.rx_pos.shape[0], M))
+        mine = _dep_meta(dep)
+        for k, v in meta.items():
+            if k in mine and mine[k] != v:
+                raise ValueError("channel %s was traced for %s = %r, deployment %s has %r"
+                                 % (path, k, v, dep_key, mine[k]))
+        with self._key_locks["chan:" + dep_key]:
+            ch = self.ctx.channel_create(E, H)
+            old = None
+            with self._lock:
+                if self._in_use[dep_key]:
+                    self.ctx.destroy(ch)
+                    raise RuntimeError("deployment %s has queries in flight" % dep_key)
+                old = self._chan.pop(dep_key, None)
+                self._chan_bytes.pop(dep_key, None)
+                self._chan[dep_key] = ch
+                self._chan_bytes[dep_key] = _channel_bytes(*H.shape)
+            if old is not None:
+                self.ctx.destroy(old)
+            self._evict(dep_key)
 
     def clear_latencies(self) -> None:
         with self._lock:
@@ -256,8 +319,9 @@ class Server:
             return self._ris_h[key]
 
     def _channel(self, dep: Deployment, stream):
-        """(channel handle, missed): missed when the channel was not cached as
-        the call began (this call traced it, or waited for the one that did)."""
+        """(channel handle, missed, segments traced): missed when the channel
+        was not cached as the call began (this call traced it, or waited for
+        the one that did)."""
         with self._lock:
             missed = dep.key not in self._chan
         with self._key_locks["chan:" + dep.key]:
@@ -266,21 +330,21 @@ class Server:
                     self._chan.move_to_end(dep.key)
                     self._in_use[dep.key] += 1
                     self.cache_hits += 1
-                    return self._chan[dep.key], missed
+                    return self._chan[dep.key], missed, 0
             self._evict(dep.key)
             scene = self._scene(dep.scene_key, stream)
             ris = self._ris(dep.ris_key)
-            ch, _ = self.ctx.trace(scene, ris, dep.tx_pos, dep.tx_axis, dep.tx_power_w, dep.tx_gain,
-                                   dep.tx_pattern, dep.tx_param, dep.rx_pos, dep.rx_axis, dep.rx_gain,
-                                   dep.rx_pattern, dep.rx_param, dep.freq_hz, dep.order, dep.n_rays,
-                                   stream=stream, stats=False)
+            ch, st = self.ctx.trace(scene, ris, dep.tx_pos, dep.tx_axis, dep.tx_power_w, dep.tx_gain,
+                                    dep.tx_pattern, dep.tx_param, dep.rx_pos, dep.rx_axis, dep.rx_gain,
+                                    dep.rx_pattern, dep.rx_param, dep.freq_hz, dep.order, dep.n_rays,
+                                    stream=stream)
             R, M, _, _ = self.ctx.channel_info(ch)
             with self._lock:
                 self._chan[dep.key] = ch
-                self._chan_bytes[dep.key] = R * M * 8 * 3 + R * 8
+                self._chan_bytes[dep.key] = _channel_bytes(R, M)
                 self._in_use[dep.key] += 1
                 self.n_traces += 1
-            return ch, True
+            return ch, True, int(st["segments"])
 
     def _evict(self, keep: str) -> None:
         with self._lock:
@@ -302,8 +366,9 @@ class Server:
         dep = self._deps[batch[0].dep]
         held = False
         try:
+            t_start = time.perf_counter()
             with torch.cuda.stream(stream):
-                ch, missed = self._channel(dep, stream)
+                ch, missed, segments = self._channel(dep, stream)
                 held = True
                 # the batch's columns are gathered straight into pinned memory and uploaded on the slot's stream
                 M = batch[0].gamma.shape[0]
@@ -336,6 +401,16 @@ class Server:
                 self.missed.extend([missed] * len(lats))
                 self.n_batches += 1
                 self.n_cols += cols
+            if self._log is not None:
+                R = P.shape[0]
+                lines = [json.dumps({"qid": q.qid, "deployment": q.dep, "columns": int(q.gamma.shape[1]),
+                                     "precision": q.precision, "cache": "miss" if missed else "hit",
+                                     "latency_ms": 1e3 * lat, "queue_ms": 1e3 * (t_start - q.t_submit),
+                                     "batch_queries": len(batch), "batch_columns": cols, "slot": slot,
+                                     "segments_traced": segments, "bytes_out": R * int(q.gamma.shape[1]) * 4})
+                         for q, lat in zip(batch, lats)]
+                with self._log_lock:
+                    self._log.write("\n".join(lines) + "\n")
         except risrt.RtError as e:
             requeue = False
             with self._lock:
@@ -363,6 +438,21 @@ class Server:
                 self._reserved -= est
                 self._free_slots.append(slot)
                 self._lock.notify_all()
+
+
+def _channel_bytes(R: int, M: int) -> int:
+    # H, its cached two-part split and E_env
+    return R * M * 8 * 3 + R * 8
+
+
+def _dep_meta(dep: Deployment) -> dict:
+    """The deployment parameters a channel depends on, JSON-ready."""
+    d = dataclasses.asdict(dep)
+    d.pop("key")
+    d.pop("rx_pos")
+    out = {k: np.asarray(v).tolist() for k, v in d.items()}   # numpy scalars and arrays to plain numbers
+    out["rx_pos_sha1"] = hashlib.sha1(np.ascontiguousarray(dep.rx_pos, np.float64)).hexdigest()
+    return out
 
 
 def run_poisson(server: Server, queries, rate_hz: float, seed: int = 0):
