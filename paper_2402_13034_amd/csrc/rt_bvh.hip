@@ -491,6 +491,13 @@ __global__ void k_surf_grid(const int32_t* s_ptr, const int32_t* s_tris, const d
 
 
 
+// the scene's vertex bounds as floats (lower x y z, upper x y z)
+__global__ void k_scene_box(const unsigned* bounds, float* box)
+{
+    const int i = threadIdx.x;
+    if (i < 6) box[i] = ord2f(bounds[6 + i]);
+}
+
 __global__ void k_ctl_init(unsigned* ctl)
 {
     int i = threadIdx.x;
@@ -570,6 +577,9 @@ void build_scene(Ctx& c, Scene& s, const float* V, int64_t nv, const int32_t* T,
     hipLaunchKernelGGL(k_scene_prep, dim3(blocks_for(nt, B)), dim3(B), 0, st, dV, dT, dS, dR, dI, nv, nt,
                        s.v64.as<double>(), s.refl.as<float2>(), s.surf.as<int32_t>(), cent.as<float4>(), bounds, bad,
                        s.t_proj.as<double>(), s.t_axes.as<int32_t>());
+    HIP_CHECK(hipGetLastError());
+    s.box = Scratch(c, 6 * sizeof(float), st);
+    hipLaunchKernelGGL(k_scene_box, dim3(1), dim3(64), 0, st, bounds, s.box.as<float>());
     HIP_CHECK(hipGetLastError());
     Scratch keys_raw(c, 2 * sizeof(uint64_t) * (size_t)nt, st), keys(c, 2 * sizeof(uint64_t) * (size_t)nt, st);
     hipLaunchKernelGGL(k_morton, dim3(blocks_for(nt, B)), dim3(B), 0, st, cent.as<float4>(), bounds, nt,

@@ -130,6 +130,7 @@ struct Scene {
     Scratch mat;   // float2 per triangle (eps_r, sigma), empty until set
     Scratch nrm;   // 3 doubles per triangle: unit normal, computed with the materials
     Scratch g_axes, g_frame, g_cnt, g_tris;
+    Scratch box;   // 6 floats: the vertices' lower and upper corner
     SceneView view() const {
         SceneView v;
         v.n_tri = (int32_t)n_tri;

@@ -482,22 +482,46 @@ __global__ __launch_bounds__(TC_B) void k_table_compact2(const unsigned long lon
     }
 }
 
-// One wave takes GEO_CPW candidates for 64 consecutive receivers, so the
-// candidate's surfaces, planes and triangles are wave-uniform (scalar loads,
-// no divergence in the loops over a surface's triangles).  A block covers 32
-// candidates = one 32-bit word of the receiver's row of the validity mask
-// (mask[r * n_words + w], bit b = candidate 32 w + b).
-// grid: x = word (group of 32 candidates), y = block of 64 receivers
+// Sort keys of the receivers: the 42-bit Morton code of the position (14 bits
+// per axis over the scene's box, clamped to it) above the 22-bit index.  A
+// scene without triangles has no box (null): every code is 0.
+constexpr int RX_IDX_BITS = 22;
+__global__ void k_rx_keys(const double* rx, int64_t R, const float* box, uint64_t* keys)
+{
+    const int64_t r = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (r >= R) return;
+    uint64_t code = 0;
+    for (int k = 0; k < 3 && box; ++k) {
+        const float lo = box[k], ext = box[3 + k] - box[k];
+        float u = ext > 0.0f ? ((float)rx[3 * r + k] - lo) / ext : 0.5f;
+        u = fminf(fmaxf(u, 0.0f), 1.0f);
+        const unsigned q = (unsigned)fminf(u * 16384.0f, 16383.0f);
+        for (int b = 0; b < 14; ++b) code |= (uint64_t)((q >> b) & 1u) << (3 * b + 2 - k);
+    }
+    keys[r] = code << RX_IDX_BITS | (uint64_t)r;
+}
+
+// One wave takes GEO_CPW candidates for 64 receivers, so the candidate's
+// surfaces, planes and triangles are wave-uniform (scalar loads, no divergence
+// in the loops over a surface's triangles).  The receivers of a wave are 64
+// consecutive ones of `order` (the receivers sorted by Morton code of their
+// positions): neighbours, so that a candidate tends to fail for all lanes of a
+// wave at the same bounce.  A block covers 32 candidates = one 32-bit word of
+// the receiver's row of the validity mask (mask[r * n_words + w], bit b =
+// candidate 32 w + b).
+// grid: x = word (group of 32 candidates), y = block of 64 slots of `order`
 constexpr int GEO_B = 256, GEO_CPW = 8;
 template <int KM>
 __global__ __launch_bounds__(GEO_B) void k_geo_mask(SceneView s, CandView cv, double sx, double sy, double sz,
-                                                    const double* rx, int64_t R, int64_t n_words, uint32_t* mask)
+                                                    const double* rx, const uint64_t* order, int64_t R,
+                                                    int64_t n_words, uint32_t* mask)
 {
     static_assert(GEO_B / 64 * GEO_CPW == 32, "one mask word per block");
     __shared__ uint32_t part[GEO_B / 64][64];
     const int wib = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
-    const int64_t r = (int64_t)blockIdx.y * 64 + lane;
+    const int64_t slot = (int64_t)blockIdx.y * 64 + lane;
+    const int64_t r = slot < R ? (int64_t)(order[slot] & ((1ull << RX_IDX_BITS) - 1ull)) : R;
     uint32_t bits = 0;
     if (r < R) {
         const double S[3] = {sx, sy, sz};
@@ -1550,7 +1574,8 @@ static int64_t cand_phase_b(Ctx& c, const TraceArgs& a, bool exhaustive, Branch&
 
 // candidate images and the geometric test of every (receiver, candidate) cell
 template <int KM>
-static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& br, int64_t n_cand)
+static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& br, int64_t n_cand,
+                       const uint64_t* rx_order)
 {
     hipStream_t st = br.st;
     Cands& cd = br.cd;
@@ -1571,7 +1596,8 @@ static void geo_launch(Ctx& c, const SceneView& sv, const TraceArgs& a, Branch& 
     br.mask = Scratch(c, sizeof(uint32_t) * (size_t)(R * n_words), st);
     if (R * n_words > 0) {
         hipLaunchKernelGGL(k_geo_mask<KM>, dim3((unsigned)n_words, nblk(R, 64)), dim3(GEO_B), 0, st, sv, cd.view(),
-                           br.src[0], br.src[1], br.src[2], a.rx_dev, R, n_words, br.mask.as<uint32_t>());
+                           br.src[0], br.src[1], br.src[2], a.rx_dev, rx_order, R, n_words,
+                           br.mask.as<uint32_t>());
         HIP_CHECK(hipGetLastError());
     }
     // receivers' offsets into the valid cells; entry R = total
@@ -1739,6 +1765,19 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
     // 1-3: candidates
     cand_phase_a<KM>(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bt, d_disc);
     if (two) cand_phase_a<KM>(c, sv, stk, a, brute, exhaustive, keep_hits, ch, bu, d_disc);
+    // the receivers in Morton order of their positions, for the geometry kernel
+    // (queued behind the Tx discovery; the centre branch waits for it below)
+    if (R >= ((int64_t)1 << RX_IDX_BITS)) throw inval_error("too many receivers");
+    Scratch rx_order(c, sizeof(uint64_t) * (size_t)(R > 0 ? R : 1), st);
+    Event rx_ready;
+    if (R > 0) {
+        Scratch rx_keys(c, sizeof(uint64_t) * (size_t)R, st);
+        hipLaunchKernelGGL(k_rx_keys, dim3(nblk(R, 256)), dim3(256), 0, st, a.rx_dev, R, a.scene->box.as<float>(),
+                           rx_keys.as<uint64_t>());
+        HIP_CHECK(hipGetLastError());
+        sort_keys(c, rx_keys.as<uint64_t>(), rx_order.as<uint64_t>(), R, 1, RX_IDX_BITS, 64, st);
+    }
+    HIP_CHECK(hipEventRecord(rx_ready.e, st));
     // Each branch goes on as soon as its own count is back, so the Tx branch
     // (launched first) does not wait for the centre branch's discovery.  An
     // overflow of a hash set repeats phase A with the next level (the
@@ -1757,9 +1796,12 @@ static void trace_km(Ctx& c, const TraceArgs& a, Channel& ch, TraceOut& out, boo
     const int64_t n_tx = cand_phase_b(c, a, exhaustive, bt, count_of(bt));
     tm.mark();   // 2
     // 4: geometry of every (receiver, candidate)
-    geo_launch<KM>(c, sv, a, bt, n_tx);
+    geo_launch<KM>(c, sv, a, bt, n_tx, rx_order.as<uint64_t>());
     const int64_t n_u0 = two ? cand_phase_b(c, a, exhaustive, bu, count_of(bu)) : 0;
-    if (two) geo_launch<KM>(c, sv, a, bu, n_u0);
+    if (two) {
+        HIP_CHECK(hipStreamWaitEvent(bu.st, rx_ready.e, 0));
+        geo_launch<KM>(c, sv, a, bu, n_u0, rx_order.as<uint64_t>());
+    }
     out.n_cand_tx = n_tx;
     out.n_cand_u = n_u0;
     // the field reaching every element, on its own stream (forked here, launched
