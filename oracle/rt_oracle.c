@@ -717,21 +717,21 @@ int64_t or_find_paths(const float* V, const int32_t* T, const int32_t* surf, int
     uint8_t* ok = (uint8_t*)calloc((size_t)(cells > 0 ? cells : 1), 1);
     double* pts = (double*)calloc((size_t)(cells * K * 3 > 0 ? cells * K * 3 : 1), sizeof(double));
     int32_t* trs = (int32_t*)malloc(sizeof(int32_t) * (size_t)(cells * K > 0 ? cells * K : 1));
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t r = 0; r < R; ++r) {
-        for (int64_t c = 0; c < nc; ++c) {
-            const int32_t* seq = cands + c * K;
-            int k = seq_len(seq, K);
-            double P[8][3];
-            int64_t tri_of[8];
-            for (int j = 0; j < K; ++j) trs[(r * nc + c) * K + j] = -1;
-            if (!image_path(t64, &st, seq, k, S, rx + 3 * r, P, tri_of)) continue;
-            if (!path_clear(t32, surf, nt, seq, k, S, rx + 3 * r, P)) continue;
-            ok[r * nc + c] = 1;
-            for (int j = 0; j < k; ++j) {
-                trs[(r * nc + c) * K + j] = (int32_t)tri_of[j];
-                for (int q = 0; q < 3; ++q) pts[((r * nc + c) * K + j) * 3 + q] = P[j][q];
-            }
+    /* every (rx, cand) cell on its own: the threads share all cells, not only receivers */
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t cell = 0; cell < cells; ++cell) {
+        const int64_t r = cell / nc, c = cell - r * nc;
+        const int32_t* seq = cands + c * K;
+        int k = seq_len(seq, K);
+        double P[8][3];
+        int64_t tri_of[8];
+        for (int j = 0; j < K; ++j) trs[cell * K + j] = -1;
+        if (!image_path(t64, &st, seq, k, S, rx + 3 * r, P, tri_of)) continue;
+        if (!path_clear(t32, surf, nt, seq, k, S, rx + 3 * r, P)) continue;
+        ok[cell] = 1;
+        for (int j = 0; j < k; ++j) {
+            trs[cell * K + j] = (int32_t)tri_of[j];
+            for (int q = 0; q < 3; ++q) pts[(cell * K + j) * 3 + q] = P[j][q];
         }
     }
     int64_t n = 0;
@@ -788,32 +788,34 @@ void or_ris_paths(const float* V, const int32_t* T, const int32_t* surf, int64_t
 #pragma omp parallel for schedule(dynamic, 1)
     for (int64_t m = 0; m < M; ++m)
         txm_clear[m] = (uint8_t)!leg_blocked(t32, surf, nt, tx, elems + 3 * m, -1, -1);
-#pragma omp parallel for schedule(dynamic, 1)
-    for (int64_t r = 0; r < R; ++r) {
-        int64_t ns = uptr[r + 1] - uptr[r] + 1;
-        for (int64_t s = 0; s < ns; ++s) {
-            int64_t slot = uptr[r] + r + s;
-            int32_t empty[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
-            const int32_t* seq = (s == 0) ? empty : useq + (uptr[r] + s - 1) * K;
-            int k = (s == 0) ? 0 : seq_len(seq, K);
-            for (int64_t m = 0; m < M; ++m) {
-                double P[8][3];
-                int64_t tri_of[8];
-                int64_t cell = slot * M + m;
-                for (int j = 0; j < K * 3; ++j) pts[cell * K * 3 + j] = 0.0;
-                for (int j = 0; j < K; ++j) tri[cell * K + j] = -1;
-                int ok = lit ? lit[m] : txm_clear[m];
-                if (ok) ok = image_path(t64, &st, seq, k, elems + 3 * m, rx + 3 * r, P, tri_of);
-                if (ok) ok = path_clear(t32, surf, nt, seq, k, elems + 3 * m, rx + 3 * r, P);
-                valid[cell] = (uint8_t)ok;
-                if (ok)
-                    for (int j = 0; j < k; ++j) {
-                        tri[cell * K + j] = (int32_t)tri_of[j];
-                        for (int q = 0; q < 3; ++q) pts[(cell * K + j) * 3 + q] = P[j][q];
-                    }
+    /* receiver of every slot (receiver r owns slots uptr[r] + r .. uptr[r + 1] + r) */
+    const int64_t n_slots = R > 0 ? uptr[R] + R : 0;
+    int64_t* slot_rx = (int64_t*)malloc(sizeof(int64_t) * (size_t)(n_slots > 0 ? n_slots : 1));
+    for (int64_t r = 0; r < R; ++r)
+        for (int64_t slot = uptr[r] + r; slot <= uptr[r + 1] + r; ++slot) slot_rx[slot] = r;
+    /* every (slot, element) cell on its own: the threads share all cells, not only receivers */
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t cell = 0; cell < n_slots * M; ++cell) {
+        const int64_t slot = cell / M, m = cell - slot * M;
+        const int64_t r = slot_rx[slot], s = slot - (uptr[r] + r);
+        int32_t empty[8] = {-1, -1, -1, -1, -1, -1, -1, -1};
+        const int32_t* seq = (s == 0) ? empty : useq + (uptr[r] + s - 1) * K;
+        int k = (s == 0) ? 0 : seq_len(seq, K);
+        double P[8][3];
+        int64_t tri_of[8];
+        for (int j = 0; j < K * 3; ++j) pts[cell * K * 3 + j] = 0.0;
+        for (int j = 0; j < K; ++j) tri[cell * K + j] = -1;
+        int ok = lit ? lit[m] : txm_clear[m];
+        if (ok) ok = image_path(t64, &st, seq, k, elems + 3 * m, rx + 3 * r, P, tri_of);
+        if (ok) ok = path_clear(t32, surf, nt, seq, k, elems + 3 * m, rx + 3 * r, P);
+        valid[cell] = (uint8_t)ok;
+        if (ok)
+            for (int j = 0; j < k; ++j) {
+                tri[cell * K + j] = (int32_t)tri_of[j];
+                for (int q = 0; q < 3; ++q) pts[(cell * K + j) * 3 + q] = P[j][q];
             }
-        }
     }
+    free(slot_rx);
     free(t32);
     free(t64);
     free_surfaces(&st);
