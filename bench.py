@@ -279,6 +279,11 @@ def run_large_bench(ctx, reps=2):
     ctx.destroy(ch)
     ms_tx = float(np.mean([s_["ms_discovery"][0] for s_ in stage]))
     ms_span = float(np.mean([s_["ms_discovery"][2] for s_ in stage]))
+    # the per-element kernel priced as on the lab room (same unit costs)
+    ris_units = dict(zip(["node", "tri", "contain", "pair", "leg"], cst["ris_work"]))
+    ris_ms = float(np.mean([s_["ms_stage"][5] for s_ in stage]))
+    ris_flops = sum(FLOPS_PER[k] * ris_units[k] for k in ris_units)
+    ris_ach = ris_flops / (ris_ms * 1e-3) / 1e12
     w = cst["discovery_work"]
     units_tx = {"node": w[0], "tri": w[1], "segment": w[2]}
     units_all = {"node": w[0] + w[3], "tri": w[1] + w[4], "segment": w[2] + w[5]}
@@ -321,6 +326,11 @@ def run_large_bench(ctx, reps=2):
                                    "work_per_launch": units_tx, "bytes_per_unit": DISC_BYTES,
                                    "both_sources": {"achieved": ach_all, "frac": ach_all / HBM_PEAK_GBS,
                                                     "work": units_all}},
+            "roofline_ris": {"kernel": "k_ris (order 5)", "bound": "alu", "achieved": ris_ach,
+                             "peak": VECTOR_PEAK_TFLOPS, "unit": "TFLOP/s", "frac": ris_ach / VECTOR_PEAK_TFLOPS,
+                             "traffic": None, "launch_ms": ris_ms, "work_per_launch": ris_units,
+                             "flops_per_unit": FLOPS_PER,
+                             "binary_node_visits_per_leg": ris_units["node"] / max(ris_units["leg"], 1)},
             "ris_sum_1024": {"ms": ms_sum, "shape": {"R": R, "M": M, "C": C},
                              "tflops_complex_equiv": 8.0 * R * M * C / (ms_sum * 1e-3) / 1e12,
                              "tflops_executed": 8.0 * R * M * C / (ms_sum * 1e-3) / 1e12}}
