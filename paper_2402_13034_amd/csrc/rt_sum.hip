@@ -193,6 +193,7 @@ __global__ __launch_bounds__(256) void k_split_B(const float2* G, int64_t M, int
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef float f32x2 __attribute__((ext_vector_type(2)));
 
 constexpr int GBM = 128, GBN = 128, GBK = 32;
 constexpr int LDA = GBK + 8;   // padded row (bf16 elements)
@@ -506,8 +507,10 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
                     const float sr = sv[i][e / 4][(e % 4) / 2];
                     const float er = e0.x + sr * acc[i][j][e];
                     const float ei = e0.y + sr * acc[i][j][e + 1];
-                    if (Eout) Eout[r * C + c] = make_float2(er, ei);
-                    if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
+                    // streaming stores: the outputs are not read again here, and they drain
+                    // faster at the end of a tile without taking room in the L2s
+                    if (Eout) __builtin_nontemporal_store(f32x2{er, ei}, (f32x2*)&Eout[r * C + c]);
+                    if (Pout) __builtin_nontemporal_store((er * er + ei * ei) / (2.0f * ETA0_F), &Pout[r * C + c]);
                 }
             }
     }
