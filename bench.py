@@ -574,6 +574,25 @@ def cpu_baseline(n_rx_side=40, n_rays=1_000_000):
                       % (n_rays, idx.size, n_rx_side, n_rx_side, segs, dt)}
 
 
+def environment() -> dict:
+    """Where the numbers were taken: device, software versions and host CPU."""
+    import platform
+    import torch
+    p = torch.cuda.get_device_properties(0)
+    cpu = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    cpu = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"gpu": p.name, "gpu_arch": getattr(p, "gcnArchName", None), "compute_units": p.multi_processor_count,
+            "hbm_gib": round(p.total_memory / 2 ** 30, 1), "hip": torch.version.hip, "torch": torch.__version__,
+            "host_cpu": cpu, "host_logical_cpus": os.cpu_count()}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -687,6 +706,7 @@ def main():
         "latency_p99_ms": serving["p99_ms"] if serving else None,
         "ris_field_tflops": gemm["bf16x2"]["tflops_complex_equiv"] if gemm else None,
         "cpu_baseline": cpu,
+        "env": environment(),
     }
     print(json.dumps(out))
 
