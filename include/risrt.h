@@ -210,7 +210,8 @@ rt_status rt_ris_create(rt_ctx ctx, const double* elem_xyz, int64_t M, const dou
  *               Tx -> m -> r plus m -> surfaces -> r for every sequence valid
  *               from the RIS centre to r (eqs. (4)-(8), Section II-B);
  *   E_env[r]  = field of Tx -> surfaces -> r paths, orders 0..K (eq. (3)).
- * ris may be 0 (no RIS: only E_env).  rx_xyz: R float64 receiver points.
+ * ris may be 0 (no RIS: only E_env).  rx_xyz: R float64 receiver points,
+ * R <= 65535 x 64 (RT_EUNSUPPORTED beyond, before any work is queued).
  * Waits for `stream` several times (candidate and path counts). */
 rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, const double* rx_xyz,
                    int64_t R, const rt_rx* rx, const rt_params* params, void* stream,

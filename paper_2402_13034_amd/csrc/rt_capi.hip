@@ -649,7 +649,9 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         if (params->max_order < 0 || params->max_order > RT_MAX_K)
             return fail(RT_EUNSUPPORTED, "max_order must be 0.." + std::to_string(RT_MAX_K));
         if (!(params->freq_hz > 0) || params->n_rays < 0) return fail(RT_EINVAL, "bad frequency or ray count");
-        if (R > ((int64_t)1 << 31) - 1) return fail(RT_EUNSUPPORTED, "too many receivers");
+        // the geometry kernel's grid covers the receivers in blocks of 64 (at most 65535 of them);
+        // checked here, before any work is queued
+        if (R > (int64_t)65535 * 64) return fail(RT_EUNSUPPORTED, "at most 65535 x 64 receivers per trace");
         for (int32_t p : {tx->pattern, rx->pattern})
             if (p < 0 || p > 2) return fail(RT_EINVAL, "unknown pattern kind");
         double ta = tx->axis[0] * tx->axis[0] + tx->axis[1] * tx->axis[1] + tx->axis[2] * tx->axis[2];

@@ -411,6 +411,7 @@ class Server:
                          for q, lat in zip(batch, lats)]
                 with self._log_lock:
                     self._log.write("\n".join(lines) + "\n")
+                    self._log.flush()   # a batch's lines survive a crash of the process
         except risrt.RtError as e:
             requeue = False
             with self._lock:

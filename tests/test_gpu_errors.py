@@ -108,6 +108,10 @@ def test_trace_argument_errors(ctx):
     assert _status(lambda: risrt.trace_problem(ctx, prob, scene, ris, flags=1 << 20)) == risrt.RT_EINVAL
     _say("case negative ray count")
     assert _status(lambda: risrt.trace_problem(ctx, prob, scene, ris, n_rays=-5)) == risrt.RT_EINVAL
+    _say("case too many receivers (rejected before any work)")
+    many = np.zeros((65535 * 64 + 1, 3))
+    assert _status(lambda: risrt.trace_problem(ctx, prob, scene, ris, rx=many)) == risrt.RT_EUNSUPPORTED
+    del many
     _say("case stale handles")
     assert _status(lambda: risrt.trace_problem(ctx, prob, scene + 1000, ris)) == risrt.RT_ENOTFOUND
     assert _status(lambda: risrt.trace_problem(ctx, prob, scene, ris + 1000)) == risrt.RT_ENOTFOUND
