@@ -316,9 +316,17 @@ rt_status guarded(rt_ctx ctx, F&& f, bool batch_frees = true)
         HIP_CHECK(hipSetDevice(ctx->c.device));
         std::unique_ptr<FreeBatch> batch;
         if (batch_frees) batch = std::make_unique<FreeBatch>(ctx->c);
-        rt_status s = f();
-        if (s == RT_OK) g_err.clear();
-        return s;
+        try {
+            rt_status s = f();
+            if (s == RT_OK) g_err.clear();
+            return s;
+        } catch (...) {
+            // A call that fails part-way (out of budget in the middle of a trace, say) may have
+            // queued work on several streams that still reads buffers its unwinding released;
+            // they reach the cache (where any stream may take them) only after that work is done.
+            (void)hipDeviceSynchronize();
+            throw;
+        }
     } catch (const nomem_error& e) {
         return fail(RT_ENOMEM, e.what());
     } catch (const inval_error& e) {
