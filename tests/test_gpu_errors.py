@@ -196,3 +196,45 @@ def test_split_rebuilt_while_other_stream_reads(ctx):
     for prec, P in outs:
         assert np.array_equal(P.cpu().numpy(), ref[prec])
     ctx.destroy(ch)
+
+
+
+def test_out_of_budget_part_way_leaves_context_sound():
+    """In one context, a channel held as ballast leaves 0.5 to 10 MiB of the
+    budget free, so that traces run out of memory at different points (both
+    branches' work already queued); each fails with RT_ENOMEM, and after the
+    ballast is released the same context traces the problem bit-identically
+    to its first trace."""
+    from paper_2402_13034_amd import risrt
+    prob = synth.lab_room(nx=16, ny=16)
+    n_rays = 100_000
+    failed = succeeded = 0
+    with risrt.Context(0, mem_budget_bytes=96 << 20) as ctx:
+        scene, ris = risrt.upload_problem(ctx, prob)
+        ch, _ = risrt.trace_problem(ctx, prob, scene, ris, n_rays=n_rays)
+        E_ref, H_ref = ctx.channel_read(ch)
+        ctx.destroy(ch)
+        for left_kib in (512, 1024, 2048, 3072, 4096, 5120, 6144, 8192):
+            in_use, budget = ctx.mem_info()[:2]
+            # allocations above 4 MiB are whole 2 MiB blocks: H is one such size, E_env (at most
+            # 128 KiB here) takes a power-of-two block; about left_kib to left_kib + 2 MiB stay free
+            h_bytes = (budget - in_use - (left_kib << 10) - (128 << 10)) // (2 << 20) * (2 << 20)
+            rows = h_bytes // (8 * 1024)
+            _say("case ballast leaving about %d KiB of the budget: %d x 1024 complex" % (left_kib, rows))
+            ballast = ctx.channel_create(np.zeros(rows, np.complex64), np.zeros((rows, 1024), np.complex64))
+            try:
+                ch, _ = risrt.trace_problem(ctx, prob, scene, ris, n_rays=n_rays)
+                ctx.destroy(ch)
+                succeeded += 1
+            except risrt.RtError as e:
+                assert e.status == risrt.RT_ENOMEM, e
+                failed += 1
+            ctx.destroy(ballast)
+            ch, _ = risrt.trace_problem(ctx, prob, scene, ris, n_rays=n_rays)
+            E, H = ctx.channel_read(ch)
+            ctx.destroy(ch)
+            assert E.tobytes() == E_ref.tobytes() and H.tobytes() == H_ref.tobytes()
+        for h in (scene, ris):
+            ctx.destroy(h)
+    _say("traces that ran out of budget: %d, that fit: %d" % (failed, succeeded))
+    assert failed > 0
