@@ -63,7 +63,7 @@ def test_lab_room_full_size(ctx):
     assert np.array_equal(c_tx, O.candidates_from_hits_np(O.surface_hits(prob.scene, ref_tx), K))
     assert np.array_equal(c_u, O.candidates_from_hits_np(O.surface_hits(prob.scene, ref_u), K))
     # receivers sampled across the grid, first and last included
-    sample = np.unique(np.concatenate([[0, R - 1], np.random.default_rng(4).choice(R, 22, replace=False)]))
+    sample = np.unique(np.concatenate([[0, R - 1], np.random.default_rng(4).choice(R, 510, replace=False)]))
     sub = synth.lab_room()
     sub.rx_pos = prob.rx_pos[sample]
     ref = O.trace(sub, n_rays=prob.n_rays)
