@@ -16,6 +16,9 @@ answer is the received power map P [R x C] (eqs. (9)-(10)).
   its own column of Gamma, so a result is bit-identical alone and in a mix.
 * A query that does not fit the budget waits; one that cannot fit even alone
   fails with the library's RT_ENOMEM instead of blocking the queue.
+* Batches whose channel is not cached (they trace first, for milliseconds)
+  hold at most n_slots - 1 slots; queued cache hits may pass queued misses,
+  so a hit never waits behind traces occupying every slot.
 * Latency = completion time - submission time (host clock), per query, kept
   apart for cache hits and misses (a miss: the deployment's channel was not
   cached when its batch started, so the batch traced it or waited for the
@@ -114,6 +117,7 @@ class Server:
         torch.cuda.init()   # creating a stream does not initialise torch's device state by itself
         self._streams = [torch.cuda.Stream() for _ in range(n_slots)]
         self._reserved = 0
+        self._misses_running = 0   # admitted batches whose channel was not cached at admission
         self._next_id = 0
         self._running = True
         self.latencies: List[float] = []
@@ -273,11 +277,20 @@ class Server:
                     self._lock.wait(0.05)
                 if not self._running:
                     return
-                head = self._queue[0]
+                # the oldest query, except that misses may not take the last free slot
+                # (with one slot there is no such limit)
+                head = None
+                for q in self._queue:
+                    if q.dep in self._chan or self.n_slots == 1 or self._misses_running < self.n_slots - 1:
+                        head = q
+                        break
+                if head is None:
+                    self._lock.wait(0.01)
+                    continue
                 batch = [head]
                 cols = head.gamma.shape[1]
-                for q in self._queue[1:]:
-                    if q.dep == head.dep and q.precision == head.precision and q.scale == head.scale \
+                for q in self._queue:
+                    if q is not head and q.dep == head.dep and q.precision == head.precision and q.scale == head.scale \
                             and cols + q.gamma.shape[1] <= self.max_cols:
                         batch.append(q)
                         cols += q.gamma.shape[1]
@@ -293,7 +306,9 @@ class Server:
                     self._queue.remove(q)
                 slot = self._free_slots.pop()
                 self._reserved += est
-            self._work[slot].put((batch, est))
+                miss = head.dep not in self._chan
+                self._misses_running += miss
+            self._work[slot].put((batch, est, miss))
 
     def _worker(self, slot: int) -> None:
         while True:
@@ -360,7 +375,7 @@ class Server:
         for _, h in victims:
             self.ctx.destroy(h)
 
-    def _run_batch(self, slot: int, batch: List[_Query], est: int) -> None:
+    def _run_batch(self, slot: int, batch: List[_Query], est: int, miss: bool = False) -> None:
         torch = self._torch
         stream = self._streams[slot]
         dep = self._deps[batch[0].dep]
@@ -437,6 +452,7 @@ class Server:
                 if held:
                     self._in_use[dep.key] -= 1
                 self._reserved -= est
+                self._misses_running -= miss
                 self._free_slots.append(slot)
                 self._lock.notify_all()
 
