@@ -49,33 +49,34 @@ FLOPS_PER_PAIR_HIGH = 300
 SQ_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_ris_lab_room_sq_counters.json")
 KERNEL_SOURCES = ["paper_2402_13034_amd/csrc/rt_trace.hip", "paper_2402_13034_amd/csrc/rt_internal.hpp"]
 COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_ris_lab_room_hbm_counters.json")
+DISC_COUNTERS_FILE = os.path.join(ROOT, "profiles", "k_discover_office_floor_hbm_counters.json")
 
 
-def kernel_source_hash():
-    """Hash of what the per-element kernel is compiled from: the device header
-    and the kernel's own text in the trace source (its template line to the
-    closing brace), so host-side changes elsewhere in the file keep it."""
+def kernel_source_hash(kernel="k_ris"):
+    """Hash of what a trace kernel is compiled from: the device header and the
+    kernel's own text in the trace source (its template line to the closing
+    brace), so host-side changes elsewhere in the file keep it."""
     import hashlib
     h = hashlib.sha256()
     with open(os.path.join(ROOT, KERNEL_SOURCES[1]), "rb") as f:
         h.update(f.read())
     with open(os.path.join(ROOT, KERNEL_SOURCES[0])) as f:
         lines = f.read().split("\n")
-    start = next(i for i, l in enumerate(lines) if " void k_ris(" in l) - 1
+    start = next(i for i, l in enumerate(lines) if (" void %s(" % kernel) in l) - 1
     end = next(i for i in range(start, len(lines)) if lines[i] == "}")
     h.update("\n".join(lines[start:end + 1]).encode())
     return h.hexdigest()[:16]
 
 
-def measured_traffic():
-    """HBM bytes per k_ris launch from the committed counter summary, if it
-    was taken on the current kernel sources."""
+def measured_traffic(path=COUNTERS_FILE, kernel="k_ris"):
+    """HBM bytes per launch of a kernel from a committed counter summary, if
+    it was taken on the current kernel sources."""
     try:
-        with open(COUNTERS_FILE) as f:
+        with open(path) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("source_hash") != kernel_source_hash():
+    if d.get("source_hash") != kernel_source_hash(kernel):
         return None
     return d.get("bytes_per_launch")
 
@@ -322,7 +323,8 @@ def run_large_bench(ctx, reps=2):
             "stage_ms": stage[-1]["ms_stage"], "discovery_kernel_ms": {"tx": ms_tx, "both_span": ms_span},
             "roofline_discovery": {"kernel": "k_discover (Tx, 1e7 rays, order 5)", "bound": "hbm",
                                    "achieved": ach_tx, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                                   "frac": ach_tx / HBM_PEAK_GBS, "traffic": None,
+                                   "frac": ach_tx / HBM_PEAK_GBS,
+                                   "traffic": measured_traffic(DISC_COUNTERS_FILE, "k_discover"),
                                    "work_per_launch": units_tx, "bytes_per_unit": DISC_BYTES,
                                    "both_sources": {"achieved": ach_all, "frac": ach_all / HBM_PEAK_GBS,
                                                     "work": units_all}},
