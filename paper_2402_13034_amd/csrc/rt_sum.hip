@@ -30,6 +30,19 @@ static inline int64_t round_up(int64_t x, int64_t m) { return (x + m - 1) / m * 
 // --------------------------------------------------------------------------
 constexpr int VT = 64;   // tile of receivers and of configurations
 constexpr int VK = 16;   // k tile
+constexpr int VN = 4;    // configurations of the narrow kernel (one per thread)
+
+// One complex multiply-add of the VALU sums, as four explicit FMAs in a fixed
+// order: both VALU kernels take it over the elements in increasing order, so
+// an output does not depend on which kernel, tile or batch of configurations
+// computed it.
+__device__ __forceinline__ void cmac(float2 h, float2 g, float& ar, float& ai)
+{
+    ar = __builtin_fmaf(h.x, g.x, ar);
+    ar = __builtin_fmaf(-h.y, g.y, ar);
+    ai = __builtin_fmaf(h.x, g.y, ai);
+    ai = __builtin_fmaf(h.y, g.x, ai);
+}
 
 __global__ __launch_bounds__(256) void k_sum_valu(const float2* H, const float2* G, const float2* Eenv, int64_t R,
                                                   int64_t M, int64_t C, float scale, float2* Eout, float* Pout)
@@ -55,10 +68,7 @@ __global__ __launch_bounds__(256) void k_sum_valu(const float2* H, const float2*
             for (int i = 0; i < 4; ++i) h[i] = sh[kk][ty * 4 + i];
             for (int j = 0; j < 4; ++j) g[j] = sg[kk][tx * 4 + j];
             for (int i = 0; i < 4; ++i)
-                for (int j = 0; j < 4; ++j) {
-                    accr[i][j] += h[i].x * g[j].x - h[i].y * g[j].y;
-                    acci[i][j] += h[i].x * g[j].y + h[i].y * g[j].x;
-                }
+                for (int j = 0; j < 4; ++j) cmac(h[i], g[j], accr[i][j], acci[i][j]);
         }
         __syncthreads();
     }
@@ -74,6 +84,43 @@ __global__ __launch_bounds__(256) void k_sum_valu(const float2* H, const float2*
             if (Eout) Eout[r * C + c] = make_float2(er, ei);
             if (Pout) Pout[r * C + c] = (er * er + ei * ei) / (2.0f * ETA0_F);
         }
+    }
+}
+
+// Few configurations (C <= VN): a block takes 64 receivers x VN configurations,
+// one output per thread, so a one-configuration sum still spreads over R / 64
+// blocks instead of filling 1/64 of a square tile.
+__global__ __launch_bounds__(256) void k_sum_valu_narrow(const float2* H, const float2* G, const float2* Eenv,
+                                                         int64_t R, int64_t M, int64_t C, float scale, float2* Eout,
+                                                         float* Pout)
+{
+    __shared__ float2 sh[VK][VT + 1];
+    __shared__ float2 sg[VK][VN];
+    const int j = threadIdx.x & (VN - 1), i = threadIdx.x / VN;   // configuration, receiver in the tile
+    const int64_t r0 = (int64_t)blockIdx.x * VT;
+    float ar = 0.0f, ai = 0.0f;
+    for (int64_t k0 = 0; k0 < M; k0 += VK) {
+        for (int e = threadIdx.x; e < VK * VT; e += 256) {
+            const int rr = e / VK, kk = e % VK;   // consecutive threads: consecutive elements of a row
+            const int64_t r = r0 + rr, m = k0 + kk;
+            sh[kk][rr] = (r < R && m < M) ? H[r * M + m] : make_float2(0.0f, 0.0f);
+        }
+        if (threadIdx.x < VK * VN) {
+            const int kk = threadIdx.x / VN, cc = threadIdx.x % VN;
+            const int64_t m = k0 + kk;
+            sg[kk][cc] = (cc < C && m < M) ? G[m * C + cc] : make_float2(0.0f, 0.0f);
+        }
+        __syncthreads();
+        for (int kk = 0; kk < VK; ++kk) cmac(sh[kk][i], sg[kk][j], ar, ai);
+        __syncthreads();
+    }
+    const int64_t r = r0 + i;
+    if (r < R && j < C) {
+        const float2 e0 = Eenv[r];
+        const float er = e0.x + scale * ar;
+        const float ei = e0.y + scale * ai;
+        if (Eout) Eout[r * C + j] = make_float2(er, ei);
+        if (Pout) Pout[r * C + j] = (er * er + ei * ei) / (2.0f * ETA0_F);
     }
 }
 
@@ -606,9 +653,15 @@ static void launch_product(const Channel& ch, const SumShape& sh, const float2* 
 static void launch_valu(const Channel& ch, const float2* G, int64_t C, float scale, float* E_out, float* P_out,
                         hipStream_t st)
 {
-    dim3 grid(nblk(C, VT), nblk(ch.R, VT));
-    hipLaunchKernelGGL(k_sum_valu, grid, dim3(256), 0, st, ch.H.as<float2>(), G, ch.E_env.as<float2>(), ch.R, ch.M, C,
-                       scale, (float2*)E_out, P_out);
+    static_assert(VT * VN == 256, "one output per thread in the narrow kernel");
+    if (C <= VN) {
+        hipLaunchKernelGGL(k_sum_valu_narrow, dim3(nblk(ch.R, VT)), dim3(256), 0, st, ch.H.as<float2>(), G,
+                           ch.E_env.as<float2>(), ch.R, ch.M, C, scale, (float2*)E_out, P_out);
+    } else {
+        dim3 grid(nblk(C, VT), nblk(ch.R, VT));
+        hipLaunchKernelGGL(k_sum_valu, grid, dim3(256), 0, st, ch.H.as<float2>(), G, ch.E_env.as<float2>(), ch.R,
+                           ch.M, C, scale, (float2*)E_out, P_out);
+    }
     HIP_CHECK(hipGetLastError());
 }
 

@@ -563,12 +563,34 @@ def _gemm_case(ctx, R, M, C, real, precision, seed=0):
     return E, P, E_ref, P_ref, P_inc
 
 
-@pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (257, 1024, 129, True)])
+@pytest.mark.parametrize("R,M,C,real", [(37, 49, 5, True), (130, 127, 200, False), (257, 1024, 129, True),
+                                        # the narrow kernel (at most 4 configurations)
+                                        (4096, 127, 1, True), (300, 70, 3, False), (65, 16, 4, True)])
 def test_ris_sum_valu(ctx, R, M, C, real):
     E, P, E_ref, P_ref, P_inc = _gemm_case(ctx, R, M, C, real, 0)
     sel = P_ref >= 1e-3 * P_inc
     assert np.max(np.abs(P[sel] / P_ref[sel] - 1)) < 1e-4
     assert np.max(np.abs(E - E_ref) ** 2 / np.maximum(np.abs(E_ref) ** 2, 1e-3 * (P_inc * 2 * ETA0))) < 1e-6
+
+
+def test_ris_sum_valu_column_independent_of_batch(ctx):
+    """A configuration's VALU result is the same bits alone (narrow kernel, one
+    to four configurations) and inside a batch of many (tiled kernel)."""
+    import torch
+    from paper_2402_13034_amd import risrt
+    rng = np.random.default_rng(17)
+    R, M, C = 257, 131, 70
+    H = (rng.normal(size=(R, M)) + 1j * rng.normal(size=(R, M))).astype(np.complex64)
+    E = (rng.normal(size=R) + 1j * rng.normal(size=R)).astype(np.complex64)
+    G = (rng.normal(size=(M, C)) + 1j * rng.normal(size=(M, C))).astype(np.complex64)
+    ch = ctx.channel_create(E, H)
+    Ef, _ = ctx.ris_sum(ch, torch.from_numpy(G).cuda(), scale=0.7, precision=risrt.PREC_VALU_F32, want_E=True)
+    full = Ef.cpu().numpy()
+    for cols in ([0], [5, 6, 7], [10, 20, 30, 40], [69]):
+        g = torch.from_numpy(np.ascontiguousarray(G[:, cols])).cuda()
+        Es, _ = ctx.ris_sum(ch, g, scale=0.7, precision=risrt.PREC_VALU_F32, want_E=True)
+        assert Es.cpu().numpy().tobytes() == np.ascontiguousarray(full[:, cols]).tobytes(), cols
+    ctx.destroy(ch)
 
 
 @pytest.mark.parametrize("prec", [1, 2, 3])
