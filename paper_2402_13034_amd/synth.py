@@ -550,7 +550,7 @@ def office_floor_scene(rng, nx: int = 20, ny: int = 10, room: float = 2.0, heigh
                        cell_wall: float = 0.18, cell_floor: float = 0.1, cell_clutter: float = 0.08,
                        coef=(0.2, 0.8)) -> Scene:
     """An office floor of nx x ny rooms of room x room metres (40 x 20 x 3 m
-    for the defaults), like SURVEY's large configuration: floor and ceiling
+    for the defaults), the large indoor configuration: floor and ceiling
     tiles per room; partitions between neighbouring rooms as wall-thick boxes
     from floor to ceiling, a seeded fraction of them with a door gap (two
     boxes); the outer walls as boxes; `clutter` furniture boxes per room
@@ -610,7 +610,7 @@ def office_floor_scene(rng, nx: int = 20, ny: int = 10, room: float = 2.0, heigh
 
 def office_floor(seed: int = BASE_SEED + 4, n_rays: int = 10_000_000, order: int = 5, n_rx: int = 256,
                  n_side: int = 64, rx_region=None, n_cfg: int = 1, **scene_kw) -> Problem:
-    """SURVEY's large configuration: the office floor (about 10^6 triangles
+    """The large configuration: an office floor (about 10^6 triangles
     with the defaults), 28 GHz, a 64 x 64 square RIS (lambda/2) 1 mm in front
     of the partition wall x = 10 m of room (4, 4) facing -x, a horn Tx
     (cos^8, G_t = 18) in that room aimed at the RIS centre, an n_rx x n_rx
