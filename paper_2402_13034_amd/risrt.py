@@ -489,7 +489,12 @@ def read_channel_file(path: str):
         E, H, raw = f["E_env"], f["H"], f["meta"]
     if raw.shape != () or raw.dtype.kind != "U":
         raise ValueError("%s: meta is not a string" % path)
-    meta = json.loads(str(raw))
+    try:
+        meta = json.loads(str(raw))
+    except json.JSONDecodeError as e:
+        raise ValueError("%s: meta is not JSON (%s)" % (path, e)) from None
+    if not isinstance(meta, dict):
+        raise ValueError("%s: meta is not a JSON object" % path)
     if meta.get("version") != CHANNEL_FILE_VERSION:
         raise ValueError("%s: channel file version %r" % (path, meta.get("version")))
     if E.dtype != np.complex64 or H.dtype != np.complex64:

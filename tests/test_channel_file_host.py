@@ -37,7 +37,8 @@ def test_empty_channel(tmp_path):
     assert E2.shape == (0,) and H2.shape == (0, 4)
 
 
-@pytest.mark.parametrize("mistake", ["dtype", "rows", "meta_shape", "nan", "version", "missing", "pickled"])
+@pytest.mark.parametrize("mistake", ["dtype", "rows", "meta_shape", "nan", "version", "missing", "pickled",
+                                     "meta_not_json", "meta_not_object"])
 def test_rejects(tmp_path, mistake):
     E, H = _good()
     p = tmp_path / "bad.npz"
@@ -56,6 +57,10 @@ def test_rejects(tmp_path, mistake):
         np.savez(p, E_env=E, H=H)
     elif mistake == "pickled":
         np.savez(p, E_env=E, H=H, meta=np.array([{"version": 1}], dtype=object))
+    elif mistake == "meta_not_json":
+        np.savez(p, E_env=E, H=H, meta=np.array("{version: 1"))
+    elif mistake == "meta_not_object":
+        np.savez(p, E_env=E, H=H, meta=np.array(json.dumps([1, 5, 3])))
     with pytest.raises(ValueError):
         risrt.read_channel_file(str(p))
 
