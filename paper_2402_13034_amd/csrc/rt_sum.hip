@@ -518,12 +518,14 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
         }
         if (kt < nk) body(st0, st1, kt);
         if (kt + 1 < nk) body(st1, st2, kt + 1);
-        G2_SYNC(G2_STAGE_WAIT_0);   // the repeated loads landed and every LDS read is done
         // epilogue: lane holds column (lane & 31); values e: row 8 (e / 4) + 4 (lane / 32) + (e % 4),
-        // receiver = row / 2.  E_env and the row scales are loaded first, then the
-        // next tile's stages
+        // receiver = row / 2.  E_env and the row scales are loaded ahead of the wait that ends
+        // the tile's products, so that wait covers them and the stores wait for nothing
+        // (loaded after the next tile's stages, the compiler's waits for them would also
+        // hold back those stages, and its waits for the stage reads after the loop would
+        // no longer be exact)
         float2 ev[2][4][2];
-        float sv[2][4][2];
+        int32_t sx[2][4][2];
 #pragma unroll
         for (int i = 0; i < 2; ++i)
 #pragma unroll
@@ -533,8 +535,9 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
                     int64_t r = (row0 + wm + i * 32 + 8 * eb + 4 * (lane >> 5) + 2 * h) >> 1;
                     r = r < R ? r : R - 1;
                     ev[i][eb][h] = Eenv[r];
-                    sv[i][eb][h] = F16 ? ldexpf(scale, -sexp[r]) : scale;   // exact: a power of two
+                    sx[i][eb][h] = F16 ? sexp[r] : 0;
                 }
+        G2_SYNC(G2_STAGE_WAIT_0);   // the repeated loads and E_env landed, every LDS read is done
         asm volatile("" ::: "memory");
         const int t2 = t + (int)gridDim.x;
         if (t2 < T) {
@@ -551,7 +554,7 @@ __global__ __launch_bounds__(512) void k_sum_mfma_2x(const uint16_t* __restrict_
                     const int64_t r = (row0 + wm + i * 32 + 8 * (e / 4) + 4 * (lane >> 5) + (e % 4)) >> 1;
                     if (r >= R || c >= C) continue;
                     const float2 e0 = ev[i][e / 4][(e % 4) / 2];
-                    const float sr = sv[i][e / 4][(e % 4) / 2];
+                    const float sr = F16 ? ldexpf(scale, -sx[i][e / 4][(e % 4) / 2]) : scale;   // exact: a power of two
                     const float er = e0.x + sr * acc[i][j][e];
                     const float ei = e0.y + sr * acc[i][j][e + 1];
                     // streaming stores: the outputs are not read again here, and they drain
