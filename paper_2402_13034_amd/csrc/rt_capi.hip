@@ -684,6 +684,8 @@ rt_status rt_trace(rt_ctx ctx, uint64_t scene, uint64_t ris, const rt_tx* tx, co
         a.n_rays = params->n_rays;
         TraceConst& tc = a.tc;
         tc.lambda = 299792458.0 / params->freq_hz;
+        tc.inv_lambda = 1.0 / tc.lambda;
+        tc.lam_4pi = (float)(tc.lambda / (4.0 * 3.141592653589793));
         tc.two_eta0_pt_gt = 2.0 * 120.0 * 3.141592653589793 * tx->power_w * tx->gain;
         for (int k = 0; k < 3; ++k) tc.tx[k] = tx->pos[k];
         fill_antenna(tc.txa, tx->axis, tx->gain, tx->pattern, tx->param);

@@ -94,6 +94,9 @@ struct TraceConst {
     int32_t fresnel;       // 0: fixed coefficients; 1 TE, 2 TM Fresnel coefficients of the materials
     int32_t pad;
     double sig_scale;      // 1 / (omega eps0): eps = eps_r - j sigma sig_scale
+    double inv_lambda;     // 1 / lambda (phase in turns = length x this)
+    float lam_4pi;         // lambda / (4 pi) in FP32 (free-space amplitude factor over the length)
+    int32_t pad2;
 };
 
 struct RisView {
@@ -1040,9 +1043,9 @@ __device__ __forceinline__ float pattern_amp(int kind, double param, double c64)
 {
     c64 = fmin(1.0, fmax(-1.0, c64));
     if (kind == 0) return 1.0f;
-    if (kind == 1) {
+    if (kind == 1) {   // 2^((p/2) log2 c) with the hardware's base-2 logarithm and exponential (1 ulp each)
         const float c = (float)c64;
-        return c > 0.0f ? powf(c, (float)(0.5 * param)) : 0.0f;
+        return c > 0.0f ? __builtin_amdgcn_exp2f((float)(0.5 * param) * __builtin_amdgcn_logf(c)) : 0.0f;
     }
     const double s2 = 1.0 - c64 * c64;   // sin^2(theta) in FP64: no cancellation to 0 near the axis
     if (!(s2 > 0.0)) return 0.0f;
@@ -1050,13 +1053,14 @@ __device__ __forceinline__ float pattern_amp(int kind, double param, double c64)
     return fabsf(cosf(kh * c) - cosf(kh)) / sqrtf((float)s2);
 }
 
-// e^{-j 2 pi d / lambda} = e^{-j 2 pi f}, f = frac(d / lambda) taken in FP64;
-// cosine and sine of the fraction of a turn by the hardware's v_cos/v_sin
-// (their argument is in turns).
-__device__ __forceinline__ void phase_cs(double d, double lambda, float& cs, float& sn)
+// e^{-j 2 pi d / lambda} = e^{-j 2 pi f}, f = frac(d / lambda) taken in FP64
+// (d times 1 / lambda: a relative error of a few 1e-16 in turns); cosine and
+// sine of the fraction of a turn by the hardware's v_cos/v_sin (their argument
+// is in turns).
+__device__ __forceinline__ void phase_cs(double d, double inv_lambda, float& cs, float& sn)
 {
 #pragma clang fp contract(off)
-    const double x = d / lambda;
+    const double x = d * inv_lambda;
     const float f = (float)(x - floor(x));
     cs = __builtin_amdgcn_cosf(f);
     sn = -__builtin_amdgcn_sinf(f);

@@ -659,7 +659,8 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                 vl[q] = L[q] - X[q];
             }
             const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
-            const double cr = cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm);
+            // an isotropic receiver's pattern neither gates nor weights: no angle needed
+            const double cr = tc.rxa.pattern != 0 ? cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm) : 1.0;
             Ft = pattern_amp(tc.txa.pattern, tc.txa.param, ct);
             Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);
             ok = pattern_on(tc.txa.pattern, ct) && pattern_on(tc.rxa.pattern, cr);
@@ -713,9 +714,9 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                     ai = ni;
                 }
                 float mag = sqrtf((float)tc.two_eta0_pt_gt) * Ft * sqrtf((float)tc.rxa.gain) * Fr *
-                            (float)(tc.lambda / (4.0 * 3.141592653589793 * D));
+                            (tc.lam_4pi * __builtin_amdgcn_rcpf((float)D));
                 float cs, sn;
-                phase_cs(D, tc.lambda, cs, sn);
+                phase_cs(D, tc.inv_lambda, cs, sn);
                 a = make_float2(mag * (ar * cs - ai * sn), mag * (ar * sn + ai * cs));
             }
             amp[i] = a;
@@ -875,7 +876,7 @@ __global__ __launch_bounds__(64) void k_txm(SceneView s, TraceConst tc, RisView 
             const float fac = (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
                                       sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / dt);
             float cs, sn;
-            phase_cs(dt, tc.lambda, cs, sn);
+            phase_cs(dt, tc.inv_lambda, cs, sn);
             r.T = make_float2(fac * cs, fac * sn);
         }
         out[m] = r;
@@ -1005,7 +1006,7 @@ __global__ __launch_bounds__(LEG_B) void k_in_elem(SceneView s, CandView cv, Tra
             const float mag = (float)(sqrt(tc.two_eta0_pt_gt) * (double)Ft *
                                       sqrt(rv.gain * rv.dy * rv.dz / (4.0 * 3.141592653589793)) * (double)Fin / D);
             float cs, sn;
-            phase_cs(D, tc.lambda, cs, sn);
+            phase_cs(D, tc.inv_lambda, cs, sn);
             a = make_float2(mag * (ar * cs - ai * sn), mag * (ar * sn + ai * cs));
             emitted = 1;
         }
@@ -1183,7 +1184,8 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                     double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
                     double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
                     const double co = cos_between(v1, rv.normal, rv.normal_norm);
-                    const double cr = cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm);
+                    const double cr =
+                        tc.rxa.pattern != 0 ? cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm) : 1.0;   // as in k_paths
                     Fout = pattern_amp(1, rv.q, co);                           // sqrt(F_out)
                     Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);        // sqrt(F_r)
                     ok = pattern_on(1, co) && pattern_on(tc.rxa.pattern, cr);
@@ -1230,10 +1232,9 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         ar = nr;
                         ai = ni;
                     }
-                    const float mag = Fout * sqrtf((float)tc.rxa.gain) * Fr *
-                                      (float)(tc.lambda / (4.0 * 3.141592653589793 * Dr));
+                    const float mag = Fout * sqrtf((float)tc.rxa.gain) * Fr * (tc.lam_4pi * __builtin_amdgcn_rcpf((float)Dr));
                     float cs, sn;
-                    phase_cs(Dr, tc.lambda, cs, sn);
+                    phase_cs(Dr, tc.inv_lambda, cs, sn);
                     // incoming field x reflections x out-going phase
                     const float zr = t.T.x * ar - t.T.y * ai, zi = t.T.x * ai + t.T.y * ar;
                     amp_r = mag * (zr * cs - zi * sn);
