@@ -464,14 +464,16 @@ int64_t or_discover(const float* V, const int32_t* T, int64_t nt, const double s
 /* The leg A -> B (FP64 end points) is blocked if some triangle that is not
  * part of surface skip_a or skip_b (the surfaces its end points lie on, -1 for
  * none) is met at EPS < t < L - EPS by the FP32 ray with origin fl(A) and
- * direction fl((B - A) / L). */
+ * direction fl((B - A) x (1 / L)) (one correctly rounded division, three
+ * products). */
 static int leg_blocked(const tri32* tris, const int32_t* surf, int64_t nt, const double A[3],
                        const double B[3], int64_t skip_a, int64_t skip_b)
 {
     double w0 = B[0] - A[0], w1 = B[1] - A[1], w2 = B[2] - A[2];
     double L = sqrt(w0 * w0 + w1 * w1 + w2 * w2);
     rfloat o[3] = {(rfloat)A[0], (rfloat)A[1], (rfloat)A[2]};
-    rfloat d[3] = {(rfloat)(w0 / L), (rfloat)(w1 / L), (rfloat)(w2 / L)};
+    double il = 1.0 / L;
+    rfloat d[3] = {(rfloat)(w0 * il), (rfloat)(w1 * il), (rfloat)(w2 * il)};
     rfloat tmin = (rfloat)OR_EPS;
     rfloat tmax = (rfloat)(L - OR_EPS);
 #pragma omp atomic

@@ -333,7 +333,7 @@ __device__ bool any_hit(const SceneView& s, float ox, float oy, float oz, float 
     return false;
 }
 
-// Leg A -> B blocked?  FP32 ray from fl(A) along fl((B - A) / L), EPS < t < L - EPS,
+// Leg A -> B blocked?  FP32 ray from fl(A) along fl((B - A) x (1 / L)), EPS < t < L - EPS,
 // ignoring the surfaces sa, sb of its end points.
 template <bool BRUTE, bool CNT = false>
 __device__ bool leg_blocked(const SceneView& s, const double* A, const double* B, int sa, int sb,
@@ -345,8 +345,9 @@ __device__ bool leg_blocked(const SceneView& s, const double* A, const double* B
     float tmin = (float)RT_EPS;
     float tmax = (float)(L - RT_EPS);
     if (!(tmax > tmin)) return false;
-    return any_hit<BRUTE, CNT>(s, (float)A[0], (float)A[1], (float)A[2], (float)(w0 / L), (float)(w1 / L),
-                               (float)(w2 / L), tmin, tmax, sa, sb, stack, stride, wc);
+    const double il = 1.0 / L;
+    return any_hit<BRUTE, CNT>(s, (float)A[0], (float)A[1], (float)A[2], (float)(w0 * il), (float)(w1 * il),
+                               (float)(w2 * il), tmin, tmax, sa, sb, stack, stride, wc);
 }
 
 // --------------------------------------------------------------------------
@@ -1051,6 +1052,31 @@ __device__ __forceinline__ float pattern_amp(int kind, double param, double c64)
     if (!(s2 > 0.0)) return 0.0f;
     const float c = (float)c64, kh = (float)(6.283185307179586 * param);
     return fabsf(cosf(kh * c) - cosf(kh)) / sqrtf((float)s2);
+}
+
+// Gate and amplitude factor sqrt(F) of a pattern for the direction v against
+// its axis.  For cos^p the gate (cos > 0) is the sign of v . axis, the
+// cosine's numerator (the same decision as the FP64 cosine's sign: its
+// denominator is positive), and the amplitude needs the cosine only in FP32;
+// the monopole's gate needs the FP64 cosine itself; the isotropic pattern
+// needs neither.
+__device__ __forceinline__ bool pattern_gate_amp(int kind, double param, const double* v, const double* axis,
+                                                 double axis_norm, float& amp)
+{
+    if (kind == 0) {
+        amp = 1.0f;
+        return true;
+    }
+    if (kind == 1) {
+        const double dn = v[0] * axis[0] + v[1] * axis[1] + v[2] * axis[2];
+        const float vv = (float)(v[0] * v[0] + v[1] * v[1] + v[2] * v[2]);
+        const float c = fminf(1.0f, (float)dn * __builtin_amdgcn_rsqf(vv) * __builtin_amdgcn_rcpf((float)axis_norm));
+        amp = c > 0.0f ? __builtin_amdgcn_exp2f((float)(0.5 * param) * __builtin_amdgcn_logf(c)) : 0.0f;
+        return dn > 0.0;
+    }
+    const double c = cos_between(v, axis, axis_norm);
+    amp = pattern_amp(kind, param, c);
+    return pattern_on(kind, c);
 }
 
 // e^{-j 2 pi d / lambda} = e^{-j 2 pi f}, f = frac(d / lambda) taken in FP64

@@ -658,12 +658,9 @@ __global__ __launch_bounds__(LEG_B) void k_paths(SceneView s, CandView cv, Trace
                 v1[q] = V[1][q] - S[q];
                 vl[q] = L[q] - X[q];
             }
-            const double ct = cos_between(v1, tc.txa.axis, tc.txa.axis_norm);
-            // an isotropic receiver's pattern neither gates nor weights: no angle needed
-            const double cr = tc.rxa.pattern != 0 ? cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm) : 1.0;
-            Ft = pattern_amp(tc.txa.pattern, tc.txa.param, ct);
-            Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);
-            ok = pattern_on(tc.txa.pattern, ct) && pattern_on(tc.rxa.pattern, cr);
+            const bool on_t = pattern_gate_amp(tc.txa.pattern, tc.txa.param, v1, tc.txa.axis, tc.txa.axis_norm, Ft);
+            const bool on_r = pattern_gate_amp(tc.rxa.pattern, tc.rxa.param, vl, tc.rxa.axis, tc.rxa.axis_norm, Fr);
+            ok = on_t && on_r;
         }
         int sq[KM];
 #pragma unroll
@@ -1183,12 +1180,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                     for (int q = 0; q < 3; ++q) f[q] = k ? P[0][q] : X[q];
                     double v1[3] = {f[0] - E[0], f[1] - E[1], f[2] - E[2]};
                     double vl[3] = {l[0] - X[0], l[1] - X[1], l[2] - X[2]};
-                    const double co = cos_between(v1, rv.normal, rv.normal_norm);
-                    const double cr =
-                        tc.rxa.pattern != 0 ? cos_between(vl, tc.rxa.axis, tc.rxa.axis_norm) : 1.0;   // as in k_paths
-                    Fout = pattern_amp(1, rv.q, co);                           // sqrt(F_out)
-                    Fr = pattern_amp(tc.rxa.pattern, tc.rxa.param, cr);        // sqrt(F_r)
-                    ok = pattern_on(1, co) && pattern_on(tc.rxa.pattern, cr);
+                    const bool on_o = pattern_gate_amp(1, rv.q, v1, rv.normal, rv.normal_norm, Fout);   // sqrt(F_out)
+                    const bool on_r =
+                        pattern_gate_amp(tc.rxa.pattern, tc.rxa.param, vl, tc.rxa.axis, tc.rxa.axis_norm, Fr);   // sqrt(F_r)
+                    ok = on_o && on_r;
                 }
                 double Dr = 0.0;
                 double Lk[KM + 1];   // leg lengths (the Fresnel angles use them)
@@ -1207,9 +1202,10 @@ __global__ __launch_bounds__(RIS_B, RT_RIS_WAVES_PER_SIMD) void k_ris(SceneView 
                         lb[0 * 64] = (float)A[0];
                         lb[1 * 64] = (float)A[1];
                         lb[2 * 64] = (float)A[2];
-                        lb[3 * 64] = (float)(w0 / L);
-                        lb[4 * 64] = (float)(w1 / L);
-                        lb[5 * 64] = (float)(w2 / L);
+                        const double il = 1.0 / L;   // the leg ray's direction as leg_blocked forms it
+                        lb[3 * 64] = (float)(w0 * il);
+                        lb[4 * 64] = (float)(w1 * il);
+                        lb[5 * 64] = (float)(w2 * il);
                         lb[6 * 64] = (float)(L - RT_EPS);
                     }
                 }
